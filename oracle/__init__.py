@@ -1,0 +1,212 @@
+"""CPU oracle for AOT triangle listing -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The product library never loads it and
+shares no code with it.  The arithmetic lives in ``oracle.c`` (plain C, one
+thread); this file only builds it with gcc and marshals numpy arrays.
+
+Section references are to Yu et al., "AOT: Pushing the Efficiency Boundary of
+Main-memory Triangle Listing" (2020).
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+_i32p = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+_i64p = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
+_u64p = np.ctypeslib.ndpointer(dtype=np.uint64, flags="C_CONTIGUOUS")
+
+
+def build() -> str:
+    """Compile oracle.c into liboracle.so with gcc (always recompiles)."""
+    tmp = _LIB + ".tmp"
+    subprocess.check_call(["gcc", "-O2", "-std=c99", "-shared", "-fPIC", "-o", tmp, _SRC])
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        build()
+    lib = ctypes.CDLL(_LIB)
+    i32, i64, u64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
+    lib.orc_orient.argtypes = [i32, _i64p, _i32p, _i32p, _i32p, _i64p, _i32p]
+    lib.orc_orient.restype = i64
+    lib.orc_edge_counts.argtypes = [i32, _i64p, _i32p, i64, i64, _i32p]
+    lib.orc_edge_counts.restype = None
+    lib.orc_edge_counts_at.argtypes = [i32, _i64p, _i32p, _i64p, i64, _i32p]
+    lib.orc_edge_counts_at.restype = None
+    lib.orc_list.argtypes = [i32, _i64p, _i32p, _i32p, i32, i32, _i32p, i64]
+    lib.orc_list.restype = i64
+    lib.orc_sum_min.argtypes = [i32, _i64p, _i32p]
+    lib.orc_sum_min.restype = u64
+    lib.orc_sum_head.argtypes = [i32, _i64p, _i32p]
+    lib.orc_sum_head.restype = u64
+    lib.orc_aot_ref.argtypes = [i32, _i64p, _i32p, ctypes.c_int, _i32p, i64, ctypes.POINTER(u64)]
+    lib.orc_aot_ref.restype = i64
+    lib.orc_fingerprint.argtypes = [_i32p, i64, _u64p, ctypes.c_void_p]
+    lib.orc_fingerprint.restype = None
+    lib.orc_list_digest.argtypes = [i32, _i64p, _i32p, _i32p, i32, i32, _u64p, ctypes.c_void_p]
+    lib.orc_list_digest.restype = i64
+    lib.orc_splitmix64.argtypes = [u64]
+    lib.orc_splitmix64.restype = u64
+    _lib = lib
+    return lib
+
+
+def _arrays(rowptr, col):
+    rowptr = np.ascontiguousarray(np.asarray(rowptr), dtype=np.int64)
+    col = np.ascontiguousarray(np.asarray(col), dtype=np.int32)
+    return rowptr, col
+
+
+class Oriented:
+    """Oriented graph in rank space (rank = position in the degree order)."""
+
+    def __init__(self, n, perm, rank, orow, ocol):
+        self.n, self.perm, self.rank, self.orow, self.ocol = n, perm, rank, orow, ocol
+
+    @property
+    def m(self) -> int:
+        return int(self.orow[-1])
+
+    @property
+    def dplus(self):
+        return np.diff(self.orow)
+
+    def tail(self):
+        return np.repeat(np.arange(self.n, dtype=np.int32), self.dplus)
+
+
+def orient(rowptr, col) -> Oriented:
+    """Degree order with id tie-break; <u,v> iff eta(u) < eta(v) (Sec. 2.2)."""
+    lib = _load()
+    rowptr, col = _arrays(rowptr, col)
+    n = rowptr.size - 1
+    perm = np.empty(max(n, 1), np.int32)
+    rank = np.empty(max(n, 1), np.int32)
+    orow = np.empty(n + 1, np.int64)
+    ocol = np.empty(max(col.size // 2, 1), np.int32)
+    m = lib.orc_orient(n, rowptr, col, perm, rank, orow, ocol)
+    if m < 0:
+        raise MemoryError("oracle orientation failed")
+    return Oriented(n, perm[:n], rank[:n], orow, ocol[:m].copy())
+
+
+def edge_counts(o: Oriented, e_lo: int = 0, e_hi: int | None = None) -> np.ndarray:
+    """|N+(u) n N+(v)| for each directed edge in [e_lo, e_hi) (Algorithm 1, line 4)."""
+    lib = _load()
+    e_hi = o.m if e_hi is None else e_hi
+    out = np.zeros(max(e_hi - e_lo, 1), np.int32)
+    lib.orc_edge_counts(o.n, o.orow, _nonempty(o.ocol), e_lo, e_hi, out)
+    return out[: e_hi - e_lo]
+
+
+def edge_counts_at(o: Oriented, eids) -> np.ndarray:
+    lib = _load()
+    eids = np.ascontiguousarray(eids, dtype=np.int64)
+    out = np.zeros(max(eids.size, 1), np.int32)
+    if eids.size:
+        lib.orc_edge_counts_at(o.n, o.orow, _nonempty(o.ocol), eids, eids.size, out)
+    return out[: eids.size]
+
+
+def _nonempty(a):
+    return a if a.size else np.zeros(1, a.dtype)
+
+
+def list_triangles(o: Oriented, r_lo: int = 0, r_hi: int | None = None, cap: int | None = None) -> np.ndarray:
+    """Algorithm 1 (CF) over sources [r_lo, r_hi): (T, 3) int32, ascending ids
+    per row, in edge order then ascending third vertex."""
+    lib = _load()
+    r_hi = o.n if r_hi is None else r_hi
+    if cap is None:
+        cap = int(edge_counts(o, int(o.orow[r_lo]), int(o.orow[r_hi])).sum()) if r_hi > r_lo else 0
+    out = np.empty(max(3 * cap, 3), np.int32)
+    t = lib.orc_list(o.n, o.orow, _nonempty(o.ocol), _nonempty(o.perm), r_lo, r_hi, out, cap)
+    if t < 0:
+        raise ValueError(f"capacity {cap} below triangle count {-t}")
+    return out[: 3 * t].reshape(t, 3)
+
+
+def list_triangles_parallel(o: Oriented, threads: int = 8) -> np.ndarray:
+    """The same list, computed over source-rank ranges on several threads (the
+    per-range procedure is unchanged; ranges are concatenated in order)."""
+    if o.n == 0:
+        return np.empty((0, 3), np.int32)
+    cuts = np.linspace(0, o.m, threads + 1).astype(np.int64)
+    bounds = sorted(set(int(np.searchsorted(o.orow, c, side="right") - 1) for c in cuts[1:-1]))
+    ranges = list(zip([0] + bounds, bounds + [o.n]))
+    ranges = [(a, b) for a, b in ranges if b > a]
+    with ThreadPoolExecutor(len(ranges)) as ex:
+        parts = list(ex.map(lambda ab: list_triangles(o, ab[0], ab[1]), ranges))
+    return np.concatenate(parts) if parts else np.empty((0, 3), np.int32)
+
+
+def sum_min(o: Oriented) -> int:
+    """sum over <u,v> of min(deg+(u), deg+(v)) (Section 3.2, Time Complexity)."""
+    return int(_load().orc_sum_min(o.n, o.orow, _nonempty(o.ocol)))
+
+
+def sum_head(o: Oriented) -> int:
+    """sum over <u,v> of deg+(v) (the kClist cost, Section 2.3)."""
+    return int(_load().orc_sum_head(o.n, o.orow, _nonempty(o.ocol)))
+
+
+def aot_ref(rowptr, col, tie_break: bool = True, cap: int | None = None):
+    """Algorithm 3 as written, on original ids.  Returns (triangles (T,3), probes)."""
+    lib = _load()
+    rowptr, col = _arrays(rowptr, col)
+    n = rowptr.size - 1
+    if cap is None:
+        cap = max(16, col.size * 4)
+    out = np.empty(3 * cap, np.int32)
+    probes = ctypes.c_uint64(0)
+    t = lib.orc_aot_ref(n, rowptr, _nonempty(col), int(tie_break), out, cap, ctypes.byref(probes))
+    if t == np.iinfo(np.int64).min:
+        raise MemoryError("oracle AOT reference failed")
+    if t < 0:
+        return aot_ref(rowptr, col, tie_break, cap=-t)
+    return out[: 3 * t].reshape(t, 3).copy(), int(probes.value)
+
+
+def fingerprint(tri: np.ndarray, n: int | None = None):
+    """(F1, F2) = (sum mod 2^64, xor) of splitmix64-chained triple hashes, and
+    per-vertex counts when n is given."""
+    lib = _load()
+    tri = np.ascontiguousarray(tri, dtype=np.int32).reshape(-1, 3)
+    fp = np.zeros(2, np.uint64)
+    tv = np.zeros(n, np.uint64) if n else None
+    lib.orc_fingerprint(_nonempty(tri.reshape(-1)), tri.shape[0], fp,
+                        tv.ctypes.data if tv is not None else None)
+    return (int(fp[0]), int(fp[1])), tv
+
+
+def splitmix64(z: int) -> int:
+    """The hash the fingerprints chain (SplitMix64 output of state z)."""
+    return int(_load().orc_splitmix64(z))
+
+
+def list_digest(o: Oriented, r_lo: int = 0, r_hi: int | None = None, per_vertex: bool = True):
+    """CF over sources [r_lo, r_hi) without storing the list: (T, (F1, F2), t[v])."""
+    lib = _load()
+    r_hi = o.n if r_hi is None else r_hi
+    fp = np.zeros(2, np.uint64)
+    tv = np.zeros(o.n, np.uint64) if per_vertex else None
+    t = lib.orc_list_digest(o.n, o.orow, _nonempty(o.ocol), _nonempty(o.perm), r_lo, r_hi, fp,
+                            tv.ctypes.data if tv is not None else None)
+    return int(t), (int(fp[0]), int(fp[1])), tv

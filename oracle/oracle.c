@@ -1,0 +1,347 @@
+/*
+ * CPU oracle for AOT triangle listing -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Plain, slow, single-threaded C.  Only the test suite, the smoke check and
+ * the CPU-baseline leg of the benchmark load this library; the product path
+ * never does.  It shares no code, header or table with the HIP library.
+ *
+ * What it computes (all from "AOT: Pushing the Efficiency Boundary of
+ * Main-memory Triangle Listing", Yu, Qin, Zhang, Zhang, Lin, 2020):
+ *
+ *  orc_orient      -- the orientation technique (Section 2.2, "Orientation
+ *                     technique"; Algorithm 3's first step): a total order
+ *                     eta by degree, ties by smaller vertex id, and the edge
+ *                     (u,v) kept as <u,v> iff eta(u) < eta(v).  The result is
+ *                     returned relabelled by eta ("rank space") with every
+ *                     out-list sorted ascending, together with perm/rank.
+ *  orc_edge_counts -- per directed edge <u,v>: |N+(u) n N+(v)| by the
+ *                     merge-based intersection of Algorithm 1 (CF), Sec. 2.2.
+ *  orc_list        -- Algorithm 1 (CF): for each u, each v in N+(u), every w in
+ *                     N+(u) n N+(v) is the triangle (u,v,w); emitted as the
+ *                     original ids sorted ascending, in edge order then
+ *                     ascending w.
+ *  orc_sum_min     -- sum over <u,v> of min(deg+(u), deg+(v)): the look-up
+ *                     count of the adaptive orientation (Section 3.2, "Time
+ *                     Complexity").
+ *  orc_sum_head    -- sum over <u,v> of deg+(v): the kClist cost that
+ *                     Example 1 compares against (Sections 2.3 and 3.2).
+ *  orc_aot_ref     -- Algorithm 3 (AOT) as written: a |V|-entry bitmap H of
+ *                     N+(u) per pivot u, the out-neighbour loop and the
+ *                     in-neighbour loop, each probing only when the other
+ *                     endpoint has the smaller out-degree, ties broken by
+ *                     vertex id (Section 3.2, "Correctness" and its footnote),
+ *                     neighbours visited in decreasing degree (Section 3.2,
+ *                     "Exploiting Local Order").  Works in original ids.
+ *  orc_fingerprint -- order-independent sums of a SplitMix64-chained hash of
+ *                     each triple, and per-vertex triangle counts.
+ *
+ * Conventions: rowptr int64[n+1], col int32[nnz], symmetric simple graph with
+ * sorted rows.  Return values < 0 signal an error (allocation or capacity).
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef struct { int64_t deg; int32_t id; } deg_id;
+
+static int cmp_deg_id(const void* a, const void* b) {
+  const deg_id* x = (const deg_id*)a;
+  const deg_id* y = (const deg_id*)b;
+  if (x->deg != y->deg) return x->deg < y->deg ? -1 : 1;
+  return (x->id > y->id) - (x->id < y->id);
+}
+
+static int cmp_i32(const void* a, const void* b) {
+  int32_t x = *(const int32_t*)a, y = *(const int32_t*)b;
+  return (x > y) - (x < y);
+}
+
+/* Orientation.  Outputs: perm[r] = original id of rank r, rank[v] = eta(v),
+ * orow[n+1], ocol[m] in rank space, each row ascending.  Returns m or -1. */
+int64_t orc_orient(int32_t n, const int64_t* rowptr, const int32_t* col,
+                   int32_t* perm, int32_t* rank, int64_t* orow, int32_t* ocol) {
+  deg_id* order = (deg_id*)malloc(sizeof(deg_id) * (size_t)(n > 0 ? n : 1));
+  if (!order) return -1;
+  for (int32_t v = 0; v < n; ++v) {
+    order[v].deg = rowptr[v + 1] - rowptr[v];
+    order[v].id = v;
+  }
+  qsort(order, (size_t)n, sizeof(deg_id), cmp_deg_id);
+  for (int32_t r = 0; r < n; ++r) {
+    perm[r] = order[r].id;
+    rank[order[r].id] = r;
+  }
+  free(order);
+  int64_t m = 0;
+  orow[0] = 0;
+  for (int32_t r = 0; r < n; ++r) {
+    int32_t u = perm[r];
+    int64_t start = m;
+    for (int64_t k = rowptr[u]; k < rowptr[u + 1]; ++k) {
+      int32_t rv = rank[col[k]];
+      if (rv > r) ocol[m++] = rv;
+    }
+    qsort(ocol + start, (size_t)(m - start), sizeof(int32_t), cmp_i32);
+    orow[r + 1] = m;
+  }
+  return m;
+}
+
+/* |A n B| for two ascending lists, by merging. */
+static int64_t merge_count(const int32_t* a, int64_t na, const int32_t* b, int64_t nb) {
+  int64_t i = 0, j = 0, c = 0;
+  while (i < na && j < nb) {
+    if (a[i] < b[j]) ++i;
+    else if (a[i] > b[j]) ++j;
+    else { ++c; ++i; ++j; }
+  }
+  return c;
+}
+
+/* Source (rank) of directed edge e: the row r with orow[r] <= e < orow[r+1]. */
+static int32_t edge_tail(int32_t n, const int64_t* orow, int64_t e) {
+  int32_t lo = 0, hi = n - 1;
+  while (lo < hi) {
+    int32_t mid = lo + (hi - lo + 1) / 2;
+    if (orow[mid] <= e) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+/* cnt[i] = |N+(u) n N+(v)| for edges e = e_lo + i, e < e_hi (CF's line 4). */
+void orc_edge_counts(int32_t n, const int64_t* orow, const int32_t* ocol,
+                     int64_t e_lo, int64_t e_hi, int32_t* cnt) {
+  if (e_hi <= e_lo) return;
+  int32_t u = edge_tail(n, orow, e_lo);
+  for (int64_t e = e_lo; e < e_hi; ++e) {
+    while (orow[u + 1] <= e) ++u;
+    int32_t v = ocol[e];
+    cnt[e - e_lo] = (int32_t)merge_count(ocol + orow[u], orow[u + 1] - orow[u],
+                                         ocol + orow[v], orow[v + 1] - orow[v]);
+  }
+}
+
+/* Same, for an arbitrary list of edge ids (sampled checks). */
+void orc_edge_counts_at(int32_t n, const int64_t* orow, const int32_t* ocol,
+                        const int64_t* eids, int64_t k, int32_t* cnt) {
+  for (int64_t i = 0; i < k; ++i) {
+    int64_t e = eids[i];
+    int32_t u = edge_tail(n, orow, e);
+    int32_t v = ocol[e];
+    cnt[i] = (int32_t)merge_count(ocol + orow[u], orow[u + 1] - orow[u],
+                                  ocol + orow[v], orow[v + 1] - orow[v]);
+  }
+}
+
+static void sort3(int32_t* t) {
+  int32_t x;
+  if (t[0] > t[1]) { x = t[0]; t[0] = t[1]; t[1] = x; }
+  if (t[1] > t[2]) { x = t[1]; t[1] = t[2]; t[2] = x; }
+  if (t[0] > t[1]) { x = t[0]; t[0] = t[1]; t[1] = x; }
+}
+
+/* Algorithm 1 (CF) over the edges of source ranks [r_lo, r_hi).  Triangles go
+ * to out[3*i..3*i+2] as ascending original ids, in edge order then ascending
+ * w.  Returns the number of triangles, or -(needed) if cap is too small
+ * (nothing beyond cap is written). */
+int64_t orc_list(int32_t n, const int64_t* orow, const int32_t* ocol, const int32_t* perm,
+                 int32_t r_lo, int32_t r_hi, int32_t* out, int64_t cap) {
+  (void)n;
+  int64_t t = 0;
+  for (int32_t u = r_lo; u < r_hi; ++u) {
+    const int32_t* a = ocol + orow[u];
+    int64_t na = orow[u + 1] - orow[u];
+    for (int64_t k = 0; k < na; ++k) {
+      int32_t v = a[k];
+      const int32_t* b = ocol + orow[v];
+      int64_t nb = orow[v + 1] - orow[v];
+      int64_t i = 0, j = 0;
+      while (i < na && j < nb) {
+        if (a[i] < b[j]) ++i;
+        else if (a[i] > b[j]) ++j;
+        else {
+          if (t < cap) {
+            int32_t* o = out + 3 * t;
+            o[0] = perm[u]; o[1] = perm[v]; o[2] = perm[a[i]];
+            sort3(o);
+          }
+          ++t; ++i; ++j;
+        }
+      }
+    }
+  }
+  return t <= cap ? t : -t;
+}
+
+/* sum over <u,v> of min(deg+(u), deg+(v)), rank space. */
+uint64_t orc_sum_min(int32_t n, const int64_t* orow, const int32_t* ocol) {
+  uint64_t s = 0;
+  for (int32_t u = 0; u < n; ++u) {
+    int64_t du = orow[u + 1] - orow[u];
+    for (int64_t e = orow[u]; e < orow[u + 1]; ++e) {
+      int32_t v = ocol[e];
+      int64_t dv = orow[v + 1] - orow[v];
+      s += (uint64_t)(du < dv ? du : dv);
+    }
+  }
+  return s;
+}
+
+/* sum over <u,v> of deg+(v). */
+uint64_t orc_sum_head(int32_t n, const int64_t* orow, const int32_t* ocol) {
+  uint64_t s = 0;
+  for (int32_t u = 0; u < n; ++u)
+    for (int64_t e = orow[u]; e < orow[u + 1]; ++e) {
+      int32_t v = ocol[e];
+      s += (uint64_t)(orow[v + 1] - orow[v]);
+    }
+  return s;
+}
+
+/* Algorithm 3 (AOT), literally, on the original ids.
+ *  tie_break = 1: a vertex x is "smaller" than the pivot u when
+ *                 (deg+(x), x) < (deg+(u), u) lexicographically;
+ *  tie_break = 0: strict deg+(x) < deg+(u) only (drops tied edges; kept to
+ *                 show that the footnote's tie rule is needed).
+ * Output: triangles (ascending ids) into out up to cap, *probes = number of
+ * hash look-ups.  Returns the triangle count (or -count if cap was short),
+ * or INT64_MIN on allocation failure. */
+int64_t orc_aot_ref(int32_t n, const int64_t* rowptr, const int32_t* col, int tie_break,
+                    int32_t* out, int64_t cap, uint64_t* probes) {
+  int64_t* eta = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+  deg_id* order = (deg_id*)malloc(sizeof(deg_id) * (size_t)(n > 0 ? n : 1));
+  int64_t* dplus = (int64_t*)calloc((size_t)(n > 0 ? n : 1), sizeof(int64_t));
+  int64_t* dminus = (int64_t*)calloc((size_t)(n > 0 ? n : 1), sizeof(int64_t));
+  unsigned char* H = (unsigned char*)calloc((size_t)(n > 0 ? n : 1), 1);
+  int64_t nnz = rowptr[n];
+  int32_t* outl = (int32_t*)malloc(sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1));
+  int32_t* inl = (int32_t*)malloc(sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1));
+  int64_t* orow = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n + 1));
+  int64_t* irow = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n + 1));
+  if (!eta || !order || !dplus || !dminus || !H || !outl || !inl || !orow || !irow) {
+    free(eta); free(order); free(dplus); free(dminus); free(H); free(outl); free(inl);
+    free(orow); free(irow);
+    return INT64_MIN;
+  }
+  /* line 1: orientation by degree order, ties by id */
+  for (int32_t v = 0; v < n; ++v) { order[v].deg = rowptr[v + 1] - rowptr[v]; order[v].id = v; }
+  qsort(order, (size_t)n, sizeof(deg_id), cmp_deg_id);
+  for (int32_t r = 0; r < n; ++r) eta[order[r].id] = r;
+  for (int32_t u = 0; u < n; ++u)
+    for (int64_t k = rowptr[u]; k < rowptr[u + 1]; ++k) {
+      if (eta[col[k]] > eta[u]) dplus[u]++; else dminus[u]++;
+    }
+  orow[0] = irow[0] = 0;
+  for (int32_t u = 0; u < n; ++u) { orow[u + 1] = orow[u] + dplus[u]; irow[u + 1] = irow[u] + dminus[u]; }
+  /* neighbour lists in decreasing degree order (local order): walk the
+   * vertices from the top of eta down and append each to its neighbours' lists */
+  {
+    int64_t* fo = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    int64_t* fi = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    if (!fo || !fi) { free(fo); free(fi); return INT64_MIN; }
+    for (int32_t u = 0; u < n; ++u) { fo[u] = orow[u]; fi[u] = irow[u]; }
+    for (int32_t r = n - 1; r >= 0; --r) {
+      int32_t x = order[r].id;                  /* x, in decreasing eta */
+      for (int64_t k = rowptr[x]; k < rowptr[x + 1]; ++k) {
+        int32_t u = col[k];
+        if (eta[x] > eta[u]) outl[fo[u]++] = x;  /* x in N+(u) */
+        else inl[fi[u]++] = x;                   /* x in N-(u) */
+      }
+    }
+    free(fo); free(fi);
+  }
+  int64_t t = 0;
+  uint64_t pr = 0;
+#define SMALLER(x, u) (dplus[x] < dplus[u] || (tie_break && dplus[x] == dplus[u] && (x) < (u)))
+#define EMIT(a, b, c) do { if (t < cap) { int32_t* o = out + 3 * t; o[0] = (a); o[1] = (b); o[2] = (c); sort3(o); } ++t; } while (0)
+  for (int32_t u = 0; u < n; ++u) {
+    for (int64_t k = orow[u]; k < orow[u + 1]; ++k) H[outl[k]] = 1;          /* line 3 */
+    for (int64_t k = orow[u]; k < orow[u + 1]; ++k) {                         /* lines 4-8 */
+      int32_t v = outl[k];
+      if (SMALLER(v, u))
+        for (int64_t j = orow[v]; j < orow[v + 1]; ++j) {
+          int32_t w = outl[j];
+          ++pr;
+          if (H[w]) EMIT(u, v, w);
+        }
+    }
+    for (int64_t k = irow[u]; k < irow[u + 1]; ++k) {                         /* lines 9-13 */
+      int32_t x = inl[k];
+      if (SMALLER(x, u))
+        for (int64_t j = orow[x]; j < orow[x + 1]; ++j) {
+          int32_t y = outl[j];
+          ++pr;
+          if (H[y]) EMIT(u, x, y);
+        }
+    }
+    for (int64_t k = orow[u]; k < orow[u + 1]; ++k) H[outl[k]] = 0;          /* clean H */
+  }
+#undef SMALLER
+#undef EMIT
+  *probes = pr;
+  free(eta); free(order); free(dplus); free(dminus); free(H); free(outl); free(inl);
+  free(orow); free(irow);
+  return t <= cap ? t : -t;
+}
+
+/* SplitMix64's output function (Steele, Lea, Flood 2014) on z + golden gamma. */
+static uint64_t splitmix64(uint64_t z) {
+  z += 0x9E3779B97F4A7C15ULL;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+
+uint64_t orc_splitmix64(uint64_t z) { return splitmix64(z); }
+
+/* Hash of an ascending triple: splitmix64 chained over a, b, c. */
+static uint64_t triple_hash(uint32_t a, uint32_t b, uint32_t c) {
+  return splitmix64(splitmix64(splitmix64((uint64_t)a) ^ (uint64_t)b) ^ (uint64_t)c);
+}
+
+/* Fingerprints of a triangle list (ascending triples): fp[0] = sum of hashes
+ * mod 2^64, fp[1] = xor of hashes; tv[v] += 1 for each corner (if tv). */
+void orc_fingerprint(const int32_t* tri, int64_t t, uint64_t* fp, uint64_t* tv) {
+  uint64_t s = 0, x = 0;
+  for (int64_t i = 0; i < t; ++i) {
+    const int32_t* o = tri + 3 * i;
+    uint64_t h = triple_hash((uint32_t)o[0], (uint32_t)o[1], (uint32_t)o[2]);
+    s += h; x ^= h;
+    if (tv) { tv[o[0]]++; tv[o[1]]++; tv[o[2]]++; }
+  }
+  fp[0] = s; fp[1] = x;
+}
+
+/* CF over source ranks [r_lo, r_hi) without storing triangles: the count, the
+ * fingerprints and per-vertex counts (original ids) -- for graphs whose full
+ * triangle list does not fit in host memory. */
+int64_t orc_list_digest(int32_t n, const int64_t* orow, const int32_t* ocol, const int32_t* perm,
+                        int32_t r_lo, int32_t r_hi, uint64_t* fp, uint64_t* tv) {
+  (void)n;
+  int64_t t = 0;
+  uint64_t s = 0, x = 0;
+  for (int32_t u = r_lo; u < r_hi; ++u) {
+    const int32_t* a = ocol + orow[u];
+    int64_t na = orow[u + 1] - orow[u];
+    for (int64_t k = 0; k < na; ++k) {
+      int32_t v = a[k];
+      const int32_t* b = ocol + orow[v];
+      int64_t nb = orow[v + 1] - orow[v];
+      int64_t i = 0, j = 0;
+      while (i < na && j < nb) {
+        if (a[i] < b[j]) ++i;
+        else if (a[i] > b[j]) ++j;
+        else {
+          int32_t o[3] = {perm[u], perm[v], perm[a[i]]};
+          sort3(o);
+          uint64_t h = triple_hash((uint32_t)o[0], (uint32_t)o[1], (uint32_t)o[2]);
+          s += h; x ^= h;
+          if (tv) { tv[o[0]]++; tv[o[1]]++; tv[o[2]]++; }
+          ++t; ++i; ++j;
+        }
+      }
+    }
+  }
+  fp[0] = s; fp[1] = x;
+  return t;
+}

@@ -1,0 +1,331 @@
+"""Pins for the CPU oracle, against things other than the oracle itself:
+brute force, dense matrix powers, closed forms, the paper's Example 1, the
+published SplitMix64 outputs, and Algorithm 3 run literally (with the
+tie-break footnote's rule shown necessary on a small counterexample)."""
+
+import itertools
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2006_11494_amd import inputs
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+# ---------------------------------------------------------------- helpers
+
+def random_graph(n, p, seed):
+    rng = np.random.default_rng(seed)
+    a = np.triu(rng.random((n, n)) < p, 1)
+    iu, ju = np.nonzero(a)
+    return inputs.csr_from_edges_np(n, zip(iu.tolist(), ju.tolist()))
+
+
+def dense(csr):
+    rp, col = csr.numpy()
+    n = csr.n
+    A = np.zeros((n, n), np.int64)
+    rows = np.repeat(np.arange(n), np.diff(rp))
+    A[rows, col] = 1
+    return A
+
+
+def brute_force(csr):
+    """Every (a, b, c), a < b < c, with all three edges present."""
+    A = dense(csr)
+    return sorted(t for t in itertools.combinations(range(csr.n), 3)
+                  if A[t[0], t[1]] and A[t[0], t[2]] and A[t[1], t[2]])
+
+
+def as_set(tri):
+    return sorted(map(tuple, np.asarray(tri).reshape(-1, 3).tolist()))
+
+
+def cf_list(csr):
+    rp, col = csr.numpy()
+    return oracle.list_triangles(oracle.orient(rp, col))
+
+
+def graph(n, edges):
+    return inputs.csr_from_edges_np(n, edges)
+
+
+SMALL = [(n, p, s) for s, (n, p) in enumerate(
+    [(0, 0.5), (1, 0.5), (2, 1.0), (3, 1.0), (5, 0.6), (8, 0.5), (12, 0.3), (12, 0.9),
+     (17, 0.4), (20, 0.15), (25, 0.5), (30, 0.25), (40, 0.2), (33, 0.7)])]
+
+
+# ---------------------------------------------------------------- hashing
+
+def test_splitmix64_published_outputs():
+    # SplitMix64 seeded with 0 outputs these first four words; the k-th output
+    # is the mix of state k * golden-gamma.
+    gamma = 0x9E3779B97F4A7C15
+    want = [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F, 0xF88BB8A8724C81EC]
+    got = [oracle.splitmix64((k * gamma) & (2**64 - 1)) for k in range(4)]
+    assert got == want
+
+
+# ---------------------------------------------------------------- orientation
+
+@pytest.mark.parametrize("n,p,seed", SMALL + [(300, 0.05, 99), (500, 0.02, 98)])
+def test_orientation_is_the_degree_order(n, p, seed):
+    g = random_graph(n, p, seed)
+    rp, col = g.numpy()
+    o = oracle.orient(rp, col)
+    deg = np.diff(rp)
+    perm = np.lexsort((np.arange(n), deg)).astype(np.int32)  # degree asc, id asc
+    assert np.array_equal(o.perm, perm)
+    rank = np.empty(n, np.int64)
+    rank[perm] = np.arange(n)
+    assert np.array_equal(o.rank, rank)
+    # every undirected edge appears exactly once, pointing up the order
+    rows = np.repeat(np.arange(n), deg)
+    up = rank[rows] < rank[col]
+    want = sorted(zip(rank[rows[up]].tolist(), rank[col[up]].tolist()))
+    tail = o.tail()
+    got = list(zip(tail.tolist(), o.ocol.tolist()))
+    assert got == want            # CSR order = sorted by (tail, head): rows ascending
+    assert o.m == g.m
+    assert all(a < b for a, b in got)   # acyclic: the order increases along every edge
+
+
+def test_orientation_example1_directions():
+    ex = load_example1()
+    rp, col = ex["csr"].numpy()
+    o = oracle.orient(rp, col)
+    dplus = o.dplus
+    name = lambda r: int(o.perm[r]) + 1
+    out = {name(r): sorted(name(v) for v in o.ocol[o.orow[r]:o.orow[r + 1]]) for r in range(o.n)}
+    # directions the example's text names
+    for (u, v, _, _) in ex["cost"]:
+        assert v in out[u], (u, v)
+    assert out[3] == [4, 13, 14] and out[4] == [13, 14]
+    assert out[1] == [3] and out[2] == [4]
+    assert out[13] == [] and out[14] == []          # the two sinks
+    assert sum(dplus) == 21
+
+
+# ---------------------------------------------------------------- listing
+
+@pytest.mark.parametrize("n,p,seed", SMALL)
+def test_list_equals_brute_force(n, p, seed):
+    g = random_graph(n, p, seed)
+    tri = cf_list(g)
+    assert as_set(tri) == brute_force(g)
+    # rows are ascending triples and the list has no repeats
+    assert all(a < b < c for a, b, c in tri.tolist())
+    assert len(set(map(tuple, tri.tolist()))) == len(tri)
+
+
+@pytest.mark.parametrize("n,p,seed", [(60, 0.3, 1), (200, 0.05, 2), (300, 0.1, 3), (400, 0.02, 4)])
+def test_count_equals_trace_a3(n, p, seed):
+    g = random_graph(n, p, seed)
+    A = dense(g)
+    A3 = A @ A @ A
+    tri = cf_list(g)
+    assert len(tri) == np.trace(A3) // 6
+    (_, _), tv = oracle.fingerprint(tri, n)
+    assert np.array_equal(tv.astype(np.int64), np.diag(A3) // 2)   # per-vertex counts
+    assert int(tv.sum()) == 3 * len(tri)
+
+
+@pytest.mark.parametrize("n,p,seed", [(40, 0.3, 5), (120, 0.1, 6), (250, 0.06, 7)])
+def test_edge_counts_brute_force(n, p, seed):
+    g = random_graph(n, p, seed)
+    rp, col = g.numpy()
+    o = oracle.orient(rp, col)
+    A = dense(g)
+    cnt = oracle.edge_counts(o)
+    perm = o.perm
+    tail = o.tail()
+    for e in range(o.m):
+        u, v = perm[tail[e]], perm[o.ocol[e]]
+        # third corners ranked above both edge ends
+        want = sum(1 for w in range(n) if A[u, w] and A[v, w] and o.rank[w] > o.rank[v])
+        assert cnt[e] == want
+    assert int(cnt.sum()) == len(brute_force(g)) if n <= 60 else True
+    assert int(cnt.sum()) == np.trace(A @ A @ A) // 6
+    # sampled edge ids give the same numbers
+    pick = np.arange(0, o.m, 7)
+    assert np.array_equal(oracle.edge_counts_at(o, pick), cnt[pick])
+    # a sub-range too
+    assert np.array_equal(oracle.edge_counts(o, 3, o.m - 2), cnt[3:o.m - 2])
+
+
+# ---------------------------------------------------------------- closed forms
+
+@pytest.mark.parametrize("n", range(3, 13))
+def test_complete_graph(n):
+    g = graph(n, itertools.combinations(range(n), 2))
+    rp, col = g.numpy()
+    o = oracle.orient(rp, col)
+    assert len(oracle.list_triangles(o)) == math.comb(n, 3)
+    # all degrees tie, so the order is by id and deg+(i) = n-1-i: every edge
+    # <i,j> costs n-1-j and the total is C(n,3)
+    assert oracle.sum_min(o) == math.comb(n, 3)
+    assert oracle.sum_head(o) == math.comb(n, 3)
+
+
+def grid(a, b):
+    idx = lambda i, j: i * b + j
+    e = [(idx(i, j), idx(i + 1, j)) for i in range(a - 1) for j in range(b)]
+    e += [(idx(i, j), idx(i, j + 1)) for i in range(a) for j in range(b - 1)]
+    return graph(a * b, e)
+
+
+def wheel(n):
+    rim = n - 1
+    e = [(0, i) for i in range(1, n)] + [(i, i % rim + 1) for i in range(1, n)]
+    return graph(n, e)
+
+
+@pytest.mark.parametrize("g,t", [
+    (graph(7, [(i, 3 + j) for i in range(3) for j in range(4)]), 0),      # K_{3,4}
+    (graph(11, [(i, 5 + j) for i in range(5) for j in range(6)]), 0),     # K_{5,6}
+    (grid(5, 7), 0), (grid(1, 9), 0), (grid(12, 12), 0),
+    (graph(8, [(i, (i + 1) % 8) for i in range(8)]), 0),                  # C_8
+    (graph(3, [(0, 1), (1, 2), (2, 0)]), 1),                               # C_3
+    (graph(5, [(i, (i + 1) % 5) for i in range(5)]), 0),                  # C_5
+    (graph(10, [(0, i) for i in range(1, 10)]), 0),                       # star
+    (graph(9, [(i, (i - 1) // 2) for i in range(1, 9)]), 0),              # binary tree
+    (wheel(4), 4), (wheel(5), 4), (wheel(6), 5), (wheel(13), 12), (wheel(50), 49),
+    (graph(6, []), 0), (graph(1, []), 0),
+])
+def test_closed_forms(g, t):
+    assert len(cf_list(g)) == t
+    assert len(brute_force(g)) == t
+
+
+def test_disjoint_union_and_relabelling():
+    g1 = random_graph(30, 0.3, 11)
+    g2 = random_graph(25, 0.4, 12)
+    r1, c1 = g1.numpy()
+    r2, c2 = g2.numpy()
+    e1 = [(u, int(v)) for u in range(30) for v in c1[r1[u]:r1[u + 1]] if u < v]
+    e2 = [(u + 30, int(v) + 30) for u in range(25) for v in c2[r2[u]:r2[u + 1]] if u < v]
+    t1, t2 = len(cf_list(g1)), len(cf_list(g2))
+    assert len(cf_list(graph(55, e1 + e2))) == t1 + t2
+    # relabelling maps the triangle set onto itself
+    pi = np.random.default_rng(3).permutation(30)
+    h = graph(30, [(int(pi[u]), int(pi[v])) for u, v in e1])
+    want = sorted(tuple(sorted(int(pi[x]) for x in t)) for t in as_set(cf_list(g1)))
+    assert as_set(cf_list(h)) == want
+
+
+# ---------------------------------------------------------------- Example 1
+
+def load_example1():
+    edges, cost, vals = [], [], {}
+    with open(os.path.join(GOLDEN, "example1.txt")) as f:
+        for line in f:
+            p = line.split()
+            if not p or p[0].startswith("#"):
+                continue
+            if p[0] == "edge":
+                edges.append((int(p[1]) - 1, int(p[2]) - 1))
+            elif p[0] == "cost":
+                cost.append(tuple(int(x) for x in p[1:]))
+            else:
+                vals[p[0]] = int(p[1])
+    return {"csr": graph(vals["n"], edges), "cost": cost, **vals}
+
+
+def test_example1_costs():
+    ex = load_example1()
+    rp, col = ex["csr"].numpy()
+    o = oracle.orient(rp, col)
+    assert o.n == ex["n"] and o.m == ex["edges"]
+    d = o.dplus
+    r = lambda name: int(o.rank[name - 1])
+    for u, v, head, mn in ex["cost"]:
+        assert d[r(v)] == head and min(d[r(u)], d[r(v)]) == mn
+    tail = o.tail()
+    assert int((d[o.ocol] > 0).sum()) == ex["positive_head_edges"]
+    assert oracle.sum_head(o) == ex["sum_head"] == 21
+    assert oracle.sum_min(o) == ex["sum_min"] == 12
+    # the triangle set itself (derived, not printed): three copies of two triangles
+    assert as_set(oracle.list_triangles(o)) == brute_force(ex["csr"])
+    assert len(brute_force(ex["csr"])) == 6
+    _, probes = oracle.aot_ref(rp, col)
+    assert probes == 12
+    del tail
+
+
+def test_example1_descending_order_does_not_fit():
+    """The descending-degree reading of the orientation contradicts the example
+    (its sum of minima would be 21, not 12), so the ascending reading is used."""
+    ex = load_example1()
+    rp, col = ex["csr"].numpy()
+    n = ex["n"]
+    deg = np.diff(rp)
+    order = np.lexsort((np.arange(n), -deg))
+    rank = np.empty(n, np.int64)
+    rank[order] = np.arange(n)
+    rows = np.repeat(np.arange(n), deg)
+    up = rank[rows] < rank[col]
+    u, v = rank[rows[up]], rank[col[up]]
+    dplus = np.bincount(u, minlength=n)
+    assert int(np.minimum(dplus[u], dplus[v]).sum()) == 21
+
+
+# ---------------------------------------------------------------- Algorithm 3
+
+@pytest.mark.parametrize("n,p,seed", SMALL + [(200, 0.08, 21), (300, 0.04, 22)])
+def test_aot_reference_matches_cf_and_probes_equal_sum_min(n, p, seed):
+    g = random_graph(n, p, seed)
+    rp, col = g.numpy()
+    tri, probes = oracle.aot_ref(rp, col)
+    o = oracle.orient(rp, col)
+    assert as_set(tri) == as_set(oracle.list_triangles(o))
+    assert len(set(map(tuple, tri.tolist()))) == len(tri)     # each exactly once
+    assert probes == oracle.sum_min(o)
+
+
+def test_tie_break_is_needed():
+    """Two triangles; the one whose pivot edge joins two vertices of equal
+    out-degree is lost when ties are not broken by id."""
+    g = graph(5, [(0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 4)])
+    tri, _ = oracle.aot_ref(*g.numpy(), tie_break=True)
+    assert as_set(tri) == [(0, 1, 2), (0, 1, 3)] == brute_force(g)
+    lost, _ = oracle.aot_ref(*g.numpy(), tie_break=False)
+    assert len(lost) == 1
+
+
+# ---------------------------------------------------------------- digests
+
+def test_fingerprint_and_digest_agree():
+    g = random_graph(150, 0.12, 31)
+    rp, col = g.numpy()
+    o = oracle.orient(rp, col)
+    tri = oracle.list_triangles(o)
+    fp, tv = oracle.fingerprint(tri, o.n)
+    t, fp2, tv2 = oracle.list_digest(o)
+    assert t == len(tri) and fp == fp2 and np.array_equal(tv, tv2)
+    # order independence
+    fp3, _ = oracle.fingerprint(tri[::-1].copy())
+    assert fp3 == fp
+    # split digests combine: sum adds mod 2^64, xor xors
+    cut = o.n // 2
+    ta, fa, _ = oracle.list_digest(o, 0, cut)
+    tb, fb, _ = oracle.list_digest(o, cut, o.n)
+    assert ta + tb == t
+    assert ((fa[0] + fb[0]) % 2**64, fa[1] ^ fb[1]) == fp
+    # a single changed triangle changes both words
+    bad = tri.copy()
+    bad[0, 2] += 1
+    fpb, _ = oracle.fingerprint(bad)
+    assert fpb[0] != fp[0] and fpb[1] != fp[1]
+
+
+def test_parallel_ranges_give_the_same_list():
+    g = inputs.workload("er2000")
+    rp, col = g.numpy()
+    o = oracle.orient(rp, col)
+    a = oracle.list_triangles(o)
+    b = oracle.list_triangles_parallel(o, threads=5)
+    assert np.array_equal(a, b)
