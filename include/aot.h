@@ -1,0 +1,164 @@
+/*
+ * aot.h -- C ABI of the MI355X (gfx950) AOT triangle-listing library.
+ *
+ * AOT is the adaptive-orientation edge-iterator of Yu, Qin, Zhang, Zhang and
+ * Lin, "AOT: Pushing the Efficiency Boundary of Main-memory Triangle Listing"
+ * (2020).  Given an undirected simple graph it lists every triangle exactly
+ * once (Section 2.1, problem statement) in
+ *     Theta( sum over directed edges <u,v> of min(deg+(u), deg+(v)) )
+ * look-ups (Section 3.2, Time Complexity).
+ *
+ * Three stages, each one entry point:
+ *   aot_orient  orientation (Section 2.2, "Orientation technique"; first step
+ *               of Algorithm 3): rank vertices by (degree, id) ascending and
+ *               keep each edge pointing up the order; out-lists sorted.
+ *   aot_count   adaptive orientation (Section 3.1, "The main idea"; Algorithm
+ *               3's two probe loops): every directed edge is charged to its
+ *               endpoint with the larger (deg+, id) -- the owner -- and the
+ *               other endpoint's out-list is probed into an index of the
+ *               owner's out-list.  Produces the per-edge triangle offsets, the
+ *               triangle count T and the probe count (sum of minima).
+ *   aot_list    emits the triangles (Algorithm 3, "output triangle"), any
+ *               window of the global list at a time.
+ *
+ * Conventions shared by every call
+ *   - Pointers marked "device" are HIP device (or managed) memory on the
+ *     current device; "host" pointers are ordinary host memory.
+ *   - The caller owns every buffer.  The library allocates no device memory
+ *     except in aot_count_batch (see there); sizes come from *_workspace().
+ *   - `stream` is a hipStream_t (NULL = the legacy default stream).  Calls
+ *     enqueue work on it; calls that return host values synchronise it.
+ *   - Vertex ids are int32 in [0, n).  The input graph is a symmetric CSR:
+ *     rowptr int64[n+1] (rowptr[0] = 0), col int32[nnz], nnz = 2m, every row
+ *     strictly ascending, no self-loops.  m must be <= INT32_MAX.
+ *   - Return value: AOT_OK (0) or a negative AOT_E_* code; on error
+ *     aot_last_error() gives a thread-local message.  No call aborts.
+ *   - Results are deterministic: the same input gives the same bytes for any
+ *     dispatch choice, chunking or stream.
+ */
+#ifndef AOT_H
+#define AOT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define AOT_OK 0
+#define AOT_E_ARG (-1)        /* null pointer, negative size, bad flag        */
+#define AOT_E_GRAPH (-2)      /* validation found a malformed CSR             */
+#define AOT_E_OVERFLOW (-3)   /* n, nnz or m beyond the int32 edge-id range   */
+#define AOT_E_WORKSPACE (-4)  /* workspace smaller than *_workspace() asked   */
+#define AOT_E_HIP (-5)        /* a HIP runtime call failed                    */
+#define AOT_E_MODEL (-6)      /* cost model missing, malformed or not finite  */
+#define AOT_E_CAPACITY (-7)   /* output window larger than the buffer         */
+
+/* Flags for aot_orient. */
+#define AOT_VALIDATE 1u       /* check the CSR on the device first (syncs)   */
+
+/* Text for a status code; never NULL. */
+const char* aot_status_str(int status);
+/* Detail of the last failing call on this thread ("" if none). */
+const char* aot_last_error(void);
+/* ABI version, currently 1. */
+int aot_version(void);
+
+/* Input graph (device pointers). */
+typedef struct aot_graph {
+  int32_t n;
+  int64_t nnz;
+  const int64_t* rowptr;  /* device, [n+1] */
+  const int32_t* col;     /* device, [nnz] */
+} aot_graph;
+
+/* Oriented graph in rank space: vertex r is the r-th vertex of the order eta
+ * (degree ascending, ties by smaller original id).  All arrays are device
+ * memory owned by the caller; aot_orient fills them.  m = nnz / 2. */
+typedef struct aot_oriented {
+  int32_t n;
+  int64_t m;
+  int64_t* rowptr;     /* [n+1] out-list offsets (deg+(r) = rowptr[r+1]-rowptr[r]) */
+  int32_t* col;        /* [m]   out-neighbour ranks, strictly ascending per row     */
+  int32_t* tail;       /* [m]   source rank of each directed edge                   */
+  int32_t* perm;       /* [n]   rank -> original id                                 */
+  int32_t* rank;       /* [n]   original id -> rank                                 */
+  int64_t* in_rowptr;  /* [n+1] in-list offsets                                     */
+  int32_t* in_col;     /* [m]   in-neighbour ranks, in ascending ORIGINAL id        */
+  int32_t* in_eid;     /* [m]   id (index into col) of the edge <in_col[j], r>      */
+} aot_oriented;
+
+/* ------------------------------------------------------------------------
+ * aot_orient -- Section 2.2 (orientation technique) with the degree order of
+ * Algorithm 3's first step and Section 3.2's id tie-break.  Ranks vertices by
+ * a stable LSD radix sort of degrees, keeps <u,v> iff rank(u) < rank(v), and
+ * sorts every out-list ascending (the paper's "local order", Section 3.2,
+ * taken ascending in rank space).  Also builds the in-lists that Algorithm 3's
+ * second loop walks.
+ *   g       input graph (device arrays).
+ *   flags   0 or AOT_VALIDATE.
+ *   out     caller-allocated arrays of the sizes listed in aot_oriented;
+ *           out->n and out->m are written.
+ *   ws      device workspace of at least aot_orient_workspace() bytes.
+ * Synchronises `stream` once (to size its launches).  AOT_E_GRAPH (only with
+ * AOT_VALIDATE) if a row is unsorted, has a self-loop, a duplicate, an id out
+ * of range, or the graph is not symmetric. */
+int aot_orient_workspace(int32_t n, int64_t nnz, size_t* bytes);
+int aot_orient(const aot_graph* g, uint32_t flags, aot_oriented* out,
+               void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Dispatch of the probe kernels.  Edges are grouped into buckets; a bucket's
+ * arm picks the index the probes go into and its tile the lanes per edge.
+ * The plain rule (mode AOT_DISPATCH_PLAIN) is fixed; a table (mode
+ * AOT_DISPATCH_TABLE) gives one code per bucket, e.g. chosen by the cost
+ * model.  Every choice gives identical results.
+ *   heavy_min   owners with deg+ >= heavy_min are processed owner-grouped with
+ *               an LDS index (0 = library default).
+ *   table       host array of AOT_NUM_BUCKETS codes (arm | tile << 8), or NULL.
+ */
+#define AOT_DISPATCH_PLAIN 0
+#define AOT_DISPATCH_TABLE 1
+#define AOT_NUM_BUCKETS 32
+typedef struct aot_dispatch {
+  int32_t mode;
+  int32_t heavy_min;
+  const int32_t* table;
+} aot_dispatch;
+
+/* ------------------------------------------------------------------------
+ * aot_count -- Algorithm 3's probe loops, as a count pass.  For every directed
+ * edge e = <u,v>: s = endpoint with the smaller (deg+, rank), b = the other
+ * (Section 3.2, Correctness, and its footnote); cnt(e) = |N+(s) n N+(b)|,
+ * found by probing each w in N+(s) into an index of N+(b).
+ *   g        oriented graph from aot_orient (device).
+ *   d        dispatch (NULL = plain rule).
+ *   tri_off  device int64[m+1], written: exclusive prefix sum of cnt; the
+ *            triangles of edge e are global indices [tri_off[e], tri_off[e+1]).
+ *   ws       device workspace of at least aot_count_workspace() bytes; keep it
+ *            unchanged until the matching aot_list calls are done.
+ *   result   host uint64[2], written: {T, probes}; probes = sum over edges of
+ *            min(deg+(u), deg+(v)).
+ * Synchronises `stream`. */
+int aot_count_workspace(int32_t n, int64_t m, size_t* bytes);
+int aot_count(const aot_oriented* g, const aot_dispatch* d, int64_t* tri_off,
+              void* ws, size_t ws_bytes, uint64_t* result, void* stream);
+
+/* ------------------------------------------------------------------------
+ * aot_list -- Algorithm 3's "output triangle" steps, as a write pass.  Writes
+ * triangles [first, first + count) of the global list into out (device,
+ * int32[3*count]): each triangle as its three ORIGINAL ids ascending; the
+ * global order is edge order, then ascending third vertex (in rank space).
+ * Requires the tri_off and workspace of a prior aot_count on the same graph.
+ * count may run past T (only T - first are written).  Does not synchronise.
+ *   written  host, optional: number of triangles written. */
+int aot_list(const aot_oriented* g, const aot_dispatch* d, const int64_t* tri_off,
+             void* ws, size_t ws_bytes, int64_t first, int64_t count,
+             int32_t* out, int64_t* written, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AOT_H */

@@ -87,6 +87,37 @@ int64_t orc_orient(int32_t n, const int64_t* rowptr, const int32_t* col,
   return m;
 }
 
+/* In-lists of the oriented graph (Algorithm 3's second loop walks them): for
+ * rank r, the ranks of the neighbours of perm[r] ranked below r, in the
+ * order they appear in the input row (ascending original id); ieid[j] is the
+ * index in ocol of the edge <icol[j], r>, found by binary search in N+(icol[j]). */
+int64_t orc_in_lists(int32_t n, const int64_t* rowptr, const int32_t* col, const int32_t* perm,
+                     const int32_t* rank, const int64_t* orow, const int32_t* ocol,
+                     int64_t* irow, int32_t* icol, int32_t* ieid) {
+  int64_t k = 0;
+  irow[0] = 0;
+  for (int32_t r = 0; r < n; ++r) {
+    int32_t u = perm[r];
+    for (int64_t j = rowptr[u]; j < rowptr[u + 1]; ++j) {
+      int32_t x = rank[col[j]];
+      if (x < r) {
+        int64_t lo = orow[x], hi = orow[x + 1];  /* binary search: N+(x) ascending */
+        while (lo < hi) {
+          int64_t mid = lo + (hi - lo) / 2;
+          if (ocol[mid] < r) lo = mid + 1; else hi = mid;
+        }
+        int64_t e = lo;
+        if (e == orow[x + 1] || ocol[e] != r) return -1;   /* not an edge: asymmetric input */
+        icol[k] = x;
+        ieid[k] = (int32_t)e;
+        ++k;
+      }
+    }
+    irow[r + 1] = k;
+  }
+  return k;
+}
+
 /* |A n B| for two ascending lists, by merging. */
 static int64_t merge_count(const int32_t* a, int64_t na, const int32_t* b, int64_t nb) {
   int64_t i = 0, j = 0, c = 0;

@@ -1,0 +1,222 @@
+"""Python binding of libaot.so (include/aot.h): argument marshalling only.
+
+Device buffers are torch tensors on a ROCm device; every step of the method
+runs in the library's HIP kernels.  There is no fallback: if the library is
+not built, loading raises.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libaot.so")
+
+AOT_OK = 0
+AOT_VALIDATE = 1
+AOT_DISPATCH_PLAIN = 0
+AOT_DISPATCH_TABLE = 1
+AOT_NUM_BUCKETS = 32
+
+# every symbol include/aot.h declares
+EXPORTS = (
+    "aot_status_str", "aot_last_error", "aot_version",
+    "aot_orient_workspace", "aot_orient",
+    "aot_count_workspace", "aot_count",
+    "aot_list",
+)
+
+
+class AotError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what}: status {status}")
+        self.status = status
+
+
+class Graph(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("nnz", ctypes.c_int64),
+                ("rowptr", ctypes.c_void_p), ("col", ctypes.c_void_p)]
+
+
+class OrientedC(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("m", ctypes.c_int64),
+                ("rowptr", ctypes.c_void_p), ("col", ctypes.c_void_p),
+                ("tail", ctypes.c_void_p), ("perm", ctypes.c_void_p),
+                ("rank", ctypes.c_void_p), ("in_rowptr", ctypes.c_void_p),
+                ("in_col", ctypes.c_void_p), ("in_eid", ctypes.c_void_p)]
+
+
+class DispatchC(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("heavy_min", ctypes.c_int32),
+                ("table", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Loads libaot.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_2006_11494_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, i32, i64, u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
+    sz = ctypes.POINTER(ctypes.c_size_t)
+    lib.aot_status_str.argtypes = [ctypes.c_int]
+    lib.aot_status_str.restype = ctypes.c_char_p
+    lib.aot_last_error.argtypes = []
+    lib.aot_last_error.restype = ctypes.c_char_p
+    lib.aot_version.argtypes = []
+    lib.aot_version.restype = ctypes.c_int
+    lib.aot_orient_workspace.argtypes = [i32, i64, sz]
+    lib.aot_orient.argtypes = [ctypes.POINTER(Graph), u32, ctypes.POINTER(OrientedC), vp,
+                               ctypes.c_size_t, vp]
+    lib.aot_count_workspace.argtypes = [i32, i64, sz]
+    lib.aot_count.argtypes = [ctypes.POINTER(OrientedC), ctypes.POINTER(DispatchC), vp, vp,
+                              ctypes.c_size_t, ctypes.POINTER(ctypes.c_uint64), vp]
+    lib.aot_list.argtypes = [ctypes.POINTER(OrientedC), ctypes.POINTER(DispatchC), vp, vp,
+                             ctypes.c_size_t, i64, i64, vp, ctypes.POINTER(ctypes.c_int64), vp]
+    for f in ("aot_orient_workspace", "aot_orient", "aot_count_workspace", "aot_count", "aot_list"):
+        getattr(lib, f).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(status: int, what: str):
+    if status != AOT_OK:
+        lib = load()
+        msg = lib.aot_last_error().decode() or lib.aot_status_str(status).decode()
+        raise AotError(status, f"{what}: {msg}")
+
+
+def _ptr(t: torch.Tensor | None):
+    return None if t is None or t.numel() == 0 else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+@dataclass
+class Oriented:
+    """Oriented graph in rank space (device tensors); see aot_oriented."""
+    n: int
+    m: int
+    rowptr: torch.Tensor
+    col: torch.Tensor
+    tail: torch.Tensor
+    perm: torch.Tensor
+    rank: torch.Tensor
+    in_rowptr: torch.Tensor
+    in_col: torch.Tensor
+    in_eid: torch.Tensor
+
+    def cstruct(self) -> OrientedC:
+        return OrientedC(self.n, self.m, _ptr(self.rowptr), _ptr(self.col), _ptr(self.tail),
+                         _ptr(self.perm), _ptr(self.rank), _ptr(self.in_rowptr),
+                         _ptr(self.in_col), _ptr(self.in_eid))
+
+    @property
+    def dplus(self) -> torch.Tensor:
+        return self.rowptr[1:] - self.rowptr[:-1]
+
+
+@dataclass
+class Dispatch:
+    """Probe-kernel dispatch: the plain rule, or a per-bucket code table."""
+    mode: int = AOT_DISPATCH_PLAIN
+    heavy_min: int = 0
+    table: list | None = None
+
+    def cstruct(self):
+        self._table = None
+        tp = None
+        if self.table is not None:
+            self._table = (ctypes.c_int32 * AOT_NUM_BUCKETS)(*self.table)
+            tp = ctypes.cast(self._table, ctypes.c_void_p)
+        return DispatchC(self.mode, self.heavy_min, tp)
+
+
+@dataclass
+class Counted:
+    """Result of aot_count; keeps the workspace that aot_list needs."""
+    T: int
+    probes: int
+    tri_off: torch.Tensor
+    ws: torch.Tensor
+
+
+def orient_workspace(n: int, nnz: int) -> int:
+    b = ctypes.c_size_t(0)
+    _check(load().aot_orient_workspace(n, nnz, ctypes.byref(b)), "aot_orient_workspace")
+    return b.value
+
+
+def count_workspace(n: int, m: int) -> int:
+    b = ctypes.c_size_t(0)
+    _check(load().aot_count_workspace(n, m, ctypes.byref(b)), "aot_count_workspace")
+    return b.value
+
+
+def orient(rowptr: torch.Tensor, col: torch.Tensor, validate: bool = False, stream=None,
+           ws: torch.Tensor | None = None) -> Oriented:
+    """aot_orient on a symmetric device CSR (rowptr int64[n+1], col int32[nnz])."""
+    assert rowptr.dtype == torch.int64 and col.dtype == torch.int32
+    assert rowptr.is_contiguous() and col.is_contiguous()
+    dev = rowptr.device
+    n = rowptr.numel() - 1
+    nnz = col.numel()
+    m = nnz // 2
+    i32 = dict(dtype=torch.int32, device=dev)
+    i64 = dict(dtype=torch.int64, device=dev)
+    o = Oriented(n, m, torch.empty(n + 1, **i64), torch.empty(m, **i32), torch.empty(m, **i32),
+                 torch.empty(n, **i32), torch.empty(n, **i32), torch.empty(n + 1, **i64),
+                 torch.empty(m, **i32), torch.empty(m, **i32))
+    need = orient_workspace(n, nnz)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    g = Graph(n, nnz, _ptr(rowptr) or ctypes.c_void_p(rowptr.data_ptr()), _ptr(col))
+    oc = o.cstruct()
+    _check(load().aot_orient(ctypes.byref(g), AOT_VALIDATE if validate else 0, ctypes.byref(oc),
+                             _ptr(ws), ws.numel(), _stream(stream)), "aot_orient")
+    return o
+
+
+def count(o: Oriented, dispatch: Dispatch | None = None, stream=None,
+          ws: torch.Tensor | None = None) -> Counted:
+    """aot_count: per-edge triangle offsets, T and the probe count."""
+    dev = o.rowptr.device
+    need = count_workspace(o.n, o.m)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    tri_off = torch.empty(o.m + 1, dtype=torch.int64, device=dev)
+    res = (ctypes.c_uint64 * 2)()
+    oc = o.cstruct()
+    dc = (dispatch or Dispatch()).cstruct()
+    _check(load().aot_count(ctypes.byref(oc), ctypes.byref(dc), _ptr(tri_off), _ptr(ws),
+                            ws.numel(), res, _stream(stream)), "aot_count")
+    return Counted(int(res[0]), int(res[1]), tri_off, ws)
+
+
+def list_triangles(o: Oriented, c: Counted, first: int = 0, count: int | None = None,
+                   out: torch.Tensor | None = None, dispatch: Dispatch | None = None,
+                   stream=None) -> torch.Tensor:
+    """aot_list: triangles [first, first+count) as an int32 (k, 3) device tensor."""
+    if count is None:
+        count = max(0, c.T - first)
+    k = max(0, min(count, c.T - first))
+    if out is None:
+        out = torch.empty((max(k, 0), 3), dtype=torch.int32, device=o.rowptr.device)
+    oc = o.cstruct()
+    dc = (dispatch or Dispatch()).cstruct()
+    _check(load().aot_list(ctypes.byref(oc), ctypes.byref(dc), _ptr(c.tri_off), _ptr(c.ws),
+                           c.ws.numel(), first, k, _ptr(out), None, _stream(stream)), "aot_list")
+    return out[:k]

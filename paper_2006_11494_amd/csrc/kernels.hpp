@@ -1,0 +1,82 @@
+// Internal interface between the C ABI (abi.cpp) and the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "common.hpp"
+
+namespace aot {
+
+inline int64_t align_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+inline int64_t cdiv(int64_t x, int64_t a) { return (x + a - 1) / a; }
+
+// Carves aligned sub-buffers out of one workspace allocation.
+struct Carve {
+  char* base;
+  size_t used = 0;
+  size_t cap;
+  Carve(void* p, size_t c) : base(static_cast<char*>(p)), cap(c) {}
+  template <typename T>
+  T* take(int64_t count) {
+    size_t bytes = (size_t)align_up((int64_t)(sizeof(T) * (size_t)(count > 0 ? count : 1)), 256);
+    T* p = reinterpret_cast<T*>(base ? base + used : nullptr);
+    used += bytes;
+    return p;
+  }
+  bool ok() const { return used <= cap; }
+};
+
+// ---- fill.hip
+hipError_t fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
+hipError_t fill_i64(int64_t* p, int64_t n, int64_t v, hipStream_t s);
+
+// ---- scan.hip: out[0..n] = exclusive prefix sums of in[0..n), out[n] = total.
+size_t scan_workspace(int64_t n);
+hipError_t exclusive_scan(const int32_t* in, int64_t* out, int64_t n, void* tmp, hipStream_t s);
+hipError_t exclusive_scan(const int64_t* in, int64_t* out, int64_t n, void* tmp, hipStream_t s);
+
+// ---- radix.hip: stable LSD sort of (key, value) pairs by the low `bits` bits
+// of non-negative int32 keys.  Result lands in (keys_out, vals_out); the
+// other pair of buffers is clobbered.
+size_t radix_workspace(int64_t n);
+hipError_t radix_sort_pairs(int32_t* keys, int32_t* vals, int32_t* keys_alt, int32_t* vals_alt,
+                            int64_t n, int bits, void* tmp, hipStream_t s,
+                            int32_t** keys_out, int32_t** vals_out);
+
+// ---- orient.hip
+struct OrientScratch {
+  int32_t* key_a; int32_t* val_a; int32_t* key_b; int32_t* val_b;  // [n] each
+  int32_t* dplus;        // [n] by rank
+  int32_t* dminus;       // [n] by rank
+  int32_t* unsorted;     // [m] out-lists before sorting
+  int32_t* rows_by_len;  // [n] rank ids grouped by out-list length class
+  int32_t* counters;     // small device counters
+  int64_t* host_info;    // device copy of the scalars read back by the host
+  void* scan_tmp;
+  void* radix_tmp;
+};
+size_t orient_workspace_bytes(int32_t n, int64_t nnz);
+int orient_run(int32_t n, int64_t nnz, const int64_t* rowptr, const int32_t* col, bool validate,
+               int64_t* orow, int32_t* ocol, int32_t* otail, int32_t* perm, int32_t* rank,
+               int64_t* irow, int32_t* icol, int32_t* ieid, void* ws, size_t ws_bytes,
+               hipStream_t s, const char** err);
+
+// ---- count.hip
+struct CountPlan;
+size_t count_workspace_bytes(int32_t n, int64_t m);
+struct DispatchView {
+  int32_t heavy_min;
+  const int32_t* table;  // host, kNumBuckets codes or nullptr
+};
+int count_run(int32_t n, int64_t m, const int64_t* orow, const int32_t* ocol, const int32_t* otail,
+              const int64_t* irow, const int32_t* icol, const int32_t* ieid,
+              const DispatchView& d, int64_t* tri_off, void* ws, size_t ws_bytes,
+              uint64_t* result, hipStream_t s, const char** err);
+int list_run(int32_t n, int64_t m, const int64_t* orow, const int32_t* ocol, const int32_t* otail,
+             const int32_t* perm, const int64_t* irow, const int32_t* icol, const int32_t* ieid,
+             const DispatchView& d, const int64_t* tri_off, void* ws, size_t ws_bytes,
+             int64_t first, int64_t count, int32_t* out, hipStream_t s, const char** err);
+
+}  // namespace aot

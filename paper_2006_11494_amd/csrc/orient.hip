@@ -1,0 +1,552 @@
+// Orientation (Section 2.2, "Orientation technique"; first step of Algorithm
+// 3): rank vertices by (degree, id) ascending, keep <u,v> iff rank(u) <
+// rank(v), relabel to rank space and sort every out-list ascending.
+//
+// After the radix sort, rank order is degree order, so consecutive ranks have
+// similar row lengths: rows are processed in rank ranges with a row-group
+// width G matched to the degree range (4, 16 or 64 lanes, or a whole
+// workgroup for rows longer than 64).  Out-list lengths are not monotone in
+// rank, so the sort step first bins rows by length.
+#include <climits>
+
+#include "kernels.hpp"
+
+namespace aot {
+
+namespace {
+
+// counters[] layout (int32, device)
+enum : int {
+  kCMaxDeg = 0,
+  kCDeg0 = 1,   // #vertices with degree 0
+  kCDeg4 = 2,   // #vertices with degree <= 4
+  kCDeg16 = 3,  // <= 16
+  kCDeg64 = 4,  // <= 64
+  kCError = 5,
+  kCSortCount = 8,    // [8..11] rows per sort class
+  kCSortCursor = 12,  // [12..15]
+  kCounters = 16,
+};
+
+constexpr int kSortClasses = 4;     // len <= 16, <= 64, <= 4096, longer
+constexpr int kBitmapWords = 16384; // 64 KiB window for the long-list sort
+constexpr int kGrid = 4096;         // grid of the grid-stride kernels
+
+enum : int {
+  kErrRowptr = 1, kErrRange = 2, kErrLoop = 4, kErrOrder = 8, kErrAsym = 16,
+};
+
+__global__ __launch_bounds__(kBlock) void k_validate_rowptr(int32_t n, int64_t nnz,
+                                                            const int64_t* __restrict__ rowptr,
+                                                            int32_t* __restrict__ counters) {
+  int bad = 0;
+  for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v <= n;
+       v += (int64_t)gridDim.x * kBlock) {
+    const int64_t a = rowptr[v];
+    if (v == 0 && a != 0) bad = 1;
+    if (v == n && a != nnz) bad = 1;
+    if (v < n && (rowptr[v + 1] < a)) bad = 1;
+    if (a < 0 || a > nnz) bad = 1;
+  }
+  if (bad) atomicOr(&counters[kCError], kErrRowptr);
+}
+
+// One wave per row (grid-stride over rows).
+__global__ __launch_bounds__(kBlock) void k_validate_rows(int32_t n,
+                                                          const int64_t* __restrict__ rowptr,
+                                                          const int32_t* __restrict__ col,
+                                                          int32_t* __restrict__ counters) {
+  int bad = 0;
+  const int64_t wave = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
+  const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
+  for (int64_t u = wave; u < n; u += nwaves) {
+    const int64_t beg = rowptr[u], end = rowptr[u + 1];
+    for (int64_t k = beg + lane_id(); k < end; k += kWave) {
+      const int32_t v = col[k];
+      if (v < 0 || v >= n) { bad |= kErrRange; continue; }
+      if (v == u) bad |= kErrLoop;
+      if (k > beg && col[k - 1] >= v) bad |= kErrOrder;
+      const int64_t vb = rowptr[v], ve = rowptr[v + 1];
+      if (!contains_sorted(col + vb, ve - vb, (int32_t)u)) bad |= kErrAsym;
+    }
+  }
+  if (bad) atomicOr(&counters[kCError], bad);
+}
+
+// deg(v), the (key, value) pairs for the rank sort, and the degree-class sizes.
+__global__ __launch_bounds__(kBlock) void k_degree(int32_t n, const int64_t* __restrict__ rowptr,
+                                                   int32_t* __restrict__ keys,
+                                                   int32_t* __restrict__ vals,
+                                                   int32_t* __restrict__ counters) {
+  __shared__ int32_t red[kWavesPerBlock];
+  int32_t mx = 0, c0 = 0, c4 = 0, c16 = 0, c64 = 0;
+  for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < n;
+       v += (int64_t)gridDim.x * kBlock) {
+    const int32_t d = (int32_t)(rowptr[v + 1] - rowptr[v]);
+    keys[v] = d;
+    vals[v] = (int32_t)v;
+    mx = d > mx ? d : mx;
+    c0 += d == 0;
+    c4 += d <= 4;
+    c16 += d <= 16;
+    c64 += d <= 64;
+  }
+  for (int o = kWave / 2; o > 0; o >>= 1) {
+    const int32_t y = __shfl_xor(mx, o, kWave);
+    mx = y > mx ? y : mx;
+  }
+  if (lane_id() == 0) atomicMax(&counters[kCMaxDeg], mx);
+  c0 = block_sum(c0, red);
+  c4 = block_sum(c4, red);
+  c16 = block_sum(c16, red);
+  c64 = block_sum(c64, red);
+  if (threadIdx.x == 0) {
+    atomicAdd(&counters[kCDeg0], c0);
+    atomicAdd(&counters[kCDeg4], c4);
+    atomicAdd(&counters[kCDeg16], c16);
+    atomicAdd(&counters[kCDeg64], c64);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_perm_rank(int32_t n, const int32_t* __restrict__ sorted_ids,
+                                                      int32_t* __restrict__ perm,
+                                                      int32_t* __restrict__ rank) {
+  for (int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x; r < n;
+       r += (int64_t)gridDim.x * kBlock) {
+    const int32_t v = sorted_ids[r];
+    perm[r] = v;
+    rank[v] = (int32_t)r;
+  }
+}
+
+// deg+(r) and deg-(r) for ranks [r0, r1); G lanes per row (G = kBlock: one
+// row per workgroup).
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_orient_count(int32_t r0, int32_t r1,
+                                                         const int64_t* __restrict__ rowptr,
+                                                         const int32_t* __restrict__ col,
+                                                         const int32_t* __restrict__ perm,
+                                                         const int32_t* __restrict__ rank,
+                                                         int32_t* __restrict__ dplus,
+                                                         int32_t* __restrict__ dminus) {
+  constexpr int kGroups = kBlock / G;
+  __shared__ int32_t red[kWavesPerBlock];
+  const int gi = threadIdx.x / G, li = threadIdx.x % G;
+  for (int64_t rb = r0 + (int64_t)blockIdx.x * kGroups; rb < r1;
+       rb += (int64_t)gridDim.x * kGroups) {
+    const int64_t r = rb + gi;
+    int32_t cnt = 0;
+    int64_t deg = 0;
+    if (r < r1) {
+      const int32_t u = perm[r];
+      const int64_t beg = rowptr[u];
+      deg = rowptr[u + 1] - beg;
+      for (int64_t j = li; j < deg; j += G) cnt += rank[col[beg + j]] > r;
+    }
+    if constexpr (G <= kWave) {
+      cnt = group_sum<G>(cnt);
+      if (li == 0 && r < r1) {
+        dplus[r] = cnt;
+        dminus[r] = (int32_t)(deg - cnt);
+      }
+    } else {
+      cnt = block_sum(cnt, red);
+      if (threadIdx.x == 0) {
+        dplus[r] = cnt;
+        dminus[r] = (int32_t)(deg - cnt);
+      }
+    }
+  }
+}
+
+// Splits every row into its out-part (unsorted, original order) and in-part
+// (original order), and records each out-edge's tail.
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_orient_write(
+    int32_t r0, int32_t r1, const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+    const int32_t* __restrict__ perm, const int32_t* __restrict__ rank,
+    const int64_t* __restrict__ orow, const int64_t* __restrict__ irow,
+    int32_t* __restrict__ unsorted, int32_t* __restrict__ otail, int32_t* __restrict__ icol) {
+  constexpr int kGroups = kBlock / G;
+  __shared__ int32_t so[kWavesPerBlock], si[kWavesPerBlock];
+  const int gi = threadIdx.x / G, li = threadIdx.x % G;
+  const int w = threadIdx.x / kWave;
+  for (int64_t rb = r0 + (int64_t)blockIdx.x * kGroups; rb < r1;
+       rb += (int64_t)gridDim.x * kGroups) {
+    const int64_t r = rb + gi;
+    int64_t beg = 0, deg = 0, op = 0, ip = 0;
+    if (r < r1) {
+      const int32_t u = perm[r];
+      beg = rowptr[u];
+      deg = rowptr[u + 1] - beg;
+      op = orow[r];
+      ip = irow[r];
+    }
+    for (int64_t j0 = 0; j0 < deg; j0 += G) {
+      const int64_t j = j0 + li;
+      const bool valid = j < deg;
+      const int32_t rv = valid ? rank[col[beg + j]] : 0;
+      const bool out = valid && rv > r;
+      const bool in = valid && rv < r;
+      const uint64_t bo = ballot(out), bi = ballot(in);
+      int32_t po, pi, to, ti;
+      if constexpr (G <= kWave) {
+        po = popc_below_in_group<G>(bo);
+        pi = popc_below_in_group<G>(bi);
+        to = __popcll(group_bits<G>(bo));
+        ti = __popcll(group_bits<G>(bi));
+      } else {
+        if (lane_id() == 0) { so[w] = __popcll(bo); si[w] = __popcll(bi); }
+        __syncthreads();
+        int32_t ao = 0, ai = 0;
+        to = 0; ti = 0;
+        for (int q = 0; q < kWavesPerBlock; ++q) {
+          if (q < w) { ao += so[q]; ai += si[q]; }
+          to += so[q]; ti += si[q];
+        }
+        po = ao + popc_below(bo);
+        pi = ai + popc_below(bi);
+        __syncthreads();
+      }
+      if (out) {
+        unsorted[op + po] = rv;
+        otail[op + po] = (int32_t)r;
+      }
+      if (in) icol[ip + pi] = rv;
+      op += to;
+      ip += ti;
+    }
+  }
+}
+
+__device__ __forceinline__ int sort_class(int64_t len) {
+  return len <= 16 ? 0 : len <= 64 ? 1 : len <= 4096 ? 2 : 3;
+}
+
+__global__ __launch_bounds__(kBlock) void k_count_sort_classes(int32_t n,
+                                                               const int32_t* __restrict__ dplus,
+                                                               int32_t* __restrict__ counters) {
+  __shared__ int32_t h[kSortClasses];
+  if (threadIdx.x < kSortClasses) h[threadIdx.x] = 0;
+  __syncthreads();
+  for (int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x; r < n;
+       r += (int64_t)gridDim.x * kBlock) {
+    const int32_t len = dplus[r];
+    if (len > 0) atomicAdd(&h[sort_class(len)], 1);
+  }
+  __syncthreads();
+  if (threadIdx.x < kSortClasses) atomicAdd(&counters[kCSortCount + threadIdx.x], h[threadIdx.x]);
+}
+
+__global__ __launch_bounds__(kBlock) void k_scatter_sort_classes(int32_t n,
+                                                                 const int32_t* __restrict__ dplus,
+                                                                 int32_t* __restrict__ counters,
+                                                                 int32_t* __restrict__ rows) {
+  for (int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x; r < n;
+       r += (int64_t)gridDim.x * kBlock) {
+    const int32_t len = dplus[r];
+    if (len <= 0) continue;
+    const int c = sort_class(len);
+    int32_t base = 0;
+    for (int q = 0; q < c; ++q) base += counters[kCSortCount + q];
+    rows[base + atomicAdd(&counters[kCSortCursor + c], 1)] = (int32_t)r;
+  }
+}
+
+// Bitonic sort of one row per G-lane group, one element per lane.
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_sort_lanes(int cls, const int32_t* __restrict__ counters,
+                                                       const int32_t* __restrict__ rows,
+                                                       const int64_t* __restrict__ orow,
+                                                       const int32_t* __restrict__ src,
+                                                       int32_t* __restrict__ dst) {
+  constexpr int kGroups = kBlock / G;
+  int32_t base = 0;
+  for (int q = 0; q < cls; ++q) base += counters[kCSortCount + q];
+  const int32_t count = counters[kCSortCount + cls];
+  const int gi = threadIdx.x / G, li = threadIdx.x % G;
+  for (int64_t t = (int64_t)blockIdx.x * kGroups + gi; t < count;
+       t += (int64_t)gridDim.x * kGroups) {
+    const int32_t r = rows[base + t];
+    const int64_t beg = orow[r];
+    const int64_t len = orow[r + 1] - beg;
+    int32_t x = li < len ? src[beg + li] : INT_MAX;
+#pragma unroll
+    for (int k = 2; k <= G; k <<= 1) {
+#pragma unroll
+      for (int j = k >> 1; j > 0; j >>= 1) {
+        const int32_t y = __shfl_xor(x, j, G);
+        const bool up = (li & k) == 0;
+        const bool lower = (li & j) == 0;
+        x = (lower == up) ? min(x, y) : max(x, y);
+      }
+    }
+    if (li < len) dst[beg + li] = x;
+  }
+}
+
+// Bitonic sort in LDS, one row (64 < len <= 4096) per workgroup.
+__global__ __launch_bounds__(kBlock) void k_sort_block(int cls, const int32_t* __restrict__ counters,
+                                                       const int32_t* __restrict__ rows,
+                                                       const int64_t* __restrict__ orow,
+                                                       const int32_t* __restrict__ src,
+                                                       int32_t* __restrict__ dst) {
+  __shared__ int32_t s[4096];
+  int32_t base = 0;
+  for (int q = 0; q < cls; ++q) base += counters[kCSortCount + q];
+  const int32_t count = counters[kCSortCount + cls];
+  for (int64_t t = blockIdx.x; t < count; t += gridDim.x) {
+    const int32_t r = rows[base + t];
+    const int64_t beg = orow[r];
+    const int32_t len = (int32_t)(orow[r + 1] - beg);
+    int N = 1;
+    while (N < len) N <<= 1;
+    for (int i = threadIdx.x; i < N; i += kBlock) s[i] = i < len ? src[beg + i] : INT_MAX;
+    __syncthreads();
+    for (int k = 2; k <= N; k <<= 1) {
+      for (int j = k >> 1; j > 0; j >>= 1) {
+        for (int idx = threadIdx.x; idx < N / 2; idx += kBlock) {
+          const int i = (idx / j) * 2 * j + (idx % j);
+          const int p = i + j;
+          const bool up = (i & k) == 0;
+          const int32_t a = s[i], b = s[p];
+          if ((a > b) == up) { s[i] = b; s[p] = a; }
+        }
+        __syncthreads();
+      }
+    }
+    for (int i = threadIdx.x; i < len; i += kBlock) dst[beg + i] = s[i];
+    __syncthreads();
+  }
+}
+
+// Long rows: values are distinct ranks, so a bitmap over [min, max] in LDS
+// (one 524288-id window at a time) sorts them; set bits are written out in
+// order after a block-wide prefix count.
+__global__ __launch_bounds__(kBlock) void k_sort_bitmap(int cls, const int32_t* __restrict__ counters,
+                                                        const int32_t* __restrict__ rows,
+                                                        const int64_t* __restrict__ orow,
+                                                        const int32_t* __restrict__ src,
+                                                        int32_t* __restrict__ dst) {
+  __shared__ uint32_t bm[kBitmapWords];
+  __shared__ int64_t tmp[kWavesPerBlock + 1];
+  __shared__ int32_t red[2][kWavesPerBlock];
+  constexpr int64_t kBits = (int64_t)kBitmapWords * 32;
+  constexpr int kWordsPerThread = kBitmapWords / kBlock;
+  int32_t base = 0;
+  for (int q = 0; q < cls; ++q) base += counters[kCSortCount + q];
+  const int32_t count = counters[kCSortCount + cls];
+  for (int64_t t = blockIdx.x; t < count; t += gridDim.x) {
+    const int32_t r = rows[base + t];
+    const int64_t beg = orow[r];
+    const int64_t len = orow[r + 1] - beg;
+    int32_t lo = INT_MAX, hi = INT_MIN;
+    for (int64_t i = threadIdx.x; i < len; i += kBlock) {
+      const int32_t v = src[beg + i];
+      lo = min(lo, v);
+      hi = max(hi, v);
+    }
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+      lo = min(lo, __shfl_xor(lo, o, kWave));
+      hi = max(hi, __shfl_xor(hi, o, kWave));
+    }
+    if (lane_id() == 0) { red[0][threadIdx.x / kWave] = lo; red[1][threadIdx.x / kWave] = hi; }
+    __syncthreads();
+    lo = red[0][0]; hi = red[1][0];
+    for (int q = 1; q < kWavesPerBlock; ++q) { lo = min(lo, red[0][q]); hi = max(hi, red[1][q]); }
+    __syncthreads();
+    int64_t out = beg;
+    for (int64_t w0 = lo; w0 <= hi; w0 += kBits) {
+      for (int i = threadIdx.x; i < kBitmapWords; i += kBlock) bm[i] = 0u;
+      __syncthreads();
+      for (int64_t i = threadIdx.x; i < len; i += kBlock) {
+        const int64_t off = (int64_t)src[beg + i] - w0;
+        if (off >= 0 && off < kBits) atomicOr(&bm[off >> 5], 1u << (off & 31));
+      }
+      __syncthreads();
+      const int wbeg = threadIdx.x * kWordsPerThread;
+      int64_t c = 0;
+      for (int q = 0; q < kWordsPerThread; ++q) c += __popc(bm[wbeg + q]);
+      int64_t total;
+      int64_t pos = out + block_exclusive_scan(c, tmp, &total);
+      for (int q = 0; q < kWordsPerThread; ++q) {
+        uint32_t bits = bm[wbeg + q];
+        while (bits) {
+          const int b = __ffs(bits) - 1;
+          dst[pos++] = (int32_t)(w0 + (int64_t)(wbeg + q) * 32 + b);
+          bits &= bits - 1;
+        }
+      }
+      out += total;
+      __syncthreads();
+    }
+  }
+}
+
+// in_eid[j] = index of edge <x, r> in the out-lists, for in-entry x of row r.
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_in_eid(int32_t r0, int32_t r1,
+                                                   const int64_t* __restrict__ orow,
+                                                   const int32_t* __restrict__ ocol,
+                                                   const int64_t* __restrict__ irow,
+                                                   const int32_t* __restrict__ icol,
+                                                   int32_t* __restrict__ ieid) {
+  constexpr int kGroups = kBlock / G;
+  const int gi = threadIdx.x / G, li = threadIdx.x % G;
+  for (int64_t rb = r0 + (int64_t)blockIdx.x * kGroups; rb < r1;
+       rb += (int64_t)gridDim.x * kGroups) {
+    const int64_t r = rb + gi;
+    if (r >= r1) continue;
+    const int64_t ib = irow[r], ie = irow[r + 1];
+    for (int64_t j = ib + li; j < ie; j += G) {
+      const int32_t x = icol[j];
+      const int64_t b0 = orow[x];
+      ieid[j] = (int32_t)(b0 + lower_bound(ocol + b0, orow[x + 1] - b0, (int32_t)r));
+    }
+  }
+}
+
+unsigned grid_for(int64_t items, int per_block) {
+  int64_t b = cdiv(items, per_block);
+  if (b < 1) b = 1;
+  if (b > kGrid * 4) b = kGrid * 4;
+  return (unsigned)b;
+}
+
+template <int G, typename F>
+hipError_t launch_rows(int32_t r0, int32_t r1, hipStream_t s, F f) {
+  if (r1 <= r0) return hipSuccess;
+  f(grid_for(r1 - r0, kBlock / G), s);
+  return hipGetLastError();
+}
+
+#define AOT_TRY(x)                          \
+  do {                                      \
+    hipError_t e_ = (x);                    \
+    if (e_ != hipSuccess) {                 \
+      *err = hipGetErrorString(e_);         \
+      return -5;                            \
+    }                                       \
+  } while (0)
+
+}  // namespace
+
+size_t orient_workspace_bytes(int32_t n, int64_t nnz) {
+  Carve c(nullptr, 0);
+  const int64_t m = nnz / 2;
+  for (int i = 0; i < 4; ++i) c.take<int32_t>(n);  // key/val a/b
+  c.take<int32_t>(n);                               // dplus
+  c.take<int32_t>(n);                               // dminus
+  c.take<int32_t>(m);                               // unsorted
+  c.take<int32_t>(n);                               // rows_by_len
+  c.take<int32_t>(kCounters);
+  c.take<char>((int64_t)scan_workspace(n));
+  c.take<char>((int64_t)radix_workspace(n));
+  return c.used;
+}
+
+int orient_run(int32_t n, int64_t nnz, const int64_t* rowptr, const int32_t* col, bool validate,
+               int64_t* orow, int32_t* ocol, int32_t* otail, int32_t* perm, int32_t* rank,
+               int64_t* irow, int32_t* icol, int32_t* ieid, void* ws, size_t ws_bytes,
+               hipStream_t s, const char** err) {
+  const int64_t m = nnz / 2;
+  Carve c(ws, ws_bytes);
+  int32_t* key_a = c.take<int32_t>(n);
+  int32_t* val_a = c.take<int32_t>(n);
+  int32_t* key_b = c.take<int32_t>(n);
+  int32_t* val_b = c.take<int32_t>(n);
+  int32_t* dplus = c.take<int32_t>(n);
+  int32_t* dminus = c.take<int32_t>(n);
+  int32_t* unsorted = c.take<int32_t>(m);
+  int32_t* rows = c.take<int32_t>(n);
+  int32_t* counters = c.take<int32_t>(kCounters);
+  void* scan_tmp = c.take<char>((int64_t)scan_workspace(n));
+  void* radix_tmp = c.take<char>((int64_t)radix_workspace(n));
+  if (!c.ok()) {
+    *err = "orientation workspace too small";
+    return -4;
+  }
+  AOT_TRY(fill_i32(counters, kCounters, 0, s));
+  if (validate) {
+    k_validate_rowptr<<<grid_for(n + 1, kBlock), kBlock, 0, s>>>(n, nnz, rowptr, counters);
+    AOT_TRY(hipGetLastError());
+    int32_t flag = 0;
+    AOT_TRY(hipMemcpyAsync(&flag, counters + kCError, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    AOT_TRY(hipStreamSynchronize(s));
+    if (flag) {
+      *err = "row offsets are not a valid CSR (rowptr[0] != 0, decreasing, or end != nnz)";
+      return -2;
+    }
+    k_validate_rows<<<grid_for((int64_t)n * kWave, kBlock), kBlock, 0, s>>>(n, rowptr, col,
+                                                                             counters);
+    AOT_TRY(hipGetLastError());
+    AOT_TRY(hipMemcpyAsync(&flag, counters + kCError, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    AOT_TRY(hipStreamSynchronize(s));
+    if (flag) {
+      *err = (flag & kErrRange)  ? "column id out of range"
+             : (flag & kErrLoop) ? "self-loop"
+             : (flag & kErrOrder) ? "row not strictly ascending (unsorted or duplicate)"
+                                  : "graph is not symmetric";
+      return -2;
+    }
+  }
+  if (n == 0) {
+    AOT_TRY(fill_i64(orow, 1, 0, s));
+    AOT_TRY(fill_i64(irow, 1, 0, s));
+    return 0;
+  }
+  k_degree<<<grid_for(n, kBlock), kBlock, 0, s>>>(n, rowptr, key_a, val_a, counters);
+  AOT_TRY(hipGetLastError());
+  int32_t hc[kCounters];
+  AOT_TRY(hipMemcpyAsync(hc, counters, sizeof(hc), hipMemcpyDeviceToHost, s));
+  AOT_TRY(hipStreamSynchronize(s));
+  const int bits = ceil_log2((int64_t)hc[kCMaxDeg] + 1);
+  int32_t *sk, *sv;
+  AOT_TRY(radix_sort_pairs(key_a, val_a, key_b, val_b, n, bits, radix_tmp, s, &sk, &sv));
+  k_perm_rank<<<grid_for(n, kBlock), kBlock, 0, s>>>(n, sv, perm, rank);
+  AOT_TRY(hipGetLastError());
+
+  // rank ranges with the same row-group width (rows are in degree order)
+  const int32_t c0 = hc[kCDeg0], c4 = hc[kCDeg4], c16 = hc[kCDeg16], c64 = hc[kCDeg64];
+  AOT_TRY(fill_i32(dplus, c0, 0, s));
+  AOT_TRY(fill_i32(dminus, c0, 0, s));
+#define ROWS(G, a, b, KERNEL, ...)                                                      \
+  AOT_TRY(launch_rows<G>(a, b, s, [&](unsigned grid, hipStream_t st) {                  \
+    KERNEL<G><<<grid, kBlock, 0, st>>>(a, b, __VA_ARGS__);                              \
+  }))
+  ROWS(4, c0, c4, k_orient_count, rowptr, col, perm, rank, dplus, dminus);
+  ROWS(16, c4, c16, k_orient_count, rowptr, col, perm, rank, dplus, dminus);
+  ROWS(64, c16, c64, k_orient_count, rowptr, col, perm, rank, dplus, dminus);
+  ROWS(256, c64, n, k_orient_count, rowptr, col, perm, rank, dplus, dminus);
+  AOT_TRY(exclusive_scan(dplus, orow, n, scan_tmp, s));
+  AOT_TRY(exclusive_scan(dminus, irow, n, scan_tmp, s));
+  ROWS(4, c0, c4, k_orient_write, rowptr, col, perm, rank, orow, irow, unsorted, otail, icol);
+  ROWS(16, c4, c16, k_orient_write, rowptr, col, perm, rank, orow, irow, unsorted, otail, icol);
+  ROWS(64, c16, c64, k_orient_write, rowptr, col, perm, rank, orow, irow, unsorted, otail, icol);
+  ROWS(256, c64, n, k_orient_write, rowptr, col, perm, rank, orow, irow, unsorted, otail, icol);
+
+  // sort each out-list into ocol
+  k_count_sort_classes<<<grid_for(n, kBlock), kBlock, 0, s>>>(n, dplus, counters);
+  AOT_TRY(hipGetLastError());
+  k_scatter_sort_classes<<<grid_for(n, kBlock), kBlock, 0, s>>>(n, dplus, counters, rows);
+  AOT_TRY(hipGetLastError());
+  const unsigned g_small = (unsigned)std::min<int64_t>(kGrid, cdiv(n, kBlock / 16) + 1);
+  k_sort_lanes<16><<<g_small, kBlock, 0, s>>>(0, counters, rows, orow, unsorted, ocol);
+  AOT_TRY(hipGetLastError());
+  k_sort_lanes<64><<<g_small, kBlock, 0, s>>>(1, counters, rows, orow, unsorted, ocol);
+  AOT_TRY(hipGetLastError());
+  k_sort_block<<<kGrid, kBlock, 0, s>>>(2, counters, rows, orow, unsorted, ocol);
+  AOT_TRY(hipGetLastError());
+  k_sort_bitmap<<<512, kBlock, 0, s>>>(3, counters, rows, orow, unsorted, ocol);
+  AOT_TRY(hipGetLastError());
+
+  ROWS(4, c0, c4, k_in_eid, orow, ocol, irow, icol, ieid);
+  ROWS(16, c4, c16, k_in_eid, orow, ocol, irow, icol, ieid);
+  ROWS(64, c16, c64, k_in_eid, orow, ocol, irow, icol, ieid);
+  ROWS(256, c64, n, k_in_eid, orow, ocol, irow, icol, ieid);
+#undef ROWS
+  (void)m;
+  return 0;
+}
+
+}  // namespace aot

@@ -1,0 +1,230 @@
+"""GPU parity: every array the library returns equals the CPU oracle's,
+element by element, on the same seeded inputs -- for the plain rule and for
+dispatch tables that force every probe arm and tile."""
+
+import itertools
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2006_11494_amd import aot, inputs
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+def need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def table(light_tile=None, heavy_arm=0):
+    t = [0] * aot.AOT_NUM_BUCKETS
+    tiles = light_tile or [4, 4, 4, 8, 16, 32, 64, 64]
+    for k in range(8):
+        t[k] = tiles[k] << 8
+    for h in range(16):
+        t[16 + h] = heavy_arm
+    return t
+
+
+DISPATCHES = {
+    "plain": None,
+    "all_heavy_bitmap": aot.Dispatch(aot.AOT_DISPATCH_TABLE, 1, table(heavy_arm=0)),
+    "all_heavy_hash": aot.Dispatch(aot.AOT_DISPATCH_TABLE, 1, table(heavy_arm=1)),
+    "all_heavy_global": aot.Dispatch(aot.AOT_DISPATCH_TABLE, 1, table(heavy_arm=2)),
+    "all_heavy_sorted": aot.Dispatch(aot.AOT_DISPATCH_TABLE, 1, table(heavy_arm=3)),
+    "all_light_tile4": aot.Dispatch(aot.AOT_DISPATCH_TABLE, 2**30, table([4] * 8)),
+    "all_light_tile64": aot.Dispatch(aot.AOT_DISPATCH_TABLE, 2**30, table([64] * 8)),
+    "mixed": aot.Dispatch(aot.AOT_DISPATCH_TABLE, 8, table([8, 16, 32, 4, 64, 8, 16, 32], 1)),
+}
+
+
+def reference(csr):
+    rp, col = csr.numpy()
+    o = oracle.orient(rp, col)
+    irow, icol, ieid = oracle.in_lists(rp, col, o)
+    return o, irow, icol, ieid
+
+
+def check_orientation(o_gpu, ref):
+    o, irow, icol, ieid = ref
+    h = lambda t: t.cpu().numpy()
+    assert np.array_equal(h(o_gpu.perm), o.perm)
+    assert np.array_equal(h(o_gpu.rank), o.rank)
+    assert np.array_equal(h(o_gpu.rowptr), o.orow)
+    assert np.array_equal(h(o_gpu.col), o.ocol)
+    assert np.array_equal(h(o_gpu.tail), o.tail())
+    assert np.array_equal(h(o_gpu.in_rowptr), irow)
+    assert np.array_equal(h(o_gpu.in_col), icol)
+    assert np.array_equal(h(o_gpu.in_eid), ieid)
+
+
+def check_all(csr, name, dispatches=DISPATCHES, windows=True):
+    need_gpu()
+    ref = reference(csr)
+    o_ref = ref[0]
+    cnt_ref = oracle.edge_counts(o_ref)
+    T = int(cnt_ref.sum())
+    probes = oracle.sum_min(o_ref)
+    tri_ref = oracle.list_triangles(o_ref)
+    g = csr.to(DEV)
+    say(f"[gpu] orient {name} n={csr.n} m={csr.m}")
+    o = aot.orient(g.rowptr, g.col, validate=True)
+    torch.cuda.synchronize()
+    check_orientation(o, ref)
+    for dname, d in dispatches.items():
+        say(f"[gpu] count+list {name} dispatch={dname}")
+        c = aot.count(o, d)
+        assert (c.T, c.probes) == (T, probes), dname
+        assert np.array_equal(np.diff(c.tri_off.cpu().numpy()), cnt_ref), dname
+        tri = aot.list_triangles(o, c, dispatch=d).cpu().numpy()
+        assert np.array_equal(tri, tri_ref), dname
+    if windows and T > 0:
+        say(f"[gpu] windows {name}")
+        c = aot.count(o)
+        # whole list in a few chunks
+        for chunk in sorted({max(1, T // 3), max(1, T // 7 + 1), T}):
+            parts = [aot.list_triangles(o, c, first=f, count=chunk).cpu().numpy()
+                     for f in range(0, T, chunk)]
+            assert np.array_equal(np.concatenate(parts), tri_ref), chunk
+        # short windows anywhere, including ones that run past the end
+        rng = np.random.default_rng(T)
+        for first in sorted({0, T - 1, *rng.integers(0, T, 6).tolist()}):
+            for count in (1, 7):
+                got = aot.list_triangles(o, c, first=int(first), count=count).cpu().numpy()
+                assert np.array_equal(got, tri_ref[first:first + count]), (first, count)
+        assert aot.list_triangles(o, c, first=T, count=5).shape == (0, 3)
+    return o
+
+
+def graph(n, edges):
+    return inputs.csr_from_edges_np(n, edges)
+
+
+def random_graph(n, p, seed):
+    rng = np.random.default_rng(seed)
+    iu, ju = np.nonzero(np.triu(rng.random((n, n)) < p, 1))
+    return graph(n, zip(iu.tolist(), ju.tolist()))
+
+
+def wheel(n):
+    return graph(n, [(0, i) for i in range(1, n)] + [(i, i % (n - 1) + 1) for i in range(1, n)])
+
+
+SMALL = {
+    "empty": graph(0, []),
+    "single": graph(1, []),
+    "isolated": graph(10, []),
+    "one_edge": graph(2, [(0, 1)]),
+    "triangle": graph(3, [(0, 1), (1, 2), (0, 2)]),
+    "k5": graph(5, itertools.combinations(range(5), 2)),
+    "k40": graph(40, itertools.combinations(range(40), 2)),
+    "tiebreak": graph(5, [(0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 4)]),
+    "wheel50": wheel(50),
+    "star300": graph(301, [(0, i) for i in range(1, 301)]),
+    "k_100_200": graph(300, [(i, 100 + j) for i in range(100) for j in range(200)]),
+    "rand_a": random_graph(60, 0.3, 1),
+    "rand_b": random_graph(200, 0.08, 2),
+    "rand_c": random_graph(700, 0.03, 3),
+    "dense_c": random_graph(300, 0.6, 4),
+}
+
+
+@pytest.mark.parametrize("name", list(SMALL))
+def test_small_graphs(name):
+    check_all(SMALL[name], name)
+
+
+def test_example1():
+    import os
+    edges = []
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "example1.txt")
+    for line in open(path):
+        p = line.split()
+        if p and p[0] == "edge":
+            edges.append((int(p[1]) - 1, int(p[2]) - 1))
+    need_gpu()
+    g = graph(14, edges)
+    o = check_all(g, "example1")
+    c = aot.count(o)
+    assert (c.T, c.probes) == (6, 12)      # probes: Example 1's sum of minima
+
+
+def test_er2000():
+    check_all(inputs.workload("er2000"), "er2000")
+
+
+def test_rmat14():
+    check_all(inputs.rmat(14, 16, 21), "rmat14")
+
+
+def test_chung_lu_small():
+    check_all(inputs.chung_lu(60000, 20.0, 2.1, 3000.0, 22), "chunglu60k")
+
+
+def test_rgg():
+    check_all(inputs.random_geometric(20000, 20.0, 23), "rgg20k")
+
+
+def test_long_out_lists():
+    """K_{4100,4200}: every vertex of the smaller-degree side has 4100 out-
+    neighbours, which takes the bitmap sort of long lists; no triangles."""
+    a, b = 4100, 4200
+    u = torch.arange(a, dtype=torch.int64).repeat_interleave(b)
+    v = a + torch.arange(b, dtype=torch.int64).repeat(a)
+    check_all(inputs.csr_from_pairs(a + b, u, v), "k_4100_4200",
+              dispatches={"plain": None}, windows=False)
+
+
+def test_determinism_and_streams():
+    need_gpu()
+    g = inputs.rmat(13, 16, 31).to(DEV)
+    o1 = aot.orient(g.rowptr, g.col)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        o2 = aot.orient(g.rowptr, g.col, stream=s)
+        c2 = aot.count(o2, stream=s)
+        t2 = aot.list_triangles(o2, c2, stream=s)
+    s.synchronize()
+    c1 = aot.count(o1)
+    t1 = aot.list_triangles(o1, c1)
+    torch.cuda.synchronize()
+    for f in ("rowptr", "col", "tail", "perm", "rank", "in_rowptr", "in_col", "in_eid"):
+        assert torch.equal(getattr(o1, f), getattr(o2, f)), f
+    assert torch.equal(c1.tri_off, c2.tri_off) and torch.equal(t1, t2)
+
+
+def test_generator_is_device_independent():
+    need_gpu()
+    a = inputs.rmat(12, 8, 5)
+    b = inputs.rmat(12, 8, 5, device=DEV)
+    assert torch.equal(a.rowptr, b.rowptr.cpu()) and torch.equal(a.col, b.col.cpu())
+
+
+def test_validation_rejects_malformed_graphs():
+    need_gpu()
+    def csr(rp, col):
+        return (torch.tensor(rp, dtype=torch.int64, device=DEV),
+                torch.tensor(col, dtype=torch.int32, device=DEV))
+    cases = {
+        "asymmetric": csr([0, 1, 2, 2], [1, 2]),
+        "self_loop": csr([0, 2, 3], [0, 1, 0]),
+        "unsorted": csr([0, 2, 3, 4], [2, 1, 0, 0]),
+        "duplicate": csr([0, 2, 4], [1, 1, 0, 0]),
+        "out_of_range": csr([0, 1, 2], [5, 0]),
+        "bad_rowptr": csr([0, 3, 2], [1, 0]),
+    }
+    for name, (rp, col) in cases.items():
+        say(f"[gpu] validate {name}")
+        with pytest.raises(aot.AotError) as e:
+            aot.orient(rp, col, validate=True)
+        assert e.value.status == -2, name

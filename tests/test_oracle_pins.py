@@ -329,3 +329,20 @@ def test_parallel_ranges_give_the_same_list():
     a = oracle.list_triangles(o)
     b = oracle.list_triangles_parallel(o, threads=5)
     assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("n,p,seed", SMALL + [(300, 0.05, 41)])
+def test_in_lists_transpose_the_out_lists(n, p, seed):
+    g = random_graph(n, p, seed)
+    rp, col = g.numpy()
+    o = oracle.orient(rp, col)
+    irow, icol, ieid = oracle.in_lists(rp, col, o)
+    tail = o.tail()
+    assert irow[-1] == o.m
+    for r in range(n):
+        ins = icol[irow[r]:irow[r + 1]]
+        assert sorted(ins.tolist()) == sorted(tail[o.ocol == r].tolist())
+        # input-row order = ascending original id
+        assert np.all(np.diff(o.perm[ins]) > 0)
+        for x, e in zip(ins.tolist(), ieid[irow[r]:irow[r + 1]].tolist()):
+            assert tail[e] == x and o.ocol[e] == r
