@@ -1,0 +1,217 @@
+"""Benchmark of the AOT hot path on one MI355X.
+
+One step = the whole path on one synthetic graph already resident in HBM:
+aot_orient (degree-order ranking, orientation, out-list sort, in-lists),
+aot_count (binning, probe count pass, scan) and aot_list (write pass of every
+triangle into device memory).
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload rmat20]
+
+Prints one JSON line: value = triangles/s of the whole step, plus per-pass
+times, probes/s, the dominant kernel's roofline (algorithmic bytes per launch
+over its live HIP-event launch time) and the CPU oracle baseline.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=5)
+    p.add_argument("--warmup", type=int, default=2)
+    p.add_argument("--workload", default="rmat20")
+    p.add_argument("--seed", type=int, default=None)
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--cpu-sample", type=float, default=0.5,
+                   help="fraction of the oriented edges the CPU oracle lists")
+    return p.parse_args()
+
+
+# Algorithmic bytes of one bucket launch (what the method must move):
+#  count pass: 4 B per probe (the probed out-list id), 4 B per staged owner
+#    list entry, 8 B per edge (its id and its count);
+#  write pass: the same plus 8 B per edge (its two triangle offsets) and
+#    12 B per triangle written.
+def launch_bytes(r) -> int:
+    b = 4 * r["probes"] + 4 * r["staged"] + 8 * r["edges"]
+    if r["pass"] == 1:
+        b += 8 * r["edges"] + 12 * r["triangles"]
+    return b
+
+
+def kernel_of(r) -> str:
+    path = "k_heavy" if r["bucket"] >= 16 else f"k_light<{r['tile']}>"
+    return f"{path}<{'write' if r['pass'] == 1 else 'count'}>"
+
+
+def roofline(recs):
+    """HBM roofline of the kernel with the most recorded time."""
+    per = {}
+    for r in recs:
+        k = kernel_of(r)
+        d = per.setdefault(k, {"ms": 0.0, "bytes": 0, "launches": 0})
+        d["ms"] += r["ms"]
+        d["bytes"] += launch_bytes(r)
+        d["launches"] += 1
+    kern, d = max(per.items(), key=lambda kv: kv[1]["ms"])
+    achieved = d["bytes"] / (d["ms"] / 1000.0) / 1e9
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": kern,
+            "launches": d["launches"], "avg_launch_ms": d["ms"] / d["launches"],
+            "bytes_per_launch": d["bytes"] / d["launches"],
+            "per_unit": "4 B/probe + 4 B/staged owner-list entry + 8 B/edge"
+                        " (+ 8 B/edge + 12 B/triangle in the write pass)"}
+
+
+def cpu_baseline(csr, frac: float):
+    """The CPU oracle (plain C, one thread) on a bounded sample of the same
+    graph: orientation of the whole graph, then the oracle's CF listing over
+    64 source-rank ranges spread across the edge list that together hold
+    about `frac` of the oriented edges; triangles/s extrapolated to the
+    whole graph as (T_sample / f) / (t_orient + t_list / f)."""
+    import numpy as np
+
+    import oracle
+
+    rp, col = csr.numpy()
+    t0 = time.perf_counter()
+    o = oracle.orient(rp, col)
+    t_orient = time.perf_counter() - t0
+    m = o.m
+    k = 64
+    per = max(1, int(frac * m / k))
+    ranges = []
+    for st in np.linspace(0, m, k, endpoint=False).astype(np.int64):
+        r_lo = int(np.searchsorted(o.orow, st, side="right") - 1)
+        r_hi = int(np.searchsorted(o.orow, min(m, st + per), side="left"))
+        r_hi = max(r_hi, r_lo + 1)
+        if not ranges or r_lo >= ranges[-1][1]:
+            ranges.append((r_lo, min(r_hi, o.n)))
+    edges = sum(int(o.orow[b] - o.orow[a]) for a, b in ranges)
+    f = edges / max(m, 1)
+    t0 = time.perf_counter()
+    tri = sum(len(oracle.list_triangles(o, a, b)) for a, b in ranges)
+    t_list = time.perf_counter() - t0
+    value = (tri / f) / (t_orient + t_list / f)
+    log(f"[bench] cpu oracle: orient {t_orient:.2f}s, list {t_list:.2f}s over {f * 100:.1f}% "
+        f"of the edges ({tri} triangles)")
+    return {"value": value, "unit": "triangles/s", "cores": 1, "kind": "oracle",
+            "sample": f"orientation of the whole graph ({t_orient:.2f} s) + CF listing of "
+                      f"{len(ranges)} source-rank ranges holding {f * 100:.1f}% of the oriented "
+                      f"edges ({t_list:.2f} s, {tri} triangles), extrapolated to all edges; "
+                      f"host: {os.cpu_count()} cores visible, oracle single-threaded"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+
+    from paper_2006_11494_amd import aot, inputs
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    t0 = time.time()
+    csr = inputs.workload(args.workload, args.seed, device=dev)
+    torch.cuda.synchronize()
+    log(f"[bench] generated {csr.name}: n={csr.n} m={csr.m} in {time.time() - t0:.1f}s")
+
+    o = aot.alloc_oriented(csr.n, csr.m, dev)
+    ows = torch.empty(aot.orient_workspace(csr.n, csr.nnz), dtype=torch.uint8, device=dev)
+    cws = torch.empty(aot.count_workspace(csr.n, csr.m), dtype=torch.uint8, device=dev)
+    tri_off = torch.empty(csr.m + 1, dtype=torch.int64, device=dev)
+    aot.orient(csr.rowptr, csr.col, out=o, ws=ows)
+    c = aot.count(o, ws=cws, tri_off=tri_off)
+    T, probes = c.T, c.probes
+    out = torch.empty((max(T, 1), 3), dtype=torch.int32, device=dev)
+    log(f"[bench] T={T} probes={probes}; output {T * 12 / 1e9:.2f} GB")
+
+    def step(ev=None):
+        if ev:
+            ev[0].record()
+        aot.orient(csr.rowptr, csr.col, out=o, ws=ows)
+        if ev:
+            ev[1].record()
+        cc = aot.count(o, ws=cws, tri_off=tri_off)
+        if ev:
+            ev[2].record()
+        aot.list_triangles(o, cc, out=out)
+        if ev:
+            ev[3].record()
+        return cc
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    aot.timing_start()          # per-launch HIP events on the launch stream
+    t_start = time.perf_counter()
+    for k in range(args.steps):
+        cc = step(evs[k])
+        assert (cc.T, cc.probes) == (T, probes)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    recs = aot.timing_stop(cap=1 << 16)
+    ms_orient = sum(e[0].elapsed_time(e[1]) for e in evs) / args.steps
+    ms_count = sum(e[1].elapsed_time(e[2]) for e in evs) / args.steps
+    ms_list = sum(e[2].elapsed_time(e[3]) for e in evs) / args.steps
+    ms_step = wall * 1000.0 / args.steps
+    log(f"[bench] step {ms_step:.3f} ms: orient {ms_orient:.3f} count {ms_count:.3f} "
+        f"list {ms_list:.3f}")
+
+    roof = roofline(recs)
+    log(f"[bench] dominant kernel {roof['kernel']}: {roof['achieved']:.1f} GB/s "
+        f"({roof['frac'] * 100:.1f}% of peak) over {roof['launches']} launches")
+    base = None if args.no_cpu_baseline else cpu_baseline(csr, args.cpu_sample)
+
+    result = {
+        "metric": "triangles/s (whole orient+count+list step); probes/s = sum of min(deg+) "
+                  "per second of the count pass",
+        "value": T / (ms_step / 1000.0),
+        "unit": "triangles/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "graph": csr.name, "n": csr.n, "m": csr.m,
+                   "triangles": T, "probes": probes, "dispatch": "plain"},
+        "probes_per_s": probes / (ms_count / 1000.0),
+        "ms_orient": ms_orient,
+        "ms_count": ms_count,
+        "ms_list": ms_list,
+        "roofline": {k: roof[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic")},
+        "roofline_kernel": {k: roof[k] for k in ("kernel", "launches", "avg_launch_ms",
+                                                 "bytes_per_launch", "per_unit")},
+        "cpu_baseline": base,
+    }
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -24,8 +24,8 @@
  * Conventions shared by every call
  *   - Pointers marked "device" are HIP device (or managed) memory on the
  *     current device; "host" pointers are ordinary host memory.
- *   - The caller owns every buffer.  The library allocates no device memory
- *     except in aot_count_batch (see there); sizes come from *_workspace().
+ *   - The caller owns every buffer; the library allocates no device memory.
+ *     Workspace sizes come from the *_workspace() queries.
  *   - `stream` is a hipStream_t (NULL = the legacy default stream).  Calls
  *     enqueue work on it; calls that return host values synchronise it.
  *   - Vertex ids are int32 in [0, n).  The input graph is a symmetric CSR:
@@ -115,8 +115,14 @@ int aot_orient(const aot_graph* g, uint32_t flags, aot_oriented* out,
  * AOT_DISPATCH_TABLE) gives one code per bucket, e.g. chosen by the cost
  * model.  Every choice gives identical results.
  *   heavy_min   owners with deg+ >= heavy_min are processed owner-grouped with
- *               an LDS index (0 = library default).
- *   table       host array of AOT_NUM_BUCKETS codes (arm | tile << 8), or NULL.
+ *               an LDS index (0 = library default, 32).
+ *   table       host array of AOT_NUM_BUCKETS codes, or NULL: entry k in 0..7
+ *               (light bin k, see the timing recorder) = tile << 8 with tile in
+ *               {4, 8, 16, 32, 64} lanes per edge; entry 16 + h (heavy class h)
+ *               = index arm 0 bitmap, 1 hash, 2 global binary search, 3 LDS
+ *               sorted copy (an owner whose list does not fit the arm's LDS
+ *               budget uses the next of bitmap, hash, sorted, global that
+ *               does).  Other entries are ignored.  AOT_E_MODEL on a bad code.
  */
 #define AOT_DISPATCH_PLAIN 0
 #define AOT_DISPATCH_TABLE 1
@@ -156,6 +162,33 @@ int aot_count(const aot_oriented* g, const aot_dispatch* d, int64_t* tri_off,
 int aot_list(const aot_oriented* g, const aot_dispatch* d, const int64_t* tri_off,
              void* ws, size_t ws_bytes, int64_t first, int64_t count,
              int32_t* out, int64_t* written, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Timing recorder.  While on, every bucket launch of aot_count / aot_list on
+ * the calling thread is bracketed by HIP events on its stream, and a record
+ * keeps what the launch did -- the per-bucket timings the cost model of the
+ * dispatch learns from.  Buckets: 0..7 = light bins of c = min(deg+)
+ * ({1}, {2}, (2,4], ..., (64, inf)); 16 + h = heavy owners with
+ * ceil(log2 deg+(b)) = h.  Recording adds event overhead; results are the
+ * same bytes either way.
+ *   aot_timing_start  clears earlier records and starts recording.
+ *   aot_timing_stop   stops, waits for the recorded launches, copies up to
+ *                     cap records to out (host) and the total to *count;
+ *                     AOT_E_CAPACITY if records were dropped. */
+typedef struct aot_timing {
+  int32_t pass;       /* 0 = count pass, 1 = write pass                       */
+  int32_t bucket;     /* see above                                            */
+  int32_t arm;        /* heavy: requested index arm (0 bitmap, 1 hash,
+                         2 global binary search, 3 LDS sorted copy); light: 0 */
+  int32_t tile;       /* lanes per edge (light) or workgroup size (heavy)    */
+  int64_t edges;      /* directed edges in the bucket                        */
+  int64_t probes;     /* their sum of min(deg+): look-ups made               */
+  int64_t staged;     /* owner out-list entries staged into LDS (heavy)      */
+  int64_t triangles;  /* triangles the bucket's edges hold                   */
+  double ms;          /* launch time from HIP events on the launch stream    */
+} aot_timing;
+int aot_timing_start(void);
+int aot_timing_stop(aot_timing* out, int32_t cap, int32_t* count);
 
 #ifdef __cplusplus
 }

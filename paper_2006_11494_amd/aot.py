@@ -28,6 +28,7 @@ EXPORTS = (
     "aot_orient_workspace", "aot_orient",
     "aot_count_workspace", "aot_count",
     "aot_list",
+    "aot_timing_start", "aot_timing_stop",
 )
 
 
@@ -48,6 +49,13 @@ class OrientedC(ctypes.Structure):
                 ("tail", ctypes.c_void_p), ("perm", ctypes.c_void_p),
                 ("rank", ctypes.c_void_p), ("in_rowptr", ctypes.c_void_p),
                 ("in_col", ctypes.c_void_p), ("in_eid", ctypes.c_void_p)]
+
+
+class TimingC(ctypes.Structure):
+    _fields_ = [("pass_", ctypes.c_int32), ("bucket", ctypes.c_int32), ("arm", ctypes.c_int32),
+                ("tile", ctypes.c_int32), ("edges", ctypes.c_int64), ("probes", ctypes.c_int64),
+                ("staged", ctypes.c_int64), ("triangles", ctypes.c_int64),
+                ("ms", ctypes.c_double)]
 
 
 class DispatchC(ctypes.Structure):
@@ -82,7 +90,10 @@ def load(path: str = LIB_PATH):
                               ctypes.c_size_t, ctypes.POINTER(ctypes.c_uint64), vp]
     lib.aot_list.argtypes = [ctypes.POINTER(OrientedC), ctypes.POINTER(DispatchC), vp, vp,
                              ctypes.c_size_t, i64, i64, vp, ctypes.POINTER(ctypes.c_int64), vp]
-    for f in ("aot_orient_workspace", "aot_orient", "aot_count_workspace", "aot_count", "aot_list"):
+    lib.aot_timing_start.argtypes = []
+    lib.aot_timing_stop.argtypes = [ctypes.POINTER(TimingC), i32, ctypes.POINTER(i32)]
+    for f in ("aot_orient_workspace", "aot_orient", "aot_count_workspace", "aot_count", "aot_list",
+              "aot_timing_start", "aot_timing_stop"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -166,8 +177,17 @@ def count_workspace(n: int, m: int) -> int:
     return b.value
 
 
+def alloc_oriented(n: int, m: int, device) -> Oriented:
+    """Output buffers of aot_orient for a graph with n vertices and m edges."""
+    i32 = dict(dtype=torch.int32, device=device)
+    i64 = dict(dtype=torch.int64, device=device)
+    return Oriented(n, m, torch.empty(n + 1, **i64), torch.empty(m, **i32),
+                    torch.empty(m, **i32), torch.empty(n, **i32), torch.empty(n, **i32),
+                    torch.empty(n + 1, **i64), torch.empty(m, **i32), torch.empty(m, **i32))
+
+
 def orient(rowptr: torch.Tensor, col: torch.Tensor, validate: bool = False, stream=None,
-           ws: torch.Tensor | None = None) -> Oriented:
+           ws: torch.Tensor | None = None, out: Oriented | None = None) -> Oriented:
     """aot_orient on a symmetric device CSR (rowptr int64[n+1], col int32[nnz])."""
     assert rowptr.dtype == torch.int64 and col.dtype == torch.int32
     assert rowptr.is_contiguous() and col.is_contiguous()
@@ -175,11 +195,8 @@ def orient(rowptr: torch.Tensor, col: torch.Tensor, validate: bool = False, stre
     n = rowptr.numel() - 1
     nnz = col.numel()
     m = nnz // 2
-    i32 = dict(dtype=torch.int32, device=dev)
-    i64 = dict(dtype=torch.int64, device=dev)
-    o = Oriented(n, m, torch.empty(n + 1, **i64), torch.empty(m, **i32), torch.empty(m, **i32),
-                 torch.empty(n, **i32), torch.empty(n, **i32), torch.empty(n + 1, **i64),
-                 torch.empty(m, **i32), torch.empty(m, **i32))
+    o = out if out is not None else alloc_oriented(n, m, dev)
+    assert (o.n, o.m) == (n, m)
     need = orient_workspace(n, nnz)
     if ws is None or ws.numel() < need:
         ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
@@ -191,13 +208,14 @@ def orient(rowptr: torch.Tensor, col: torch.Tensor, validate: bool = False, stre
 
 
 def count(o: Oriented, dispatch: Dispatch | None = None, stream=None,
-          ws: torch.Tensor | None = None) -> Counted:
+          ws: torch.Tensor | None = None, tri_off: torch.Tensor | None = None) -> Counted:
     """aot_count: per-edge triangle offsets, T and the probe count."""
     dev = o.rowptr.device
     need = count_workspace(o.n, o.m)
     if ws is None or ws.numel() < need:
         ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
-    tri_off = torch.empty(o.m + 1, dtype=torch.int64, device=dev)
+    if tri_off is None:
+        tri_off = torch.empty(o.m + 1, dtype=torch.int64, device=dev)
     res = (ctypes.c_uint64 * 2)()
     oc = o.cstruct()
     dc = (dispatch or Dispatch()).cstruct()
@@ -220,3 +238,18 @@ def list_triangles(o: Oriented, c: Counted, first: int = 0, count: int | None = 
     _check(load().aot_list(ctypes.byref(oc), ctypes.byref(dc), _ptr(c.tri_off), _ptr(c.ws),
                            c.ws.numel(), first, k, _ptr(out), None, _stream(stream)), "aot_list")
     return out[:k]
+
+
+def timing_start():
+    """Starts the per-launch recorder of this thread."""
+    _check(load().aot_timing_start(), "aot_timing_start")
+
+
+def timing_stop(cap: int = 4096) -> list[dict]:
+    """Stops recording; returns one dict per recorded bucket launch."""
+    buf = (TimingC * cap)()
+    n = ctypes.c_int32(0)
+    _check(load().aot_timing_stop(buf, cap, ctypes.byref(n)), "aot_timing_stop")
+    keys = ("bucket", "arm", "tile", "edges", "probes", "staged", "triangles", "ms")
+    return [dict({"pass": buf[i].pass_}, **{k: getattr(buf[i], k) for k in keys})
+            for i in range(min(n.value, cap))]

@@ -1,26 +1,30 @@
 // Adaptive-orientation probe passes (Algorithm 3's two loops; Section 3.1,
-// "The main idea"; Section 3.2, Correctness, Time Complexity).
+// "The main idea"; Section 3.2, Correctness and Time Complexity).
 //
 // Every directed edge e = <u,v> of the oriented graph is charged to its owner
 // b, the endpoint with the larger (deg+, rank) (ties by id, the footnote of
 // Section 3.2); the other endpoint s is probed: each w in N+(s) is looked up
 // in an index of N+(b), so edge e costs min(deg+(u), deg+(v)) look-ups.
 //
-// Two paths, by the owner's out-degree:
-//  * heavy owners (deg+(b) >= heavy_min): owner-grouped, as in Algorithm 3,
-//    where each pivot builds its index once (Section 3.2, the remark on the
-//    bitmap).  A workgroup takes one work item = an owner and a window of up
-//    to kItemSpan of its neighbours (out-list then in-list), stages N+(b) in
-//    LDS as a bitmap over [min N+(b), max N+(b)] or as an open-addressing
-//    hash, then each wave probes one owned neighbour's out-list at a time.
-//  * light owners: edge-centric.  Edges are binned by c = min(deg+) so that
-//    a bin's edges get G lanes each with G close to c, and every lane
-//    binary-searches its w in the (short, cache-resident) sorted N+(b).
-// The count pass writes cnt[e]; an exclusive scan gives each edge's slot in
+// Edges fall into buckets:
+//  * heavy owner classes (deg+(b) >= heavy_min), one per ceil(log2 deg+(b)):
+//    owner-grouped as in Algorithm 3, where a pivot builds its index once
+//    (Section 3.2, the remark on the bitmap).  A workgroup takes a work item
+//    = an owner and a window of up to kItemSpan of its neighbours (out-list,
+//    then in-list), compacts the neighbours it owns into LDS with a prefix sum
+//    of their out-degrees, stages N+(b) in LDS (bitmap over [min, max] of the
+//    list, open-addressing hash, or a sorted copy), and then spreads the
+//    flattened probes over all its lanes: each lane takes consecutive probes,
+//    so reads of the probed out-lists are coalesced and no lane idles on
+//    short lists.
+//  * light bins by c = min(deg+) (owners below heavy_min): edge-centric, G
+//    lanes per edge, each lane binary-searching the short sorted N+(b).
+// The count pass writes cnt[e]; an exclusive scan gives each edge its slot in
 // the global triangle list; the write pass repeats the probes and stores the
-// hits in ascending w at those slots.
+// hits of an edge in ascending w at those slots.
 #include <algorithm>
 #include <climits>
+#include <vector>
 
 #include "kernels.hpp"
 
@@ -28,34 +32,38 @@ namespace aot {
 
 namespace {
 
-constexpr int kLightBins = 8;       // c in {1}, {2}, (2,4], (4,8], ..., (64,128]
-constexpr int kItemSpan = 1024;     // neighbours of one owner per work item
-constexpr int kIndexWords = 8192;   // LDS index: 32 KiB
+constexpr int kLightBins = 8;       // c in {1}, {2}, (2,4], (4,8], ..., last bin open-ended
+constexpr int kHeavyClasses = 16;   // owner classes by ceil(log2 deg+(b))
+constexpr int kHeavyBase = 16;      // bucket id of heavy class 0
+constexpr int kItemSpan = 512;      // neighbours of one owner per work item
+constexpr int kIndexWords = 5120;   // LDS index: 20 KiB (bitmap window of 163840 ids)
+constexpr int kHashSlots = 4096;    // largest power of two <= kIndexWords
+constexpr int kUnroll = 4;          // probes per lane per round
+constexpr int kRound = kBlock * kUnroll;
+constexpr int kRoundWords = kRound / 32;
 constexpr int kGrid = 4096;
 constexpr int kDefaultHeavyMin = 32;
 
+static_assert(kNumBuckets == kHeavyBase + kHeavyClasses, "bucket layout");
+static_assert(kRoundWords <= kWave, "one wave scans a round's flag words");
+static_assert(kHashSlots <= kIndexWords && (kHashSlots & (kHashSlots - 1)) == 0, "hash table");
+
+// per-bucket statistics (int64, device), bucket = light bin or kHeavyBase + class
 enum : int {
-  kCBinCount = 0,                   // [0..7]
-  kCBinCursor = 8,                  // [8..15]
-  kCItems = 16,
-  kCounters32 = 32,
+  kSEdges = 0, kSProbes, kSTriangles, kSItems, kSStaged, kSCursor, kSItemBase, kStats,
 };
+constexpr int kStatWords = kNumBuckets * kStats;
 
-// Index arms of the heavy (owner-grouped) path; the numbers are the codes
-// of a dispatch table's heavy entries.
 enum Arm : int { kArmBitmap = 0, kArmHash = 1, kArmGlobal = 2, kArmSorted = 3, kNumArms = 4 };
-constexpr int kHeavyClasses = 16;   // owner classes by ceil(log2 deg+(b))
 
-// Per-bucket choices: lanes per edge of each light bin, index arm of each
-// heavy owner class.
-struct Plan {
-  int32_t light_tile[kLightBins];
-  int32_t heavy_arm[kHeavyClasses];
-};
-
-__device__ __forceinline__ int light_bin(int32_t c) {
+__host__ __device__ __forceinline__ int light_bin(int32_t c) {
   const int k = c <= 1 ? 0 : ceil_log2(c);
-  return k < kLightBins ? k : kLightBins - 1;   // last bin takes everything longer
+  return k < kLightBins ? k : kLightBins - 1;
+}
+
+__host__ __device__ __forceinline__ int heavy_class(int32_t db) {
+  const int h = ceil_log2(db);
+  return h < kHeavyClasses ? h : kHeavyClasses - 1;
 }
 
 struct EdgeEnds {
@@ -74,110 +82,163 @@ __device__ __forceinline__ EdgeEnds edge_ends(const int64_t* __restrict__ orow, 
   return r;
 }
 
+__device__ __forceinline__ unsigned long long* u64p(int64_t* p) {
+  return reinterpret_cast<unsigned long long*>(p);
+}
+
 // ---------------------------------------------------------------- binning
 
+// Per-bucket edge and probe counts, and the probe total.
 __global__ __launch_bounds__(kBlock) void k_bin_count(int64_t m, const int64_t* __restrict__ orow,
                                                       const int32_t* __restrict__ ocol,
                                                       const int32_t* __restrict__ otail,
                                                       int32_t heavy_min,
                                                       int32_t* __restrict__ cnt,
-                                                      int32_t* __restrict__ counters,
+                                                      int64_t* __restrict__ stats,
                                                       unsigned long long* __restrict__ probes) {
-  __shared__ int32_t h[kLightBins];
-  __shared__ unsigned long long red[kWavesPerBlock];
-  if (threadIdx.x < kLightBins) h[threadIdx.x] = 0;
+  __shared__ unsigned long long se[kNumBuckets], sp[kNumBuckets];
+  if (threadIdx.x < kNumBuckets) { se[threadIdx.x] = 0; sp[threadIdx.x] = 0; }
   __syncthreads();
-  unsigned long long sum = 0;
   for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < m;
        e += (int64_t)gridDim.x * kBlock) {
     const EdgeEnds x = edge_ends(orow, otail[e], ocol[e]);
-    sum += (unsigned long long)x.c;
-    if (x.db >= heavy_min) continue;             // the owner's work item counts it
-    if (x.c == 0) { cnt[e] = 0; continue; }
-    atomicAdd(&h[light_bin(x.c)], 1);
+    int bucket;
+    if (x.db >= heavy_min) bucket = kHeavyBase + heavy_class(x.db);
+    else if (x.c == 0) { cnt[e] = 0; continue; }
+    else bucket = light_bin(x.c);
+    atomicAdd(&se[bucket], 1ull);
+    atomicAdd(&sp[bucket], (unsigned long long)x.c);
   }
-  sum = wave_sum(sum);
-  if (lane_id() == 0) red[threadIdx.x / kWave] = sum;
   __syncthreads();
-  if (threadIdx.x < kLightBins) atomicAdd(&counters[kCBinCount + threadIdx.x], h[threadIdx.x]);
-  if (threadIdx.x == 0) {
-    unsigned long long t = 0;
-    for (int q = 0; q < kWavesPerBlock; ++q) t += red[q];
-    atomicAdd(probes, t);
+  if (threadIdx.x < kNumBuckets && se[threadIdx.x]) {
+    atomicAdd(u64p(&stats[threadIdx.x * kStats + kSEdges]), se[threadIdx.x]);
+    atomicAdd(u64p(&stats[threadIdx.x * kStats + kSProbes]), sp[threadIdx.x]);
+    atomicAdd(probes, sp[threadIdx.x]);
   }
 }
 
+// Light edges into their bins; one global atomic per wave and bin.
 __global__ __launch_bounds__(kBlock) void k_bin_scatter(int64_t m, const int64_t* __restrict__ orow,
                                                         const int32_t* __restrict__ ocol,
                                                         const int32_t* __restrict__ otail,
                                                         int32_t heavy_min,
-                                                        int32_t* __restrict__ counters,
+                                                        int64_t* __restrict__ stats,
                                                         int32_t* __restrict__ elist) {
-  __shared__ int32_t base[kLightBins];
+  __shared__ int64_t base[kLightBins];
   if (threadIdx.x == 0) {
-    int32_t run = 0;
-    for (int q = 0; q < kLightBins; ++q) { base[q] = run; run += counters[kCBinCount + q]; }
+    int64_t run = 0;
+    for (int q = 0; q < kLightBins; ++q) { base[q] = run; run += stats[q * kStats + kSEdges]; }
   }
   __syncthreads();
-  for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < m;
-       e += (int64_t)gridDim.x * kBlock) {
-    const EdgeEnds x = edge_ends(orow, otail[e], ocol[e]);
-    if (x.db >= heavy_min || x.c == 0) continue;
-    const int k = light_bin(x.c);
-    elist[base[k] + atomicAdd(&counters[kCBinCursor + k], 1)] = (int32_t)e;
+  const int64_t step = (int64_t)gridDim.x * kBlock;
+  for (int64_t e0 = (int64_t)blockIdx.x * kBlock; e0 < m; e0 += step) {
+    const int64_t e = e0 + threadIdx.x;
+    int bin = -1;
+    if (e < m) {
+      const EdgeEnds x = edge_ends(orow, otail[e], ocol[e]);
+      if (x.db < heavy_min && x.c > 0) bin = light_bin(x.c);
+    }
+    for (int k = 0; k < kLightBins; ++k) {
+      const uint64_t mask = ballot(bin == k);
+      if (!mask) continue;
+      const int leader = __ffsll((long long)mask) - 1;
+      long long at = 0;
+      if (lane_id() == leader)
+        at = (long long)atomicAdd(u64p(&stats[k * kStats + kSCursor]),
+                                  (unsigned long long)__popcll(mask));
+      at = __shfl(at, leader, kWave);
+      if (bin == k) elist[base[k] + at + popc_below(mask)] = (int32_t)e;
+    }
   }
 }
 
-// Work items of the heavy owners: (owner, first neighbour index).
-__global__ __launch_bounds__(kBlock) void k_make_items(int32_t n, const int64_t* __restrict__ orow,
+// Work items per heavy class, and the owner-list entries they stage.
+__global__ __launch_bounds__(kBlock) void k_item_count(int32_t n, const int64_t* __restrict__ orow,
                                                        const int64_t* __restrict__ irow,
                                                        int32_t heavy_min,
-                                                       int32_t* __restrict__ counters,
-                                                       int2* __restrict__ items) {
+                                                       int64_t* __restrict__ stats) {
+  __shared__ unsigned long long si[kHeavyClasses], ss[kHeavyClasses];
+  if (threadIdx.x < kHeavyClasses) { si[threadIdx.x] = 0; ss[threadIdx.x] = 0; }
+  __syncthreads();
+  for (int64_t b = (int64_t)blockIdx.x * kBlock + threadIdx.x; b < n;
+       b += (int64_t)gridDim.x * kBlock) {
+    const int64_t db = orow[b + 1] - orow[b];
+    if (db < heavy_min) continue;
+    const int64_t deg = db + irow[b + 1] - irow[b];
+    const int64_t k = (deg + kItemSpan - 1) / kItemSpan;
+    const int h = heavy_class((int32_t)db);
+    atomicAdd(&si[h], (unsigned long long)k);
+    atomicAdd(&ss[h], (unsigned long long)(k * db));
+  }
+  __syncthreads();
+  if (threadIdx.x < kHeavyClasses && si[threadIdx.x]) {
+    int64_t* st = stats + (kHeavyBase + threadIdx.x) * kStats;
+    atomicAdd(u64p(&st[kSItems]), si[threadIdx.x]);
+    atomicAdd(u64p(&st[kSStaged]), ss[threadIdx.x]);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_item_scatter(int32_t n, const int64_t* __restrict__ orow,
+                                                         const int64_t* __restrict__ irow,
+                                                         int32_t heavy_min,
+                                                         int64_t* __restrict__ stats,
+                                                         int2* __restrict__ items) {
+  __shared__ int64_t base[kHeavyClasses];
+  if (threadIdx.x == 0) {
+    int64_t run = 0;
+    for (int q = 0; q < kHeavyClasses; ++q) {
+      base[q] = run;
+      run += stats[(kHeavyBase + q) * kStats + kSItems];
+    }
+  }
+  __syncthreads();
+  if (blockIdx.x == 0 && threadIdx.x < kHeavyClasses)
+    stats[(kHeavyBase + threadIdx.x) * kStats + kSItemBase] = base[threadIdx.x];
   for (int64_t b = (int64_t)blockIdx.x * kBlock + threadIdx.x; b < n;
        b += (int64_t)gridDim.x * kBlock) {
     const int64_t db = orow[b + 1] - orow[b];
     if (db < heavy_min) continue;
     const int64_t deg = db + irow[b + 1] - irow[b];
     const int32_t k = (int32_t)((deg + kItemSpan - 1) / kItemSpan);
-    const int32_t at = atomicAdd(&counters[kCItems], k);
-    for (int32_t q = 0; q < k; ++q) items[at + q] = make_int2((int32_t)b, q * kItemSpan);
+    const int h = heavy_class((int32_t)db);
+    const int64_t at = (int64_t)atomicAdd(u64p(&stats[(kHeavyBase + h) * kStats + kSCursor]),
+                                          (unsigned long long)k);
+    for (int32_t q = 0; q < k; ++q) items[base[h] + at + q] = make_int2((int32_t)b, q * kItemSpan);
   }
 }
 
 // ---------------------------------------------------------------- LDS index
 
+__device__ __forceinline__ uint32_t hash_slot(int32_t w) { return (uint32_t)w * 0x9E3779B1u; }
+
 struct Index {
-  int arm;
   int32_t lo, span;   // bitmap window
-  int32_t mask;       // hash table size - 1
+  uint32_t mask;      // hash table size - 1
   int shift;          // hash: 32 - log2(size)
   const int32_t* list;
   int32_t len;
 };
 
-__device__ __forceinline__ uint32_t hash_slot(int32_t w) {
-  return (uint32_t)w * 0x9E3779B1u;
+// The arm an owner actually uses: the requested one if its list fits that
+// arm's LDS budget, else the next that fits (bitmap -> hash -> sorted -> global).
+__device__ __forceinline__ int resolve_arm(int arm, int32_t db, int64_t span) {
+  if (arm == kArmBitmap && span > (int64_t)kIndexWords * 32) arm = kArmHash;
+  if (arm == kArmHash && 2 * (int64_t)db > kHashSlots) arm = kArmSorted;
+  if (arm == kArmSorted && db > kIndexWords) arm = kArmGlobal;
+  return arm;
 }
 
-// Builds the index of N+(b) (sorted list `a` of length db) in `lds` with the
-// requested arm, falling back (bitmap -> hash -> sorted -> global) when the
-// owner does not fit the arm's LDS budget.
-__device__ Index build_index(const int32_t* __restrict__ a, int32_t db, uint32_t* lds, int arm) {
+template <int ARM>
+__device__ __forceinline__ Index build_index(const int32_t* __restrict__ a, int32_t db,
+                                             uint32_t* lds) {
   Index ix;
   ix.list = a;
   ix.len = db;
   ix.lo = a[0];
-  const int32_t hi = a[db - 1];
-  ix.span = hi - ix.lo + 1;
-  const bool bitmap_fits = (int64_t)ix.span <= (int64_t)kIndexWords * 32;
-  const bool hash_fits = 2 * (int64_t)db <= kIndexWords;
-  const bool sorted_fits = (int64_t)db <= kIndexWords;
-  if (arm == kArmBitmap && !bitmap_fits) arm = kArmHash;
-  if (arm == kArmHash && !hash_fits) arm = kArmSorted;
-  if (arm == kArmSorted && !sorted_fits) arm = kArmGlobal;
-  ix.arm = arm;
-  if (arm == kArmBitmap) {
+  ix.span = a[db - 1] - ix.lo + 1;
+  ix.mask = 0;
+  ix.shift = 0;
+  if constexpr (ARM == kArmBitmap) {
     const int words = (ix.span + 31) >> 5;
     for (int i = threadIdx.x; i < words; i += kBlock) lds[i] = 0u;
     __syncthreads();
@@ -185,41 +246,40 @@ __device__ Index build_index(const int32_t* __restrict__ a, int32_t db, uint32_t
       const int32_t off = a[i] - ix.lo;
       atomicOr(&lds[off >> 5], 1u << (off & 31));
     }
-  } else if (arm == kArmHash) {
-    int size = 1;
+  } else if constexpr (ARM == kArmHash) {
+    int size = 2;
     while (size < 2 * db) size <<= 1;
-    ix.mask = size - 1;
+    ix.mask = (uint32_t)size - 1u;
     ix.shift = 32 - ceil_log2(size);
     for (int i = threadIdx.x; i < size; i += kBlock) lds[i] = 0xFFFFFFFFu;
     __syncthreads();
     for (int i = threadIdx.x; i < db; i += kBlock) {
       const uint32_t w = (uint32_t)a[i];
       uint32_t h = hash_slot((int32_t)w) >> ix.shift;
-      while (atomicCAS(&lds[h], 0xFFFFFFFFu, w) != 0xFFFFFFFFu) h = (h + 1) & (uint32_t)ix.mask;
+      while (atomicCAS(&lds[h], 0xFFFFFFFFu, w) != 0xFFFFFFFFu) h = (h + 1) & ix.mask;
     }
-  } else if (arm == kArmSorted) {
+  } else if constexpr (ARM == kArmSorted) {
     for (int i = threadIdx.x; i < db; i += kBlock) lds[i] = (uint32_t)a[i];
   }
   __syncthreads();
   return ix;
 }
 
+template <int ARM>
 __device__ __forceinline__ bool index_has(const Index& ix, const uint32_t* lds, int32_t w) {
-  if (ix.arm == kArmBitmap) {
+  if constexpr (ARM == kArmBitmap) {
     const uint32_t off = (uint32_t)(w - ix.lo);
     if (off >= (uint32_t)ix.span) return false;
     return (lds[off >> 5] >> (off & 31)) & 1u;
-  }
-  if (ix.arm == kArmHash) {
+  } else if constexpr (ARM == kArmHash) {
     uint32_t h = hash_slot(w) >> ix.shift;
     while (true) {
       const uint32_t k = lds[h];
       if (k == (uint32_t)w) return true;
       if (k == 0xFFFFFFFFu) return false;
-      h = (h + 1) & (uint32_t)ix.mask;
+      h = (h + 1) & ix.mask;
     }
-  }
-  if (ix.arm == kArmSorted) {
+  } else if constexpr (ARM == kArmSorted) {
     const int32_t* l = reinterpret_cast<const int32_t*>(lds);
     int lo = 0, hi = ix.len;
     while (lo < hi) {
@@ -227,97 +287,308 @@ __device__ __forceinline__ bool index_has(const Index& ix, const uint32_t* lds, 
       if (l[mid] < w) lo = mid + 1; else hi = mid;
     }
     return lo < ix.len && l[lo] == w;
+  } else {
+    return contains_sorted(ix.list, ix.len, w);
   }
-  return contains_sorted(ix.list, ix.len, w);
 }
 
 // ---------------------------------------------------------------- heavy path
 
-// kEmit = false: count pass (writes cnt); true: write pass (emits triangles
-// whose global index falls in [first, first + count)).
+// Largest k in [kc, K) with pre[k] <= p, given pre[kc] <= p < pre[K].
+__device__ __forceinline__ int advance(const int32_t* pre, int kc, int K, int32_t p) {
+  if (pre[kc + 1] > p) return kc;
+  int lo = kc + 1, step = 1, hi;
+  while (true) {
+    hi = lo + step;
+    if (hi >= K || pre[hi] > p) break;
+    lo = hi;
+    step <<= 1;
+  }
+  if (hi > K) hi = K;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (pre[mid] <= p) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+struct HeavyArgs {
+  int arm;                      // requested arm of this class
+  const int2* items;
+  int64_t item_base, item_count;
+  const int64_t* orow;
+  const int32_t* ocol;
+  const int64_t* irow;
+  const int32_t* icol;
+  const int32_t* ieid;
+  int32_t* cnt;                 // count pass
+  int64_t* tri_stat;            // count pass: the bucket's triangle total
+  const int64_t* tri_off;       // write pass
+  const int32_t* perm;
+  int64_t first, count;
+  int32_t* out;
+};
+
 template <bool kEmit>
-__global__ __launch_bounds__(kBlock) void k_heavy(Plan plan, const int32_t* __restrict__ counters,
-                                                  const int2* __restrict__ items,
-                                                  const int64_t* __restrict__ orow,
-                                                  const int32_t* __restrict__ ocol,
-                                                  const int64_t* __restrict__ irow,
-                                                  const int32_t* __restrict__ icol,
-                                                  const int32_t* __restrict__ ieid,
-                                                  int32_t* __restrict__ cnt,
-                                                  const int64_t* __restrict__ tri_off,
-                                                  const int32_t* __restrict__ perm,
-                                                  int64_t first, int64_t count,
-                                                  int32_t* __restrict__ out) {
-  __shared__ uint32_t lds[kIndexWords];
-  const int32_t nitems = counters[kCItems];
-  const int w_id = threadIdx.x / kWave;
+struct HeavyShared {
+  uint32_t lds[kIndexWords];
+  int64_t nb_oy[kItemSpan];
+  int64_t nb_base[kEmit ? kItemSpan : 1];
+  int32_t nb_pre[kItemSpan + 1];
+  int32_t nb_e[kItemSpan];
+  int32_t nb_acc[kItemSpan];          // count: hits; write: running carry
+  int32_t nb_py[kEmit ? kItemSpan : 1];
+  uint64_t flags[kEmit ? kRound / 64 : 1];
+  int32_t wpre[kEmit ? kRoundWords + 1 : 1];
+  int64_t scan_tmp[kWavesPerBlock + 1];
+};
+
+// Count pass over one item's compacted neighbours (K of them, P probes):
+// wave-contiguous windows of 64 probes, a per-lane cursor into the
+// neighbours, hits summed per neighbour segment of the window.
+template <int ARM>
+__device__ int64_t probe_count(HeavyShared<false>& sh, const HeavyArgs& a, const Index& ix, int K,
+                               int32_t P) {
+  const int wave = threadIdx.x / kWave;
   const int lane = lane_id();
-  for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
-    const int2 item = items[it];
-    const int32_t b = item.x;
-    const int64_t ob = orow[b];
-    const int32_t db = (int32_t)(orow[b + 1] - ob);
-    const int64_t ib = irow[b];
-    const int32_t deg = db + (int32_t)(irow[b + 1] - ib);
-    const int32_t j1 = min(deg, item.y + kItemSpan);
-    const int cls = min(kHeavyClasses - 1, ceil_log2(db));
-    const Index ix = build_index(ocol + ob, db, lds, plan.heavy_arm[cls]);
-    for (int32_t j = item.y + w_id; j < j1; j += kWavesPerBlock) {
-      int32_t y, e;
-      if (j < db) { y = ocol[ob + j]; e = (int32_t)(ob + j); }
-      else { y = icol[ib + (j - db)]; e = ieid[ib + (j - db)]; }
-      const int64_t oy = orow[y];
-      const int32_t dy = (int32_t)(orow[y + 1] - oy);
-      const bool owned = dy < db || (dy == db && y < b);
-      if (!owned) continue;
-      if constexpr (!kEmit) {
-        int32_t hits = 0;
-        for (int32_t q = lane; q < dy; q += kWave) hits += index_has(ix, lds, ocol[oy + q]);
-        hits = wave_sum(hits);
-        if (lane == 0) cnt[e] = hits;
-      } else {
-        int64_t pos = tri_off[e];
-        const int64_t end = tri_off[e + 1];
-        if (end <= first || pos >= first + count || pos == end) continue;
-        const int32_t pb = perm[b], py = perm[y];
-        for (int32_t q0 = 0; q0 < dy; q0 += kWave) {
-          const int32_t q = q0 + lane;
-          const int32_t w = q < dy ? ocol[oy + q] : 0;
-          const bool hit = q < dy && index_has(ix, lds, w);
-          const uint64_t mask = ballot(hit);
-          const int64_t at = pos + popc_below(mask);
-          if (hit && at >= first && at < first + count) {
-            int32_t t0 = pb, t1 = py, t2 = perm[w];
-            sort3(t0, t1, t2);
-            int32_t* o = out + 3 * (at - first);
-            o[0] = t0; o[1] = t1; o[2] = t2;
-          }
-          pos += __popcll(mask);
-        }
+  int kc = 0;
+  int64_t hits_lane = 0;
+  for (int32_t w0 = wave * kWave * kUnroll; w0 < P; w0 += kBlock * kUnroll) {
+    int32_t wv[kUnroll];
+    int kk[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int32_t p = w0 + u * kWave + lane;
+      kk[u] = -1;
+      wv[u] = 0;
+      if (p < P) {
+        kc = advance(sh.nb_pre, kc, K, p);
+        kk[u] = kc;
+        wv[u] = a.ocol[sh.nb_oy[kc] + (p - sh.nb_pre[kc])];
       }
     }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const bool valid = kk[u] >= 0;
+      const bool hit = valid && index_has<ARM>(ix, sh.lds, wv[u]);
+      hits_lane += hit;
+      const uint64_t hm = ballot(hit);
+      if (!hm) continue;
+      const int kprev = __shfl_up(kk[u], 1, kWave);
+      const bool start = valid && (lane == 0 || kprev != kk[u]);
+      const uint64_t sm = ballot(start);
+      if (start) {
+        const uint64_t above = lane < 63 ? (sm & ~((2ull << lane) - 1ull)) : 0ull;
+        const int end = above ? __ffsll((long long)above) - 1 : 64;
+        const uint64_t seg = (end == 64 ? ~0ull : ((1ull << end) - 1ull)) & ~((1ull << lane) - 1ull);
+        const int c = __popcll(hm & seg);
+        if (c) atomicAdd(&sh.nb_acc[kk[u]], c);
+      }
+    }
+  }
+  return hits_lane;
+}
+
+// Write pass over one item's compacted neighbours: rounds of kRound probes
+// taken by all waves together so that hit ranks follow probe order (hit
+// flags -> prefix popcounts of the flag words -> positions -> carries).
+template <int ARM>
+__device__ void probe_emit(HeavyShared<true>& sh, const HeavyArgs& a, const Index& ix, int K,
+                           int32_t P, int32_t pb) {
+  const int wave = threadIdx.x / kWave;
+  const int lane = lane_id();
+  int kc = 0;
+  for (int32_t r0 = 0; r0 < P; r0 += kRound) {
+    int32_t wv[kUnroll];
+    int kk[kUnroll];
+    bool hit[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int32_t p = r0 + wave * kWave * kUnroll + u * kWave + lane;
+      kk[u] = -1;
+      wv[u] = 0;
+      if (p < P) {
+        kc = advance(sh.nb_pre, kc, K, p);
+        kk[u] = kc;
+        wv[u] = a.ocol[sh.nb_oy[kc] + (p - sh.nb_pre[kc])];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      hit[u] = kk[u] >= 0 && index_has<ARM>(ix, sh.lds, wv[u]);
+      const uint64_t hm = ballot(hit[u]);
+      if (lane == 0) sh.flags[wave * kUnroll + u] = hm;
+    }
     __syncthreads();
+    if (wave == 0) {
+      const int q = lane;
+      int32_t c = 0;
+      if (q < kRoundWords) c = __popc((uint32_t)(sh.flags[q >> 1] >> ((q & 1) * 32)));
+      const int32_t inc = wave_inclusive_scan(c);
+      if (q < kRoundWords) sh.wpre[q] = inc - c;
+      if (q == kRoundWords - 1) sh.wpre[kRoundWords] = inc;
+    }
+    __syncthreads();
+    auto rank = [&](int32_t x) -> int32_t {     // hits among the round's probes [0, x)
+      const int q = x >> 5;
+      if (q >= kRoundWords) return sh.wpre[kRoundWords];
+      const uint32_t wd = (uint32_t)(sh.flags[q >> 1] >> ((q & 1) * 32));
+      return sh.wpre[q] + __popc(wd & ((1u << (x & 31)) - 1u));
+    };
+    int32_t delta[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      delta[u] = 0;
+      if (kk[u] < 0) continue;
+      const int k = kk[u];
+      const int32_t p = r0 + wave * kWave * kUnroll + u * kWave + lane;
+      const int32_t seg_lo = max(sh.nb_pre[k], r0) - r0;
+      if (hit[u]) {
+        const int64_t pos = sh.nb_base[k] + sh.nb_acc[k] + (rank(p - r0) - rank(seg_lo));
+        if (pos >= a.first && pos < a.first + a.count) {
+          int32_t t0 = pb, t1 = sh.nb_py[k], t2 = a.perm[wv[u]];
+          sort3(t0, t1, t2);
+          int32_t* o = a.out + 3 * (pos - a.first);
+          o[0] = t0; o[1] = t1; o[2] = t2;
+        }
+      }
+      const int32_t seg_end = min(sh.nb_pre[k + 1], r0 + kRound);
+      if (p == seg_end - 1) delta[u] = rank(seg_end - r0) - rank(seg_lo);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u)
+      if (delta[u]) sh.nb_acc[kk[u]] += delta[u];
+    __syncthreads();
+  }
+}
+
+template <int ARM, bool kEmit>
+__device__ int64_t run_item(HeavyShared<kEmit>& sh, const HeavyArgs& a, const int32_t* list,
+                            int32_t db, int K, int32_t P, int32_t pb) {
+  const Index ix = build_index<ARM>(list, db, sh.lds);   // ends with a barrier
+  if constexpr (!kEmit) {
+    return probe_count<ARM>(sh, a, ix, K, P);
+  } else {
+    probe_emit<ARM>(sh, a, ix, K, P, pb);
+    return 0;
+  }
+}
+
+// A launch covers the work items of one heavy class.
+template <bool kEmit>
+__global__ __launch_bounds__(kBlock) void k_heavy(HeavyArgs a) {
+  __shared__ HeavyShared<kEmit> sh;
+  const int tid = threadIdx.x;
+  int64_t tri_block = 0;
+  for (int64_t it = blockIdx.x; it < a.item_count; it += gridDim.x) {
+    const int2 item = a.items[a.item_base + it];
+    const int32_t b = item.x;
+    const int64_t ob = a.orow[b];
+    const int32_t db = (int32_t)(a.orow[b + 1] - ob);
+    const int64_t ib = a.irow[b];
+    const int32_t deg = db + (int32_t)(a.irow[b + 1] - ib);
+    const int32_t j0 = item.y;
+    const int32_t j1 = min(deg, j0 + kItemSpan);
+
+    // owned neighbours of this window, compacted with a prefix of their probe counts
+    constexpr int kPer = kItemSpan / kBlock;
+    int32_t ny[kPer], ne[kPer], nd[kPer];
+    int64_t noy[kPer], nbase[kPer];
+    bool keep[kPer];
+    int64_t packed = 0;
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      const int32_t j = j0 + tid + i * kBlock;
+      keep[i] = false;
+      nd[i] = 0;
+      ny[i] = 0; ne[i] = 0; noy[i] = 0; nbase[i] = 0;
+      if (j < j1) {
+        int32_t y, e;
+        if (j < db) { y = a.ocol[ob + j]; e = (int32_t)(ob + j); }
+        else { y = a.icol[ib + (j - db)]; e = a.ieid[ib + (j - db)]; }
+        const int64_t oy = a.orow[y];
+        const int32_t dy = (int32_t)(a.orow[y + 1] - oy);
+        const bool owned = dy < db || (dy == db && y < b);
+        ny[i] = y; ne[i] = e; noy[i] = oy; nd[i] = dy;
+        if constexpr (!kEmit) {
+          if (owned && dy == 0) a.cnt[e] = 0;
+          keep[i] = owned && dy > 0;
+        } else {
+          if (owned) {
+            const int64_t lo = a.tri_off[e], hi = a.tri_off[e + 1];
+            nbase[i] = lo;
+            keep[i] = hi > lo && hi > a.first && lo < a.first + a.count;
+          }
+        }
+      }
+      if (keep[i]) packed += (int64_t(1) << 32) + nd[i];
+    }
+    int64_t total;
+    int64_t at = block_exclusive_scan(packed, sh.scan_tmp, &total);
+    const int K = (int)(total >> 32);
+    const int32_t P = (int32_t)(total & 0xFFFFFFFF);
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      if (keep[i]) {
+        const int slot = (int)(at >> 32);
+        sh.nb_oy[slot] = noy[i];
+        sh.nb_pre[slot] = (int32_t)(at & 0xFFFFFFFF);
+        sh.nb_e[slot] = ne[i];
+        sh.nb_acc[slot] = 0;
+        if constexpr (kEmit) {
+          sh.nb_base[slot] = nbase[i];
+          sh.nb_py[slot] = a.perm[ny[i]];
+        }
+        at += (int64_t(1) << 32) + nd[i];
+      }
+    }
+    if (tid == 0) sh.nb_pre[K] = P;
+    if (K == 0) {                 // nothing owned in this window: no index needed
+      __syncthreads();
+      continue;
+    }
+    const int32_t* list = a.ocol + ob;
+    const int64_t span = (int64_t)list[db - 1] - list[0] + 1;
+    const int arm = resolve_arm(a.arm, db, span);
+    const int32_t pb = kEmit ? a.perm[b] : 0;
+    int64_t t = 0;
+    switch (arm) {
+      case kArmBitmap: t = run_item<kArmBitmap, kEmit>(sh, a, list, db, K, P, pb); break;
+      case kArmHash: t = run_item<kArmHash, kEmit>(sh, a, list, db, K, P, pb); break;
+      case kArmSorted: t = run_item<kArmSorted, kEmit>(sh, a, list, db, K, P, pb); break;
+      default: t = run_item<kArmGlobal, kEmit>(sh, a, list, db, K, P, pb); break;
+    }
+    if constexpr (!kEmit) {
+      tri_block += t;
+      __syncthreads();
+      for (int s = tid; s < K; s += kBlock) a.cnt[sh.nb_e[s]] = sh.nb_acc[s];
+    }
+    __syncthreads();
+  }
+  if constexpr (!kEmit) {
+    const int64_t t = block_sum(tri_block, sh.scan_tmp);
+    if (tid == 0 && t) atomicAdd(u64p(a.tri_stat), (unsigned long long)t);
   }
 }
 
 // ---------------------------------------------------------------- light path
 
 template <int G, bool kEmit>
-__global__ __launch_bounds__(kBlock) void k_light(int bin, const int32_t* __restrict__ counters,
+__global__ __launch_bounds__(kBlock) void k_light(int64_t base, int64_t total,
                                                   const int32_t* __restrict__ elist,
                                                   const int64_t* __restrict__ orow,
                                                   const int32_t* __restrict__ ocol,
                                                   const int32_t* __restrict__ otail,
                                                   int32_t* __restrict__ cnt,
+                                                  int64_t* __restrict__ tri_stat,
                                                   const int64_t* __restrict__ tri_off,
                                                   const int32_t* __restrict__ perm,
                                                   int64_t first, int64_t count,
                                                   int32_t* __restrict__ out) {
   constexpr int kGroups = kBlock / G;
-  int32_t base = 0;
-  for (int q = 0; q < bin; ++q) base += counters[kCBinCount + q];
-  const int32_t total = counters[kCBinCount + bin];
   const int gi = threadIdx.x / G, li = threadIdx.x % G;
+  int64_t tri = 0;
   for (int64_t t = (int64_t)blockIdx.x * kGroups + gi; t < total;
        t += (int64_t)gridDim.x * kGroups) {
     const int32_t e = elist[base + t];
@@ -328,6 +599,7 @@ __global__ __launch_bounds__(kBlock) void k_light(int bin, const int32_t* __rest
     if constexpr (!kEmit) {
       int32_t hits = 0;
       for (int32_t q = li; q < x.c; q += G) hits += contains_sorted(pb, x.db, ps[q]);
+      tri += hits;
       hits = group_sum<G>(hits);
       if (li == 0) cnt[e] = hits;
     } else {
@@ -351,29 +623,24 @@ __global__ __launch_bounds__(kBlock) void k_light(int bin, const int32_t* __rest
       }
     }
   }
-}
-
-template <bool kEmit>
-hipError_t launch_light(int bin, int tile, const int32_t* counters, const int32_t* elist,
-                        const int64_t* orow, const int32_t* ocol, const int32_t* otail,
-                        int32_t* cnt, const int64_t* tri_off, const int32_t* perm,
-                        int64_t first, int64_t count, int32_t* out, int64_t m, hipStream_t s) {
-  const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(kGrid * 4, cdiv(m, kBlock / tile)));
-#define L(G) k_light<G, kEmit><<<grid, kBlock, 0, s>>>(bin, counters, elist, orow, ocol, otail, \
-                                                     cnt, tri_off, perm, first, count, out)
-  switch (tile) {
-    case 4: L(4); break;
-    case 8: L(8); break;
-    case 16: L(16); break;
-    case 32: L(32); break;
-    default: L(64); break;
+  if constexpr (!kEmit) {
+    __shared__ int64_t red[kWavesPerBlock];
+    const int64_t s = block_sum(tri, red);
+    if (threadIdx.x == 0 && s) atomicAdd(u64p(tri_stat), (unsigned long long)s);
   }
-#undef L
-  return hipGetLastError();
 }
 
-// The plain rule: lanes per edge about the bin's c; for heavy owners the
-// bitmap (falling back to hash / sorted / global by size).
+// ---------------------------------------------------------------- host side
+
+// Per-bucket choices: lanes per edge of each light bin, index arm of each
+// heavy owner class.
+struct Plan {
+  int32_t light_tile[kLightBins];
+  int32_t heavy_arm[kHeavyClasses];
+};
+
+// The plain rule: lanes per edge about the bin's c; heavy owners use the
+// bitmap (falling back to hash / sorted / global when it does not fit).
 Plan plain_plan() {
   Plan p;
   for (int k = 0; k < kLightBins; ++k)
@@ -384,9 +651,8 @@ Plan plain_plan() {
 
 bool valid_tile(int t) { return t == 4 || t == 8 || t == 16 || t == 32 || t == 64; }
 
-// Table codes: entry k < kLightBins is the light bin's tile << 8 (arm byte 0,
-// binary search); entry 16 + h is heavy class h's arm.  Returns false on a
-// code outside those sets.
+// Table codes: entry k < kLightBins is tile << 8 (arm byte 0 = binary
+// search); entry kHeavyBase + h is heavy class h's arm.
 bool plan_from(const DispatchView& d, Plan* p) {
   *p = plain_plan();
   if (!d.table) return true;
@@ -397,30 +663,30 @@ bool plan_from(const DispatchView& d, Plan* p) {
     p->light_tile[k] = tile;
   }
   for (int h = 0; h < kHeavyClasses; ++h) {
-    const int arm = d.table[16 + h];
+    const int arm = d.table[kHeavyBase + h];
     if (arm < 0 || arm >= kNumArms) return false;
     p->heavy_arm[h] = arm;
   }
   return true;
 }
 
+int64_t max_items(int32_t n, int64_t m) { return (int64_t)n + cdiv(2 * m, kItemSpan) + 16; }
+
 struct CountWs {
   int32_t* cnt;
   int32_t* elist;
   int2* items;
-  int32_t* counters;
+  int64_t* stats;
   unsigned long long* probes;
   void* scan_tmp;
 };
-
-int64_t max_items(int32_t n, int64_t m) { return (int64_t)n + cdiv(2 * m, kItemSpan) + 16; }
 
 CountWs carve_count(Carve& c, int32_t n, int64_t m) {
   CountWs w;
   w.cnt = c.take<int32_t>(m);
   w.elist = c.take<int32_t>(m);
   w.items = c.take<int2>(max_items(n, m));
-  w.counters = c.take<int32_t>(kCounters32);
+  w.stats = c.take<int64_t>(kStatWords);
   w.probes = c.take<unsigned long long>(4);
   w.scan_tmp = c.take<char>((int64_t)scan_workspace(m));
   return w;
@@ -434,6 +700,85 @@ CountWs carve_count(Carve& c, int32_t n, int64_t m) {
       return -5;                            \
     }                                       \
   } while (0)
+
+template <bool kEmit>
+hipError_t launch_light(int tile, unsigned grid, int64_t base, int64_t total,
+                        const int32_t* elist, const int64_t* orow, const int32_t* ocol,
+                        const int32_t* otail, int32_t* cnt, int64_t* tri_stat,
+                        const int64_t* tri_off, const int32_t* perm, int64_t first,
+                        int64_t count, int32_t* out, hipStream_t s) {
+#define L(G) k_light<G, kEmit><<<grid, kBlock, 0, s>>>(base, total, elist, orow, ocol, otail, \
+                                                     cnt, tri_stat, tri_off, perm, first, count, out)
+  switch (tile) {
+    case 4: L(4); break;
+    case 8: L(8); break;
+    case 16: L(16); break;
+    case 32: L(32); break;
+    default: L(64); break;
+  }
+#undef L
+  return hipGetLastError();
+}
+
+unsigned grid_cap(int64_t work_units) {
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(kGrid * 4, work_units));
+}
+
+// Launches every non-empty bucket of one pass, recording each launch when
+// the timing recorder is on.
+int run_buckets(bool emit, const Plan& plan, const int64_t* hs, const CountWs& w,
+                const int64_t* orow, const int32_t* ocol, const int32_t* otail,
+                const int32_t* perm, const int64_t* irow, const int32_t* icol, const int32_t* ieid,
+                const int64_t* tri_off, int64_t first, int64_t count, int32_t* out, hipStream_t s,
+                const char** err) {
+  int64_t lbase = 0;
+  for (int k = 0; k < kLightBins; ++k) {
+    const int64_t* st = hs + k * kStats;
+    const int64_t edges = st[kSEdges];
+    if (edges > 0) {
+      const int tile = plan.light_tile[k];
+      const unsigned grid = grid_cap(cdiv(edges, kBlock / tile));
+      const int rec = timing_begin(emit ? 1 : 0, k, 0, tile, edges, st[kSProbes], 0,
+                                   st[kSTriangles], s);
+      hipError_t e;
+      if (!emit)
+        e = launch_light<false>(tile, grid, lbase, edges, w.elist, orow, ocol, otail, w.cnt,
+                                w.stats + k * kStats + kSTriangles, nullptr, nullptr, 0, 0,
+                                nullptr, s);
+      else
+        e = launch_light<true>(tile, grid, lbase, edges, w.elist, orow, ocol, otail, nullptr,
+                               nullptr, tri_off, perm, first, count, out, s);
+      AOT_TRY(e);
+      timing_end(rec, s);
+    }
+    lbase += edges;
+  }
+  for (int h = 0; h < kHeavyClasses; ++h) {
+    const int64_t* st = hs + (kHeavyBase + h) * kStats;
+    const int64_t items = st[kSItems];
+    if (items <= 0) continue;
+    HeavyArgs a;
+    a.arm = plan.heavy_arm[h];
+    a.items = w.items;
+    a.item_base = st[kSItemBase];
+    a.item_count = items;
+    a.orow = orow; a.ocol = ocol; a.irow = irow; a.icol = icol; a.ieid = ieid;
+    a.cnt = w.cnt;
+    a.tri_stat = w.stats + (kHeavyBase + h) * kStats + kSTriangles;
+    a.tri_off = tri_off;
+    a.perm = perm;
+    a.first = first;
+    a.count = count;
+    a.out = out;
+    const int rec = timing_begin(emit ? 1 : 0, kHeavyBase + h, a.arm, kBlock, st[kSEdges],
+                                 st[kSProbes], st[kSStaged], st[kSTriangles], s);
+    if (emit) k_heavy<true><<<grid_cap(items), kBlock, 0, s>>>(a);
+    else k_heavy<false><<<grid_cap(items), kBlock, 0, s>>>(a);
+    AOT_TRY(hipGetLastError());
+    timing_end(rec, s);
+  }
+  return 0;
+}
 
 }  // namespace
 
@@ -459,32 +804,39 @@ int count_run(int32_t n, int64_t m, const int64_t* orow, const int32_t* ocol, co
     *err = "dispatch table holds an unknown arm or tile code";
     return -6;
   }
-  AOT_TRY(fill_i32(w.counters, kCounters32, 0, s));
+  AOT_TRY(fill_i64(w.stats, kStatWords, 0, s));
   AOT_TRY(fill_i64(reinterpret_cast<int64_t*>(w.probes), 4, 0, s));
+  std::vector<int64_t> hs(kStatWords, 0);
   if (m > 0) {
-    const unsigned ge = (unsigned)std::min<int64_t>(kGrid * 4, cdiv(m, kBlock));
-    k_bin_count<<<ge, kBlock, 0, s>>>(m, orow, ocol, otail, heavy_min, w.cnt, w.counters, w.probes);
+    const unsigned ge = grid_cap(std::min<int64_t>(cdiv(m, kBlock), 2048));
+    k_bin_count<<<ge, kBlock, 0, s>>>(m, orow, ocol, otail, heavy_min, w.cnt, w.stats, w.probes);
     AOT_TRY(hipGetLastError());
-    k_bin_scatter<<<ge, kBlock, 0, s>>>(m, orow, ocol, otail, heavy_min, w.counters, w.elist);
+    k_bin_scatter<<<grid_cap(cdiv(m, kBlock)), kBlock, 0, s>>>(m, orow, ocol, otail, heavy_min,
+                                                               w.stats, w.elist);
     AOT_TRY(hipGetLastError());
-    const unsigned gv = (unsigned)std::max<int64_t>(1, std::min<int64_t>(kGrid * 4, cdiv(n, kBlock)));
-    k_make_items<<<gv, kBlock, 0, s>>>(n, orow, irow, heavy_min, w.counters, w.items);
+    const unsigned gv = grid_cap(std::min<int64_t>(cdiv(n, kBlock), 1024));
+    k_item_count<<<gv, kBlock, 0, s>>>(n, orow, irow, heavy_min, w.stats);
     AOT_TRY(hipGetLastError());
-    for (int bin = 0; bin < kLightBins; ++bin)
-      AOT_TRY(launch_light<false>(bin, plan.light_tile[bin], w.counters, w.elist, orow, ocol,
-                                  otail, w.cnt, nullptr, nullptr, 0, 0, nullptr, m, s));
-    k_heavy<false><<<kGrid, kBlock, 0, s>>>(plan, w.counters, w.items, orow, ocol, irow, icol,
-                                             ieid, w.cnt, nullptr, nullptr, 0, 0, nullptr);
+    k_item_scatter<<<gv, kBlock, 0, s>>>(n, orow, irow, heavy_min, w.stats, w.items);
     AOT_TRY(hipGetLastError());
+    AOT_TRY(hipMemcpyAsync(hs.data(), w.stats, sizeof(int64_t) * kStatWords,
+                           hipMemcpyDeviceToHost, s));
+    AOT_TRY(hipStreamSynchronize(s));
+    const int rc = run_buckets(false, plan, hs.data(), w, orow, ocol, otail, nullptr, irow, icol,
+                               ieid, nullptr, 0, 0, nullptr, s, err);
+    if (rc) return rc;
   }
   AOT_TRY(exclusive_scan(w.cnt, tri_off, m, w.scan_tmp, s));
   int64_t t = 0;
   unsigned long long pr = 0;
   AOT_TRY(hipMemcpyAsync(&t, tri_off + m, sizeof(t), hipMemcpyDeviceToHost, s));
   AOT_TRY(hipMemcpyAsync(&pr, w.probes, sizeof(pr), hipMemcpyDeviceToHost, s));
+  AOT_TRY(hipMemcpyAsync(hs.data(), w.stats, sizeof(int64_t) * kStatWords, hipMemcpyDeviceToHost,
+                         s));
   AOT_TRY(hipStreamSynchronize(s));
   result[0] = (uint64_t)t;
   result[1] = (uint64_t)pr;
+  timing_fill_triangles(hs.data(), kStats, kSTriangles);
   return 0;
 }
 
@@ -504,13 +856,12 @@ int list_run(int32_t n, int64_t m, const int64_t* orow, const int32_t* ocol, con
     return -6;
   }
   if (m == 0 || count <= 0) return 0;
-  for (int bin = 0; bin < kLightBins; ++bin)
-    AOT_TRY(launch_light<true>(bin, plan.light_tile[bin], w.counters, w.elist, orow, ocol, otail,
-                               nullptr, tri_off, perm, first, count, out, m, s));
-  k_heavy<true><<<kGrid, kBlock, 0, s>>>(plan, w.counters, w.items, orow, ocol, irow, icol, ieid,
-                                          nullptr, tri_off, perm, first, count, out);
-  AOT_TRY(hipGetLastError());
-  return 0;
+  std::vector<int64_t> hs(kStatWords, 0);
+  AOT_TRY(hipMemcpyAsync(hs.data(), w.stats, sizeof(int64_t) * kStatWords, hipMemcpyDeviceToHost,
+                         s));
+  AOT_TRY(hipStreamSynchronize(s));
+  return run_buckets(true, plan, hs.data(), w, orow, ocol, otail, perm, irow, icol, ieid, tri_off,
+                     first, count, out, s, err);
 }
 
 }  // namespace aot

@@ -63,8 +63,17 @@ int orient_run(int32_t n, int64_t nnz, const int64_t* rowptr, const int32_t* col
                int64_t* irow, int32_t* icol, int32_t* ieid, void* ws, size_t ws_bytes,
                hipStream_t s, const char** err);
 
+// ---- timing.cpp: the per-launch recorder of the probe passes.  A record is
+// opened just before a bucket's kernel launch and closed right after it,
+// with HIP events on the launch stream; disabled, both calls do nothing.
+constexpr int kNumBuckets = 32;
+int timing_begin(int pass, int bucket, int arm, int tile, int64_t edges, int64_t probes,
+                 int64_t staged, int64_t triangles, hipStream_t s);
+void timing_end(int rec, hipStream_t s);
+// Fills the triangle totals of the count-pass records still missing them.
+void timing_fill_triangles(const int64_t* stats, int stride, int offset);
+
 // ---- count.hip
-struct CountPlan;
 size_t count_workspace_bytes(int32_t n, int64_t m);
 struct DispatchView {
   int32_t heavy_min;

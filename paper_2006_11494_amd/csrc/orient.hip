@@ -7,6 +7,7 @@
 // width G matched to the degree range (4, 16 or 64 lanes, or a whole
 // workgroup for rows longer than 64).  Out-list lengths are not monotone in
 // rank, so the sort step first bins rows by length.
+#include <algorithm>
 #include <climits>
 
 #include "kernels.hpp"
@@ -95,7 +96,14 @@ __global__ __launch_bounds__(kBlock) void k_degree(int32_t n, const int64_t* __r
     const int32_t y = __shfl_xor(mx, o, kWave);
     mx = y > mx ? y : mx;
   }
-  if (lane_id() == 0) atomicMax(&counters[kCMaxDeg], mx);
+  if (lane_id() == 0) red[threadIdx.x / kWave] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int32_t b = 0;
+    for (int q = 0; q < kWavesPerBlock; ++q) b = red[q] > b ? red[q] : b;
+    atomicMax(&counters[kCMaxDeg], b);
+  }
+  __syncthreads();
   c0 = block_sum(c0, red);
   c4 = block_sum(c4, red);
   c16 = block_sum(c16, red);
@@ -226,30 +234,51 @@ __device__ __forceinline__ int sort_class(int64_t len) {
 __global__ __launch_bounds__(kBlock) void k_count_sort_classes(int32_t n,
                                                                const int32_t* __restrict__ dplus,
                                                                int32_t* __restrict__ counters) {
-  __shared__ int32_t h[kSortClasses];
-  if (threadIdx.x < kSortClasses) h[threadIdx.x] = 0;
-  __syncthreads();
+  int32_t h[kSortClasses] = {0, 0, 0, 0};
   for (int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x; r < n;
        r += (int64_t)gridDim.x * kBlock) {
     const int32_t len = dplus[r];
-    if (len > 0) atomicAdd(&h[sort_class(len)], 1);
+    if (len > 0) {
+      const int c = sort_class(len);
+#pragma unroll
+      for (int q = 0; q < kSortClasses; ++q) h[q] += c == q;
+    }
   }
-  __syncthreads();
-  if (threadIdx.x < kSortClasses) atomicAdd(&counters[kCSortCount + threadIdx.x], h[threadIdx.x]);
+  __shared__ int32_t red[kWavesPerBlock];
+#pragma unroll
+  for (int q = 0; q < kSortClasses; ++q) {
+    const int32_t t = block_sum(h[q], red);
+    if (threadIdx.x == 0 && t) atomicAdd(&counters[kCSortCount + q], t);
+  }
 }
 
+// Rows into their length classes; one global atomic per wave and class.
 __global__ __launch_bounds__(kBlock) void k_scatter_sort_classes(int32_t n,
                                                                  const int32_t* __restrict__ dplus,
                                                                  int32_t* __restrict__ counters,
                                                                  int32_t* __restrict__ rows) {
-  for (int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x; r < n;
-       r += (int64_t)gridDim.x * kBlock) {
-    const int32_t len = dplus[r];
-    if (len <= 0) continue;
-    const int c = sort_class(len);
-    int32_t base = 0;
-    for (int q = 0; q < c; ++q) base += counters[kCSortCount + q];
-    rows[base + atomicAdd(&counters[kCSortCursor + c], 1)] = (int32_t)r;
+  __shared__ int32_t base[kSortClasses];
+  if (threadIdx.x == 0) {
+    int32_t run = 0;
+    for (int q = 0; q < kSortClasses; ++q) { base[q] = run; run += counters[kCSortCount + q]; }
+  }
+  __syncthreads();
+  for (int64_t r0 = (int64_t)blockIdx.x * kBlock; r0 < n; r0 += (int64_t)gridDim.x * kBlock) {
+    const int64_t r = r0 + threadIdx.x;
+    int c = -1;
+    if (r < n) {
+      const int32_t len = dplus[r];
+      if (len > 0) c = sort_class(len);
+    }
+    for (int q = 0; q < kSortClasses; ++q) {
+      const uint64_t mask = ballot(c == q);
+      if (!mask) continue;
+      const int leader = __ffsll((long long)mask) - 1;
+      int32_t at = 0;
+      if (lane_id() == leader) at = atomicAdd(&counters[kCSortCursor + q], (int32_t)__popcll(mask));
+      at = __shfl(at, leader, kWave);
+      if (c == q) rows[base[q] + at + popc_below(mask)] = (int32_t)r;
+    }
   }
 }
 
@@ -495,7 +524,8 @@ int orient_run(int32_t n, int64_t nnz, const int64_t* rowptr, const int32_t* col
     AOT_TRY(fill_i64(irow, 1, 0, s));
     return 0;
   }
-  k_degree<<<grid_for(n, kBlock), kBlock, 0, s>>>(n, rowptr, key_a, val_a, counters);
+  k_degree<<<std::min(grid_for(n, kBlock), 1024u), kBlock, 0, s>>>(n, rowptr, key_a, val_a,
+                                                                   counters);
   AOT_TRY(hipGetLastError());
   int32_t hc[kCounters];
   AOT_TRY(hipMemcpyAsync(hc, counters, sizeof(hc), hipMemcpyDeviceToHost, s));
@@ -526,7 +556,8 @@ int orient_run(int32_t n, int64_t nnz, const int64_t* rowptr, const int32_t* col
   ROWS(256, c64, n, k_orient_write, rowptr, col, perm, rank, orow, irow, unsorted, otail, icol);
 
   // sort each out-list into ocol
-  k_count_sort_classes<<<grid_for(n, kBlock), kBlock, 0, s>>>(n, dplus, counters);
+  k_count_sort_classes<<<std::min(grid_for(n, kBlock), 1024u), kBlock, 0, s>>>(n, dplus,
+                                                                               counters);
   AOT_TRY(hipGetLastError());
   k_scatter_sort_classes<<<grid_for(n, kBlock), kBlock, 0, s>>>(n, dplus, counters, rows);
   AOT_TRY(hipGetLastError());

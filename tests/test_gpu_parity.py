@@ -228,3 +228,25 @@ def test_validation_rejects_malformed_graphs():
         with pytest.raises(aot.AotError) as e:
             aot.orient(rp, col, validate=True)
         assert e.value.status == -2, name
+
+
+def test_timing_recorder():
+    need_gpu()
+    g = inputs.rmat(13, 16, 7).to(DEV)
+    o = aot.orient(g.rowptr, g.col)
+    c0 = aot.count(o)
+    t0 = aot.list_triangles(o, c0)
+    aot.timing_start()
+    c1 = aot.count(o)
+    t1 = aot.list_triangles(o, c1)
+    recs = aot.timing_stop()
+    assert (c0.T, c0.probes) == (c1.T, c1.probes) and torch.equal(t0, t1)
+    cnt = [r for r in recs if r["pass"] == 0]
+    wrt = [r for r in recs if r["pass"] == 1]
+    assert cnt and [r["bucket"] for r in cnt] == [r["bucket"] for r in wrt]
+    assert sum(r["probes"] for r in cnt) == c1.probes
+    assert sum(r["triangles"] for r in cnt) == c1.T
+    assert [r["triangles"] for r in cnt] == [r["triangles"] for r in wrt]
+    assert all(r["ms"] > 0 for r in recs)
+    assert any(r["bucket"] >= 16 for r in cnt) and any(r["bucket"] < 8 for r in cnt)
+    assert aot.timing_stop() == []          # stopped: nothing new recorded
