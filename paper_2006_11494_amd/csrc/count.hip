@@ -36,21 +36,16 @@ constexpr int kLightBins = 8;       // c in {1}, {2}, (2,4], (4,8], ..., last bi
 constexpr int kHeavyClasses = 16;   // owner classes by ceil(log2 deg+(b))
 constexpr int kHeavyBase = 16;      // bucket id of heavy class 0
 constexpr int kItemSpan = 512;      // neighbours of one owner per work item
-constexpr int kIndexWords = 5120;   // LDS index: 20 KiB (bitmap window of 163840 ids)
-constexpr int kHashSlots = 4096;    // largest power of two <= kIndexWords
-constexpr int kUnroll = 4;          // probes per lane per round
-constexpr int kRound = kBlock * kUnroll;
-constexpr int kRoundWords = kRound / 32;
+constexpr int kMaxIndexWords = 12288;  // LDS index cap: 48 KiB (bitmap window of 393216 ids)
+constexpr int kUnroll = 4;          // probes per lane per window step
 constexpr int kGrid = 4096;
 constexpr int kDefaultHeavyMin = 32;
 
 static_assert(kNumBuckets == kHeavyBase + kHeavyClasses, "bucket layout");
-static_assert(kRoundWords <= kWave, "one wave scans a round's flag words");
-static_assert(kHashSlots <= kIndexWords && (kHashSlots & (kHashSlots - 1)) == 0, "hash table");
 
 // per-bucket statistics (int64, device), bucket = light bin or kHeavyBase + class
 enum : int {
-  kSEdges = 0, kSProbes, kSTriangles, kSItems, kSStaged, kSCursor, kSItemBase, kStats,
+  kSEdges = 0, kSProbes, kSTriangles, kSItems, kSStaged, kSCursor, kSItemBase, kSSpan, kStats,
 };
 constexpr int kStatWords = kNumBuckets * kStats;
 
@@ -89,11 +84,13 @@ __device__ __forceinline__ unsigned long long* u64p(int64_t* p) {
 // ---------------------------------------------------------------- binning
 
 // Per-bucket edge and probe counts, and the probe total.
+// Also stores each edge's light bin (or 0xFF) for the scatter.
 __global__ __launch_bounds__(kBlock) void k_bin_count(int64_t m, const int64_t* __restrict__ orow,
                                                       const int32_t* __restrict__ ocol,
                                                       const int32_t* __restrict__ otail,
                                                       int32_t heavy_min,
                                                       int32_t* __restrict__ cnt,
+                                                      uint8_t* __restrict__ code,
                                                       int64_t* __restrict__ stats,
                                                       unsigned long long* __restrict__ probes) {
   __shared__ unsigned long long se[kNumBuckets], sp[kNumBuckets];
@@ -104,8 +101,9 @@ __global__ __launch_bounds__(kBlock) void k_bin_count(int64_t m, const int64_t* 
     const EdgeEnds x = edge_ends(orow, otail[e], ocol[e]);
     int bucket;
     if (x.db >= heavy_min) bucket = kHeavyBase + heavy_class(x.db);
-    else if (x.c == 0) { cnt[e] = 0; continue; }
+    else if (x.c == 0) { cnt[e] = 0; code[e] = 0xFF; continue; }
     else bucket = light_bin(x.c);
+    code[e] = bucket < kLightBins ? (uint8_t)bucket : (uint8_t)0xFF;
     atomicAdd(&se[bucket], 1ull);
     atomicAdd(&sp[bucket], (unsigned long long)x.c);
   }
@@ -118,10 +116,7 @@ __global__ __launch_bounds__(kBlock) void k_bin_count(int64_t m, const int64_t* 
 }
 
 // Light edges into their bins; one global atomic per wave and bin.
-__global__ __launch_bounds__(kBlock) void k_bin_scatter(int64_t m, const int64_t* __restrict__ orow,
-                                                        const int32_t* __restrict__ ocol,
-                                                        const int32_t* __restrict__ otail,
-                                                        int32_t heavy_min,
+__global__ __launch_bounds__(kBlock) void k_bin_scatter(int64_t m, const uint8_t* __restrict__ code,
                                                         int64_t* __restrict__ stats,
                                                         int32_t* __restrict__ elist) {
   __shared__ int64_t base[kLightBins];
@@ -135,9 +130,10 @@ __global__ __launch_bounds__(kBlock) void k_bin_scatter(int64_t m, const int64_t
     const int64_t e = e0 + threadIdx.x;
     int bin = -1;
     if (e < m) {
-      const EdgeEnds x = edge_ends(orow, otail[e], ocol[e]);
-      if (x.db < heavy_min && x.c > 0) bin = light_bin(x.c);
+      const int c = code[e];
+      if (c != 0xFF) bin = c;
     }
+    if (!ballot(bin >= 0)) continue;
     for (int k = 0; k < kLightBins; ++k) {
       const uint64_t mask = ballot(bin == k);
       if (!mask) continue;
@@ -152,32 +148,39 @@ __global__ __launch_bounds__(kBlock) void k_bin_scatter(int64_t m, const int64_t
   }
 }
 
-// Work items per heavy class, and the owner-list entries they stage.
+// Work items per heavy class, the owner-list entries they stage, and the
+// largest owner-list span of the class (which sizes the bitmap arm's LDS).
 __global__ __launch_bounds__(kBlock) void k_item_count(int32_t n, const int64_t* __restrict__ orow,
+                                                       const int32_t* __restrict__ ocol,
                                                        const int64_t* __restrict__ irow,
                                                        int32_t heavy_min,
                                                        int64_t* __restrict__ stats) {
-  __shared__ unsigned long long si[kHeavyClasses], ss[kHeavyClasses];
-  if (threadIdx.x < kHeavyClasses) { si[threadIdx.x] = 0; ss[threadIdx.x] = 0; }
+  __shared__ unsigned long long si[kHeavyClasses], ss[kHeavyClasses], sx[kHeavyClasses];
+  if (threadIdx.x < kHeavyClasses) { si[threadIdx.x] = 0; ss[threadIdx.x] = 0; sx[threadIdx.x] = 0; }
   __syncthreads();
   for (int64_t b = (int64_t)blockIdx.x * kBlock + threadIdx.x; b < n;
        b += (int64_t)gridDim.x * kBlock) {
-    const int64_t db = orow[b + 1] - orow[b];
+    const int64_t ob = orow[b];
+    const int64_t db = orow[b + 1] - ob;
     if (db < heavy_min) continue;
     const int64_t deg = db + irow[b + 1] - irow[b];
     const int64_t k = (deg + kItemSpan - 1) / kItemSpan;
     const int h = heavy_class((int32_t)db);
+    const unsigned long long span = (unsigned long long)(ocol[ob + db - 1] - ocol[ob] + 1);
     atomicAdd(&si[h], (unsigned long long)k);
     atomicAdd(&ss[h], (unsigned long long)(k * db));
+    atomicMax(&sx[h], span);
   }
   __syncthreads();
   if (threadIdx.x < kHeavyClasses && si[threadIdx.x]) {
     int64_t* st = stats + (kHeavyBase + threadIdx.x) * kStats;
     atomicAdd(u64p(&st[kSItems]), si[threadIdx.x]);
     atomicAdd(u64p(&st[kSStaged]), ss[threadIdx.x]);
+    atomicMax(u64p(&st[kSSpan]), sx[threadIdx.x]);
   }
 }
 
+// Work items into their classes; one global atomic per wave and class.
 __global__ __launch_bounds__(kBlock) void k_item_scatter(int32_t n, const int64_t* __restrict__ orow,
                                                          const int64_t* __restrict__ irow,
                                                          int32_t heavy_min,
@@ -194,16 +197,37 @@ __global__ __launch_bounds__(kBlock) void k_item_scatter(int32_t n, const int64_
   __syncthreads();
   if (blockIdx.x == 0 && threadIdx.x < kHeavyClasses)
     stats[(kHeavyBase + threadIdx.x) * kStats + kSItemBase] = base[threadIdx.x];
-  for (int64_t b = (int64_t)blockIdx.x * kBlock + threadIdx.x; b < n;
-       b += (int64_t)gridDim.x * kBlock) {
-    const int64_t db = orow[b + 1] - orow[b];
-    if (db < heavy_min) continue;
-    const int64_t deg = db + irow[b + 1] - irow[b];
-    const int32_t k = (int32_t)((deg + kItemSpan - 1) / kItemSpan);
-    const int h = heavy_class((int32_t)db);
-    const int64_t at = (int64_t)atomicAdd(u64p(&stats[(kHeavyBase + h) * kStats + kSCursor]),
-                                          (unsigned long long)k);
-    for (int32_t q = 0; q < k; ++q) items[base[h] + at + q] = make_int2((int32_t)b, q * kItemSpan);
+  for (int64_t b0 = (int64_t)blockIdx.x * kBlock; b0 < n; b0 += (int64_t)gridDim.x * kBlock) {
+    const int64_t b = b0 + threadIdx.x;
+    int h = -1;
+    int32_t k = 0;
+    if (b < n) {
+      const int64_t db = orow[b + 1] - orow[b];
+      if (db >= heavy_min) {
+        const int64_t deg = db + irow[b + 1] - irow[b];
+        k = (int32_t)((deg + kItemSpan - 1) / kItemSpan);
+        h = heavy_class((int32_t)db);
+      }
+    }
+    if (!ballot(h >= 0)) continue;
+    for (int q = 0; q < kHeavyClasses; ++q) {
+      const uint64_t mask = ballot(h == q);
+      if (!mask) continue;
+      // exclusive prefix of k over the lanes of this class
+      int32_t kin = h == q ? k : 0;
+      int32_t inc = wave_inclusive_scan(kin);
+      const int32_t tot = __shfl(inc, 63, kWave);
+      const int leader = __ffsll((long long)mask) - 1;
+      long long at = 0;
+      if (lane_id() == leader)
+        at = (long long)atomicAdd(u64p(&stats[(kHeavyBase + q) * kStats + kSCursor]),
+                                  (unsigned long long)tot);
+      at = __shfl(at, leader, kWave);
+      if (h == q) {
+        const int64_t first = base[q] + at + (inc - kin);
+        for (int32_t r = 0; r < k; ++r) items[first + r] = make_int2((int32_t)b, r * kItemSpan);
+      }
+    }
   }
 }
 
@@ -219,12 +243,19 @@ struct Index {
   int32_t len;
 };
 
+__host__ __device__ __forceinline__ int64_t floor_pow2(int64_t x) {
+  int64_t p = 1;
+  while (p * 2 <= x) p *= 2;
+  return p;
+}
+
 // The arm an owner actually uses: the requested one if its list fits that
-// arm's LDS budget, else the next that fits (bitmap -> hash -> sorted -> global).
-__device__ __forceinline__ int resolve_arm(int arm, int32_t db, int64_t span) {
-  if (arm == kArmBitmap && span > (int64_t)kIndexWords * 32) arm = kArmHash;
-  if (arm == kArmHash && 2 * (int64_t)db > kHashSlots) arm = kArmSorted;
-  if (arm == kArmSorted && db > kIndexWords) arm = kArmGlobal;
+// arm in `words` LDS words, else the next that fits (bitmap -> hash ->
+// sorted -> global).
+__host__ __device__ __forceinline__ int resolve_arm(int arm, int64_t db, int64_t span, int words) {
+  if (arm == kArmBitmap && span > (int64_t)words * 32) arm = kArmHash;
+  if (arm == kArmHash && 2 * db > floor_pow2(words)) arm = kArmSorted;
+  if (arm == kArmSorted && db > words) arm = kArmGlobal;
   return arm;
 }
 
@@ -314,6 +345,7 @@ __device__ __forceinline__ int advance(const int32_t* pre, int kc, int K, int32_
 
 struct HeavyArgs {
   int arm;                      // requested arm of this class
+  int idx_words;                // LDS words of the index (dynamic shared memory)
   const int2* items;
   int64_t item_base, item_count;
   const int64_t* orow;
@@ -331,24 +363,47 @@ struct HeavyArgs {
 
 template <bool kEmit>
 struct HeavyShared {
-  uint32_t lds[kIndexWords];
   int64_t nb_oy[kItemSpan];
   int64_t nb_base[kEmit ? kItemSpan : 1];
   int32_t nb_pre[kItemSpan + 1];
   int32_t nb_e[kItemSpan];
-  int32_t nb_acc[kItemSpan];          // count: hits; write: running carry
+  int32_t nb_acc[kItemSpan];          // count: hits; write: running rank within the edge
   int32_t nb_py[kEmit ? kItemSpan : 1];
-  uint64_t flags[kEmit ? kRound / 64 : 1];
-  int32_t wpre[kEmit ? kRoundWords + 1 : 1];
+  int32_t wave_k[kWavesPerBlock + 1];
   int64_t scan_tmp[kWavesPerBlock + 1];
 };
 
+// Per-lane hits of one 64-probe window, reduced per neighbour segment (lanes
+// hold non-decreasing neighbour indices k).  Returns, for each lane, the
+// number of hits of its own segment in lanes below it; `seg_total` gets the
+// segment's hit count in the window (valid on the segment's first lane,
+// flagged by `first_lane`).
+__device__ __forceinline__ int segment_rank(bool valid, int k, uint64_t hm, int* seg_total,
+                                            bool* first_lane) {
+  const int lane = lane_id();
+  const int kprev = __shfl_up(k, 1, kWave);
+  const bool start = valid && (lane == 0 || kprev != k);
+  const uint64_t sm = ballot(start);
+  const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+  const uint64_t below_sm = sm & upto;
+  const int s = below_sm ? 63 - __clzll((long long)below_sm) : 0;  // my segment's first lane
+  const uint64_t lt = (1ull << lane) - 1ull;
+  const uint64_t from_s = ~((1ull << s) - 1ull);
+  const int rank = __popcll(hm & lt & from_s);
+  const uint64_t above = lane < 63 ? (sm & ~((2ull << lane) - 1ull)) : 0ull;
+  const int end = above ? __ffsll((long long)above) - 1 : 64;
+  const uint64_t seg = (end == 64 ? ~0ull : ((1ull << end) - 1ull)) & ~lt;
+  *seg_total = __popcll(hm & seg);
+  *first_lane = start;
+  return rank;
+}
+
 // Count pass over one item's compacted neighbours (K of them, P probes):
-// wave-contiguous windows of 64 probes, a per-lane cursor into the
-// neighbours, hits summed per neighbour segment of the window.
+// waves take interleaved windows of 64 probes, each lane keeps a cursor into
+// the neighbours, and hits are summed per neighbour segment of a window.
 template <int ARM>
-__device__ int64_t probe_count(HeavyShared<false>& sh, const HeavyArgs& a, const Index& ix, int K,
-                               int32_t P) {
+__device__ int64_t probe_count(HeavyShared<false>& sh, const uint32_t* lds, const HeavyArgs& a,
+                               const Index& ix, int K, int32_t P) {
   const int wave = threadIdx.x / kWave;
   const int lane = lane_id();
   int kc = 0;
@@ -370,81 +425,59 @@ __device__ int64_t probe_count(HeavyShared<false>& sh, const HeavyArgs& a, const
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
       const bool valid = kk[u] >= 0;
-      const bool hit = valid && index_has<ARM>(ix, sh.lds, wv[u]);
+      const bool hit = valid && index_has<ARM>(ix, lds, wv[u]);
       hits_lane += hit;
       const uint64_t hm = ballot(hit);
       if (!hm) continue;
-      const int kprev = __shfl_up(kk[u], 1, kWave);
-      const bool start = valid && (lane == 0 || kprev != kk[u]);
-      const uint64_t sm = ballot(start);
-      if (start) {
-        const uint64_t above = lane < 63 ? (sm & ~((2ull << lane) - 1ull)) : 0ull;
-        const int end = above ? __ffsll((long long)above) - 1 : 64;
-        const uint64_t seg = (end == 64 ? ~0ull : ((1ull << end) - 1ull)) & ~((1ull << lane) - 1ull);
-        const int c = __popcll(hm & seg);
-        if (c) atomicAdd(&sh.nb_acc[kk[u]], c);
-      }
+      int tot;
+      bool first;
+      segment_rank(valid, kk[u], hm, &tot, &first);
+      if (first && tot) atomicAdd(&sh.nb_acc[kk[u]], tot);
     }
   }
   return hits_lane;
 }
 
-// Write pass over one item's compacted neighbours: rounds of kRound probes
-// taken by all waves together so that hit ranks follow probe order (hit
-// flags -> prefix popcounts of the flag words -> positions -> carries).
+// Write pass over one item's compacted neighbours.  Each wave owns a run of
+// whole neighbours holding about a quarter of the probes and walks it in
+// order, so an edge's hits are ranked by probe order inside one wave: the
+// rank is the edge's running count (LDS, touched by this wave only) plus the
+// hits of its segment in lower lanes of the window.
 template <int ARM>
-__device__ void probe_emit(HeavyShared<true>& sh, const HeavyArgs& a, const Index& ix, int K,
-                           int32_t P, int32_t pb) {
+__device__ void probe_emit(HeavyShared<true>& sh, const uint32_t* lds, const HeavyArgs& a,
+                           const Index& ix, int K, int32_t P, int32_t pb) {
   const int wave = threadIdx.x / kWave;
   const int lane = lane_id();
-  int kc = 0;
-  for (int32_t r0 = 0; r0 < P; r0 += kRound) {
+  const int k_lo = sh.wave_k[wave], k_hi = sh.wave_k[wave + 1];
+  if (k_lo >= k_hi) return;
+  const int32_t p_lo = sh.nb_pre[k_lo], p_hi = sh.nb_pre[k_hi];
+  int kc = k_lo;
+  for (int32_t w0 = p_lo; w0 < p_hi; w0 += kWave * kUnroll) {
     int32_t wv[kUnroll];
     int kk[kUnroll];
-    bool hit[kUnroll];
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
-      const int32_t p = r0 + wave * kWave * kUnroll + u * kWave + lane;
+      const int32_t p = w0 + u * kWave + lane;
       kk[u] = -1;
       wv[u] = 0;
-      if (p < P) {
-        kc = advance(sh.nb_pre, kc, K, p);
+      if (p < p_hi) {
+        kc = advance(sh.nb_pre, kc, k_hi, p);
         kk[u] = kc;
         wv[u] = a.ocol[sh.nb_oy[kc] + (p - sh.nb_pre[kc])];
       }
     }
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
-      hit[u] = kk[u] >= 0 && index_has<ARM>(ix, sh.lds, wv[u]);
-      const uint64_t hm = ballot(hit[u]);
-      if (lane == 0) sh.flags[wave * kUnroll + u] = hm;
-    }
-    __syncthreads();
-    if (wave == 0) {
-      const int q = lane;
-      int32_t c = 0;
-      if (q < kRoundWords) c = __popc((uint32_t)(sh.flags[q >> 1] >> ((q & 1) * 32)));
-      const int32_t inc = wave_inclusive_scan(c);
-      if (q < kRoundWords) sh.wpre[q] = inc - c;
-      if (q == kRoundWords - 1) sh.wpre[kRoundWords] = inc;
-    }
-    __syncthreads();
-    auto rank = [&](int32_t x) -> int32_t {     // hits among the round's probes [0, x)
-      const int q = x >> 5;
-      if (q >= kRoundWords) return sh.wpre[kRoundWords];
-      const uint32_t wd = (uint32_t)(sh.flags[q >> 1] >> ((q & 1) * 32));
-      return sh.wpre[q] + __popc(wd & ((1u << (x & 31)) - 1u));
-    };
-    int32_t delta[kUnroll];
-#pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
-      delta[u] = 0;
-      if (kk[u] < 0) continue;
-      const int k = kk[u];
-      const int32_t p = r0 + wave * kWave * kUnroll + u * kWave + lane;
-      const int32_t seg_lo = max(sh.nb_pre[k], r0) - r0;
-      if (hit[u]) {
-        const int64_t pos = sh.nb_base[k] + sh.nb_acc[k] + (rank(p - r0) - rank(seg_lo));
+      const bool valid = kk[u] >= 0;
+      const bool hit = valid && index_has<ARM>(ix, lds, wv[u]);
+      const uint64_t hm = ballot(hit);
+      if (!hm) continue;
+      int tot;
+      bool first;
+      const int rank = segment_rank(valid, kk[u], hm, &tot, &first);
+      if (hit) {
+        const int k = kk[u];
+        const int64_t pos = sh.nb_base[k] + sh.nb_acc[k] + rank;
         if (pos >= a.first && pos < a.first + a.count) {
           int32_t t0 = pb, t1 = sh.nb_py[k], t2 = a.perm[wv[u]];
           sort3(t0, t1, t2);
@@ -452,33 +485,29 @@ __device__ void probe_emit(HeavyShared<true>& sh, const HeavyArgs& a, const Inde
           o[0] = t0; o[1] = t1; o[2] = t2;
         }
       }
-      const int32_t seg_end = min(sh.nb_pre[k + 1], r0 + kRound);
-      if (p == seg_end - 1) delta[u] = rank(seg_end - r0) - rank(seg_lo);
+      if (first && tot) sh.nb_acc[kk[u]] += tot;   // read above by this wave only
     }
-    __syncthreads();
-#pragma unroll
-    for (int u = 0; u < kUnroll; ++u)
-      if (delta[u]) sh.nb_acc[kk[u]] += delta[u];
-    __syncthreads();
   }
 }
 
 template <int ARM, bool kEmit>
-__device__ int64_t run_item(HeavyShared<kEmit>& sh, const HeavyArgs& a, const int32_t* list,
-                            int32_t db, int K, int32_t P, int32_t pb) {
-  const Index ix = build_index<ARM>(list, db, sh.lds);   // ends with a barrier
+__device__ int64_t run_item(HeavyShared<kEmit>& sh, uint32_t* lds, const HeavyArgs& a,
+                            const int32_t* list, int32_t db, int K, int32_t P, int32_t pb) {
+  const Index ix = build_index<ARM>(list, db, lds);   // ends with a barrier
   if constexpr (!kEmit) {
-    return probe_count<ARM>(sh, a, ix, K, P);
+    return probe_count<ARM>(sh, lds, a, ix, K, P);
   } else {
-    probe_emit<ARM>(sh, a, ix, K, P, pb);
+    probe_emit<ARM>(sh, lds, a, ix, K, P, pb);
     return 0;
   }
 }
 
-// A launch covers the work items of one heavy class.
+// A launch covers the work items of one heavy class; the LDS index lives in
+// dynamic shared memory of a.idx_words words.
 template <bool kEmit>
 __global__ __launch_bounds__(kBlock) void k_heavy(HeavyArgs a) {
   __shared__ HeavyShared<kEmit> sh;
+  extern __shared__ uint32_t lds[];
   const int tid = threadIdx.x;
   int64_t tri_block = 0;
   for (int64_t it = blockIdx.x; it < a.item_count; it += gridDim.x) {
@@ -544,26 +573,36 @@ __global__ __launch_bounds__(kBlock) void k_heavy(HeavyArgs a) {
       }
     }
     if (tid == 0) sh.nb_pre[K] = P;
-    if (K == 0) {                 // nothing owned in this window: no index needed
-      __syncthreads();
-      continue;
+    __syncthreads();
+    if (K == 0) continue;         // nothing owned in this window: no index needed
+    if constexpr (kEmit) {
+      // neighbour-aligned probe ranges of the four waves: wave w starts at the
+      // first neighbour whose probes begin at or after w * P / 4
+      if (tid <= kWavesPerBlock) {
+        const int32_t target = (int32_t)(((int64_t)P * tid) / kWavesPerBlock);
+        int lo = 0, hi = K;
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if (sh.nb_pre[mid] < target) lo = mid + 1; else hi = mid;
+        }
+        sh.wave_k[tid] = tid == kWavesPerBlock ? K : lo;
+      }
     }
     const int32_t* list = a.ocol + ob;
     const int64_t span = (int64_t)list[db - 1] - list[0] + 1;
-    const int arm = resolve_arm(a.arm, db, span);
+    const int arm = resolve_arm(a.arm, db, span, a.idx_words);
     const int32_t pb = kEmit ? a.perm[b] : 0;
     int64_t t = 0;
     switch (arm) {
-      case kArmBitmap: t = run_item<kArmBitmap, kEmit>(sh, a, list, db, K, P, pb); break;
-      case kArmHash: t = run_item<kArmHash, kEmit>(sh, a, list, db, K, P, pb); break;
-      case kArmSorted: t = run_item<kArmSorted, kEmit>(sh, a, list, db, K, P, pb); break;
-      default: t = run_item<kArmGlobal, kEmit>(sh, a, list, db, K, P, pb); break;
+      case kArmBitmap: t = run_item<kArmBitmap, kEmit>(sh, lds, a, list, db, K, P, pb); break;
+      case kArmHash: t = run_item<kArmHash, kEmit>(sh, lds, a, list, db, K, P, pb); break;
+      case kArmSorted: t = run_item<kArmSorted, kEmit>(sh, lds, a, list, db, K, P, pb); break;
+      default: t = run_item<kArmGlobal, kEmit>(sh, lds, a, list, db, K, P, pb); break;
     }
-    if constexpr (!kEmit) {
-      tri_block += t;
-      __syncthreads();
+    if constexpr (!kEmit) tri_block += t;
+    __syncthreads();
+    if constexpr (!kEmit)
       for (int s = tid; s < K; s += kBlock) a.cnt[sh.nb_e[s]] = sh.nb_acc[s];
-    }
     __syncthreads();
   }
   if constexpr (!kEmit) {
@@ -674,6 +713,7 @@ int64_t max_items(int32_t n, int64_t m) { return (int64_t)n + cdiv(2 * m, kItemS
 
 struct CountWs {
   int32_t* cnt;
+  uint8_t* code;
   int32_t* elist;
   int2* items;
   int64_t* stats;
@@ -684,6 +724,7 @@ struct CountWs {
 CountWs carve_count(Carve& c, int32_t n, int64_t m) {
   CountWs w;
   w.cnt = c.take<int32_t>(m);
+  w.code = c.take<uint8_t>(m);
   w.elist = c.take<int32_t>(m);
   w.items = c.take<int2>(max_items(n, m));
   w.stats = c.take<int64_t>(kStatWords);
@@ -718,6 +759,28 @@ hipError_t launch_light(int tile, unsigned grid, int64_t base, int64_t total,
   }
 #undef L
   return hipGetLastError();
+}
+
+// LDS words a heavy class's launch reserves for its index: enough for the
+// requested arm on every owner of the class (bitmap: the class's widest
+// span; hash: a power-of-two table of twice deg+; sorted: deg+), capped at
+// kMaxIndexWords, beyond which owners fall back to the next arm.
+int index_words(int arm, int h, int64_t max_span) {
+  const int64_t dmax = int64_t(1) << h;       // class h holds deg+ in (2^(h-1), 2^h]
+  int64_t need = 0;
+  if (arm == kArmBitmap) {
+    need = (max_span + 31) / 32;
+    if (need > kMaxIndexWords) need = kMaxIndexWords;
+    else return (int)std::max<int64_t>(need, 1);
+  }
+  if (arm == kArmBitmap || arm == kArmHash) {
+    int64_t t = 2;
+    while (t < 2 * dmax) t <<= 1;
+    need = std::max(need, t);
+  } else if (arm == kArmSorted) {
+    need = dmax;
+  }
+  return (int)std::min<int64_t>(std::max<int64_t>(need, 1), kMaxIndexWords);
 }
 
 unsigned grid_cap(int64_t work_units) {
@@ -759,6 +822,7 @@ int run_buckets(bool emit, const Plan& plan, const int64_t* hs, const CountWs& w
     if (items <= 0) continue;
     HeavyArgs a;
     a.arm = plan.heavy_arm[h];
+    a.idx_words = index_words(a.arm, h, st[kSSpan]);
     a.items = w.items;
     a.item_base = st[kSItemBase];
     a.item_count = items;
@@ -772,8 +836,9 @@ int run_buckets(bool emit, const Plan& plan, const int64_t* hs, const CountWs& w
     a.out = out;
     const int rec = timing_begin(emit ? 1 : 0, kHeavyBase + h, a.arm, kBlock, st[kSEdges],
                                  st[kSProbes], st[kSStaged], st[kSTriangles], s);
-    if (emit) k_heavy<true><<<grid_cap(items), kBlock, 0, s>>>(a);
-    else k_heavy<false><<<grid_cap(items), kBlock, 0, s>>>(a);
+    const size_t dyn = sizeof(uint32_t) * (size_t)std::max(a.idx_words, 1);
+    if (emit) k_heavy<true><<<grid_cap(items), kBlock, dyn, s>>>(a);
+    else k_heavy<false><<<grid_cap(items), kBlock, dyn, s>>>(a);
     AOT_TRY(hipGetLastError());
     timing_end(rec, s);
   }
@@ -809,13 +874,14 @@ int count_run(int32_t n, int64_t m, const int64_t* orow, const int32_t* ocol, co
   std::vector<int64_t> hs(kStatWords, 0);
   if (m > 0) {
     const unsigned ge = grid_cap(std::min<int64_t>(cdiv(m, kBlock), 2048));
-    k_bin_count<<<ge, kBlock, 0, s>>>(m, orow, ocol, otail, heavy_min, w.cnt, w.stats, w.probes);
+    k_bin_count<<<ge, kBlock, 0, s>>>(m, orow, ocol, otail, heavy_min, w.cnt, w.code, w.stats,
+                                      w.probes);
     AOT_TRY(hipGetLastError());
-    k_bin_scatter<<<grid_cap(cdiv(m, kBlock)), kBlock, 0, s>>>(m, orow, ocol, otail, heavy_min,
-                                                               w.stats, w.elist);
+    k_bin_scatter<<<grid_cap(std::min<int64_t>(cdiv(m, kBlock), 4096)), kBlock, 0, s>>>(
+        m, w.code, w.stats, w.elist);
     AOT_TRY(hipGetLastError());
     const unsigned gv = grid_cap(std::min<int64_t>(cdiv(n, kBlock), 1024));
-    k_item_count<<<gv, kBlock, 0, s>>>(n, orow, irow, heavy_min, w.stats);
+    k_item_count<<<gv, kBlock, 0, s>>>(n, orow, ocol, irow, heavy_min, w.stats);
     AOT_TRY(hipGetLastError());
     k_item_scatter<<<gv, kBlock, 0, s>>>(n, orow, irow, heavy_min, w.stats, w.items);
     AOT_TRY(hipGetLastError());

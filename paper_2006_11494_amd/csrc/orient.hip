@@ -435,6 +435,29 @@ __global__ __launch_bounds__(kBlock) void k_in_eid(int32_t r0, int32_t r1,
   }
 }
 
+// The same for the rows [r0, r1) of the longest degree class, flattened over
+// their in-entries (a thread per entry, its row found by binary search) so
+// that a hub's in-list is spread over the whole grid.
+__global__ __launch_bounds__(kBlock) void k_in_eid_flat(int32_t r0, int32_t r1,
+                                                        const int64_t* __restrict__ orow,
+                                                        const int32_t* __restrict__ ocol,
+                                                        const int64_t* __restrict__ irow,
+                                                        const int32_t* __restrict__ icol,
+                                                        int32_t* __restrict__ ieid) {
+  const int64_t j_lo = irow[r0], j_hi = irow[r1];
+  for (int64_t j = j_lo + (int64_t)blockIdx.x * kBlock + threadIdx.x; j < j_hi;
+       j += (int64_t)gridDim.x * kBlock) {
+    int64_t lo = r0, hi = r1;     // last row r with irow[r] <= j
+    while (hi - lo > 1) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (irow[mid] <= j) lo = mid; else hi = mid;
+    }
+    const int32_t x = icol[j];
+    const int64_t b0 = orow[x];
+    ieid[j] = (int32_t)(b0 + lower_bound(ocol + b0, orow[x + 1] - b0, (int32_t)lo));
+  }
+}
+
 unsigned grid_for(int64_t items, int per_block) {
   int64_t b = cdiv(items, per_block);
   if (b < 1) b = 1;
@@ -574,7 +597,10 @@ int orient_run(int32_t n, int64_t nnz, const int64_t* rowptr, const int32_t* col
   ROWS(4, c0, c4, k_in_eid, orow, ocol, irow, icol, ieid);
   ROWS(16, c4, c16, k_in_eid, orow, ocol, irow, icol, ieid);
   ROWS(64, c16, c64, k_in_eid, orow, ocol, irow, icol, ieid);
-  ROWS(256, c64, n, k_in_eid, orow, ocol, irow, icol, ieid);
+  if (n > c64) {
+    k_in_eid_flat<<<kGrid, kBlock, 0, s>>>(c64, n, orow, ocol, irow, icol, ieid);
+    AOT_TRY(hipGetLastError());
+  }
 #undef ROWS
   (void)m;
   return 0;

@@ -1,0 +1,60 @@
+"""Parity at the benchmark's full size (R-MAT scale 20, edge factor 16, the
+graph bench.py times) in the launch configuration bench.py uses: every
+oriented array, every per-edge count and the whole triangle list equal the
+CPU oracle's (the oracle runs its own per-range procedure on host threads)."""
+
+import sys
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2006_11494_amd import aot, inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def oracle_edge_counts(o, threads=16):
+    cuts = np.linspace(0, o.m, threads + 1).astype(np.int64)
+    with ThreadPoolExecutor(threads) as ex:
+        parts = ex.map(lambda ab: oracle.edge_counts(o, int(ab[0]), int(ab[1])),
+                       zip(cuts[:-1], cuts[1:]))
+        return np.concatenate(list(parts))
+
+
+def test_rmat20_full_size():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    say("[gpu] rmat20 full size: generate on the device")
+    csr = inputs.workload("rmat20", device="cuda")
+    o = aot.alloc_oriented(csr.n, csr.m, csr.rowptr.device)
+    ows = torch.empty(aot.orient_workspace(csr.n, csr.nnz), dtype=torch.uint8, device="cuda")
+    cws = torch.empty(aot.count_workspace(csr.n, csr.m), dtype=torch.uint8, device="cuda")
+    tri_off = torch.empty(csr.m + 1, dtype=torch.int64, device="cuda")
+    aot.orient(csr.rowptr, csr.col, out=o, ws=ows)
+    c = aot.count(o, ws=cws, tri_off=tri_off)
+    out = torch.empty((c.T, 3), dtype=torch.int32, device="cuda")
+    aot.list_triangles(o, c, out=out)
+    torch.cuda.synchronize()
+    say(f"[gpu] rmat20: n={csr.n} m={csr.m} T={c.T}; oracle on host threads")
+    rp, col = csr.numpy()
+    ref = oracle.orient(rp, col)
+    assert np.array_equal(o.perm.cpu().numpy(), ref.perm)
+    assert np.array_equal(o.rowptr.cpu().numpy(), ref.orow)
+    assert np.array_equal(o.col.cpu().numpy(), ref.ocol)
+    irow, icol, ieid = oracle.in_lists(rp, col, ref)
+    assert np.array_equal(o.in_rowptr.cpu().numpy(), irow)
+    assert np.array_equal(o.in_col.cpu().numpy(), icol)
+    assert np.array_equal(o.in_eid.cpu().numpy(), ieid)
+    cnt_ref = oracle_edge_counts(ref)
+    assert np.array_equal(np.diff(c.tri_off.cpu().numpy()), cnt_ref)
+    assert c.T == int(cnt_ref.sum()) and c.probes == oracle.sum_min(ref)
+    say("[gpu] rmat20: counts equal; comparing the list")
+    tri_ref = oracle.list_triangles_parallel(ref, threads=16)
+    assert np.array_equal(out.cpu().numpy(), tri_ref)
