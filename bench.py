@@ -41,7 +41,26 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample", type=float, default=0.5,
                    help="fraction of the oriented edges the CPU oracle lists")
+    p.add_argument("--heavy-arm", default=None, choices=["bitmap", "hash", "global", "sorted"],
+                   help="force one index arm for every heavy owner class")
+    p.add_argument("--heavy-min", type=int, default=0)
+    p.add_argument("--copy-calibration", action="store_true",
+                   help="only run a plain 1 GiB read + 1 GiB write elementwise kernel, the "
+                        "reference that scales rocprofv3's FETCH_SIZE / WRITE_SIZE counters")
     return p.parse_args()
+
+
+def copy_calibration():
+    import torch
+
+    n = (1 << 30) // 4
+    src = torch.ones(n, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        torch.add(src, 1, out=dst)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration": {"read_bytes": 4 * n, "write_bytes": 4 * n,
+                                           "launches": 3}}), flush=True)
 
 
 # Algorithmic bytes of one bucket launch (what the method must move):
@@ -61,7 +80,33 @@ def kernel_of(r) -> str:
     return f"{path}<{'write' if r['pass'] == 1 else 'count'}>"
 
 
-def roofline(recs):
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("count.hip", "common.hpp", "kernels.hpp"):
+        with open(os.path.join(ROOT, "paper_2006_11494_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def profiled_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+    summary, or None when there is none for this kernel and workload or the
+    kernel source changed since it was taken."""
+    name = {"k_heavy<write>": "k_heavy_write"}.get(kernel)
+    if name is None:
+        return None
+    path = os.path.join(ROOT, "profiles", f"{name}_{workload}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        prof = json.load(f)
+    if prof.get("source_hash") != kernel_source_hash():
+        return None
+    return prof["traffic_bytes_per_launch"]
+
+
+def roofline(recs, workload: str):
     """HBM roofline of the kernel with the most recorded time."""
     per = {}
     for r in recs:
@@ -73,7 +118,8 @@ def roofline(recs):
     kern, d = max(per.items(), key=lambda kv: kv[1]["ms"])
     achieved = d["bytes"] / (d["ms"] / 1000.0) / 1e9
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": kern,
+            "frac": achieved / HBM_PEAK_GBS, "traffic": profiled_traffic(kern, workload),
+            "kernel": kern,
             "launches": d["launches"], "avg_launch_ms": d["ms"] / d["launches"],
             "bytes_per_launch": d["bytes"] / d["launches"],
             "per_unit": "4 B/probe + 4 B/staged owner-list entry + 8 B/edge"
@@ -125,6 +171,9 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration()
+        return
     import torch
 
     from paper_2006_11494_amd import aot, inputs
@@ -136,12 +185,20 @@ def main():
     torch.cuda.synchronize()
     log(f"[bench] generated {csr.name}: n={csr.n} m={csr.m} in {time.time() - t0:.1f}s")
 
+    dispatch = None
+    if args.heavy_arm or args.heavy_min:
+        table = None
+        if args.heavy_arm:
+            arm = ["bitmap", "hash", "global", "sorted"].index(args.heavy_arm)
+            table = [t << 8 for t in (4, 4, 4, 8, 16, 32, 64, 64)] + [0] * 8 + [arm] * 16
+        dispatch = aot.Dispatch(aot.AOT_DISPATCH_TABLE if table else aot.AOT_DISPATCH_PLAIN,
+                                args.heavy_min, table)
     o = aot.alloc_oriented(csr.n, csr.m, dev)
     ows = torch.empty(aot.orient_workspace(csr.n, csr.nnz), dtype=torch.uint8, device=dev)
     cws = torch.empty(aot.count_workspace(csr.n, csr.m), dtype=torch.uint8, device=dev)
     tri_off = torch.empty(csr.m + 1, dtype=torch.int64, device=dev)
     aot.orient(csr.rowptr, csr.col, out=o, ws=ows)
-    c = aot.count(o, ws=cws, tri_off=tri_off)
+    c = aot.count(o, dispatch, ws=cws, tri_off=tri_off)
     T, probes = c.T, c.probes
     out = torch.empty((max(T, 1), 3), dtype=torch.int32, device=dev)
     log(f"[bench] T={T} probes={probes}; output {T * 12 / 1e9:.2f} GB")
@@ -152,10 +209,10 @@ def main():
         aot.orient(csr.rowptr, csr.col, out=o, ws=ows)
         if ev:
             ev[1].record()
-        cc = aot.count(o, ws=cws, tri_off=tri_off)
+        cc = aot.count(o, dispatch, ws=cws, tri_off=tri_off)
         if ev:
             ev[2].record()
-        aot.list_triangles(o, cc, out=out)
+        aot.list_triangles(o, cc, out=out, dispatch=dispatch)
         if ev:
             ev[3].record()
         return cc
@@ -180,7 +237,7 @@ def main():
     log(f"[bench] step {ms_step:.3f} ms: orient {ms_orient:.3f} count {ms_count:.3f} "
         f"list {ms_list:.3f}")
 
-    roof = roofline(recs)
+    roof = roofline(recs, args.workload)
     log(f"[bench] dominant kernel {roof['kernel']}: {roof['achieved']:.1f} GB/s "
         f"({roof['frac'] * 100:.1f}% of peak) over {roof['launches']} launches")
     base = None if args.no_cpu_baseline else cpu_baseline(csr, args.cpu_sample)
@@ -200,7 +257,8 @@ def main():
         "dtype": "int32",
         "data": "synthetic",
         "config": {"workload": args.workload, "graph": csr.name, "n": csr.n, "m": csr.m,
-                   "triangles": T, "probes": probes, "dispatch": "plain"},
+                   "triangles": T, "probes": probes,
+                   "dispatch": args.heavy_arm or "plain", "heavy_min": args.heavy_min or 32},
         "probes_per_s": probes / (ms_count / 1000.0),
         "ms_orient": ms_orient,
         "ms_count": ms_count,

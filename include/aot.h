@@ -86,7 +86,6 @@ typedef struct aot_oriented {
   int32_t* rank;       /* [n]   original id -> rank                                 */
   int64_t* in_rowptr;  /* [n+1] in-list offsets                                     */
   int32_t* in_col;     /* [m]   in-neighbour ranks, in ascending ORIGINAL id        */
-  int32_t* in_eid;     /* [m]   id (index into col) of the edge <in_col[j], r>      */
 } aot_oriented;
 
 /* ------------------------------------------------------------------------

@@ -48,7 +48,7 @@ class OrientedC(ctypes.Structure):
                 ("rowptr", ctypes.c_void_p), ("col", ctypes.c_void_p),
                 ("tail", ctypes.c_void_p), ("perm", ctypes.c_void_p),
                 ("rank", ctypes.c_void_p), ("in_rowptr", ctypes.c_void_p),
-                ("in_col", ctypes.c_void_p), ("in_eid", ctypes.c_void_p)]
+                ("in_col", ctypes.c_void_p)]
 
 
 class TimingC(ctypes.Structure):
@@ -128,12 +128,11 @@ class Oriented:
     rank: torch.Tensor
     in_rowptr: torch.Tensor
     in_col: torch.Tensor
-    in_eid: torch.Tensor
 
     def cstruct(self) -> OrientedC:
         return OrientedC(self.n, self.m, _ptr(self.rowptr), _ptr(self.col), _ptr(self.tail),
                          _ptr(self.perm), _ptr(self.rank), _ptr(self.in_rowptr),
-                         _ptr(self.in_col), _ptr(self.in_eid))
+                         _ptr(self.in_col))
 
     @property
     def dplus(self) -> torch.Tensor:
@@ -183,7 +182,7 @@ def alloc_oriented(n: int, m: int, device) -> Oriented:
     i64 = dict(dtype=torch.int64, device=device)
     return Oriented(n, m, torch.empty(n + 1, **i64), torch.empty(m, **i32),
                     torch.empty(m, **i32), torch.empty(n, **i32), torch.empty(n, **i32),
-                    torch.empty(n + 1, **i64), torch.empty(m, **i32), torch.empty(m, **i32))
+                    torch.empty(n + 1, **i64), torch.empty(m, **i32))
 
 
 def orient(rowptr: torch.Tensor, col: torch.Tensor, validate: bool = False, stream=None,

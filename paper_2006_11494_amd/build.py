@@ -33,27 +33,28 @@ def sources():
                   if f.endswith(".hip") or f.endswith(".cpp"))
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(OBJDIR, os.path.basename(src) + ".o")
-    cmd = ["hipcc", *FLAGS, "-x", "hip", "-c", src, "-o", obj]
+def _compile(src: str, objdir: str = OBJDIR, defines=()) -> str:
+    obj = os.path.join(objdir, os.path.basename(src) + ".o")
+    cmd = ["hipcc", *FLAGS, *[f"-D{d}" for d in defines], "-x", "hip", "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed on {src}:\n{r.stderr}")
     return obj
 
 
-def build(jobs: int = 8) -> str:
-    """Compiles every source (always) and links libaot.so; returns its path."""
-    os.makedirs(OBJDIR, exist_ok=True)
+def build(jobs: int = 8, lib: str = LIB, objdir: str = OBJDIR, defines=()) -> str:
+    """Compiles every source (always) and links the library (default
+    libaot.so next to this file); `defines` are extra -D tunables."""
+    os.makedirs(objdir, exist_ok=True)
     with ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(_compile, sources()))
-    tmp = LIB + ".tmp"
+        objs = list(ex.map(lambda s: _compile(s, objdir, defines), sources()))
+    tmp = lib + ".tmp"
     cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":

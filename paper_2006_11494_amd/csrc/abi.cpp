@@ -33,7 +33,7 @@ int check_oriented(const aot_oriented* g) {
   if (g->n < 0 || g->m < 0) return fail(AOT_E_ARG, "negative n or m");
   if (g->m > INT32_MAX) return fail(AOT_E_OVERFLOW, "m exceeds INT32_MAX edge ids");
   if (!g->rowptr || !g->in_rowptr) return fail(AOT_E_ARG, "rowptr / in_rowptr is NULL");
-  if (g->m > 0 && (!g->col || !g->tail || !g->in_col || !g->in_eid))
+  if (g->m > 0 && (!g->col || !g->tail || !g->in_col))
     return fail(AOT_E_ARG, "an edge array of the oriented graph is NULL");
   if (g->n > 0 && (!g->perm || !g->rank)) return fail(AOT_E_ARG, "perm / rank is NULL");
   return AOT_OK;
@@ -105,7 +105,7 @@ int aot_orient(const aot_graph* g, uint32_t flags, aot_oriented* out, void* ws, 
   const int64_t m = g->nnz / 2;
   if (!out->rowptr || !out->in_rowptr) return fail(AOT_E_ARG, "output rowptr is NULL");
   if (g->n > 0 && (!out->perm || !out->rank)) return fail(AOT_E_ARG, "output perm/rank is NULL");
-  if (m > 0 && (!out->col || !out->tail || !out->in_col || !out->in_eid))
+  if (m > 0 && (!out->col || !out->tail || !out->in_col))
     return fail(AOT_E_ARG, "an output edge array is NULL");
   const size_t need = aot::orient_workspace_bytes(g->n, g->nnz);
   if (ws_bytes < need || (!ws && need > 0))
@@ -115,7 +115,7 @@ int aot_orient(const aot_graph* g, uint32_t flags, aot_oriented* out, void* ws, 
   const char* err = nullptr;
   rc = aot::orient_run(g->n, g->nnz, g->rowptr, g->col, (flags & AOT_VALIDATE) != 0, out->rowptr,
                        out->col, out->tail, out->perm, out->rank, out->in_rowptr, out->in_col,
-                       out->in_eid, ws, ws_bytes, static_cast<hipStream_t>(stream), &err);
+                       ws, ws_bytes, static_cast<hipStream_t>(stream), &err);
   return hip_status(rc, err);
 }
 
@@ -138,8 +138,8 @@ int aot_count(const aot_oriented* g, const aot_dispatch* d, int64_t* tri_off, vo
   const size_t need = aot::count_workspace_bytes(g->n, g->m);
   if (ws_bytes < need || !ws) return fail(AOT_E_WORKSPACE, "count workspace smaller than aot_count_workspace()");
   const char* err = nullptr;
-  rc = aot::count_run(g->n, g->m, g->rowptr, g->col, g->tail, g->in_rowptr, g->in_col, g->in_eid,
-                      dv, tri_off, ws, ws_bytes, result, static_cast<hipStream_t>(stream), &err);
+  rc = aot::count_run(g->n, g->m, g->rowptr, g->col, g->tail, g->in_rowptr, g->in_col, dv,
+                      tri_off, ws, ws_bytes, result, static_cast<hipStream_t>(stream), &err);
   return hip_status(rc, err);
 }
 
@@ -160,7 +160,7 @@ int aot_list(const aot_oriented* g, const aot_dispatch* d, const int64_t* tri_of
   hipStream_t s = static_cast<hipStream_t>(stream);
   const char* err = nullptr;
   rc = aot::list_run(g->n, g->m, g->rowptr, g->col, g->tail, g->perm, g->in_rowptr, g->in_col,
-                     g->in_eid, dv, tri_off, ws, ws_bytes, first, count, out, s, &err);
+                     dv, tri_off, ws, ws_bytes, first, count, out, s, &err);
   if (rc) return hip_status(rc, err);
   if (written) {
     int64_t t = 0;

@@ -37,7 +37,13 @@ constexpr int kHeavyClasses = 16;   // owner classes by ceil(log2 deg+(b))
 constexpr int kHeavyBase = 16;      // bucket id of heavy class 0
 constexpr int kItemSpan = 512;      // neighbours of one owner per work item
 constexpr int kMaxIndexWords = 12288;  // LDS index cap: 48 KiB (bitmap window of 393216 ids)
-constexpr int kUnroll = 4;          // probes per lane per window step
+#ifndef AOT_PROBE_UNROLL
+#define AOT_PROBE_UNROLL 4
+#endif
+#ifndef AOT_CHAINED_CURSOR
+#define AOT_CHAINED_CURSOR 1
+#endif
+constexpr int kUnroll = AOT_PROBE_UNROLL;   // 64-probe windows a wave keeps in flight
 constexpr int kGrid = 4096;
 constexpr int kDefaultHeavyMin = 32;
 
@@ -115,36 +121,39 @@ __global__ __launch_bounds__(kBlock) void k_bin_count(int64_t m, const int64_t* 
   }
 }
 
-// Light edges into their bins; one global atomic per wave and bin.
+// Light edges into their bins.  A block takes a contiguous chunk of edges,
+// counts its bins in LDS, reserves its ranges with one global atomic per bin,
+// then scatters with LDS cursors.
+constexpr int kScatterChunk = 8192;
 __global__ __launch_bounds__(kBlock) void k_bin_scatter(int64_t m, const uint8_t* __restrict__ code,
                                                         int64_t* __restrict__ stats,
                                                         int32_t* __restrict__ elist) {
   __shared__ int64_t base[kLightBins];
-  if (threadIdx.x == 0) {
-    int64_t run = 0;
-    for (int q = 0; q < kLightBins; ++q) { base[q] = run; run += stats[q * kStats + kSEdges]; }
-  }
-  __syncthreads();
-  const int64_t step = (int64_t)gridDim.x * kBlock;
-  for (int64_t e0 = (int64_t)blockIdx.x * kBlock; e0 < m; e0 += step) {
-    const int64_t e = e0 + threadIdx.x;
-    int bin = -1;
-    if (e < m) {
+  __shared__ int32_t cnt[kLightBins], cur[kLightBins];
+  for (int64_t c0 = (int64_t)blockIdx.x * kScatterChunk; c0 < m;
+       c0 += (int64_t)gridDim.x * kScatterChunk) {
+    const int64_t c1 = min(m, c0 + kScatterChunk);
+    if (threadIdx.x < kLightBins) { cnt[threadIdx.x] = 0; cur[threadIdx.x] = 0; }
+    __syncthreads();
+    for (int64_t e = c0 + threadIdx.x; e < c1; e += kBlock) {
       const int c = code[e];
-      if (c != 0xFF) bin = c;
+      if (c != 0xFF) atomicAdd(&cnt[c], 1);
     }
-    if (!ballot(bin >= 0)) continue;
-    for (int k = 0; k < kLightBins; ++k) {
-      const uint64_t mask = ballot(bin == k);
-      if (!mask) continue;
-      const int leader = __ffsll((long long)mask) - 1;
-      long long at = 0;
-      if (lane_id() == leader)
-        at = (long long)atomicAdd(u64p(&stats[k * kStats + kSCursor]),
-                                  (unsigned long long)__popcll(mask));
-      at = __shfl(at, leader, kWave);
-      if (bin == k) elist[base[k] + at + popc_below(mask)] = (int32_t)e;
+    __syncthreads();
+    if (threadIdx.x < kLightBins) {
+      int64_t bin_base = 0;
+      for (int q = 0; q < (int)threadIdx.x; ++q) bin_base += stats[q * kStats + kSEdges];
+      const int32_t k = cnt[threadIdx.x];
+      base[threadIdx.x] = bin_base + (k ? (int64_t)atomicAdd(u64p(&stats[threadIdx.x * kStats + kSCursor]),
+                                                             (unsigned long long)k)
+                                        : 0);
     }
+    __syncthreads();
+    for (int64_t e = c0 + threadIdx.x; e < c1; e += kBlock) {
+      const int c = code[e];
+      if (c != 0xFF) elist[base[c] + atomicAdd(&cur[c], 1)] = (int32_t)e;
+    }
+    __syncthreads();
   }
 }
 
@@ -352,7 +361,6 @@ struct HeavyArgs {
   const int32_t* ocol;
   const int64_t* irow;
   const int32_t* icol;
-  const int32_t* ieid;
   int32_t* cnt;                 // count pass
   int64_t* tri_stat;            // count pass: the bucket's triangle total
   const int64_t* tri_off;       // write pass
@@ -363,7 +371,7 @@ struct HeavyArgs {
 
 template <bool kEmit>
 struct HeavyShared {
-  int64_t nb_oy[kItemSpan];
+  int32_t nb_src[kItemSpan];          // start of N+(y) minus its probe prefix (int32: m <= INT32_MAX)
   int64_t nb_base[kEmit ? kItemSpan : 1];
   int32_t nb_pre[kItemSpan + 1];
   int32_t nb_e[kItemSpan];
@@ -398,94 +406,145 @@ __device__ __forceinline__ int segment_rank(bool valid, int k, uint64_t hm, int*
   return rank;
 }
 
+// The probes of kUnroll consecutive 64-probe windows starting at w0: each
+// lane finds the neighbour of its probe with a cursor chained across the
+// windows (usually one LDS read: the probe lies in the same out-list as the
+// previous one) and issues the load of the probed id.  kk = -1 marks lanes
+// at or past `end`.
+struct Windows {
+  int kk[kUnroll];
+  int32_t wv[kUnroll];
+};
+
+__device__ __forceinline__ void load_windows(Windows& W, const int32_t* pre, const int32_t* src,
+                                             const int32_t* __restrict__ ocol, int& kc, int kend,
+                                             int32_t w0, int32_t end) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int u = 0; u < kUnroll; ++u) {
+    const int32_t p = w0 + u * kWave + lane;
+    W.kk[u] = p < end ? advance(pre, kc, kend, p) : -1;
+    if (W.kk[u] >= 0) kc = W.kk[u];
+  }
+#pragma unroll
+  for (int u = 0; u < kUnroll; ++u) {
+    const int32_t p = w0 + u * kWave + lane;
+    W.wv[u] = W.kk[u] >= 0 ? ocol[src[W.kk[u]] + p] : 0;
+  }
+}
+
 // Count pass over one item's compacted neighbours (K of them, P probes):
-// waves take interleaved windows of 64 probes, each lane keeps a cursor into
-// the neighbours, and hits are summed per neighbour segment of a window.
+// waves take interleaved runs of kUnroll windows.  A window
+// inside one out-list adds the popcount of its hit ballot to a wave-uniform
+// accumulator, flushed to LDS when the neighbour changes; a window across a
+// boundary sums hits per neighbour segment.
 template <int ARM>
 __device__ int64_t probe_count(HeavyShared<false>& sh, const uint32_t* lds, const HeavyArgs& a,
                                const Index& ix, int K, int32_t P) {
   const int wave = threadIdx.x / kWave;
   const int lane = lane_id();
+  constexpr int32_t kStride = kBlock * kUnroll;
   int kc = 0;
-  int64_t hits_lane = 0;
-  for (int32_t w0 = wave * kWave * kUnroll; w0 < P; w0 += kBlock * kUnroll) {
-    int32_t wv[kUnroll];
-    int kk[kUnroll];
+  int64_t hits_wave = 0;
+  int acc_k = -1;     // wave-uniform: neighbour being accumulated
+  int acc = 0;        // and its hits so far
+  for (int32_t w0 = wave * kWave * kUnroll; w0 < P; w0 += kStride) {
+    Windows cur;
+    load_windows(cur, sh.nb_pre, sh.nb_src, a.ocol, kc, K, w0, P);
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
-      const int32_t p = w0 + u * kWave + lane;
-      kk[u] = -1;
-      wv[u] = 0;
-      if (p < P) {
-        kc = advance(sh.nb_pre, kc, K, p);
-        kk[u] = kc;
-        wv[u] = a.ocol[sh.nb_oy[kc] + (p - sh.nb_pre[kc])];
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
-      const bool valid = kk[u] >= 0;
-      const bool hit = valid && index_has<ARM>(ix, lds, wv[u]);
-      hits_lane += hit;
+      const bool valid = cur.kk[u] >= 0;
+      const bool hit = valid && index_has<ARM>(ix, lds, cur.wv[u]);
       const uint64_t hm = ballot(hit);
       if (!hm) continue;
-      int tot;
-      bool first;
-      segment_rank(valid, kk[u], hm, &tot, &first);
-      if (first && tot) atomicAdd(&sh.nb_acc[kk[u]], tot);
+      const int c = (int)__popcll(hm);
+      hits_wave += c;
+      const uint64_t vm = ballot(valid);
+      const int k0 = __builtin_amdgcn_readfirstlane(cur.kk[u]);
+      const int k1 = __builtin_amdgcn_readlane(cur.kk[u], 63 - __clzll((long long)vm));
+      if (k0 == k1) {
+        if (k0 == acc_k) {
+          acc += c;
+        } else {
+          if (acc_k >= 0 && lane == 0) atomicAdd(&sh.nb_acc[acc_k], acc);
+          acc_k = k0;
+          acc = c;
+        }
+      } else {
+        if (acc_k >= 0 && lane == 0 && acc) atomicAdd(&sh.nb_acc[acc_k], acc);
+        acc_k = -1;
+        acc = 0;
+        int tot;
+        bool first;
+        segment_rank(valid, cur.kk[u], hm, &tot, &first);
+        if (first && tot) atomicAdd(&sh.nb_acc[cur.kk[u]], tot);
+      }
     }
   }
-  return hits_lane;
+  if (acc_k >= 0 && lane == 0 && acc) atomicAdd(&sh.nb_acc[acc_k], acc);
+  return lane == 0 ? hits_wave : 0;
 }
 
 // Write pass over one item's compacted neighbours.  Each wave owns a run of
 // whole neighbours holding about a quarter of the probes and walks it in
-// order, so an edge's hits are ranked by probe order inside one wave: the
-// rank is the edge's running count (LDS, touched by this wave only) plus the
-// hits of its segment in lower lanes of the window.
+// order, so an edge's hits are
+// ranked by probe order inside one wave, with the running count of the
+// current edge in a wave-uniform register.  In a window inside one out-list
+// a hit's rank is its count of hitting lanes below it; a window across a
+// boundary ranks hits per segment.
 template <int ARM>
 __device__ void probe_emit(HeavyShared<true>& sh, const uint32_t* lds, const HeavyArgs& a,
                            const Index& ix, int K, int32_t P, int32_t pb) {
   const int wave = threadIdx.x / kWave;
-  const int lane = lane_id();
   const int k_lo = sh.wave_k[wave], k_hi = sh.wave_k[wave + 1];
   if (k_lo >= k_hi) return;
   const int32_t p_lo = sh.nb_pre[k_lo], p_hi = sh.nb_pre[k_hi];
+  const int32_t* __restrict__ perm = a.perm;
+  constexpr int32_t kStride = kWave * kUnroll;
   int kc = k_lo;
-  for (int32_t w0 = p_lo; w0 < p_hi; w0 += kWave * kUnroll) {
-    int32_t wv[kUnroll];
-    int kk[kUnroll];
+  int run_k = -1;     // wave-uniform: edge whose hits are being ranked
+  int run = 0;        // hits of run_k emitted so far
+  for (int32_t w0 = p_lo; w0 < p_hi; w0 += kStride) {
+    Windows cur;
+    load_windows(cur, sh.nb_pre, sh.nb_src, a.ocol, kc, k_hi, w0, p_hi);
+    bool hit[kUnroll];
+    int32_t third[kUnroll];
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
-      const int32_t p = w0 + u * kWave + lane;
-      kk[u] = -1;
-      wv[u] = 0;
-      if (p < p_hi) {
-        kc = advance(sh.nb_pre, kc, k_hi, p);
-        kk[u] = kc;
-        wv[u] = a.ocol[sh.nb_oy[kc] + (p - sh.nb_pre[kc])];
-      }
+      hit[u] = cur.kk[u] >= 0 && index_has<ARM>(ix, lds, cur.wv[u]);
+      third[u] = hit[u] ? perm[cur.wv[u]] : 0;      // gathers issued before any store
     }
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
-      const bool valid = kk[u] >= 0;
-      const bool hit = valid && index_has<ARM>(ix, lds, wv[u]);
-      const uint64_t hm = ballot(hit);
+      const bool valid = cur.kk[u] >= 0;
+      const uint64_t hm = ballot(hit[u]);
       if (!hm) continue;
-      int tot;
-      bool first;
-      const int rank = segment_rank(valid, kk[u], hm, &tot, &first);
-      if (hit) {
-        const int k = kk[u];
-        const int64_t pos = sh.nb_base[k] + sh.nb_acc[k] + rank;
-        if (pos >= a.first && pos < a.first + a.count) {
-          int32_t t0 = pb, t1 = sh.nb_py[k], t2 = a.perm[wv[u]];
-          sort3(t0, t1, t2);
-          int32_t* o = a.out + 3 * (pos - a.first);
-          o[0] = t0; o[1] = t1; o[2] = t2;
-        }
+      const uint64_t vm = ballot(valid);
+      const int k0 = __builtin_amdgcn_readfirstlane(cur.kk[u]);
+      const int k1 = __builtin_amdgcn_readlane(cur.kk[u], 63 - __clzll((long long)vm));
+      int64_t pos;
+      int k;
+      if (k0 == k1) {
+        k = k0;
+        if (k != run_k) { run_k = k; run = 0; }
+        pos = sh.nb_base[k] + run + popc_below(hm);
+        run += (int)__popcll(hm);
+      } else {
+        int tot;
+        bool first;
+        k = cur.kk[u];
+        const int rank = segment_rank(valid, k, hm, &tot, &first);
+        pos = sh.nb_base[k] + (k == run_k ? run : 0) + rank;
+        const int last_hits = (int)__popcll(hm & ballot(valid && k == k1));
+        run = (k1 == run_k ? run : 0) + last_hits;
+        run_k = k1;
       }
-      if (first && tot) sh.nb_acc[kk[u]] += tot;   // read above by this wave only
+      if (hit[u] && pos >= a.first && pos < a.first + a.count) {
+        int32_t t0 = pb, t1 = sh.nb_py[k], t2 = third[u];
+        sort3(t0, t1, t2);
+        int32_t* o = a.out + 3 * (pos - a.first);
+        o[0] = t0; o[1] = t1; o[2] = t2;
+      }
     }
   }
 }
@@ -533,12 +592,15 @@ __global__ __launch_bounds__(kBlock) void k_heavy(HeavyArgs a) {
       nd[i] = 0;
       ny[i] = 0; ne[i] = 0; noy[i] = 0; nbase[i] = 0;
       if (j < j1) {
-        int32_t y, e;
-        if (j < db) { y = a.ocol[ob + j]; e = (int32_t)(ob + j); }
-        else { y = a.icol[ib + (j - db)]; e = a.ieid[ib + (j - db)]; }
+        int32_t y, e = 0;
+        const bool out_edge = j < db;
+        if (out_edge) { y = a.ocol[ob + j]; e = (int32_t)(ob + j); }
+        else y = a.icol[ib + (j - db)];
         const int64_t oy = a.orow[y];
         const int32_t dy = (int32_t)(a.orow[y + 1] - oy);
         const bool owned = dy < db || (dy == db && y < b);
+        // an owned in-edge <y, b>: its id is b's place in N+(y), the list probed next
+        if (owned && !out_edge) e = (int32_t)(oy + lower_bound(a.ocol + oy, dy, b));
         ny[i] = y; ne[i] = e; noy[i] = oy; nd[i] = dy;
         if constexpr (!kEmit) {
           if (owned && dy == 0) a.cnt[e] = 0;
@@ -561,7 +623,7 @@ __global__ __launch_bounds__(kBlock) void k_heavy(HeavyArgs a) {
     for (int i = 0; i < kPer; ++i) {
       if (keep[i]) {
         const int slot = (int)(at >> 32);
-        sh.nb_oy[slot] = noy[i];
+        sh.nb_src[slot] = (int32_t)(noy[i] - (at & 0xFFFFFFFF));
         sh.nb_pre[slot] = (int32_t)(at & 0xFFFFFFFF);
         sh.nb_e[slot] = ne[i];
         sh.nb_acc[slot] = 0;
@@ -791,7 +853,7 @@ unsigned grid_cap(int64_t work_units) {
 // the timing recorder is on.
 int run_buckets(bool emit, const Plan& plan, const int64_t* hs, const CountWs& w,
                 const int64_t* orow, const int32_t* ocol, const int32_t* otail,
-                const int32_t* perm, const int64_t* irow, const int32_t* icol, const int32_t* ieid,
+                const int32_t* perm, const int64_t* irow, const int32_t* icol,
                 const int64_t* tri_off, int64_t first, int64_t count, int32_t* out, hipStream_t s,
                 const char** err) {
   int64_t lbase = 0;
@@ -826,7 +888,7 @@ int run_buckets(bool emit, const Plan& plan, const int64_t* hs, const CountWs& w
     a.items = w.items;
     a.item_base = st[kSItemBase];
     a.item_count = items;
-    a.orow = orow; a.ocol = ocol; a.irow = irow; a.icol = icol; a.ieid = ieid;
+    a.orow = orow; a.ocol = ocol; a.irow = irow; a.icol = icol;
     a.cnt = w.cnt;
     a.tri_stat = w.stats + (kHeavyBase + h) * kStats + kSTriangles;
     a.tri_off = tri_off;
@@ -854,8 +916,7 @@ size_t count_workspace_bytes(int32_t n, int64_t m) {
 }
 
 int count_run(int32_t n, int64_t m, const int64_t* orow, const int32_t* ocol, const int32_t* otail,
-              const int64_t* irow, const int32_t* icol, const int32_t* ieid,
-              const DispatchView& d, int64_t* tri_off, void* ws, size_t ws_bytes,
+              const int64_t* irow, const int32_t* icol, const DispatchView& d, int64_t* tri_off, void* ws, size_t ws_bytes,
               uint64_t* result, hipStream_t s, const char** err) {
   Carve c(ws, ws_bytes);
   CountWs w = carve_count(c, n, m);
@@ -877,7 +938,7 @@ int count_run(int32_t n, int64_t m, const int64_t* orow, const int32_t* ocol, co
     k_bin_count<<<ge, kBlock, 0, s>>>(m, orow, ocol, otail, heavy_min, w.cnt, w.code, w.stats,
                                       w.probes);
     AOT_TRY(hipGetLastError());
-    k_bin_scatter<<<grid_cap(std::min<int64_t>(cdiv(m, kBlock), 4096)), kBlock, 0, s>>>(
+    k_bin_scatter<<<grid_cap(std::min<int64_t>(cdiv(m, kScatterChunk), 4096)), kBlock, 0, s>>>(
         m, w.code, w.stats, w.elist);
     AOT_TRY(hipGetLastError());
     const unsigned gv = grid_cap(std::min<int64_t>(cdiv(n, kBlock), 1024));
@@ -889,7 +950,7 @@ int count_run(int32_t n, int64_t m, const int64_t* orow, const int32_t* ocol, co
                            hipMemcpyDeviceToHost, s));
     AOT_TRY(hipStreamSynchronize(s));
     const int rc = run_buckets(false, plan, hs.data(), w, orow, ocol, otail, nullptr, irow, icol,
-                               ieid, nullptr, 0, 0, nullptr, s, err);
+                               nullptr, 0, 0, nullptr, s, err);
     if (rc) return rc;
   }
   AOT_TRY(exclusive_scan(w.cnt, tri_off, m, w.scan_tmp, s));
@@ -907,7 +968,7 @@ int count_run(int32_t n, int64_t m, const int64_t* orow, const int32_t* ocol, co
 }
 
 int list_run(int32_t n, int64_t m, const int64_t* orow, const int32_t* ocol, const int32_t* otail,
-             const int32_t* perm, const int64_t* irow, const int32_t* icol, const int32_t* ieid,
+             const int32_t* perm, const int64_t* irow, const int32_t* icol,
              const DispatchView& d, const int64_t* tri_off, void* ws, size_t ws_bytes,
              int64_t first, int64_t count, int32_t* out, hipStream_t s, const char** err) {
   Carve c(ws, ws_bytes);
@@ -926,7 +987,7 @@ int list_run(int32_t n, int64_t m, const int64_t* orow, const int32_t* ocol, con
   AOT_TRY(hipMemcpyAsync(hs.data(), w.stats, sizeof(int64_t) * kStatWords, hipMemcpyDeviceToHost,
                          s));
   AOT_TRY(hipStreamSynchronize(s));
-  return run_buckets(true, plan, hs.data(), w, orow, ocol, otail, perm, irow, icol, ieid, tri_off,
+  return run_buckets(true, plan, hs.data(), w, orow, ocol, otail, perm, irow, icol, tri_off,
                      first, count, out, s, err);
 }
 

@@ -60,8 +60,8 @@ struct OrientScratch {
 size_t orient_workspace_bytes(int32_t n, int64_t nnz);
 int orient_run(int32_t n, int64_t nnz, const int64_t* rowptr, const int32_t* col, bool validate,
                int64_t* orow, int32_t* ocol, int32_t* otail, int32_t* perm, int32_t* rank,
-               int64_t* irow, int32_t* icol, int32_t* ieid, void* ws, size_t ws_bytes,
-               hipStream_t s, const char** err);
+               int64_t* irow, int32_t* icol, void* ws, size_t ws_bytes, hipStream_t s,
+               const char** err);
 
 // ---- timing.cpp: the per-launch recorder of the probe passes.  A record is
 // opened just before a bucket's kernel launch and closed right after it,
@@ -80,12 +80,10 @@ struct DispatchView {
   const int32_t* table;  // host, kNumBuckets codes or nullptr
 };
 int count_run(int32_t n, int64_t m, const int64_t* orow, const int32_t* ocol, const int32_t* otail,
-              const int64_t* irow, const int32_t* icol, const int32_t* ieid,
-              const DispatchView& d, int64_t* tri_off, void* ws, size_t ws_bytes,
+              const int64_t* irow, const int32_t* icol, const DispatchView& d, int64_t* tri_off, void* ws, size_t ws_bytes,
               uint64_t* result, hipStream_t s, const char** err);
 int list_run(int32_t n, int64_t m, const int64_t* orow, const int32_t* ocol, const int32_t* otail,
-             const int32_t* perm, const int64_t* irow, const int32_t* icol, const int32_t* ieid,
-             const DispatchView& d, const int64_t* tri_off, void* ws, size_t ws_bytes,
+             const int32_t* perm, const int64_t* irow, const int32_t* icol, const DispatchView& d, const int64_t* tri_off, void* ws, size_t ws_bytes,
              int64_t first, int64_t count, int32_t* out, hipStream_t s, const char** err);
 
 }  // namespace aot

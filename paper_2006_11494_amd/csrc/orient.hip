@@ -1,6 +1,7 @@
 // Orientation (Section 2.2, "Orientation technique"; first step of Algorithm
 // 3): rank vertices by (degree, id) ascending, keep <u,v> iff rank(u) <
-// rank(v), relabel to rank space and sort every out-list ascending.
+// rank(v), relabel to rank space and sort every out-list ascending; the
+// in-lists Algorithm 3's second loop walks are the rest of each row.
 //
 // After the radix sort, rank order is degree order, so consecutive ranks have
 // similar row lengths: rows are processed in rank ranges with a row-group
@@ -412,52 +413,6 @@ __global__ __launch_bounds__(kBlock) void k_sort_bitmap(int cls, const int32_t* 
   }
 }
 
-// in_eid[j] = index of edge <x, r> in the out-lists, for in-entry x of row r.
-template <int G>
-__global__ __launch_bounds__(kBlock) void k_in_eid(int32_t r0, int32_t r1,
-                                                   const int64_t* __restrict__ orow,
-                                                   const int32_t* __restrict__ ocol,
-                                                   const int64_t* __restrict__ irow,
-                                                   const int32_t* __restrict__ icol,
-                                                   int32_t* __restrict__ ieid) {
-  constexpr int kGroups = kBlock / G;
-  const int gi = threadIdx.x / G, li = threadIdx.x % G;
-  for (int64_t rb = r0 + (int64_t)blockIdx.x * kGroups; rb < r1;
-       rb += (int64_t)gridDim.x * kGroups) {
-    const int64_t r = rb + gi;
-    if (r >= r1) continue;
-    const int64_t ib = irow[r], ie = irow[r + 1];
-    for (int64_t j = ib + li; j < ie; j += G) {
-      const int32_t x = icol[j];
-      const int64_t b0 = orow[x];
-      ieid[j] = (int32_t)(b0 + lower_bound(ocol + b0, orow[x + 1] - b0, (int32_t)r));
-    }
-  }
-}
-
-// The same for the rows [r0, r1) of the longest degree class, flattened over
-// their in-entries (a thread per entry, its row found by binary search) so
-// that a hub's in-list is spread over the whole grid.
-__global__ __launch_bounds__(kBlock) void k_in_eid_flat(int32_t r0, int32_t r1,
-                                                        const int64_t* __restrict__ orow,
-                                                        const int32_t* __restrict__ ocol,
-                                                        const int64_t* __restrict__ irow,
-                                                        const int32_t* __restrict__ icol,
-                                                        int32_t* __restrict__ ieid) {
-  const int64_t j_lo = irow[r0], j_hi = irow[r1];
-  for (int64_t j = j_lo + (int64_t)blockIdx.x * kBlock + threadIdx.x; j < j_hi;
-       j += (int64_t)gridDim.x * kBlock) {
-    int64_t lo = r0, hi = r1;     // last row r with irow[r] <= j
-    while (hi - lo > 1) {
-      const int64_t mid = (lo + hi) >> 1;
-      if (irow[mid] <= j) lo = mid; else hi = mid;
-    }
-    const int32_t x = icol[j];
-    const int64_t b0 = orow[x];
-    ieid[j] = (int32_t)(b0 + lower_bound(ocol + b0, orow[x + 1] - b0, (int32_t)lo));
-  }
-}
-
 unsigned grid_for(int64_t items, int per_block) {
   int64_t b = cdiv(items, per_block);
   if (b < 1) b = 1;
@@ -499,8 +454,8 @@ size_t orient_workspace_bytes(int32_t n, int64_t nnz) {
 
 int orient_run(int32_t n, int64_t nnz, const int64_t* rowptr, const int32_t* col, bool validate,
                int64_t* orow, int32_t* ocol, int32_t* otail, int32_t* perm, int32_t* rank,
-               int64_t* irow, int32_t* icol, int32_t* ieid, void* ws, size_t ws_bytes,
-               hipStream_t s, const char** err) {
+               int64_t* irow, int32_t* icol, void* ws, size_t ws_bytes, hipStream_t s,
+               const char** err) {
   const int64_t m = nnz / 2;
   Carve c(ws, ws_bytes);
   int32_t* key_a = c.take<int32_t>(n);
@@ -594,15 +549,7 @@ int orient_run(int32_t n, int64_t nnz, const int64_t* rowptr, const int32_t* col
   k_sort_bitmap<<<512, kBlock, 0, s>>>(3, counters, rows, orow, unsorted, ocol);
   AOT_TRY(hipGetLastError());
 
-  ROWS(4, c0, c4, k_in_eid, orow, ocol, irow, icol, ieid);
-  ROWS(16, c4, c16, k_in_eid, orow, ocol, irow, icol, ieid);
-  ROWS(64, c16, c64, k_in_eid, orow, ocol, irow, icol, ieid);
-  if (n > c64) {
-    k_in_eid_flat<<<kGrid, kBlock, 0, s>>>(c64, n, orow, ocol, irow, icol, ieid);
-    AOT_TRY(hipGetLastError());
-  }
 #undef ROWS
-  (void)m;
   return 0;
 }
 

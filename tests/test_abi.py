@@ -62,10 +62,10 @@ FAKE = ctypes.c_void_p(0x1000)   # never dereferenced: every case fails its chec
 
 def oriented(n=4, m=3, **kw):
     f = dict(rowptr=FAKE, col=FAKE, tail=FAKE, perm=FAKE, rank=FAKE, in_rowptr=FAKE,
-             in_col=FAKE, in_eid=FAKE)
+             in_col=FAKE)
     f.update(kw)
     return aot.OrientedC(n, m, *[f[k] for k in ("rowptr", "col", "tail", "perm", "rank",
-                                                "in_rowptr", "in_col", "in_eid")])
+                                                "in_rowptr", "in_col")])
 
 
 def test_orient_argument_errors():

@@ -65,7 +65,6 @@ def check_orientation(o_gpu, ref):
     assert np.array_equal(h(o_gpu.tail), o.tail())
     assert np.array_equal(h(o_gpu.in_rowptr), irow)
     assert np.array_equal(h(o_gpu.in_col), icol)
-    assert np.array_equal(h(o_gpu.in_eid), ieid)
 
 
 def check_all(csr, name, dispatches=DISPATCHES, windows=True):
@@ -198,7 +197,7 @@ def test_determinism_and_streams():
     c1 = aot.count(o1)
     t1 = aot.list_triangles(o1, c1)
     torch.cuda.synchronize()
-    for f in ("rowptr", "col", "tail", "perm", "rank", "in_rowptr", "in_col", "in_eid"):
+    for f in ("rowptr", "col", "tail", "perm", "rank", "in_rowptr", "in_col"):
         assert torch.equal(getattr(o1, f), getattr(o2, f)), f
     assert torch.equal(c1.tri_off, c2.tri_off) and torch.equal(t1, t2)
 
