@@ -163,6 +163,22 @@ int aot_list(const aot_oriented* g, const aot_dispatch* d, const int64_t* tri_of
              int32_t* out, int64_t* written, void* stream);
 
 /* ------------------------------------------------------------------------
+ * aot_digest -- validation mode of the write pass: the same triangles
+ * aot_list would emit (each triangle exactly once, Section 3.2 Correctness),
+ * digested instead of stored, for graphs whose list does not fit a buffer.
+ * Each ascending triple (a, b, c) of original ids hashes to
+ *     h = sm(sm(sm(a) ^ b) ^ c),  sm = SplitMix64's output function
+ * and the digest is {number of triangles, sum of h mod 2^64, xor of h}.
+ *   tri_off, ws   from a prior aot_count on the same graph.
+ *   vertex_counts device uint64[n] or NULL: overwritten with the number of
+ *                 triangles through each ORIGINAL vertex id (they sum to 3T).
+ *   digest        host uint64[3], written.
+ * Synchronises `stream`. */
+int aot_digest(const aot_oriented* g, const aot_dispatch* d, const int64_t* tri_off,
+               void* ws, size_t ws_bytes, uint64_t* vertex_counts, uint64_t* digest,
+               void* stream);
+
+/* ------------------------------------------------------------------------
  * Timing recorder.  While on, every bucket launch of aot_count / aot_list on
  * the calling thread is bracketed by HIP events on its stream, and a record
  * keeps what the launch did -- the per-bucket timings the cost model of the

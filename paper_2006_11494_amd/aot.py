@@ -27,7 +27,7 @@ EXPORTS = (
     "aot_status_str", "aot_last_error", "aot_version",
     "aot_orient_workspace", "aot_orient",
     "aot_count_workspace", "aot_count",
-    "aot_list",
+    "aot_list", "aot_digest",
     "aot_timing_start", "aot_timing_stop",
 )
 
@@ -90,10 +90,12 @@ def load(path: str = LIB_PATH):
                               ctypes.c_size_t, ctypes.POINTER(ctypes.c_uint64), vp]
     lib.aot_list.argtypes = [ctypes.POINTER(OrientedC), ctypes.POINTER(DispatchC), vp, vp,
                              ctypes.c_size_t, i64, i64, vp, ctypes.POINTER(ctypes.c_int64), vp]
+    lib.aot_digest.argtypes = [ctypes.POINTER(OrientedC), ctypes.POINTER(DispatchC), vp, vp,
+                               ctypes.c_size_t, vp, ctypes.POINTER(ctypes.c_uint64), vp]
     lib.aot_timing_start.argtypes = []
     lib.aot_timing_stop.argtypes = [ctypes.POINTER(TimingC), i32, ctypes.POINTER(i32)]
     for f in ("aot_orient_workspace", "aot_orient", "aot_count_workspace", "aot_count", "aot_list",
-              "aot_timing_start", "aot_timing_stop"):
+              "aot_digest", "aot_timing_start", "aot_timing_stop"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -237,6 +239,19 @@ def list_triangles(o: Oriented, c: Counted, first: int = 0, count: int | None = 
     _check(load().aot_list(ctypes.byref(oc), ctypes.byref(dc), _ptr(c.tri_off), _ptr(c.ws),
                            c.ws.numel(), first, k, _ptr(out), None, _stream(stream)), "aot_list")
     return out[:k]
+
+
+def digest(o: Oriented, c: Counted, vertex_counts: bool = True,
+           dispatch: Dispatch | None = None, stream=None):
+    """aot_digest: (T, hash sum, hash xor) and per-vertex counts (uint64 as
+    int64 device tensor) of the triangle list, without storing it."""
+    vc = torch.empty(max(o.n, 1), dtype=torch.int64, device=o.rowptr.device) if vertex_counts else None
+    res = (ctypes.c_uint64 * 3)()
+    oc = o.cstruct()
+    dc = (dispatch or Dispatch()).cstruct()
+    _check(load().aot_digest(ctypes.byref(oc), ctypes.byref(dc), _ptr(c.tri_off), _ptr(c.ws),
+                             c.ws.numel(), _ptr(vc), res, _stream(stream)), "aot_digest")
+    return (int(res[0]), int(res[1]), int(res[2])), (vc[:o.n] if vc is not None else None)
 
 
 def timing_start():

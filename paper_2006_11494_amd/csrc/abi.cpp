@@ -173,4 +173,21 @@ int aot_list(const aot_oriented* g, const aot_dispatch* d, const int64_t* tri_of
   return ok();
 }
 
+int aot_digest(const aot_oriented* g, const aot_dispatch* d, const int64_t* tri_off, void* ws,
+               size_t ws_bytes, uint64_t* vertex_counts, uint64_t* digest, void* stream) {
+  int rc = check_oriented(g);
+  if (rc) return rc;
+  if (!tri_off || !digest) return fail(AOT_E_ARG, "tri_off or digest is NULL");
+  aot::DispatchView dv;
+  rc = check_dispatch(d, &dv);
+  if (rc) return rc;
+  const size_t need = aot::count_workspace_bytes(g->n, g->m);
+  if (ws_bytes < need || !ws) return fail(AOT_E_WORKSPACE, "count workspace smaller than aot_count_workspace()");
+  const char* err = nullptr;
+  rc = aot::digest_run(g->n, g->m, g->rowptr, g->col, g->tail, g->perm, g->in_rowptr, g->in_col,
+                       dv, tri_off, ws, ws_bytes, vertex_counts, digest,
+                       static_cast<hipStream_t>(stream), &err);
+  return hip_status(rc, err);
+}
+
 }  // extern "C"

@@ -367,7 +367,70 @@ struct HeavyArgs {
   const int32_t* perm;
   int64_t first, count;
   int32_t* out;
+  unsigned long long* digest;   // write pass in digest mode: {triangles, hash sum, hash xor}
+  unsigned long long* vcount;   // digest mode, optional: per-vertex triangle counts
 };
+
+// SplitMix64's output function (Steele, Lea and Flood, 2014) on state z.
+__device__ __forceinline__ uint64_t splitmix64(uint64_t z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// Order-independent digest of a triangle list: each ascending triple
+// (a, b, c) hashes to splitmix64(splitmix64(splitmix64(a) ^ b) ^ c); the
+// digest is the count, the sum (mod 2^64) and the xor of the hashes.
+struct Digest {
+  uint64_t count = 0, sum = 0, xr = 0;
+  __device__ __forceinline__ void add(int32_t a, int32_t b, int32_t c) {
+    const uint64_t h = splitmix64(splitmix64(splitmix64((uint64_t)(uint32_t)a) ^
+                                             (uint64_t)(uint32_t)b) ^ (uint64_t)(uint32_t)c);
+    count += 1;
+    sum += h;
+    xr ^= h;
+  }
+};
+
+// Block-wide reduction of the per-thread digests into the global one.
+__device__ void flush_digest(const Digest& d, unsigned long long* out) {
+  __shared__ unsigned long long red[3][kWavesPerBlock];
+  uint64_t c = d.count, s = d.sum, x = d.xr;
+  for (int o = kWave / 2; o > 0; o >>= 1) {
+    c += __shfl_xor(c, o, kWave);
+    s += __shfl_xor(s, o, kWave);
+    x ^= __shfl_xor(x, o, kWave);
+  }
+  const int w = threadIdx.x / kWave;
+  if (lane_id() == 0) { red[0][w] = c; red[1][w] = s; red[2][w] = x; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint64_t tc = 0, ts = 0, tx = 0;
+    for (int q = 0; q < kWavesPerBlock; ++q) { tc += red[0][q]; ts += red[1][q]; tx ^= red[2][q]; }
+    if (tc) {
+      atomicAdd(&out[0], tc);
+      atomicAdd(&out[1], ts);
+      atomicXor(&out[2], tx);
+    }
+  }
+}
+
+// Where an emitted triangle goes: the output window, or the digest.
+__device__ __forceinline__ void sink(const HeavyArgs& a, Digest& dg, int64_t pos, int32_t t0,
+                                     int32_t t1, int32_t t2) {
+  if (a.digest) {
+    dg.add(t0, t1, t2);
+    if (a.vcount) {
+      atomicAdd(&a.vcount[t0], 1ull);
+      atomicAdd(&a.vcount[t1], 1ull);
+      atomicAdd(&a.vcount[t2], 1ull);
+    }
+  } else if (pos >= a.first && pos < a.first + a.count) {
+    int32_t* o = a.out + 3 * (pos - a.first);
+    o[0] = t0; o[1] = t1; o[2] = t2;
+  }
+}
 
 template <bool kEmit>
 struct HeavyShared {
@@ -494,7 +557,7 @@ __device__ int64_t probe_count(HeavyShared<false>& sh, const uint32_t* lds, cons
 // boundary ranks hits per segment.
 template <int ARM>
 __device__ void probe_emit(HeavyShared<true>& sh, const uint32_t* lds, const HeavyArgs& a,
-                           const Index& ix, int K, int32_t P, int32_t pb) {
+                           const Index& ix, int K, int32_t P, int32_t pb, Digest& dg) {
   const int wave = threadIdx.x / kWave;
   const int k_lo = sh.wave_k[wave], k_hi = sh.wave_k[wave + 1];
   if (k_lo >= k_hi) return;
@@ -539,11 +602,10 @@ __device__ void probe_emit(HeavyShared<true>& sh, const uint32_t* lds, const Hea
         run = (k1 == run_k ? run : 0) + last_hits;
         run_k = k1;
       }
-      if (hit[u] && pos >= a.first && pos < a.first + a.count) {
+      if (hit[u]) {
         int32_t t0 = pb, t1 = sh.nb_py[k], t2 = third[u];
         sort3(t0, t1, t2);
-        int32_t* o = a.out + 3 * (pos - a.first);
-        o[0] = t0; o[1] = t1; o[2] = t2;
+        sink(a, dg, pos, t0, t1, t2);
       }
     }
   }
@@ -551,12 +613,13 @@ __device__ void probe_emit(HeavyShared<true>& sh, const uint32_t* lds, const Hea
 
 template <int ARM, bool kEmit>
 __device__ int64_t run_item(HeavyShared<kEmit>& sh, uint32_t* lds, const HeavyArgs& a,
-                            const int32_t* list, int32_t db, int K, int32_t P, int32_t pb) {
+                            const int32_t* list, int32_t db, int K, int32_t P, int32_t pb,
+                            Digest& dg) {
   const Index ix = build_index<ARM>(list, db, lds);   // ends with a barrier
   if constexpr (!kEmit) {
     return probe_count<ARM>(sh, lds, a, ix, K, P);
   } else {
-    probe_emit<ARM>(sh, lds, a, ix, K, P, pb);
+    probe_emit<ARM>(sh, lds, a, ix, K, P, pb, dg);
     return 0;
   }
 }
@@ -569,6 +632,7 @@ __global__ __launch_bounds__(kBlock) void k_heavy(HeavyArgs a) {
   extern __shared__ uint32_t lds[];
   const int tid = threadIdx.x;
   int64_t tri_block = 0;
+  Digest dg;
   for (int64_t it = blockIdx.x; it < a.item_count; it += gridDim.x) {
     const int2 item = a.items[a.item_base + it];
     const int32_t b = item.x;
@@ -609,7 +673,7 @@ __global__ __launch_bounds__(kBlock) void k_heavy(HeavyArgs a) {
           if (owned) {
             const int64_t lo = a.tri_off[e], hi = a.tri_off[e + 1];
             nbase[i] = lo;
-            keep[i] = hi > lo && hi > a.first && lo < a.first + a.count;
+            keep[i] = hi > lo && (a.digest || (hi > a.first && lo < a.first + a.count));
           }
         }
       }
@@ -656,10 +720,10 @@ __global__ __launch_bounds__(kBlock) void k_heavy(HeavyArgs a) {
     const int32_t pb = kEmit ? a.perm[b] : 0;
     int64_t t = 0;
     switch (arm) {
-      case kArmBitmap: t = run_item<kArmBitmap, kEmit>(sh, lds, a, list, db, K, P, pb); break;
-      case kArmHash: t = run_item<kArmHash, kEmit>(sh, lds, a, list, db, K, P, pb); break;
-      case kArmSorted: t = run_item<kArmSorted, kEmit>(sh, lds, a, list, db, K, P, pb); break;
-      default: t = run_item<kArmGlobal, kEmit>(sh, lds, a, list, db, K, P, pb); break;
+      case kArmBitmap: t = run_item<kArmBitmap, kEmit>(sh, lds, a, list, db, K, P, pb, dg); break;
+      case kArmHash: t = run_item<kArmHash, kEmit>(sh, lds, a, list, db, K, P, pb, dg); break;
+      case kArmSorted: t = run_item<kArmSorted, kEmit>(sh, lds, a, list, db, K, P, pb, dg); break;
+      default: t = run_item<kArmGlobal, kEmit>(sh, lds, a, list, db, K, P, pb, dg); break;
     }
     if constexpr (!kEmit) tri_block += t;
     __syncthreads();
@@ -670,6 +734,8 @@ __global__ __launch_bounds__(kBlock) void k_heavy(HeavyArgs a) {
   if constexpr (!kEmit) {
     const int64_t t = block_sum(tri_block, sh.scan_tmp);
     if (tid == 0 && t) atomicAdd(u64p(a.tri_stat), (unsigned long long)t);
+  } else {
+    if (a.digest) flush_digest(dg, a.digest);
   }
 }
 
@@ -686,10 +752,13 @@ __global__ __launch_bounds__(kBlock) void k_light(int64_t base, int64_t total,
                                                   const int64_t* __restrict__ tri_off,
                                                   const int32_t* __restrict__ perm,
                                                   int64_t first, int64_t count,
-                                                  int32_t* __restrict__ out) {
+                                                  int32_t* __restrict__ out,
+                                                  unsigned long long* digest,
+                                                  unsigned long long* vcount) {
   constexpr int kGroups = kBlock / G;
   const int gi = threadIdx.x / G, li = threadIdx.x % G;
   int64_t tri = 0;
+  Digest dg;
   for (int64_t t = (int64_t)blockIdx.x * kGroups + gi; t < total;
        t += (int64_t)gridDim.x * kGroups) {
     const int32_t e = elist[base + t];
@@ -706,7 +775,7 @@ __global__ __launch_bounds__(kBlock) void k_light(int64_t base, int64_t total,
     } else {
       int64_t pos = tri_off[e];
       const int64_t end = tri_off[e + 1];
-      if (end <= first || pos >= first + count || pos == end) continue;
+      if (pos == end || (!digest && (end <= first || pos >= first + count))) continue;
       const int32_t pu = perm[u], pv = perm[v];
       for (int32_t q0 = 0; q0 < x.c; q0 += G) {
         const int32_t q = q0 + li;
@@ -714,11 +783,20 @@ __global__ __launch_bounds__(kBlock) void k_light(int64_t base, int64_t total,
         const bool hit = q < x.c && contains_sorted(pb, x.db, w);
         const uint64_t mask = ballot(hit);
         const int64_t at = pos + popc_below_in_group<G>(mask);
-        if (hit && at >= first && at < first + count) {
+        if (hit) {
           int32_t t0 = pu, t1 = pv, t2 = perm[w];
           sort3(t0, t1, t2);
-          int32_t* o = out + 3 * (at - first);
-          o[0] = t0; o[1] = t1; o[2] = t2;
+          if (digest) {
+            dg.add(t0, t1, t2);
+            if (vcount) {
+              atomicAdd(&vcount[t0], 1ull);
+              atomicAdd(&vcount[t1], 1ull);
+              atomicAdd(&vcount[t2], 1ull);
+            }
+          } else if (at >= first && at < first + count) {
+            int32_t* o = out + 3 * (at - first);
+            o[0] = t0; o[1] = t1; o[2] = t2;
+          }
         }
         pos += __popcll(group_bits<G>(mask));
       }
@@ -728,6 +806,8 @@ __global__ __launch_bounds__(kBlock) void k_light(int64_t base, int64_t total,
     __shared__ int64_t red[kWavesPerBlock];
     const int64_t s = block_sum(tri, red);
     if (threadIdx.x == 0 && s) atomicAdd(u64p(tri_stat), (unsigned long long)s);
+  } else {
+    if (digest) flush_digest(dg, digest);
   }
 }
 
@@ -774,6 +854,7 @@ bool plan_from(const DispatchView& d, Plan* p) {
 int64_t max_items(int32_t n, int64_t m) { return (int64_t)n + cdiv(2 * m, kItemSpan) + 16; }
 
 struct CountWs {
+  unsigned long long* digest;
   int32_t* cnt;
   uint8_t* code;
   int32_t* elist;
@@ -785,6 +866,7 @@ struct CountWs {
 
 CountWs carve_count(Carve& c, int32_t n, int64_t m) {
   CountWs w;
+  w.digest = c.take<unsigned long long>(4);
   w.cnt = c.take<int32_t>(m);
   w.code = c.take<uint8_t>(m);
   w.elist = c.take<int32_t>(m);
@@ -809,9 +891,11 @@ hipError_t launch_light(int tile, unsigned grid, int64_t base, int64_t total,
                         const int32_t* elist, const int64_t* orow, const int32_t* ocol,
                         const int32_t* otail, int32_t* cnt, int64_t* tri_stat,
                         const int64_t* tri_off, const int32_t* perm, int64_t first,
-                        int64_t count, int32_t* out, hipStream_t s) {
+                        int64_t count, int32_t* out, unsigned long long* digest,
+                        unsigned long long* vcount, hipStream_t s) {
 #define L(G) k_light<G, kEmit><<<grid, kBlock, 0, s>>>(base, total, elist, orow, ocol, otail, \
-                                                     cnt, tri_stat, tri_off, perm, first, count, out)
+                                                     cnt, tri_stat, tri_off, perm, first, count, \
+                                                     out, digest, vcount)
   switch (tile) {
     case 4: L(4); break;
     case 8: L(8); break;
@@ -854,7 +938,8 @@ unsigned grid_cap(int64_t work_units) {
 int run_buckets(bool emit, const Plan& plan, const int64_t* hs, const CountWs& w,
                 const int64_t* orow, const int32_t* ocol, const int32_t* otail,
                 const int32_t* perm, const int64_t* irow, const int32_t* icol,
-                const int64_t* tri_off, int64_t first, int64_t count, int32_t* out, hipStream_t s,
+                const int64_t* tri_off, int64_t first, int64_t count, int32_t* out,
+                unsigned long long* digest, unsigned long long* vcount, hipStream_t s,
                 const char** err) {
   int64_t lbase = 0;
   for (int k = 0; k < kLightBins; ++k) {
@@ -869,10 +954,10 @@ int run_buckets(bool emit, const Plan& plan, const int64_t* hs, const CountWs& w
       if (!emit)
         e = launch_light<false>(tile, grid, lbase, edges, w.elist, orow, ocol, otail, w.cnt,
                                 w.stats + k * kStats + kSTriangles, nullptr, nullptr, 0, 0,
-                                nullptr, s);
+                                nullptr, nullptr, nullptr, s);
       else
         e = launch_light<true>(tile, grid, lbase, edges, w.elist, orow, ocol, otail, nullptr,
-                               nullptr, tri_off, perm, first, count, out, s);
+                               nullptr, tri_off, perm, first, count, out, digest, vcount, s);
       AOT_TRY(e);
       timing_end(rec, s);
     }
@@ -896,6 +981,8 @@ int run_buckets(bool emit, const Plan& plan, const int64_t* hs, const CountWs& w
     a.first = first;
     a.count = count;
     a.out = out;
+    a.digest = digest;
+    a.vcount = vcount;
     const int rec = timing_begin(emit ? 1 : 0, kHeavyBase + h, a.arm, kBlock, st[kSEdges],
                                  st[kSProbes], st[kSStaged], st[kSTriangles], s);
     const size_t dyn = sizeof(uint32_t) * (size_t)std::max(a.idx_words, 1);
@@ -950,7 +1037,7 @@ int count_run(int32_t n, int64_t m, const int64_t* orow, const int32_t* ocol, co
                            hipMemcpyDeviceToHost, s));
     AOT_TRY(hipStreamSynchronize(s));
     const int rc = run_buckets(false, plan, hs.data(), w, orow, ocol, otail, nullptr, irow, icol,
-                               nullptr, 0, 0, nullptr, s, err);
+                               nullptr, 0, 0, nullptr, nullptr, nullptr, s, err);
     if (rc) return rc;
   }
   AOT_TRY(exclusive_scan(w.cnt, tri_off, m, w.scan_tmp, s));
@@ -967,10 +1054,13 @@ int count_run(int32_t n, int64_t m, const int64_t* orow, const int32_t* ocol, co
   return 0;
 }
 
-int list_run(int32_t n, int64_t m, const int64_t* orow, const int32_t* ocol, const int32_t* otail,
-             const int32_t* perm, const int64_t* irow, const int32_t* icol,
-             const DispatchView& d, const int64_t* tri_off, void* ws, size_t ws_bytes,
-             int64_t first, int64_t count, int32_t* out, hipStream_t s, const char** err) {
+namespace {
+
+int emit_run(int32_t n, int64_t m, const int64_t* orow, const int32_t* ocol, const int32_t* otail,
+             const int32_t* perm, const int64_t* irow, const int32_t* icol, const DispatchView& d,
+             const int64_t* tri_off, void* ws, size_t ws_bytes, int64_t first, int64_t count,
+             int32_t* out, bool digest_mode, uint64_t* vcount, uint64_t* digest_host, hipStream_t s,
+             const char** err) {
   Carve c(ws, ws_bytes);
   CountWs w = carve_count(c, n, m);
   if (!c.ok()) {
@@ -982,13 +1072,49 @@ int list_run(int32_t n, int64_t m, const int64_t* orow, const int32_t* ocol, con
     *err = "dispatch table holds an unknown arm or tile code";
     return -6;
   }
-  if (m == 0 || count <= 0) return 0;
-  std::vector<int64_t> hs(kStatWords, 0);
-  AOT_TRY(hipMemcpyAsync(hs.data(), w.stats, sizeof(int64_t) * kStatWords, hipMemcpyDeviceToHost,
-                         s));
-  AOT_TRY(hipStreamSynchronize(s));
-  return run_buckets(true, plan, hs.data(), w, orow, ocol, otail, perm, irow, icol, tri_off,
-                     first, count, out, s, err);
+  unsigned long long* dg = digest_mode ? w.digest : nullptr;
+  unsigned long long* vc = reinterpret_cast<unsigned long long*>(vcount);
+  if (digest_mode) {
+    AOT_TRY(fill_i64(reinterpret_cast<int64_t*>(w.digest), 4, 0, s));
+    if (vc) AOT_TRY(fill_i64(reinterpret_cast<int64_t*>(vc), n, 0, s));
+  }
+  if (m > 0 && (digest_mode || count > 0)) {
+    std::vector<int64_t> hs(kStatWords, 0);
+    AOT_TRY(hipMemcpyAsync(hs.data(), w.stats, sizeof(int64_t) * kStatWords,
+                           hipMemcpyDeviceToHost, s));
+    AOT_TRY(hipStreamSynchronize(s));
+    const int rc = run_buckets(true, plan, hs.data(), w, orow, ocol, otail, perm, irow, icol,
+                               tri_off, first, count, out, dg, vc, s, err);
+    if (rc) return rc;
+  }
+  if (digest_mode) {
+    unsigned long long h[4];
+    AOT_TRY(hipMemcpyAsync(h, w.digest, sizeof(h), hipMemcpyDeviceToHost, s));
+    AOT_TRY(hipStreamSynchronize(s));
+    digest_host[0] = h[0];
+    digest_host[1] = h[1];
+    digest_host[2] = h[2];
+  }
+  return 0;
+}
+
+}  // namespace
+
+int list_run(int32_t n, int64_t m, const int64_t* orow, const int32_t* ocol, const int32_t* otail,
+             const int32_t* perm, const int64_t* irow, const int32_t* icol, const DispatchView& d,
+             const int64_t* tri_off, void* ws, size_t ws_bytes, int64_t first, int64_t count,
+             int32_t* out, hipStream_t s, const char** err) {
+  return emit_run(n, m, orow, ocol, otail, perm, irow, icol, d, tri_off, ws, ws_bytes, first,
+                  count, out, false, nullptr, nullptr, s, err);
+}
+
+int digest_run(int32_t n, int64_t m, const int64_t* orow, const int32_t* ocol,
+               const int32_t* otail, const int32_t* perm, const int64_t* irow,
+               const int32_t* icol, const DispatchView& d, const int64_t* tri_off, void* ws,
+               size_t ws_bytes, uint64_t* vcount, uint64_t* digest, hipStream_t s,
+               const char** err) {
+  return emit_run(n, m, orow, ocol, otail, perm, irow, icol, d, tri_off, ws, ws_bytes, 0, 0,
+                  nullptr, true, vcount, digest, s, err);
 }
 
 }  // namespace aot

@@ -86,4 +86,12 @@ int list_run(int32_t n, int64_t m, const int64_t* orow, const int32_t* ocol, con
              const int32_t* perm, const int64_t* irow, const int32_t* icol, const DispatchView& d, const int64_t* tri_off, void* ws, size_t ws_bytes,
              int64_t first, int64_t count, int32_t* out, hipStream_t s, const char** err);
 
+// The write pass in digest mode: nothing stored; digest = {T, hash sum, hash
+// xor} (host), vcount (device, optional) = triangles per original vertex id.
+int digest_run(int32_t n, int64_t m, const int64_t* orow, const int32_t* ocol,
+               const int32_t* otail, const int32_t* perm, const int64_t* irow,
+               const int32_t* icol, const DispatchView& d, const int64_t* tri_off, void* ws,
+               size_t ws_bytes, uint64_t* vcount, uint64_t* digest, hipStream_t s,
+               const char** err);
+
 }  // namespace aot

@@ -249,3 +249,25 @@ def test_timing_recorder():
     assert all(r["ms"] > 0 for r in recs)
     assert any(r["bucket"] >= 16 for r in cnt) and any(r["bucket"] < 8 for r in cnt)
     assert aot.timing_stop() == []          # stopped: nothing new recorded
+
+
+@pytest.mark.parametrize("name", ["er2000", "rmat14", "k40", "tiebreak", "empty", "star300"])
+def test_digest_matches_oracle(name):
+    need_gpu()
+    csr = {"er2000": lambda: inputs.workload("er2000"),
+           "rmat14": lambda: inputs.rmat(14, 16, 21)}.get(name, lambda: SMALL[name])()
+    rp, col = csr.numpy()
+    ref = oracle.orient(rp, col)
+    tri = oracle.list_triangles(ref)
+    (f1, f2), tv = oracle.fingerprint(tri, csr.n)
+    g = csr.to(DEV)
+    o = aot.orient(g.rowptr, g.col)
+    for dname, d in (("plain", None), ("all_heavy_hash", DISPATCHES["all_heavy_hash"]),
+                     ("all_light_tile4", DISPATCHES["all_light_tile4"])):
+        say(f"[gpu] digest {name} {dname}")
+        c = aot.count(o, d)
+        (t, s, x), vc = aot.digest(o, c, dispatch=d)
+        assert (t, s, x) == (len(tri), f1, f2), dname
+        if csr.n:
+            assert np.array_equal(vc.cpu().numpy().astype(np.uint64), tv), dname
+            assert int(vc.sum()) == 3 * t
