@@ -44,6 +44,8 @@ def parse():
     p.add_argument("--heavy-arm", default=None, choices=["bitmap", "hash", "global", "sorted"],
                    help="force one index arm for every heavy owner class")
     p.add_argument("--heavy-min", type=int, default=0)
+    p.add_argument("--no-learned", action="store_true",
+                   help="skip the learned-dispatch leg (training the cost model takes ~20 s)")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a plain 1 GiB read + 1 GiB write elementwise kernel, the "
                         "reference that scales rocprofv3's FETCH_SIZE / WRITE_SIZE counters")
@@ -165,6 +167,45 @@ def cpu_baseline(csr, frac: float):
                       f"host: {os.cpu_count()} cores visible, oracle single-threaded"}
 
 
+def learned_leg(aot, o, csr, cws, tri_off, out, T, probes, args):
+    """Train the cost model on other graphs (seeds >= 1000), judge it on
+    calibration graphs, then time the same step with the learned dispatch."""
+    import torch
+
+    from paper_2006_11494_amd import learn
+
+    t0 = time.time()
+    # training: the standard family mix plus two graphs of this workload's own
+    # recipe; judge: a third graph of the recipe (all seeds >= 1000)
+    training = learn.training_graphs(scale=2) + learn.workload_graphs(args.workload, (1021, 1022))
+    calibration = learn.workload_graphs(args.workload, (1020,))
+    net, report = learn.learn(training, calibration, epochs=1000, repeats=2, log=log)
+    train_s = time.time() - t0
+    if net is None:
+        return {"accepted": False, "train_s": train_s, **report}
+    d = aot.Dispatch(aot.AOT_DISPATCH_LEARNED, 0, None, net)
+
+    def step():
+        aot.orient(csr.rowptr, csr.col, out=o)
+        cc = aot.count(o, d, ws=cws, tri_off=tri_off)
+        aot.list_triangles(o, cc, out=out)
+        return cc
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(args.steps):
+        cc = step()
+        assert (cc.T, cc.probes) == (T, probes)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t) * 1000.0 / args.steps
+    table, used = aot.count_plan(o, cc)
+    log(f"[bench] learned dispatch: step {ms:.3f} ms (model used: {used})")
+    return {"accepted": True, "value": T / (ms / 1000.0), "unit": "triangles/s",
+            "ms_per_step": ms, "model_used": used, "plan": table, "train_s": train_s, **report}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -237,6 +278,10 @@ def main():
     log(f"[bench] step {ms_step:.3f} ms: orient {ms_orient:.3f} count {ms_count:.3f} "
         f"list {ms_list:.3f}")
 
+    learned = None
+    if not args.no_learned and not args.heavy_arm:
+        learned = learned_leg(aot, o, csr, cws, tri_off, out, T, probes, args)
+
     roof = roofline(recs, args.workload)
     log(f"[bench] dominant kernel {roof['kernel']}: {roof['achieved']:.1f} GB/s "
         f"({roof['frac'] * 100:.1f}% of peak) over {roof['launches']} launches")
@@ -267,6 +312,7 @@ def main():
         "roofline_kernel": {k: roof[k] for k in ("kernel", "launches", "avg_launch_ms",
                                                  "bytes_per_launch", "per_unit")},
         "cpu_baseline": base,
+        "learned": learned,
     }
     print(json.dumps(result), flush=True)
 

@@ -122,14 +122,28 @@ int aot_orient(const aot_graph* g, uint32_t flags, aot_oriented* out,
  *               sorted copy (an owner whose list does not fit the arm's LDS
  *               budget uses the next of bitmap, hash, sorted, global that
  *               does).  Other entries are ignored.  AOT_E_MODEL on a bad code.
+ *   model       AOT_DISPATCH_LEARNED: after binning, aot_count computes every
+ *               bucket's features, runs the cost model (aot_mlp_* below) and
+ *               gives each bucket the option with the lowest predicted
+ *               log(ns per probe).  A model whose parameters or predictions are
+ *               not finite, or of the wrong shape, is not used: the bucket
+ *               falls back to the plain rule (the call still succeeds;
+ *               aot_count_plan reports which rule ran).
+ * aot_count stores the plan it resolved in the workspace; aot_list and
+ * aot_digest given d = NULL use that plan.
  */
 #define AOT_DISPATCH_PLAIN 0
 #define AOT_DISPATCH_TABLE 1
+#define AOT_DISPATCH_LEARNED 2
 #define AOT_NUM_BUCKETS 32
+#define AOT_NUM_OPTIONS 9      /* cost-model outputs, see aot_bucket_features */
+#define AOT_NUM_FEATURES 8
+struct aot_mlp;
 typedef struct aot_dispatch {
   int32_t mode;
   int32_t heavy_min;
-  const int32_t* table;
+  const int32_t* table;          /* AOT_DISPATCH_TABLE                       */
+  const struct aot_mlp* model;   /* AOT_DISPATCH_LEARNED: the cost model      */
 } aot_dispatch;
 
 /* ------------------------------------------------------------------------
@@ -149,6 +163,24 @@ typedef struct aot_dispatch {
 int aot_count_workspace(int32_t n, int64_t m, size_t* bytes);
 int aot_count(const aot_oriented* g, const aot_dispatch* d, int64_t* tri_off,
               void* ws, size_t ws_bytes, uint64_t* result, void* stream);
+
+/* The plan the last aot_count on `ws` resolved: table (host int32[32], codes
+ * as in aot_dispatch) and *learned = 1 if the cost model chose it, 0 if the
+ * plain rule or a given table did. */
+int aot_count_plan(const void* ws, size_t ws_bytes, int32_t n, int64_t m, int32_t* table,
+                   int32_t* learned);
+
+/* Features of every bucket of the last aot_count on `ws` (host float[32][8]),
+ * the cost model's inputs, all from the count pass's own binning:
+ *   0 heavy class (1) or light bin (0)   1 log2(1 + edges)
+ *   2 log2(1 + mean min(deg+))           3 log2(1 + mean deg+ of the owner)
+ *   4 log2(1 + widest owner-list span)   5 log2(1 + mean staged entries per item)
+ *   6 log2(1 + work items)               7 bucket id / 32
+ * present[b] = 1 when bucket b holds edges.  The cost model's outputs are the
+ * predicted log(ns per probe) of the options 0..4 = light tile 4, 8, 16, 32,
+ * 64 and 5..8 = heavy arm bitmap, hash, global, sorted. */
+int aot_bucket_features(const void* ws, size_t ws_bytes, int32_t n, int64_t m, float* features,
+                        uint8_t* present);
 
 /* ------------------------------------------------------------------------
  * aot_list -- Algorithm 3's "output triangle" steps, as a write pass.  Writes
@@ -177,6 +209,40 @@ int aot_list(const aot_oriented* g, const aot_dispatch* d, const int64_t* tri_of
 int aot_digest(const aot_oriented* g, const aot_dispatch* d, const int64_t* tri_off,
                void* ws, size_t ws_bytes, uint64_t* vertex_counts, uint64_t* digest,
                void* stream);
+
+/* ------------------------------------------------------------------------
+ * Cost model of the dispatch: a fully connected network with ReLU, n_in ->
+ * n_hidden -> n_hidden -> n_out (fp32), trained on the per-bucket timings the
+ * recorder below collects.  `params` is a caller-owned device buffer of
+ * aot_mlp_param_count floats: input mean[n_in], 1/std[n_in] (set from the
+ * training data, not trained), W1[h][in], b1[h], W2[h][h], b2[h], W3[out][h],
+ * b3[out].  n_in <= 16, n_hidden <= 64, n_out <= 16.
+ *   aot_mlp_init       weights uniform in +-sqrt(6/fan_in) from a seeded
+ *                      counter hash, biases 0, identity normalisation.
+ *   aot_mlp_forward    y[batch][n_out] = net(x[batch][n_in]) (device arrays).
+ *   aot_mlp_loss_grad  masked mean squared error
+ *                      L = (1/N) sum mask[i][k] (y[i][k] - target[i][k])^2
+ *                      (N = set mask entries) and its gradient (device
+ *                      float[param_count - 2*n_in], trainable part in buffer
+ *                      order); reduction order fixed, so results repeat.
+ *   aot_mlp_train      sets the normalisation from x, then `epochs` full-batch
+ *                      Adam steps (beta 0.9, 0.999, eps 1e-8) at rate lr;
+ *                      losses (host float[epochs]) gets L before each step.
+ * ws: device workspace of aot_mlp_workspace(net, batch) bytes. */
+typedef struct aot_mlp {
+  int32_t n_in, n_hidden, n_out;
+  float* params;
+} aot_mlp;
+int aot_mlp_param_count(int32_t n_in, int32_t n_hidden, int32_t n_out, int64_t* count);
+int aot_mlp_workspace(const aot_mlp* net, int32_t batch, size_t* bytes);
+int aot_mlp_init(const aot_mlp* net, uint64_t seed, void* stream);
+int aot_mlp_forward(const aot_mlp* net, const float* x, int32_t batch, float* y, void* stream);
+int aot_mlp_loss_grad(const aot_mlp* net, const float* x, const float* target,
+                      const uint8_t* mask, int32_t batch, float* grad, float* loss, void* ws,
+                      size_t ws_bytes, void* stream);
+int aot_mlp_train(const aot_mlp* net, const float* x, const float* target, const uint8_t* mask,
+                  int32_t batch, int32_t epochs, float lr, float* losses, void* ws,
+                  size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
  * Timing recorder.  While on, every bucket launch of aot_count / aot_list on

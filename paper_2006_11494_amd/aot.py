@@ -20,14 +20,19 @@ AOT_OK = 0
 AOT_VALIDATE = 1
 AOT_DISPATCH_PLAIN = 0
 AOT_DISPATCH_TABLE = 1
+AOT_DISPATCH_LEARNED = 2
 AOT_NUM_BUCKETS = 32
+AOT_NUM_OPTIONS = 9
+AOT_NUM_FEATURES = 8
 
 # every symbol include/aot.h declares
 EXPORTS = (
     "aot_status_str", "aot_last_error", "aot_version",
     "aot_orient_workspace", "aot_orient",
     "aot_count_workspace", "aot_count",
-    "aot_list", "aot_digest",
+    "aot_list", "aot_digest", "aot_count_plan", "aot_bucket_features",
+    "aot_mlp_param_count", "aot_mlp_workspace", "aot_mlp_init", "aot_mlp_forward",
+    "aot_mlp_loss_grad", "aot_mlp_train",
     "aot_timing_start", "aot_timing_stop",
 )
 
@@ -60,7 +65,12 @@ class TimingC(ctypes.Structure):
 
 class DispatchC(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("heavy_min", ctypes.c_int32),
-                ("table", ctypes.c_void_p)]
+                ("table", ctypes.c_void_p), ("model", ctypes.c_void_p)]
+
+
+class MlpC(ctypes.Structure):
+    _fields_ = [("n_in", ctypes.c_int32), ("n_hidden", ctypes.c_int32),
+                ("n_out", ctypes.c_int32), ("params", ctypes.c_void_p)]
 
 
 _lib = None
@@ -92,10 +102,24 @@ def load(path: str = LIB_PATH):
                              ctypes.c_size_t, i64, i64, vp, ctypes.POINTER(ctypes.c_int64), vp]
     lib.aot_digest.argtypes = [ctypes.POINTER(OrientedC), ctypes.POINTER(DispatchC), vp, vp,
                                ctypes.c_size_t, vp, ctypes.POINTER(ctypes.c_uint64), vp]
+    lib.aot_count_plan.argtypes = [vp, ctypes.c_size_t, i32, i64, ctypes.POINTER(i32),
+                                   ctypes.POINTER(i32)]
+    lib.aot_bucket_features.argtypes = [vp, ctypes.c_size_t, i32, i64,
+                                        ctypes.POINTER(ctypes.c_float),
+                                        ctypes.POINTER(ctypes.c_uint8)]
+    mp = ctypes.POINTER(MlpC)
+    lib.aot_mlp_param_count.argtypes = [i32, i32, i32, ctypes.POINTER(i64)]
+    lib.aot_mlp_workspace.argtypes = [mp, i32, ctypes.POINTER(ctypes.c_size_t)]
+    lib.aot_mlp_init.argtypes = [mp, ctypes.c_uint64, vp]
+    lib.aot_mlp_forward.argtypes = [mp, vp, i32, vp, vp]
+    lib.aot_mlp_loss_grad.argtypes = [mp, vp, vp, vp, i32, vp, vp, vp, ctypes.c_size_t, vp]
+    lib.aot_mlp_train.argtypes = [mp, vp, vp, vp, i32, i32, ctypes.c_float,
+                                  ctypes.POINTER(ctypes.c_float), vp, ctypes.c_size_t, vp]
     lib.aot_timing_start.argtypes = []
     lib.aot_timing_stop.argtypes = [ctypes.POINTER(TimingC), i32, ctypes.POINTER(i32)]
-    for f in ("aot_orient_workspace", "aot_orient", "aot_count_workspace", "aot_count", "aot_list",
-              "aot_digest", "aot_timing_start", "aot_timing_stop"):
+    for f in EXPORTS:
+        if f in ("aot_status_str", "aot_last_error", "aot_version"):
+            continue
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -143,10 +167,12 @@ class Oriented:
 
 @dataclass
 class Dispatch:
-    """Probe-kernel dispatch: the plain rule, or a per-bucket code table."""
+    """Probe-kernel dispatch: the plain rule, a per-bucket code table, or the
+    learned cost model (`model`, an Mlp)."""
     mode: int = AOT_DISPATCH_PLAIN
     heavy_min: int = 0
     table: list | None = None
+    model: "Mlp | None" = None
 
     def cstruct(self):
         self._table = None
@@ -154,7 +180,74 @@ class Dispatch:
         if self.table is not None:
             self._table = (ctypes.c_int32 * AOT_NUM_BUCKETS)(*self.table)
             tp = ctypes.cast(self._table, ctypes.c_void_p)
-        return DispatchC(self.mode, self.heavy_min, tp)
+        mp = None
+        if self.model is not None:
+            self._model = self.model.cstruct()
+            mp = ctypes.cast(ctypes.pointer(self._model), ctypes.c_void_p)
+        return DispatchC(self.mode, self.heavy_min, tp, mp)
+
+
+class Mlp:
+    """The dispatch cost model: parameters in a device float32 tensor, every
+    operation one of the library's HIP kernels."""
+
+    def __init__(self, n_in=AOT_NUM_FEATURES, n_hidden=32, n_out=AOT_NUM_OPTIONS,
+                 device="cuda", params: torch.Tensor | None = None):
+        self.n_in, self.n_hidden, self.n_out = n_in, n_hidden, n_out
+        cnt = ctypes.c_int64(0)
+        _check(load().aot_mlp_param_count(n_in, n_hidden, n_out, ctypes.byref(cnt)),
+               "aot_mlp_param_count")
+        self.n_params = cnt.value
+        self.params = params if params is not None else torch.zeros(
+            cnt.value, dtype=torch.float32, device=device)
+        assert self.params.numel() == self.n_params and self.params.dtype == torch.float32
+
+    def cstruct(self) -> MlpC:
+        return MlpC(self.n_in, self.n_hidden, self.n_out, self.params.data_ptr())
+
+    def _ws(self, batch):
+        b = ctypes.c_size_t(0)
+        net = self.cstruct()
+        _check(load().aot_mlp_workspace(ctypes.byref(net), batch, ctypes.byref(b)),
+               "aot_mlp_workspace")
+        return torch.empty(b.value, dtype=torch.uint8, device=self.params.device)
+
+    def init(self, seed: int, stream=None):
+        net = self.cstruct()
+        _check(load().aot_mlp_init(ctypes.byref(net), seed, _stream(stream)), "aot_mlp_init")
+        return self
+
+    def forward(self, x: torch.Tensor, stream=None) -> torch.Tensor:
+        x = x.contiguous().to(torch.float32)
+        y = torch.empty((x.shape[0], self.n_out), dtype=torch.float32, device=x.device)
+        net = self.cstruct()
+        _check(load().aot_mlp_forward(ctypes.byref(net), _ptr(x), x.shape[0], _ptr(y),
+                                      _stream(stream)), "aot_mlp_forward")
+        return y
+
+    def loss_grad(self, x, target, mask, stream=None):
+        b = x.shape[0]
+        grad = torch.empty(self.n_params - 2 * self.n_in, dtype=torch.float32,
+                           device=x.device)
+        loss = torch.empty(1, dtype=torch.float32, device=x.device)
+        ws = self._ws(b)
+        net = self.cstruct()
+        _check(load().aot_mlp_loss_grad(ctypes.byref(net), _ptr(x.contiguous()),
+                                        _ptr(target.contiguous()), _ptr(mask.contiguous()), b,
+                                        _ptr(grad), _ptr(loss), _ptr(ws), ws.numel(),
+                                        _stream(stream)), "aot_mlp_loss_grad")
+        return float(loss.item()), grad
+
+    def train(self, x, target, mask, epochs: int, lr: float, stream=None):
+        b = x.shape[0]
+        losses = (ctypes.c_float * max(epochs, 1))()
+        ws = self._ws(b)
+        net = self.cstruct()
+        _check(load().aot_mlp_train(ctypes.byref(net), _ptr(x.contiguous()),
+                                    _ptr(target.contiguous()), _ptr(mask.contiguous()), b,
+                                    epochs, lr, losses, _ptr(ws), ws.numel(), _stream(stream)),
+               "aot_mlp_train")
+        return [losses[i] for i in range(epochs)]
 
 
 @dataclass
@@ -252,6 +345,26 @@ def digest(o: Oriented, c: Counted, vertex_counts: bool = True,
     _check(load().aot_digest(ctypes.byref(oc), ctypes.byref(dc), _ptr(c.tri_off), _ptr(c.ws),
                              c.ws.numel(), _ptr(vc), res, _stream(stream)), "aot_digest")
     return (int(res[0]), int(res[1]), int(res[2])), (vc[:o.n] if vc is not None else None)
+
+
+def count_plan(o: Oriented, c: Counted):
+    """The table the last aot_count resolved and whether the cost model chose it."""
+    t = (ctypes.c_int32 * AOT_NUM_BUCKETS)()
+    learned = ctypes.c_int32(0)
+    _check(load().aot_count_plan(_ptr(c.ws), c.ws.numel(), o.n, o.m, t, ctypes.byref(learned)),
+           "aot_count_plan")
+    return list(t), bool(learned.value)
+
+
+def bucket_features(o: Oriented, c: Counted):
+    """(features float32 [32, 8], present bool [32]) of the last aot_count."""
+    import numpy as np
+    f = (ctypes.c_float * (AOT_NUM_BUCKETS * AOT_NUM_FEATURES))()
+    pr = (ctypes.c_uint8 * AOT_NUM_BUCKETS)()
+    _check(load().aot_bucket_features(_ptr(c.ws), c.ws.numel(), o.n, o.m, f, pr),
+           "aot_bucket_features")
+    return (np.ctypeslib.as_array(f).reshape(AOT_NUM_BUCKETS, AOT_NUM_FEATURES).copy(),
+            np.ctypeslib.as_array(pr).astype(bool).copy())
 
 
 def timing_start():

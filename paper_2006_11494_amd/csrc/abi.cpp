@@ -40,17 +40,19 @@ int check_oriented(const aot_oriented* g) {
 }
 
 int check_dispatch(const aot_dispatch* d, aot::DispatchView* v) {
-  v->heavy_min = 0;
-  v->table = nullptr;
+  *v = aot::DispatchView();
   if (!d) return AOT_OK;
-  if (d->mode != AOT_DISPATCH_PLAIN && d->mode != AOT_DISPATCH_TABLE)
+  if (d->mode != AOT_DISPATCH_PLAIN && d->mode != AOT_DISPATCH_TABLE &&
+      d->mode != AOT_DISPATCH_LEARNED)
     return fail(AOT_E_ARG, "unknown dispatch mode");
   if (d->heavy_min < 0) return fail(AOT_E_ARG, "heavy_min < 0");
+  v->given = true;
   v->heavy_min = d->heavy_min;
   if (d->mode == AOT_DISPATCH_TABLE) {
     if (!d->table) return fail(AOT_E_MODEL, "table dispatch without a table");
     v->table = d->table;
   }
+  if (d->mode == AOT_DISPATCH_LEARNED) v->model = d->model;   // checked (and fallen back) later
   return AOT_OK;
 }
 
@@ -188,6 +190,21 @@ int aot_digest(const aot_oriented* g, const aot_dispatch* d, const int64_t* tri_
                        dv, tri_off, ws, ws_bytes, vertex_counts, digest,
                        static_cast<hipStream_t>(stream), &err);
   return hip_status(rc, err);
+}
+
+int aot_count_plan(const void* ws, size_t ws_bytes, int32_t n, int64_t m, int32_t* table,
+                   int32_t* learned) {
+  if (!ws || !table || !learned || n < 0 || m < 0) return fail(AOT_E_ARG, "bad argument");
+  if (ws_bytes < aot::count_workspace_bytes(n, m)) return fail(AOT_E_WORKSPACE, "workspace too small");
+  return aot::count_plan(ws, ws_bytes, n, m, table, learned) ? fail(AOT_E_HIP, "copy failed") : ok();
+}
+
+int aot_bucket_features(const void* ws, size_t ws_bytes, int32_t n, int64_t m, float* features,
+                        uint8_t* present) {
+  if (!ws || !features || !present || n < 0 || m < 0) return fail(AOT_E_ARG, "bad argument");
+  if (ws_bytes < aot::count_workspace_bytes(n, m)) return fail(AOT_E_WORKSPACE, "workspace too small");
+  return aot::count_features(ws, ws_bytes, n, m, features, present) ? fail(AOT_E_HIP, "copy failed")
+                                                                     : ok();
 }
 
 }  // extern "C"

@@ -24,6 +24,7 @@
 // hits of an edge in ascending w at those slots.
 #include <algorithm>
 #include <climits>
+#include <cmath>
 #include <vector>
 
 #include "kernels.hpp"
@@ -46,12 +47,15 @@ constexpr int kMaxIndexWords = 12288;  // LDS index cap: 48 KiB (bitmap window o
 constexpr int kUnroll = AOT_PROBE_UNROLL;   // 64-probe windows a wave keeps in flight
 constexpr int kGrid = 4096;
 constexpr int kDefaultHeavyMin = 32;
+constexpr int kPlanWords = 64;      // resolved table [32], learned flag, valid flag
+constexpr int kFeatures = AOT_NUM_FEATURES;
+constexpr int kOptions = AOT_NUM_OPTIONS;
 
 static_assert(kNumBuckets == kHeavyBase + kHeavyClasses, "bucket layout");
 
 // per-bucket statistics (int64, device), bucket = light bin or kHeavyBase + class
 enum : int {
-  kSEdges = 0, kSProbes, kSTriangles, kSItems, kSStaged, kSCursor, kSItemBase, kSSpan, kStats,
+  kSEdges = 0, kSProbes, kSTriangles, kSItems, kSStaged, kSCursor, kSItemBase, kSSpan, kSDb, kStats,
 };
 constexpr int kStatWords = kNumBuckets * kStats;
 
@@ -99,8 +103,8 @@ __global__ __launch_bounds__(kBlock) void k_bin_count(int64_t m, const int64_t* 
                                                       uint8_t* __restrict__ code,
                                                       int64_t* __restrict__ stats,
                                                       unsigned long long* __restrict__ probes) {
-  __shared__ unsigned long long se[kNumBuckets], sp[kNumBuckets];
-  if (threadIdx.x < kNumBuckets) { se[threadIdx.x] = 0; sp[threadIdx.x] = 0; }
+  __shared__ unsigned long long se[kNumBuckets], sp[kNumBuckets], sd[kNumBuckets];
+  if (threadIdx.x < kNumBuckets) { se[threadIdx.x] = 0; sp[threadIdx.x] = 0; sd[threadIdx.x] = 0; }
   __syncthreads();
   for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < m;
        e += (int64_t)gridDim.x * kBlock) {
@@ -112,11 +116,13 @@ __global__ __launch_bounds__(kBlock) void k_bin_count(int64_t m, const int64_t* 
     code[e] = bucket < kLightBins ? (uint8_t)bucket : (uint8_t)0xFF;
     atomicAdd(&se[bucket], 1ull);
     atomicAdd(&sp[bucket], (unsigned long long)x.c);
+    atomicAdd(&sd[bucket], (unsigned long long)x.db);
   }
   __syncthreads();
   if (threadIdx.x < kNumBuckets && se[threadIdx.x]) {
     atomicAdd(u64p(&stats[threadIdx.x * kStats + kSEdges]), se[threadIdx.x]);
     atomicAdd(u64p(&stats[threadIdx.x * kStats + kSProbes]), sp[threadIdx.x]);
+    atomicAdd(u64p(&stats[threadIdx.x * kStats + kSDb]), sd[threadIdx.x]);
     atomicAdd(probes, sp[threadIdx.x]);
   }
 }
@@ -851,9 +857,63 @@ bool plan_from(const DispatchView& d, Plan* p) {
   return true;
 }
 
+// Plan <-> table codes (the codes of aot_dispatch's table).
+void plan_to_table(const Plan& p, int32_t* t) {
+  for (int b = 0; b < kNumBuckets; ++b) t[b] = 0;
+  for (int k = 0; k < kLightBins; ++k) t[k] = p.light_tile[k] << 8;
+  for (int h = 0; h < kHeavyClasses; ++h) t[kHeavyBase + h] = p.heavy_arm[h];
+}
+
+constexpr int kLightTiles[5] = {4, 8, 16, 32, 64};
+
+// The cost model's input for every bucket, from the per-bucket statistics.
+void features_from_stats(const int64_t* hs, float* f, uint8_t* present) {
+  for (int b = 0; b < kNumBuckets; ++b) {
+    const int64_t* st = hs + b * kStats;
+    const bool heavy = b >= kHeavyBase;
+    const double e = (double)st[kSEdges];
+    float* x = f + b * kFeatures;
+    present[b] = st[kSEdges] > 0;
+    const double safe = e > 0 ? e : 1.0;
+    x[0] = heavy ? 1.f : 0.f;
+    x[1] = (float)std::log2(1.0 + e);
+    x[2] = (float)std::log2(1.0 + (double)st[kSProbes] / safe);
+    x[3] = (float)std::log2(1.0 + (double)st[kSDb] / safe);
+    x[4] = heavy ? (float)std::log2(1.0 + (double)st[kSSpan]) : 0.f;
+    const double items = (double)st[kSItems];
+    x[5] = heavy && items > 0 ? (float)std::log2(1.0 + (double)st[kSStaged] / items) : 0.f;
+    x[6] = heavy ? (float)std::log2(1.0 + items) : 0.f;
+    x[7] = (float)b / (float)kNumBuckets;
+  }
+}
+
+// Argmin of the predicted cost per bucket over the bucket's options (light:
+// outputs 0..4, heavy: 5..8).  False if any prediction of a present bucket is
+// not finite.
+bool plan_from_predictions(const float* pred, int stride, const uint8_t* present, Plan* p) {
+  *p = plain_plan();
+  for (int b = 0; b < kNumBuckets; ++b) {
+    if (!present[b]) continue;
+    const float* y = pred + b * stride;
+    const bool heavy = b >= kHeavyBase;
+    const int lo = heavy ? 5 : 0, hi = heavy ? 9 : 5;
+    int best = lo;
+    for (int o = lo; o < hi; ++o) {
+      if (!std::isfinite(y[o])) return false;
+      if (y[o] < y[best]) best = o;
+    }
+    if (heavy) p->heavy_arm[b - kHeavyBase] = best - 5;
+    else if (b < kLightBins) p->light_tile[b] = kLightTiles[best];
+  }
+  return true;
+}
+
 int64_t max_items(int32_t n, int64_t m) { return (int64_t)n + cdiv(2 * m, kItemSpan) + 16; }
 
 struct CountWs {
+  int32_t* plan;
+  float* feat;                       // [kNumBuckets][kFeatures], cost-model input
+  float* pred;                       // [kNumBuckets][16], cost-model output
   unsigned long long* digest;
   int32_t* cnt;
   uint8_t* code;
@@ -866,6 +926,9 @@ struct CountWs {
 
 CountWs carve_count(Carve& c, int32_t n, int64_t m) {
   CountWs w;
+  w.plan = c.take<int32_t>(kPlanWords);
+  w.feat = c.take<float>(kNumBuckets * kFeatures);
+  w.pred = c.take<float>(kNumBuckets * 16);
   w.digest = c.take<unsigned long long>(4);
   w.cnt = c.take<int32_t>(m);
   w.code = c.take<uint8_t>(m);
@@ -931,6 +994,39 @@ int index_words(int arm, int h, int64_t max_span) {
 
 unsigned grid_cap(int64_t work_units) {
   return (unsigned)std::max<int64_t>(1, std::min<int64_t>(kGrid * 4, work_units));
+}
+
+// The learned plan: features of every bucket -> cost model -> argmin.  A
+// model of the wrong shape or with non-finite parameters or predictions
+// leaves the plain rule in place (*learned = 0).
+int learned_plan(const aot_mlp* net, const int64_t* hs, const CountWs& w, hipStream_t s,
+                 Plan* plan, int32_t* learned) {
+  *learned = 0;
+  if (!net || !net->params || net->n_in != kFeatures || net->n_out != kOptions ||
+      net->n_hidden < 1 || net->n_hidden > 64)
+    return 0;
+  int64_t np = 0;
+  if (aot_mlp_param_count(net->n_in, net->n_hidden, net->n_out, &np) != AOT_OK) return 0;
+  std::vector<float> params((size_t)np);
+  if (hipMemcpyAsync(params.data(), net->params, sizeof(float) * np, hipMemcpyDeviceToHost, s) !=
+      hipSuccess)
+    return -5;
+  float feat[kNumBuckets * kFeatures];
+  uint8_t present[kNumBuckets];
+  features_from_stats(hs, feat, present);
+  if (hipMemcpyAsync(w.feat, feat, sizeof(feat), hipMemcpyHostToDevice, s) != hipSuccess) return -5;
+  if (mlp_predict(net, w.feat, kNumBuckets, w.pred, s)) return -5;
+  float pred[kNumBuckets * kOptions];
+  if (hipMemcpyAsync(pred, w.pred, sizeof(pred), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return -5;
+  for (float v : params)
+    if (!std::isfinite(v)) return 0;
+  Plan p;
+  if (!plan_from_predictions(pred, kOptions, present, &p)) return 0;
+  *plan = p;
+  *learned = 1;
+  return 0;
 }
 
 // Launches every non-empty bucket of one pass, recording each launch when
@@ -1017,6 +1113,7 @@ int count_run(int32_t n, int64_t m, const int64_t* orow, const int32_t* ocol, co
     *err = "dispatch table holds an unknown arm or tile code";
     return -6;
   }
+  int32_t learned = 0;
   AOT_TRY(fill_i64(w.stats, kStatWords, 0, s));
   AOT_TRY(fill_i64(reinterpret_cast<int64_t*>(w.probes), 4, 0, s));
   std::vector<int64_t> hs(kStatWords, 0);
@@ -1036,9 +1133,23 @@ int count_run(int32_t n, int64_t m, const int64_t* orow, const int32_t* ocol, co
     AOT_TRY(hipMemcpyAsync(hs.data(), w.stats, sizeof(int64_t) * kStatWords,
                            hipMemcpyDeviceToHost, s));
     AOT_TRY(hipStreamSynchronize(s));
+    if (d.model) {
+      const int rc = learned_plan(d.model, hs.data(), w, s, &plan, &learned);
+      if (rc) {
+        *err = "cost model evaluation failed";
+        return rc;
+      }
+    }
     const int rc = run_buckets(false, plan, hs.data(), w, orow, ocol, otail, nullptr, irow, icol,
                                nullptr, 0, 0, nullptr, nullptr, nullptr, s, err);
     if (rc) return rc;
+  }
+  {
+    int32_t words[kPlanWords] = {0};
+    plan_to_table(plan, words);
+    words[kNumBuckets] = learned;
+    words[kNumBuckets + 1] = 1;      // plan valid
+    AOT_TRY(hipMemcpyAsync(w.plan, words, sizeof(words), hipMemcpyHostToDevice, s));
   }
   AOT_TRY(exclusive_scan(w.cnt, tri_off, m, w.scan_tmp, s));
   int64_t t = 0;
@@ -1072,6 +1183,7 @@ int emit_run(int32_t n, int64_t m, const int64_t* orow, const int32_t* ocol, con
     *err = "dispatch table holds an unknown arm or tile code";
     return -6;
   }
+  const bool stored = !d.given || d.model;     // use the plan the count resolved
   unsigned long long* dg = digest_mode ? w.digest : nullptr;
   unsigned long long* vc = reinterpret_cast<unsigned long long*>(vcount);
   if (digest_mode) {
@@ -1080,9 +1192,16 @@ int emit_run(int32_t n, int64_t m, const int64_t* orow, const int32_t* ocol, con
   }
   if (m > 0 && (digest_mode || count > 0)) {
     std::vector<int64_t> hs(kStatWords, 0);
+    int32_t words[kPlanWords];
     AOT_TRY(hipMemcpyAsync(hs.data(), w.stats, sizeof(int64_t) * kStatWords,
                            hipMemcpyDeviceToHost, s));
+    AOT_TRY(hipMemcpyAsync(words, w.plan, sizeof(words), hipMemcpyDeviceToHost, s));
     AOT_TRY(hipStreamSynchronize(s));
+    if (stored && words[kNumBuckets + 1] == 1) {
+      DispatchView t;
+      t.table = words;
+      if (!plan_from(t, &plan)) plan = plain_plan();
+    }
     const int rc = run_buckets(true, plan, hs.data(), w, orow, ocol, otail, perm, irow, icol,
                                tri_off, first, count, out, dg, vc, s, err);
     if (rc) return rc;
@@ -1115,6 +1234,30 @@ int digest_run(int32_t n, int64_t m, const int64_t* orow, const int32_t* ocol,
                const char** err) {
   return emit_run(n, m, orow, ocol, otail, perm, irow, icol, d, tri_off, ws, ws_bytes, 0, 0,
                   nullptr, true, vcount, digest, s, err);
+}
+
+int count_plan(const void* ws, size_t ws_bytes, int32_t n, int64_t m, int32_t* table,
+               int32_t* learned) {
+  Carve c(const_cast<void*>(ws), ws_bytes);
+  CountWs w = carve_count(c, n, m);
+  int32_t words[kPlanWords];
+  if (hipMemcpy(words, w.plan, sizeof(words), hipMemcpyDeviceToHost) != hipSuccess) return -5;
+  if (words[kNumBuckets + 1] != 1) plan_to_table(plain_plan(), words);
+  for (int b = 0; b < kNumBuckets; ++b) table[b] = words[b];
+  *learned = words[kNumBuckets + 1] == 1 ? words[kNumBuckets] : 0;
+  return 0;
+}
+
+int count_features(const void* ws, size_t ws_bytes, int32_t n, int64_t m, float* features,
+                   uint8_t* present) {
+  Carve c(const_cast<void*>(ws), ws_bytes);
+  CountWs w = carve_count(c, n, m);
+  std::vector<int64_t> hs(kStatWords, 0);
+  if (hipMemcpy(hs.data(), w.stats, sizeof(int64_t) * kStatWords, hipMemcpyDeviceToHost) !=
+      hipSuccess)
+    return -5;
+  features_from_stats(hs.data(), features, present);
+  return 0;
 }
 
 }  // namespace aot

@@ -5,6 +5,7 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include "aot.h"
 #include "common.hpp"
 
 namespace aot {
@@ -76,9 +77,18 @@ void timing_fill_triangles(const int64_t* stats, int stride, int offset);
 // ---- count.hip
 size_t count_workspace_bytes(int32_t n, int64_t m);
 struct DispatchView {
-  int32_t heavy_min;
-  const int32_t* table;  // host, kNumBuckets codes or nullptr
+  bool given = false;              // a dispatch was passed (else: the stored plan / plain rule)
+  int32_t heavy_min = 0;
+  const int32_t* table = nullptr;  // host, kNumBuckets codes or nullptr
+  const aot_mlp* model = nullptr;  // learned dispatch
 };
+// Cost-model forward (mlp.hip).
+int mlp_predict(const aot_mlp* net, const float* x_dev, int32_t batch, float* y_dev, hipStream_t s);
+// The plan and bucket features of the last count on a workspace (count.hip).
+int count_plan(const void* ws, size_t ws_bytes, int32_t n, int64_t m, int32_t* table,
+               int32_t* learned);
+int count_features(const void* ws, size_t ws_bytes, int32_t n, int64_t m, float* features,
+                   uint8_t* present);
 int count_run(int32_t n, int64_t m, const int64_t* orow, const int32_t* ocol, const int32_t* otail,
               const int64_t* irow, const int32_t* icol, const DispatchView& d, int64_t* tri_off, void* ws, size_t ws_bytes,
               uint64_t* result, hipStream_t s, const char** err);
