@@ -20,6 +20,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -46,6 +48,9 @@ def parse():
     p.add_argument("--heavy-min", type=int, default=0)
     p.add_argument("--no-learned", action="store_true",
                    help="skip the learned-dispatch leg (training the cost model takes ~20 s)")
+    p.add_argument("--no-batch", action="store_true",
+                   help="skip the batched leg (512 uneven graphs, one captured pass)")
+    p.add_argument("--batch-count", type=int, default=512)
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a plain 1 GiB read + 1 GiB write elementwise kernel, the "
                         "reference that scales rocprofv3's FETCH_SIZE / WRITE_SIZE counters")
@@ -206,6 +211,99 @@ def learned_leg(aot, o, csr, cws, tri_off, out, T, probes, args):
             "ms_per_step": ms, "model_used": used, "plan": table, "train_s": train_s, **report}
 
 
+def _time_ms(fn, reps):
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        t = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        ts.append((time.perf_counter() - t) * 1000.0)
+    return float(sorted(ts)[len(ts) // 2])
+
+
+def batched_leg(aot, args, dev):
+    """The uneven batch: 512 graphs (n log-uniform in [1e3, 2e5]; ER, R-MAT,
+    RGG), listed (a) graph by graph through aot_orient / aot_count / aot_list,
+    (b) as one persistent pass captured in a HIP graph, with the plain rule and
+    with the schedule the autotuner picks on a tuning batch of other seeds."""
+    import torch
+
+    from paper_2006_11494_amd import inputs, tune
+
+    t0 = time.time()
+    csrs = [inputs.batch_member(s, device=dev) for s in inputs.batch_spec(args.batch_count, 4)]
+    voff, rowptr, col = inputs.arena(csrs)
+    b = aot.Batch(voff, voff.to(dev), rowptr, col)
+    torch.cuda.synchronize()
+    log(f"[batch] generated {b.count} graphs: n={b.n} m={b.nnz // 2} in {time.time() - t0:.1f}s")
+    t0 = time.time()
+    tcs = [inputs.batch_member(s, device=dev) for s in inputs.batch_spec(128, 1004)]
+    tv, tr, tc = inputs.arena(tcs)
+    tb = aot.Batch(tv, tv.to(dev), tr, tc)
+    sched, rep = tune.tune(tb, log=log)
+    del tcs, tb, tv, tr, tc
+    log(f"[batch] tuned on 128 graphs of other seeds in {time.time() - t0:.1f}s")
+
+    probe = aot.batch_run(b, 0)
+    torch.cuda.synchronize()
+    T = int(probe.graph_tri[-1].item())
+    gtri = probe.graph_tri.cpu()
+    del probe
+    out = torch.empty((max(T, 1), 3), dtype=torch.int32, device=dev)
+    max_n = max(c.n for c in csrs)
+    max_nnz = max(c.nnz for c in csrs)
+    ows = torch.empty(aot.orient_workspace(max_n, max_nnz), dtype=torch.uint8, device=dev)
+    cws = torch.empty(aot.count_workspace(max_n, max_nnz // 2), dtype=torch.uint8, device=dev)
+    per_T = []
+
+    def per_graph():
+        per_T.clear()
+        pos = 0
+        for c in csrs:
+            o = aot.alloc_oriented(c.n, c.m, dev)
+            aot.orient(c.rowptr, c.col, out=o, ws=ows)
+            cc = aot.count(o, ws=cws)
+            aot.list_triangles(o, cc, out=out[pos:pos + cc.T])
+            pos += cc.T
+            per_T.append(cc.T)
+
+    ms_per_graph = _time_ms(per_graph, 2)
+    assert per_T == (gtri[1:] - gtri[:-1]).tolist(), "per-graph T differs from the batch"
+    log(f"[batch] per-graph launches: {ms_per_graph:.1f} ms for T={T}")
+    run = aot.alloc_batch(b, T)
+    ms_eager = _time_ms(lambda: aot.batch_run(b, T, run=run), 3)
+    g_plain = aot.BatchGraph(b, T, run=run)
+    ms_graph_plain = _time_ms(g_plain.launch, 5)
+    g_plain.close()
+    g = aot.BatchGraph(b, T, schedule=sched, run=run)
+    ms_graph = _time_ms(g.launch, 5)
+    torch.cuda.synchronize()
+    # the batched list equals the per-graph lists (sampled graphs, arena ids
+    # shifted back to local ids)
+    rng = np.random.default_rng(0)
+    for j in sorted(set(rng.integers(0, b.count, 24).tolist()) | {int(np.argmax(per_T))}):
+        lo, hi = int(gtri[j]), int(gtri[j + 1])
+        assert torch.equal(run.tri[lo:hi] - int(voff[j]), out[lo:hi]), f"graph {j}"
+    g.close()
+    log(f"[batch] eager pass {ms_eager:.1f} ms; captured graph: plain {ms_graph_plain:.1f} ms, "
+        f"tuned {ms_graph:.1f} ms; per-graph {ms_per_graph:.1f} ms")
+    m = b.nnz // 2
+    return {"graphs": b.count, "n": b.n, "m": m, "triangles": T,
+            "per_graph_ms": ms_per_graph, "eager_pass_ms": ms_eager,
+            "graph_plain_ms": ms_graph_plain, "graph_tuned_ms": ms_graph,
+            "value": T / (ms_graph / 1000.0), "unit": "triangles/s",
+            "per_graph_value": T / (ms_per_graph / 1000.0),
+            "speedup_vs_per_graph": ms_per_graph / ms_graph,
+            "tuned_vs_plain": ms_graph_plain / ms_graph,
+            "schedule": {"heavy_min": sched.heavy_min, "light_rounds": sched.light_rounds,
+                         "table": sched.table},
+            "tune": {k: rep[k] for k in ("plain_ms", "tuned_ms", "tried", "seconds")},
+            "tuning_batch": "128 graphs of the same recipe, seeds mix(1004, j)"}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -282,6 +380,11 @@ def main():
     if not args.no_learned and not args.heavy_arm:
         learned = learned_leg(aot, o, csr, cws, tri_off, out, T, probes, args)
 
+    del out
+    batched = None
+    if not args.no_batch:
+        batched = batched_leg(aot, args, dev)
+
     roof = roofline(recs, args.workload)
     log(f"[bench] dominant kernel {roof['kernel']}: {roof['achieved']:.1f} GB/s "
         f"({roof['frac'] * 100:.1f}% of peak) over {roof['launches']} launches")
@@ -313,6 +416,7 @@ def main():
                                                  "bytes_per_launch", "per_unit")},
         "cpu_baseline": base,
         "learned": learned,
+        "batched": batched,
     }
     print(json.dumps(result), flush=True)
 

@@ -211,6 +211,84 @@ int aot_digest(const aot_oriented* g, const aot_dispatch* d, const int64_t* tri_
                void* stream);
 
 /* ------------------------------------------------------------------------
+ * Batches of graphs.  Many (small, uneven) graphs are listed as one: their
+ * CSRs sit in one arena, the block-diagonal union, and one pass of
+ * orientation, binning, count, scan and write covers all of them.  Graph g
+ * keeps exactly its own result: the orientation ranks graph by graph and,
+ * inside a graph, by (degree, id) as aot_orient does, so graph g's ranks,
+ * oriented edges and triangle slots are a contiguous block whose contents
+ * equal that graph's own aot_orient / aot_count / aot_list output shifted by
+ * the block's offsets (triangles are the same local ids plus voff[g]).  A
+ * triangle never spans two graphs (Section 2.1: a triangle is three mutually
+ * adjacent vertices, and the union adds no edge).
+ *
+ * The probe passes run as persistent kernels: a grid of resident workgroups
+ * drains a queue of work items (heavy owner windows, heaviest class first,
+ * then chunks of light edges, largest c first) through an atomic cursor.  No
+ * call reads anything back to the host, so the whole sequence can be
+ * captured once in a HIP graph (aot_batch_capture) and replayed.
+ *
+ * aot_batch      count >= 1 graphs.  voff_host (host) and voff (device) hold
+ *                the same int64[count+1] vertex offsets: graph g owns arena
+ *                vertices [voff[g], voff[g+1]), voff[0] = 0,
+ *                voff[count] = arena.n, non-decreasing.  arena is the union
+ *                CSR (device): a row of graph g lists arena ids (local id +
+ *                voff[g]) of graph g only, ascending.  AOT_E_OVERFLOW if a
+ *                (graph, degree) sort key needs more than 31 bits, i.e.
+ *                ceil(log2 count) + ceil(log2 max vertices of a graph) > 31.
+ * aot_schedule   the choices an autotuner makes: heavy_min (light/heavy bin
+ *                boundary, 0 = 32), use_table = 1 to use table (codes as in
+ *                aot_dispatch's table; 0 = the plain rule), light_rounds
+ *                (group-rounds of G lanes per light task, 0 = 4).  NULL =
+ *                all defaults.  Every schedule gives the same bytes.
+ */
+typedef struct aot_batch {
+  int32_t count;
+  const int64_t* voff_host;
+  const int64_t* voff;
+  aot_graph arena;
+} aot_batch;
+
+typedef struct aot_schedule {
+  int32_t heavy_min;
+  int32_t use_table;
+  int32_t table[AOT_NUM_BUCKETS];
+  int32_t light_rounds;
+} aot_schedule;
+
+/* Device workspace for aot_batch_run / aot_batch_capture; it also serves as
+ * the count workspace of aot_list / aot_digest on the batch afterwards. */
+int aot_batch_workspace(const aot_batch* b, size_t* bytes);
+
+/* Enqueues the whole pass over the batch on `stream`; does not synchronise.
+ *   out        caller-allocated oriented arrays of the arena (sizes as for
+ *              aot_orient with n = arena.n, m = arena.nnz / 2); rank space is
+ *              graph by graph as described above.
+ *   tri_off    device int64[m+1]: per-edge triangle offsets, as aot_count.
+ *   graph_tri  device int64[count+1], written: graph g's triangles are global
+ *              indices [graph_tri[g], graph_tri[g+1]); T = graph_tri[count].
+ *   tri        device int32[3*cap]: triangles [0, min(T, cap)) of the global
+ *              list (arena ids, ascending per triangle, order as aot_list).
+ *              If T > cap, list the rest with aot_list(out, NULL, tri_off,
+ *              ws, ...) windows: the same bytes.
+ *   ws         at least aot_batch_workspace() bytes. */
+int aot_batch_run(const aot_batch* b, const aot_schedule* sc, aot_oriented* out,
+                  int64_t* tri_off, int64_t* graph_tri, int32_t* tri, int64_t cap, void* ws,
+                  size_t ws_bytes, void* stream);
+
+/* aot_batch_run captured once into a HIP graph (instantiated, opaque).  Every
+ * pointer, size and schedule choice is fixed at capture; a launch recomputes
+ * everything from the buffers' contents at that time (same shapes).  The
+ * caller keeps every buffer alive until aot_batch_destroy.  Launches of one
+ * graph must not overlap (they share the workspace). */
+typedef struct aot_batch_graph aot_batch_graph;
+int aot_batch_capture(const aot_batch* b, const aot_schedule* sc, aot_oriented* out,
+                      int64_t* tri_off, int64_t* graph_tri, int32_t* tri, int64_t cap, void* ws,
+                      size_t ws_bytes, aot_batch_graph** graph);
+int aot_batch_launch(const aot_batch_graph* graph, void* stream);
+int aot_batch_destroy(aot_batch_graph* graph);
+
+/* ------------------------------------------------------------------------
  * Cost model of the dispatch: a fully connected network with ReLU, n_in ->
  * n_hidden -> n_hidden -> n_out (fp32), trained on the per-bucket timings the
  * recorder below collects.  `params` is a caller-owned device buffer of

@@ -34,6 +34,8 @@ EXPORTS = (
     "aot_mlp_param_count", "aot_mlp_workspace", "aot_mlp_init", "aot_mlp_forward",
     "aot_mlp_loss_grad", "aot_mlp_train",
     "aot_timing_start", "aot_timing_stop",
+    "aot_batch_workspace", "aot_batch_run", "aot_batch_capture", "aot_batch_launch",
+    "aot_batch_destroy",
 )
 
 
@@ -66,6 +68,16 @@ class TimingC(ctypes.Structure):
 class DispatchC(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("heavy_min", ctypes.c_int32),
                 ("table", ctypes.c_void_p), ("model", ctypes.c_void_p)]
+
+
+class BatchC(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_int32), ("voff_host", ctypes.c_void_p),
+                ("voff", ctypes.c_void_p), ("arena", Graph)]
+
+
+class ScheduleC(ctypes.Structure):
+    _fields_ = [("heavy_min", ctypes.c_int32), ("use_table", ctypes.c_int32),
+                ("table", ctypes.c_int32 * AOT_NUM_BUCKETS), ("light_rounds", ctypes.c_int32)]
 
 
 class MlpC(ctypes.Structure):
@@ -115,6 +127,13 @@ def load(path: str = LIB_PATH):
     lib.aot_mlp_loss_grad.argtypes = [mp, vp, vp, vp, i32, vp, vp, vp, ctypes.c_size_t, vp]
     lib.aot_mlp_train.argtypes = [mp, vp, vp, vp, i32, i32, ctypes.c_float,
                                   ctypes.POINTER(ctypes.c_float), vp, ctypes.c_size_t, vp]
+    bp, sp, op = ctypes.POINTER(BatchC), ctypes.POINTER(ScheduleC), ctypes.POINTER(OrientedC)
+    lib.aot_batch_workspace.argtypes = [bp, sz]
+    lib.aot_batch_run.argtypes = [bp, sp, op, vp, vp, vp, i64, vp, ctypes.c_size_t, vp]
+    lib.aot_batch_capture.argtypes = [bp, sp, op, vp, vp, vp, i64, vp, ctypes.c_size_t,
+                                      ctypes.POINTER(vp)]
+    lib.aot_batch_launch.argtypes = [vp, vp]
+    lib.aot_batch_destroy.argtypes = [vp]
     lib.aot_timing_start.argtypes = []
     lib.aot_timing_stop.argtypes = [ctypes.POINTER(TimingC), i32, ctypes.POINTER(i32)]
     for f in EXPORTS:
@@ -380,3 +399,125 @@ def timing_stop(cap: int = 4096) -> list[dict]:
     keys = ("bucket", "arm", "tile", "edges", "probes", "staged", "triangles", "ms")
     return [dict({"pass": buf[i].pass_}, **{k: getattr(buf[i], k) for k in keys})
             for i in range(min(n.value, cap))]
+
+
+# ---------------------------------------------------------------- batches
+
+@dataclass
+class Batch:
+    """A batch of graphs in one arena (see aot_batch): graph g owns arena
+    vertices [voff[g], voff[g+1]); rowptr/col are the union CSR (device)."""
+    voff: torch.Tensor       # host int64 [count+1]
+    voff_dev: torch.Tensor   # device int64 [count+1]
+    rowptr: torch.Tensor     # device int64 [n+1]
+    col: torch.Tensor        # device int32 [nnz]
+
+    @property
+    def count(self) -> int:
+        return self.voff.numel() - 1
+
+    @property
+    def n(self) -> int:
+        return self.rowptr.numel() - 1
+
+    @property
+    def nnz(self) -> int:
+        return self.col.numel()
+
+    def cstruct(self) -> BatchC:
+        self._voff = self.voff.contiguous()
+        g = Graph(self.n, self.nnz, ctypes.c_void_p(self.rowptr.data_ptr()), _ptr(self.col))
+        return BatchC(self.count, ctypes.c_void_p(self._voff.data_ptr()),
+                      ctypes.c_void_p(self.voff_dev.data_ptr()), g)
+
+
+@dataclass
+class Schedule:
+    """What the autotuner picks for the persistent passes (aot_schedule)."""
+    heavy_min: int = 0
+    table: list | None = None
+    light_rounds: int = 0
+
+    def cstruct(self) -> ScheduleC:
+        t = (ctypes.c_int32 * AOT_NUM_BUCKETS)(*(self.table or [0] * AOT_NUM_BUCKETS))
+        return ScheduleC(self.heavy_min, 1 if self.table is not None else 0, t,
+                         self.light_rounds)
+
+
+@dataclass
+class BatchRun:
+    """Buffers of one batch pass: the arena's oriented graph, per-edge and
+    per-graph triangle offsets, the triangle window [0, cap) and the
+    workspace (which also serves aot_list on the arena afterwards)."""
+    o: Oriented
+    tri_off: torch.Tensor
+    graph_tri: torch.Tensor
+    tri: torch.Tensor
+    ws: torch.Tensor
+
+    def counted(self) -> Counted:
+        t = int(self.graph_tri[-1].item())
+        return Counted(t, -1, self.tri_off, self.ws)
+
+
+def batch_workspace(b: Batch) -> int:
+    n = ctypes.c_size_t(0)
+    bc = b.cstruct()
+    _check(load().aot_batch_workspace(ctypes.byref(bc), ctypes.byref(n)), "aot_batch_workspace")
+    return n.value
+
+
+def alloc_batch(b: Batch, cap: int) -> BatchRun:
+    dev = b.rowptr.device
+    o = alloc_oriented(b.n, b.nnz // 2, dev)
+    return BatchRun(o, torch.empty(o.m + 1, dtype=torch.int64, device=dev),
+                    torch.empty(b.count + 1, dtype=torch.int64, device=dev),
+                    torch.empty((max(cap, 0), 3), dtype=torch.int32, device=dev),
+                    torch.empty(max(batch_workspace(b), 1), dtype=torch.uint8, device=dev))
+
+
+def batch_run(b: Batch, cap: int, schedule: Schedule | None = None, run: BatchRun | None = None,
+              stream=None) -> BatchRun:
+    """aot_batch_run: orient, count and list the whole batch in one pass
+    (enqueued, no synchronisation)."""
+    r = run if run is not None else alloc_batch(b, cap)
+    assert r.tri.shape[0] >= cap
+    bc, oc = b.cstruct(), r.o.cstruct()
+    sc = schedule.cstruct() if schedule is not None else None
+    _check(load().aot_batch_run(ctypes.byref(bc), ctypes.byref(sc) if sc is not None else None,
+                                ctypes.byref(oc), _ptr(r.tri_off), _ptr(r.graph_tri), _ptr(r.tri),
+                                cap, _ptr(r.ws), r.ws.numel(), _stream(stream)), "aot_batch_run")
+    return r
+
+
+class BatchGraph:
+    """aot_batch_run captured once in a HIP graph; launch() replays it."""
+
+    def __init__(self, b: Batch, cap: int, schedule: Schedule | None = None,
+                 run: BatchRun | None = None):
+        self.b = b
+        self.run = run if run is not None else alloc_batch(b, cap)
+        bc, oc = b.cstruct(), self.run.o.cstruct()
+        sc = schedule.cstruct() if schedule is not None else None
+        h = ctypes.c_void_p(None)
+        r = self.run
+        _check(load().aot_batch_capture(ctypes.byref(bc),
+                                        ctypes.byref(sc) if sc is not None else None,
+                                        ctypes.byref(oc), _ptr(r.tri_off), _ptr(r.graph_tri),
+                                        _ptr(r.tri), cap, _ptr(r.ws), r.ws.numel(),
+                                        ctypes.byref(h)), "aot_batch_capture")
+        self._h = h
+
+    def launch(self, stream=None):
+        _check(load().aot_batch_launch(self._h, _stream(stream)), "aot_batch_launch")
+
+    def close(self):
+        if self._h:
+            load().aot_batch_destroy(self._h)
+            self._h = ctypes.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

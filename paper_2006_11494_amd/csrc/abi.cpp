@@ -1,4 +1,5 @@
 // The C ABI (include/aot.h): argument checks, workspace sizing, status codes.
+#include <algorithm>
 #include <climits>
 #include <cstring>
 #include <string>
@@ -66,7 +67,87 @@ int hip_status(int rc, const char* err) {
   }
 }
 
+// A batch's offsets and the bits its (graph, degree) sort key needs.
+int check_batch(const aot_batch* b, int* dbits, int* gbits, int64_t* max_n) {
+  if (!b) return fail(AOT_E_ARG, "batch is NULL");
+  if (b->count < 1) return fail(AOT_E_ARG, "batch count < 1");
+  if (!b->voff_host || !b->voff) return fail(AOT_E_ARG, "batch offsets are NULL");
+  int rc = check_graph_sizes(b->arena.n, b->arena.nnz);
+  if (rc) return rc;
+  if (!b->arena.rowptr) return fail(AOT_E_ARG, "arena rowptr is NULL");
+  if (b->arena.nnz > 0 && !b->arena.col) return fail(AOT_E_ARG, "arena col is NULL");
+  const int64_t* v = b->voff_host;
+  if (v[0] != 0 || v[b->count] != b->arena.n)
+    return fail(AOT_E_ARG, "voff[0] must be 0 and voff[count] the arena's n");
+  int64_t mx = 0;
+  for (int32_t g = 0; g < b->count; ++g) {
+    if (v[g + 1] < v[g]) return fail(AOT_E_ARG, "voff is decreasing");
+    mx = std::max<int64_t>(mx, v[g + 1] - v[g]);
+  }
+  *max_n = mx;
+  *dbits = aot::ceil_log2(mx);
+  *gbits = aot::ceil_log2((int64_t)b->count);
+  if (*dbits + *gbits > 31)
+    return fail(AOT_E_OVERFLOW, "(graph, degree) sort key needs more than 31 bits");
+  return AOT_OK;
+}
+
+size_t batch_ws_bytes(int32_t n, int64_t nnz) {
+  // orientation scratch and count workspace alias: the first is dead before
+  // the second is first written (same stream)
+  return std::max(aot::orient_workspace_bytes(n, nnz), aot::count_workspace_bytes(n, nnz / 2));
+}
+
+int batch_enqueue(const aot_batch* b, const aot_schedule* sc, aot_oriented* out, int64_t* tri_off,
+                  int64_t* graph_tri, int32_t* tri, int64_t cap, void* ws, size_t ws_bytes,
+                  hipStream_t s) {
+  int dbits = 0, gbits = 0;
+  int64_t max_n = 0;
+  int rc = check_batch(b, &dbits, &gbits, &max_n);
+  if (rc) return rc;
+  const int32_t n = b->arena.n;
+  const int64_t m = b->arena.nnz / 2;
+  if (!out || !tri_off || !graph_tri) return fail(AOT_E_ARG, "output is NULL");
+  if (!out->rowptr || !out->in_rowptr) return fail(AOT_E_ARG, "output rowptr is NULL");
+  if (n > 0 && (!out->perm || !out->rank)) return fail(AOT_E_ARG, "output perm/rank is NULL");
+  if (m > 0 && (!out->col || !out->tail || !out->in_col))
+    return fail(AOT_E_ARG, "an output edge array is NULL");
+  if (cap < 0) return fail(AOT_E_ARG, "cap < 0");
+  if (cap > 0 && !tri) return fail(AOT_E_ARG, "tri is NULL");
+  if (cap > INT64_MAX / 3) return fail(AOT_E_CAPACITY, "cap too large");
+  aot::DrainSchedule ds;
+  if (sc) {
+    if (sc->heavy_min < 0 || sc->light_rounds < 0) return fail(AOT_E_ARG, "negative schedule entry");
+    if (sc->light_rounds > 1024) return fail(AOT_E_ARG, "light_rounds > 1024");
+    ds.heavy_min = sc->heavy_min;
+    ds.rounds = sc->light_rounds;
+    ds.table_given = sc->use_table != 0;
+    for (int k = 0; k < AOT_NUM_BUCKETS; ++k) ds.table[k] = sc->table[k];
+  }
+  ds.max_span = max_n;
+  if (ws_bytes < batch_ws_bytes(n, b->arena.nnz) || !ws)
+    return fail(AOT_E_WORKSPACE, "workspace smaller than aot_batch_workspace()");
+  out->n = n;
+  out->m = m;
+  const char* err = nullptr;
+  rc = aot::orient_batch_run(n, b->arena.nnz, b->arena.rowptr, b->arena.col, b->voff, b->count,
+                             dbits, gbits, out->rowptr, out->col, out->tail, out->perm,
+                             out->rank, out->in_rowptr, out->in_col, ws, ws_bytes, s, &err);
+  if (rc) return hip_status(rc, err);
+  rc = aot::drain_run(n, m, out->rowptr, out->col, out->tail, out->perm, out->in_rowptr,
+                      out->in_col, ds, tri_off, ws, ws_bytes, 0, cap, tri, s, &err);
+  if (rc) return hip_status(rc, err);
+  if (aot::batch_totals(b->count, b->voff, out->rowptr, tri_off, graph_tri, s))
+    return fail(AOT_E_HIP, "batch totals launch failed");
+  return ok();
+}
+
 }  // namespace
+
+struct aot_batch_graph {
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+};
 
 extern "C" {
 
@@ -205,6 +286,73 @@ int aot_bucket_features(const void* ws, size_t ws_bytes, int32_t n, int64_t m, f
   if (ws_bytes < aot::count_workspace_bytes(n, m)) return fail(AOT_E_WORKSPACE, "workspace too small");
   return aot::count_features(ws, ws_bytes, n, m, features, present) ? fail(AOT_E_HIP, "copy failed")
                                                                      : ok();
+}
+
+int aot_batch_workspace(const aot_batch* b, size_t* bytes) {
+  if (!bytes) return fail(AOT_E_ARG, "bytes is NULL");
+  int dbits = 0, gbits = 0;
+  int64_t max_n = 0;
+  int rc = check_batch(b, &dbits, &gbits, &max_n);
+  if (rc) return rc;
+  *bytes = batch_ws_bytes(b->arena.n, b->arena.nnz);
+  return ok();
+}
+
+int aot_batch_run(const aot_batch* b, const aot_schedule* sc, aot_oriented* out,
+                  int64_t* tri_off, int64_t* graph_tri, int32_t* tri, int64_t cap, void* ws,
+                  size_t ws_bytes, void* stream) {
+  return batch_enqueue(b, sc, out, tri_off, graph_tri, tri, cap, ws, ws_bytes,
+                       static_cast<hipStream_t>(stream));
+}
+
+int aot_batch_capture(const aot_batch* b, const aot_schedule* sc, aot_oriented* out,
+                      int64_t* tri_off, int64_t* graph_tri, int32_t* tri, int64_t cap, void* ws,
+                      size_t ws_bytes, aot_batch_graph** graph) {
+  if (!graph) return fail(AOT_E_ARG, "graph is NULL");
+  *graph = nullptr;
+  int dbits = 0, gbits = 0;
+  int64_t max_n = 0;
+  int rc = check_batch(b, &dbits, &gbits, &max_n);   // fail before opening a capture
+  if (rc) return rc;
+  hipStream_t cs = nullptr;
+  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess)
+    return fail(AOT_E_HIP, "stream creation failed");
+  if (hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed) != hipSuccess) {
+    hipStreamDestroy(cs);
+    return fail(AOT_E_HIP, "hipStreamBeginCapture failed");
+  }
+  rc = batch_enqueue(b, sc, out, tri_off, graph_tri, tri, cap, ws, ws_bytes, cs);
+  const std::string detail = g_err;
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(cs, &g);
+  hipStreamDestroy(cs);
+  if (rc) {
+    if (g) hipGraphDestroy(g);
+    return fail(rc, detail);
+  }
+  if (e != hipSuccess || !g) return fail(AOT_E_HIP, "stream capture failed");
+  hipGraphExec_t x = nullptr;
+  if (hipGraphInstantiate(&x, g, nullptr, nullptr, 0) != hipSuccess) {
+    hipGraphDestroy(g);
+    return fail(AOT_E_HIP, "hipGraphInstantiate failed");
+  }
+  *graph = new aot_batch_graph{g, x};
+  return ok();
+}
+
+int aot_batch_launch(const aot_batch_graph* graph, void* stream) {
+  if (!graph) return fail(AOT_E_ARG, "graph is NULL");
+  if (hipGraphLaunch(graph->exec, static_cast<hipStream_t>(stream)) != hipSuccess)
+    return fail(AOT_E_HIP, "hipGraphLaunch failed");
+  return ok();
+}
+
+int aot_batch_destroy(aot_batch_graph* graph) {
+  if (!graph) return ok();
+  hipGraphExecDestroy(graph->exec);
+  hipGraphDestroy(graph->graph);
+  delete graph;
+  return ok();
 }
 
 }  // extern "C"

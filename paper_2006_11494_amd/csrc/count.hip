@@ -359,7 +359,7 @@ __device__ __forceinline__ int advance(const int32_t* pre, int kc, int K, int32_
 }
 
 struct HeavyArgs {
-  int arm;                      // requested arm of this class
+  int32_t arms[kHeavyClasses];  // requested arm of each heavy class
   int idx_words;                // LDS words of the index (dynamic shared memory)
   const int2* items;
   int64_t item_base, item_count;
@@ -630,159 +630,200 @@ __device__ int64_t run_item(HeavyShared<kEmit>& sh, uint32_t* lds, const HeavyAr
   }
 }
 
+// One work item: owner b and a window of up to kItemSpan of its neighbours
+// (out-list, then in-list).  Ends with a barrier.
+template <bool kEmit>
+__device__ void heavy_item(HeavyShared<kEmit>& sh, uint32_t* lds, const HeavyArgs& a, int64_t it,
+                           int64_t& tri_block, Digest& dg) {
+  const int tid = threadIdx.x;
+  const int2 item = a.items[it];
+  const int32_t b = item.x;
+  const int64_t ob = a.orow[b];
+  const int32_t db = (int32_t)(a.orow[b + 1] - ob);
+  const int64_t ib = a.irow[b];
+  const int32_t deg = db + (int32_t)(a.irow[b + 1] - ib);
+  const int32_t j0 = item.y;
+  const int32_t j1 = min(deg, j0 + kItemSpan);
+
+  // owned neighbours of this window, compacted with a prefix of their probe counts
+  constexpr int kPer = kItemSpan / kBlock;
+  int32_t ny[kPer], ne[kPer], nd[kPer];
+  int64_t noy[kPer], nbase[kPer];
+  bool keep[kPer];
+  int64_t packed = 0;
+#pragma unroll
+  for (int i = 0; i < kPer; ++i) {
+    const int32_t j = j0 + tid + i * kBlock;
+    keep[i] = false;
+    nd[i] = 0;
+    ny[i] = 0; ne[i] = 0; noy[i] = 0; nbase[i] = 0;
+    if (j < j1) {
+      int32_t y, e = 0;
+      const bool out_edge = j < db;
+      if (out_edge) { y = a.ocol[ob + j]; e = (int32_t)(ob + j); }
+      else y = a.icol[ib + (j - db)];
+      const int64_t oy = a.orow[y];
+      const int32_t dy = (int32_t)(a.orow[y + 1] - oy);
+      const bool owned = dy < db || (dy == db && y < b);
+      // an owned in-edge <y, b>: its id is b's place in N+(y), the list probed next
+      if (owned && !out_edge) e = (int32_t)(oy + lower_bound(a.ocol + oy, dy, b));
+      ny[i] = y; ne[i] = e; noy[i] = oy; nd[i] = dy;
+      if constexpr (!kEmit) {
+        if (owned && dy == 0) a.cnt[e] = 0;
+        keep[i] = owned && dy > 0;
+      } else {
+        if (owned) {
+          const int64_t lo = a.tri_off[e], hi = a.tri_off[e + 1];
+          nbase[i] = lo;
+          keep[i] = hi > lo && (a.digest || (hi > a.first && lo < a.first + a.count));
+        }
+      }
+    }
+    if (keep[i]) packed += (int64_t(1) << 32) + nd[i];
+  }
+  int64_t total;
+  int64_t at = block_exclusive_scan(packed, sh.scan_tmp, &total);
+  const int K = (int)(total >> 32);
+  const int32_t P = (int32_t)(total & 0xFFFFFFFF);
+#pragma unroll
+  for (int i = 0; i < kPer; ++i) {
+    if (keep[i]) {
+      const int slot = (int)(at >> 32);
+      sh.nb_src[slot] = (int32_t)(noy[i] - (at & 0xFFFFFFFF));
+      sh.nb_pre[slot] = (int32_t)(at & 0xFFFFFFFF);
+      sh.nb_e[slot] = ne[i];
+      sh.nb_acc[slot] = 0;
+      if constexpr (kEmit) {
+        sh.nb_base[slot] = nbase[i];
+        sh.nb_py[slot] = a.perm[ny[i]];
+      }
+      at += (int64_t(1) << 32) + nd[i];
+    }
+  }
+  if (tid == 0) sh.nb_pre[K] = P;
+  __syncthreads();
+  if (K == 0) return;           // nothing owned in this window: no index needed
+  if constexpr (kEmit) {
+    // neighbour-aligned probe ranges of the four waves: wave w starts at the
+    // first neighbour whose probes begin at or after w * P / 4
+    if (tid <= kWavesPerBlock) {
+      const int32_t target = (int32_t)(((int64_t)P * tid) / kWavesPerBlock);
+      int lo = 0, hi = K;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (sh.nb_pre[mid] < target) lo = mid + 1; else hi = mid;
+      }
+      sh.wave_k[tid] = tid == kWavesPerBlock ? K : lo;
+    }
+  }
+  const int32_t* list = a.ocol + ob;
+  const int64_t span = (int64_t)list[db - 1] - list[0] + 1;
+  const int arm = resolve_arm(a.arms[heavy_class(db)], db, span, a.idx_words);
+  const int32_t pb = kEmit ? a.perm[b] : 0;
+  int64_t t = 0;
+  switch (arm) {
+    case kArmBitmap: t = run_item<kArmBitmap, kEmit>(sh, lds, a, list, db, K, P, pb, dg); break;
+    case kArmHash: t = run_item<kArmHash, kEmit>(sh, lds, a, list, db, K, P, pb, dg); break;
+    case kArmSorted: t = run_item<kArmSorted, kEmit>(sh, lds, a, list, db, K, P, pb, dg); break;
+    default: t = run_item<kArmGlobal, kEmit>(sh, lds, a, list, db, K, P, pb, dg); break;
+  }
+  if constexpr (!kEmit) tri_block += t;
+  __syncthreads();
+  if constexpr (!kEmit)
+    for (int s = tid; s < K; s += kBlock) a.cnt[sh.nb_e[s]] = sh.nb_acc[s];
+  __syncthreads();
+}
+
+template <bool kEmit>
+__device__ void heavy_finish(HeavyShared<kEmit>& sh, const HeavyArgs& a, int64_t tri_block,
+                             const Digest& dg) {
+  if constexpr (!kEmit) {
+    const int64_t t = block_sum(tri_block, sh.scan_tmp);
+    if (a.tri_stat && threadIdx.x == 0 && t) atomicAdd(u64p(a.tri_stat), (unsigned long long)t);
+  } else {
+    if (a.digest) flush_digest(dg, a.digest);
+  }
+}
+
 // A launch covers the work items of one heavy class; the LDS index lives in
 // dynamic shared memory of a.idx_words words.
 template <bool kEmit>
 __global__ __launch_bounds__(kBlock) void k_heavy(HeavyArgs a) {
   __shared__ HeavyShared<kEmit> sh;
   extern __shared__ uint32_t lds[];
-  const int tid = threadIdx.x;
   int64_t tri_block = 0;
   Digest dg;
-  for (int64_t it = blockIdx.x; it < a.item_count; it += gridDim.x) {
-    const int2 item = a.items[a.item_base + it];
-    const int32_t b = item.x;
-    const int64_t ob = a.orow[b];
-    const int32_t db = (int32_t)(a.orow[b + 1] - ob);
-    const int64_t ib = a.irow[b];
-    const int32_t deg = db + (int32_t)(a.irow[b + 1] - ib);
-    const int32_t j0 = item.y;
-    const int32_t j1 = min(deg, j0 + kItemSpan);
+  for (int64_t it = blockIdx.x; it < a.item_count; it += gridDim.x)
+    heavy_item<kEmit>(sh, lds, a, a.item_base + it, tri_block, dg);
+  heavy_finish<kEmit>(sh, a, tri_block, dg);
+}
 
-    // owned neighbours of this window, compacted with a prefix of their probe counts
-    constexpr int kPer = kItemSpan / kBlock;
-    int32_t ny[kPer], ne[kPer], nd[kPer];
-    int64_t noy[kPer], nbase[kPer];
-    bool keep[kPer];
-    int64_t packed = 0;
-#pragma unroll
-    for (int i = 0; i < kPer; ++i) {
-      const int32_t j = j0 + tid + i * kBlock;
-      keep[i] = false;
-      nd[i] = 0;
-      ny[i] = 0; ne[i] = 0; noy[i] = 0; nbase[i] = 0;
-      if (j < j1) {
-        int32_t y, e = 0;
-        const bool out_edge = j < db;
-        if (out_edge) { y = a.ocol[ob + j]; e = (int32_t)(ob + j); }
-        else y = a.icol[ib + (j - db)];
-        const int64_t oy = a.orow[y];
-        const int32_t dy = (int32_t)(a.orow[y + 1] - oy);
-        const bool owned = dy < db || (dy == db && y < b);
-        // an owned in-edge <y, b>: its id is b's place in N+(y), the list probed next
-        if (owned && !out_edge) e = (int32_t)(oy + lower_bound(a.ocol + oy, dy, b));
-        ny[i] = y; ne[i] = e; noy[i] = oy; nd[i] = dy;
-        if constexpr (!kEmit) {
-          if (owned && dy == 0) a.cnt[e] = 0;
-          keep[i] = owned && dy > 0;
-        } else {
-          if (owned) {
-            const int64_t lo = a.tri_off[e], hi = a.tri_off[e + 1];
-            nbase[i] = lo;
-            keep[i] = hi > lo && (a.digest || (hi > a.first && lo < a.first + a.count));
-          }
-        }
-      }
-      if (keep[i]) packed += (int64_t(1) << 32) + nd[i];
-    }
-    int64_t total;
-    int64_t at = block_exclusive_scan(packed, sh.scan_tmp, &total);
-    const int K = (int)(total >> 32);
-    const int32_t P = (int32_t)(total & 0xFFFFFFFF);
-#pragma unroll
-    for (int i = 0; i < kPer; ++i) {
-      if (keep[i]) {
-        const int slot = (int)(at >> 32);
-        sh.nb_src[slot] = (int32_t)(noy[i] - (at & 0xFFFFFFFF));
-        sh.nb_pre[slot] = (int32_t)(at & 0xFFFFFFFF);
-        sh.nb_e[slot] = ne[i];
-        sh.nb_acc[slot] = 0;
-        if constexpr (kEmit) {
-          sh.nb_base[slot] = nbase[i];
-          sh.nb_py[slot] = a.perm[ny[i]];
-        }
-        at += (int64_t(1) << 32) + nd[i];
-      }
-    }
-    if (tid == 0) sh.nb_pre[K] = P;
+// Persistent form: one launch drains the work items of every heavy class
+// through an atomic cursor, heaviest class first (items are stored in class
+// order).  The grid is sized to the resident workgroups, not to the work, so
+// the launch needs nothing from the host.
+template <bool kEmit>
+__global__ __launch_bounds__(kBlock) void k_heavy_drain(HeavyArgs a,
+                                                        const int64_t* __restrict__ stats,
+                                                        unsigned long long* cursor) {
+  __shared__ HeavyShared<kEmit> sh;
+  __shared__ int64_t next;
+  extern __shared__ uint32_t lds[];
+  int64_t total = 0;
+  for (int q = 0; q < kHeavyClasses; ++q) total += stats[(kHeavyBase + q) * kStats + kSItems];
+  int64_t tri_block = 0;
+  Digest dg;
+  while (true) {
+    if (threadIdx.x == 0) next = (int64_t)atomicAdd(cursor, 1ull);
     __syncthreads();
-    if (K == 0) continue;         // nothing owned in this window: no index needed
-    if constexpr (kEmit) {
-      // neighbour-aligned probe ranges of the four waves: wave w starts at the
-      // first neighbour whose probes begin at or after w * P / 4
-      if (tid <= kWavesPerBlock) {
-        const int32_t target = (int32_t)(((int64_t)P * tid) / kWavesPerBlock);
-        int lo = 0, hi = K;
-        while (lo < hi) {
-          const int mid = (lo + hi) >> 1;
-          if (sh.nb_pre[mid] < target) lo = mid + 1; else hi = mid;
-        }
-        sh.wave_k[tid] = tid == kWavesPerBlock ? K : lo;
-      }
-    }
-    const int32_t* list = a.ocol + ob;
-    const int64_t span = (int64_t)list[db - 1] - list[0] + 1;
-    const int arm = resolve_arm(a.arm, db, span, a.idx_words);
-    const int32_t pb = kEmit ? a.perm[b] : 0;
-    int64_t t = 0;
-    switch (arm) {
-      case kArmBitmap: t = run_item<kArmBitmap, kEmit>(sh, lds, a, list, db, K, P, pb, dg); break;
-      case kArmHash: t = run_item<kArmHash, kEmit>(sh, lds, a, list, db, K, P, pb, dg); break;
-      case kArmSorted: t = run_item<kArmSorted, kEmit>(sh, lds, a, list, db, K, P, pb, dg); break;
-      default: t = run_item<kArmGlobal, kEmit>(sh, lds, a, list, db, K, P, pb, dg); break;
-    }
-    if constexpr (!kEmit) tri_block += t;
+    const int64_t t = next;
     __syncthreads();
-    if constexpr (!kEmit)
-      for (int s = tid; s < K; s += kBlock) a.cnt[sh.nb_e[s]] = sh.nb_acc[s];
-    __syncthreads();
+    if (t >= total) break;
+    heavy_item<kEmit>(sh, lds, a, total - 1 - t, tri_block, dg);
   }
-  if constexpr (!kEmit) {
-    const int64_t t = block_sum(tri_block, sh.scan_tmp);
-    if (tid == 0 && t) atomicAdd(u64p(a.tri_stat), (unsigned long long)t);
-  } else {
-    if (a.digest) flush_digest(dg, a.digest);
-  }
+  heavy_finish<kEmit>(sh, a, tri_block, dg);
 }
 
 // ---------------------------------------------------------------- light path
 
+struct LightArgs {
+  const int32_t* elist;
+  const int64_t* orow;
+  const int32_t* ocol;
+  const int32_t* otail;
+  int32_t* cnt;                 // count pass
+  const int64_t* tri_off;       // write pass
+  const int32_t* perm;
+  int64_t first, count;
+  int32_t* out;
+  unsigned long long* digest;   // write pass in digest mode
+  unsigned long long* vcount;
+};
+
+// Binned light edges elist[t0 .. t1), G lanes per edge: each lane binary-
+// searches N+(b) for its share of N+(s).
 template <int G, bool kEmit>
-__global__ __launch_bounds__(kBlock) void k_light(int64_t base, int64_t total,
-                                                  const int32_t* __restrict__ elist,
-                                                  const int64_t* __restrict__ orow,
-                                                  const int32_t* __restrict__ ocol,
-                                                  const int32_t* __restrict__ otail,
-                                                  int32_t* __restrict__ cnt,
-                                                  int64_t* __restrict__ tri_stat,
-                                                  const int64_t* __restrict__ tri_off,
-                                                  const int32_t* __restrict__ perm,
-                                                  int64_t first, int64_t count,
-                                                  int32_t* __restrict__ out,
-                                                  unsigned long long* digest,
-                                                  unsigned long long* vcount) {
+__device__ __forceinline__ void light_range(const LightArgs& a, int64_t t0, int64_t t1,
+                                            int64_t& tri, Digest& dg) {
   constexpr int kGroups = kBlock / G;
   const int gi = threadIdx.x / G, li = threadIdx.x % G;
-  int64_t tri = 0;
-  Digest dg;
-  for (int64_t t = (int64_t)blockIdx.x * kGroups + gi; t < total;
-       t += (int64_t)gridDim.x * kGroups) {
-    const int32_t e = elist[base + t];
-    const int32_t u = otail[e], v = ocol[e];
-    const EdgeEnds x = edge_ends(orow, u, v);
-    const int32_t* ps = ocol + orow[x.s];
-    const int32_t* pb = ocol + orow[x.b];
+  for (int64_t t = t0 + gi; t < t1; t += kGroups) {
+    const int32_t e = a.elist[t];
+    const int32_t u = a.otail[e], v = a.ocol[e];
+    const EdgeEnds x = edge_ends(a.orow, u, v);
+    const int32_t* ps = a.ocol + a.orow[x.s];
+    const int32_t* pb = a.ocol + a.orow[x.b];
     if constexpr (!kEmit) {
       int32_t hits = 0;
       for (int32_t q = li; q < x.c; q += G) hits += contains_sorted(pb, x.db, ps[q]);
       tri += hits;
       hits = group_sum<G>(hits);
-      if (li == 0) cnt[e] = hits;
+      if (li == 0) a.cnt[e] = hits;
     } else {
-      int64_t pos = tri_off[e];
-      const int64_t end = tri_off[e + 1];
-      if (pos == end || (!digest && (end <= first || pos >= first + count))) continue;
-      const int32_t pu = perm[u], pv = perm[v];
+      int64_t pos = a.tri_off[e];
+      const int64_t end = a.tri_off[e + 1];
+      if (pos == end || (!a.digest && (end <= a.first || pos >= a.first + a.count))) continue;
+      const int32_t pu = a.perm[u], pv = a.perm[v];
       for (int32_t q0 = 0; q0 < x.c; q0 += G) {
         const int32_t q = q0 + li;
         const int32_t w = q < x.c ? ps[q] : 0;
@@ -790,31 +831,105 @@ __global__ __launch_bounds__(kBlock) void k_light(int64_t base, int64_t total,
         const uint64_t mask = ballot(hit);
         const int64_t at = pos + popc_below_in_group<G>(mask);
         if (hit) {
-          int32_t t0 = pu, t1 = pv, t2 = perm[w];
-          sort3(t0, t1, t2);
-          if (digest) {
-            dg.add(t0, t1, t2);
-            if (vcount) {
-              atomicAdd(&vcount[t0], 1ull);
-              atomicAdd(&vcount[t1], 1ull);
-              atomicAdd(&vcount[t2], 1ull);
+          int32_t t0_ = pu, t1_ = pv, t2_ = a.perm[w];
+          sort3(t0_, t1_, t2_);
+          if (a.digest) {
+            dg.add(t0_, t1_, t2_);
+            if (a.vcount) {
+              atomicAdd(&a.vcount[t0_], 1ull);
+              atomicAdd(&a.vcount[t1_], 1ull);
+              atomicAdd(&a.vcount[t2_], 1ull);
             }
-          } else if (at >= first && at < first + count) {
-            int32_t* o = out + 3 * (at - first);
-            o[0] = t0; o[1] = t1; o[2] = t2;
+          } else if (at >= a.first && at < a.first + a.count) {
+            int32_t* o = a.out + 3 * (at - a.first);
+            o[0] = t0_; o[1] = t1_; o[2] = t2_;
           }
         }
         pos += __popcll(group_bits<G>(mask));
       }
     }
   }
+}
+
+template <bool kEmit>
+__device__ void light_finish(const LightArgs& a, int64_t tri, const Digest& dg,
+                             int64_t* tri_stat) {
   if constexpr (!kEmit) {
     __shared__ int64_t red[kWavesPerBlock];
     const int64_t s = block_sum(tri, red);
-    if (threadIdx.x == 0 && s) atomicAdd(u64p(tri_stat), (unsigned long long)s);
+    if (tri_stat && threadIdx.x == 0 && s) atomicAdd(u64p(tri_stat), (unsigned long long)s);
   } else {
-    if (digest) flush_digest(dg, digest);
+    if (a.digest) flush_digest(dg, a.digest);
   }
+}
+
+// A launch covers one light bin, elist[base .. base + total).
+template <int G, bool kEmit>
+__global__ __launch_bounds__(kBlock) void k_light(LightArgs a, int64_t base, int64_t total,
+                                                  int64_t* tri_stat) {
+  constexpr int kGroups = kBlock / G;
+  int64_t tri = 0;
+  Digest dg;
+  for (int64_t c = (int64_t)blockIdx.x * kGroups; c < total; c += (int64_t)gridDim.x * kGroups)
+    light_range<G, kEmit>(a, base + c, base + min(c + kGroups, total), tri, dg);
+  light_finish<kEmit>(a, tri, dg, tri_stat);
+}
+
+// Lanes per edge of every light bin and the group-rounds of one task.
+struct LightPlan {
+  int32_t tile[kLightBins];
+  int32_t rounds;
+};
+
+// Persistent form: one launch drains every light bin through an atomic
+// cursor.  A task is rounds * (kBlock / G) consecutive edges of one bin; bins
+// of larger c (more probes per edge) come first.
+template <bool kEmit>
+__global__ __launch_bounds__(kBlock) void k_light_drain(LightArgs a, LightPlan p,
+                                                        const int64_t* __restrict__ stats,
+                                                        unsigned long long* cursor) {
+  __shared__ int64_t tpre[kLightBins + 1], ebase[kLightBins], eper[kLightBins], ecnt[kLightBins];
+  __shared__ int64_t next;
+  if (threadIdx.x == 0) {
+    int64_t base = 0;
+    for (int k = 0; k < kLightBins; ++k) {
+      ecnt[k] = stats[k * kStats + kSEdges];
+      ebase[k] = base;
+      base += ecnt[k];
+      eper[k] = (int64_t)(kBlock / p.tile[k]) * p.rounds;
+    }
+    int64_t run = 0;
+    for (int i = 0; i < kLightBins; ++i) {
+      const int k = kLightBins - 1 - i;
+      tpre[i] = run;
+      run += (ecnt[k] + eper[k] - 1) / eper[k];
+    }
+    tpre[kLightBins] = run;
+  }
+  __syncthreads();
+  int64_t tri = 0;
+  Digest dg;
+  while (true) {
+    if (threadIdx.x == 0) next = (int64_t)atomicAdd(cursor, 1ull);
+    __syncthreads();
+    const int64_t t = next;
+    __syncthreads();
+    if (t >= tpre[kLightBins]) break;
+    int i = 0;
+    while (tpre[i + 1] <= t) ++i;
+    const int k = kLightBins - 1 - i;
+    const int64_t lo = (t - tpre[i]) * eper[k];
+    const int64_t hi = min(lo + eper[k], ecnt[k]);
+    const int64_t t0 = ebase[k] + lo, t1 = ebase[k] + hi;
+    switch (p.tile[k]) {
+      case 4: light_range<4, kEmit>(a, t0, t1, tri, dg); break;
+      case 8: light_range<8, kEmit>(a, t0, t1, tri, dg); break;
+      case 16: light_range<16, kEmit>(a, t0, t1, tri, dg); break;
+      case 32: light_range<32, kEmit>(a, t0, t1, tri, dg); break;
+      default: light_range<64, kEmit>(a, t0, t1, tri, dg); break;
+    }
+  }
+  light_finish<kEmit>(a, tri, dg, nullptr);
 }
 
 // ---------------------------------------------------------------- host side
@@ -935,7 +1050,7 @@ CountWs carve_count(Carve& c, int32_t n, int64_t m) {
   w.elist = c.take<int32_t>(m);
   w.items = c.take<int2>(max_items(n, m));
   w.stats = c.take<int64_t>(kStatWords);
-  w.probes = c.take<unsigned long long>(4);
+  w.probes = c.take<unsigned long long>(8);   // [0] probes, [4..7] drain cursors
   w.scan_tmp = c.take<char>((int64_t)scan_workspace(m));
   return w;
 }
@@ -950,15 +1065,9 @@ CountWs carve_count(Carve& c, int32_t n, int64_t m) {
   } while (0)
 
 template <bool kEmit>
-hipError_t launch_light(int tile, unsigned grid, int64_t base, int64_t total,
-                        const int32_t* elist, const int64_t* orow, const int32_t* ocol,
-                        const int32_t* otail, int32_t* cnt, int64_t* tri_stat,
-                        const int64_t* tri_off, const int32_t* perm, int64_t first,
-                        int64_t count, int32_t* out, unsigned long long* digest,
-                        unsigned long long* vcount, hipStream_t s) {
-#define L(G) k_light<G, kEmit><<<grid, kBlock, 0, s>>>(base, total, elist, orow, ocol, otail, \
-                                                     cnt, tri_stat, tri_off, perm, first, count, \
-                                                     out, digest, vcount)
+hipError_t launch_light(int tile, unsigned grid, const LightArgs& a, int64_t base, int64_t total,
+                        int64_t* tri_stat, hipStream_t s) {
+#define L(G) k_light<G, kEmit><<<grid, kBlock, 0, s>>>(a, base, total, tri_stat)
   switch (tile) {
     case 4: L(4); break;
     case 8: L(8); break;
@@ -1046,14 +1155,15 @@ int run_buckets(bool emit, const Plan& plan, const int64_t* hs, const CountWs& w
       const unsigned grid = grid_cap(cdiv(edges, kBlock / tile));
       const int rec = timing_begin(emit ? 1 : 0, k, 0, tile, edges, st[kSProbes], 0,
                                    st[kSTriangles], s);
-      hipError_t e;
-      if (!emit)
-        e = launch_light<false>(tile, grid, lbase, edges, w.elist, orow, ocol, otail, w.cnt,
-                                w.stats + k * kStats + kSTriangles, nullptr, nullptr, 0, 0,
-                                nullptr, nullptr, nullptr, s);
-      else
-        e = launch_light<true>(tile, grid, lbase, edges, w.elist, orow, ocol, otail, nullptr,
-                               nullptr, tri_off, perm, first, count, out, digest, vcount, s);
+      LightArgs la;
+      la.elist = w.elist; la.orow = orow; la.ocol = ocol; la.otail = otail;
+      la.cnt = emit ? nullptr : w.cnt;
+      la.tri_off = tri_off; la.perm = perm; la.first = first; la.count = count; la.out = out;
+      la.digest = digest; la.vcount = vcount;
+      const hipError_t e =
+          emit ? launch_light<true>(tile, grid, la, lbase, edges, nullptr, s)
+               : launch_light<false>(tile, grid, la, lbase, edges,
+                                     w.stats + k * kStats + kSTriangles, s);
       AOT_TRY(e);
       timing_end(rec, s);
     }
@@ -1064,8 +1174,9 @@ int run_buckets(bool emit, const Plan& plan, const int64_t* hs, const CountWs& w
     const int64_t items = st[kSItems];
     if (items <= 0) continue;
     HeavyArgs a;
-    a.arm = plan.heavy_arm[h];
-    a.idx_words = index_words(a.arm, h, st[kSSpan]);
+    const int arm = plan.heavy_arm[h];
+    for (int q = 0; q < kHeavyClasses; ++q) a.arms[q] = arm;
+    a.idx_words = index_words(arm, h, st[kSSpan]);
     a.items = w.items;
     a.item_base = st[kSItemBase];
     a.item_count = items;
@@ -1079,7 +1190,7 @@ int run_buckets(bool emit, const Plan& plan, const int64_t* hs, const CountWs& w
     a.out = out;
     a.digest = digest;
     a.vcount = vcount;
-    const int rec = timing_begin(emit ? 1 : 0, kHeavyBase + h, a.arm, kBlock, st[kSEdges],
+    const int rec = timing_begin(emit ? 1 : 0, kHeavyBase + h, arm, kBlock, st[kSEdges],
                                  st[kSProbes], st[kSStaged], st[kSTriangles], s);
     const size_t dyn = sizeof(uint32_t) * (size_t)std::max(a.idx_words, 1);
     if (emit) k_heavy<true><<<grid_cap(items), kBlock, dyn, s>>>(a);
@@ -1115,7 +1226,7 @@ int count_run(int32_t n, int64_t m, const int64_t* orow, const int32_t* ocol, co
   }
   int32_t learned = 0;
   AOT_TRY(fill_i64(w.stats, kStatWords, 0, s));
-  AOT_TRY(fill_i64(reinterpret_cast<int64_t*>(w.probes), 4, 0, s));
+  AOT_TRY(fill_i64(reinterpret_cast<int64_t*>(w.probes), 8, 0, s));
   std::vector<int64_t> hs(kStatWords, 0);
   if (m > 0) {
     const unsigned ge = grid_cap(std::min<int64_t>(cdiv(m, kBlock), 2048));
@@ -1163,6 +1274,146 @@ int count_run(int32_t n, int64_t m, const int64_t* orow, const int32_t* ocol, co
   result[1] = (uint64_t)pr;
   timing_fill_triangles(hs.data(), kStats, kSTriangles);
   return 0;
+}
+
+namespace {
+
+struct PlanWords {
+  int32_t w[kPlanWords];
+};
+
+__global__ void k_store_plan(PlanWords p, int32_t* __restrict__ plan) {
+  for (int i = threadIdx.x; i < kPlanWords; i += blockDim.x) plan[i] = p.w[i];
+}
+
+// Per-graph triangle offsets of a batch: graph g's triangles are global
+// indices [gtri[g], gtri[g+1]), its edges [orow[voff[g]], orow[voff[g+1]]).
+__global__ void k_batch_totals(int32_t count, const int64_t* __restrict__ voff,
+                               const int64_t* __restrict__ orow,
+                               const int64_t* __restrict__ tri_off, int64_t* __restrict__ gtri) {
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g <= count;
+       g += (int64_t)gridDim.x * blockDim.x)
+    gtri[g] = tri_off[orow[voff[g]]];
+}
+
+// Resident workgroups of a kernel on the current device: the grid of a
+// persistent launch.
+template <typename K>
+int resident_grid(K kernel, size_t dyn, unsigned* grid) {
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, kBlock, dyn) != hipSuccess)
+    return -5;
+  *grid = (unsigned)std::max(1, cus * std::max(per, 1));
+  return 0;
+}
+
+}  // namespace
+
+// The probe passes with no host synchronisation: binning, the count pass as
+// two persistent drains (heavy owner items, then light edges), the scan, and
+// the write pass of triangles [first, first + count) the same way.  Launch
+// sizes depend only on n, m and the schedule, so the sequence can be
+// captured in a HIP graph.  Stores the plan in the workspace like count_run,
+// so list_run / digest_run work on it afterwards.
+int drain_run(int32_t n, int64_t m, const int64_t* orow, const int32_t* ocol,
+              const int32_t* otail, const int32_t* perm, const int64_t* irow,
+              const int32_t* icol, const DrainSchedule& sc, int64_t* tri_off, void* ws,
+              size_t ws_bytes, int64_t first, int64_t count, int32_t* out, hipStream_t s,
+              const char** err) {
+  Carve c(ws, ws_bytes);
+  CountWs w = carve_count(c, n, m);
+  if (!c.ok()) {
+    *err = "count workspace too small";
+    return -4;
+  }
+  Plan plan;
+  DispatchView dv;
+  dv.table = sc.table_given ? sc.table : nullptr;
+  if (!plan_from(dv, &plan)) {
+    *err = "schedule table holds an unknown arm or tile code";
+    return -6;
+  }
+  const int32_t heavy_min = sc.heavy_min > 0 ? sc.heavy_min : kDefaultHeavyMin;
+  LightPlan lp;
+  for (int k = 0; k < kLightBins; ++k) lp.tile[k] = plan.light_tile[k];
+  lp.rounds = sc.rounds > 0 ? sc.rounds : 4;
+  const int64_t span_words = sc.max_span > 0 ? cdiv(sc.max_span, 32) : kMaxIndexWords;
+  const int idx_words = (int)std::max<int64_t>(1, std::min<int64_t>(kMaxIndexWords, span_words));
+  const size_t dyn = sizeof(uint32_t) * (size_t)idx_words;
+
+  AOT_TRY(fill_i64(w.stats, kStatWords, 0, s));
+  AOT_TRY(fill_i64(reinterpret_cast<int64_t*>(w.probes), 8, 0, s));
+  {
+    PlanWords pw;
+    for (int i = 0; i < kPlanWords; ++i) pw.w[i] = 0;
+    plan_to_table(plan, pw.w);
+    pw.w[kNumBuckets] = 0;          // not learned
+    pw.w[kNumBuckets + 1] = 1;      // plan valid
+    k_store_plan<<<1, 64, 0, s>>>(pw, w.plan);
+    AOT_TRY(hipGetLastError());
+  }
+  HeavyArgs ha;
+  for (int h = 0; h < kHeavyClasses; ++h) ha.arms[h] = plan.heavy_arm[h];
+  ha.idx_words = idx_words;
+  ha.items = w.items;
+  ha.item_base = 0;
+  ha.item_count = 0;
+  ha.orow = orow; ha.ocol = ocol; ha.irow = irow; ha.icol = icol;
+  ha.cnt = w.cnt;
+  ha.tri_stat = nullptr;
+  ha.tri_off = tri_off;
+  ha.perm = perm;
+  ha.first = first;
+  ha.count = count;
+  ha.out = out;
+  ha.digest = nullptr;
+  ha.vcount = nullptr;
+  LightArgs la;
+  la.elist = w.elist; la.orow = orow; la.ocol = ocol; la.otail = otail;
+  la.cnt = w.cnt;
+  la.tri_off = tri_off; la.perm = perm; la.first = first; la.count = count; la.out = out;
+  la.digest = nullptr; la.vcount = nullptr;
+  unsigned gh0, gh1, gl0, gl1;
+  if (resident_grid(k_heavy_drain<false>, dyn, &gh0) || resident_grid(k_heavy_drain<true>, dyn, &gh1) ||
+      resident_grid(k_light_drain<false>, 0, &gl0) || resident_grid(k_light_drain<true>, 0, &gl1)) {
+    *err = "occupancy query failed";
+    return -5;
+  }
+  if (m > 0) {
+    const unsigned ge = grid_cap(std::min<int64_t>(cdiv(m, kBlock), 2048));
+    k_bin_count<<<ge, kBlock, 0, s>>>(m, orow, ocol, otail, heavy_min, w.cnt, w.code, w.stats,
+                                      w.probes);
+    AOT_TRY(hipGetLastError());
+    k_bin_scatter<<<grid_cap(std::min<int64_t>(cdiv(m, kScatterChunk), 4096)), kBlock, 0, s>>>(
+        m, w.code, w.stats, w.elist);
+    AOT_TRY(hipGetLastError());
+    const unsigned gv = grid_cap(std::min<int64_t>(cdiv(n, kBlock), 1024));
+    k_item_count<<<gv, kBlock, 0, s>>>(n, orow, ocol, irow, heavy_min, w.stats);
+    AOT_TRY(hipGetLastError());
+    k_item_scatter<<<gv, kBlock, 0, s>>>(n, orow, irow, heavy_min, w.stats, w.items);
+    AOT_TRY(hipGetLastError());
+    k_heavy_drain<false><<<gh0, kBlock, dyn, s>>>(ha, w.stats, w.probes + 4);
+    AOT_TRY(hipGetLastError());
+    k_light_drain<false><<<gl0, kBlock, 0, s>>>(la, lp, w.stats, w.probes + 5);
+    AOT_TRY(hipGetLastError());
+  }
+  AOT_TRY(exclusive_scan(w.cnt, tri_off, m, w.scan_tmp, s));
+  if (m > 0 && count > 0) {
+    k_heavy_drain<true><<<gh1, kBlock, dyn, s>>>(ha, w.stats, w.probes + 6);
+    AOT_TRY(hipGetLastError());
+    k_light_drain<true><<<gl1, kBlock, 0, s>>>(la, lp, w.stats, w.probes + 7);
+    AOT_TRY(hipGetLastError());
+  }
+  return 0;
+}
+
+int batch_totals(int32_t count, const int64_t* voff, const int64_t* orow, const int64_t* tri_off,
+                 int64_t* gtri, hipStream_t s) {
+  k_batch_totals<<<(unsigned)cdiv(count + 1, kBlock), kBlock, 0, s>>>(count, voff, orow, tri_off,
+                                                                      gtri);
+  return hipGetLastError() == hipSuccess ? 0 : -5;
 }
 
 namespace {

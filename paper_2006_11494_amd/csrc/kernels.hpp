@@ -63,6 +63,14 @@ int orient_run(int32_t n, int64_t nnz, const int64_t* rowptr, const int32_t* col
                int64_t* orow, int32_t* ocol, int32_t* otail, int32_t* perm, int32_t* rank,
                int64_t* irow, int32_t* icol, void* ws, size_t ws_bytes, hipStream_t s,
                const char** err);
+// Orientation of a batch held as one block-diagonal CSR (graph g owns
+// vertices [voff[g], voff[g+1])): ranks go graph by graph, (degree, id)
+// inside a graph; every launch is sized from n and nnz only (no host reads).
+// dbits / gbits: key bits of a degree / of a graph index.
+int orient_batch_run(int32_t n, int64_t nnz, const int64_t* rowptr, const int32_t* col,
+                     const int64_t* voff, int32_t count, int dbits, int gbits, int64_t* orow,
+                     int32_t* ocol, int32_t* otail, int32_t* perm, int32_t* rank, int64_t* irow,
+                     int32_t* icol, void* ws, size_t ws_bytes, hipStream_t s, const char** err);
 
 // ---- timing.cpp: the per-launch recorder of the probe passes.  A record is
 // opened just before a bucket's kernel launch and closed right after it,
@@ -95,6 +103,22 @@ int count_run(int32_t n, int64_t m, const int64_t* orow, const int32_t* ocol, co
 int list_run(int32_t n, int64_t m, const int64_t* orow, const int32_t* ocol, const int32_t* otail,
              const int32_t* perm, const int64_t* irow, const int32_t* icol, const DispatchView& d, const int64_t* tri_off, void* ws, size_t ws_bytes,
              int64_t first, int64_t count, int32_t* out, hipStream_t s, const char** err);
+
+// Schedule of the persistent probe passes (the autotuner's choices).
+struct DrainSchedule {
+  int32_t heavy_min = 0;             // 0 = library default
+  bool table_given = false;
+  int32_t table[kNumBuckets] = {0};  // codes as in aot_dispatch's table
+  int32_t rounds = 0;                // group-rounds per light task, 0 = default
+  int64_t max_span = 0;              // bound on an out-list's id span, 0 = unknown
+};
+int drain_run(int32_t n, int64_t m, const int64_t* orow, const int32_t* ocol,
+              const int32_t* otail, const int32_t* perm, const int64_t* irow,
+              const int32_t* icol, const DrainSchedule& sc, int64_t* tri_off, void* ws,
+              size_t ws_bytes, int64_t first, int64_t count, int32_t* out, hipStream_t s,
+              const char** err);
+int batch_totals(int32_t count, const int64_t* voff, const int64_t* orow, const int64_t* tri_off,
+                 int64_t* gtri, hipStream_t s);
 
 // The write pass in digest mode: nothing stored; digest = {T, hash sum, hash
 // xor} (host), vcount (device, optional) = triangles per original vertex id.

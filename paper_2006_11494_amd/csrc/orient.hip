@@ -27,7 +27,9 @@ enum : int {
   kCError = 5,
   kCSortCount = 8,    // [8..11] rows per sort class
   kCSortCursor = 12,  // [12..15]
-  kCounters = 16,
+  kCRowCount = 16,    // [16..19] rows per degree class (row-list mode)
+  kCRowCursor = 20,   // [20..23]
+  kCounters = 24,
 };
 
 constexpr int kSortClasses = 4;     // len <= 16, <= 64, <= 4096, longer
@@ -128,10 +130,54 @@ __global__ __launch_bounds__(kBlock) void k_perm_rank(int32_t n, const int32_t* 
   }
 }
 
-// deg+(r) and deg-(r) for ranks [r0, r1); G lanes per row (G = kBlock: one
-// row per workgroup).
+// Sort keys of a batch of graphs held as one block-diagonal CSR: vertex v of
+// graph g (voff[g] <= v < voff[g+1]) gets key (g << dbits) | deg(v), so the
+// stable sort ranks graph by graph and, inside a graph, by (degree, id).
+__global__ __launch_bounds__(kBlock) void k_batch_keys(int32_t n, const int64_t* __restrict__ voff,
+                                                       int32_t count, int dbits,
+                                                       const int64_t* __restrict__ rowptr,
+                                                       int32_t* __restrict__ keys,
+                                                       int32_t* __restrict__ vals) {
+  for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < n;
+       v += (int64_t)gridDim.x * kBlock) {
+    int lo = 0, hi = count;               // last g with voff[g] <= v
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (voff[mid] <= v) lo = mid; else hi = mid;
+    }
+    keys[v] = (int32_t)(((int64_t)lo << dbits) | (rowptr[v + 1] - rowptr[v]));
+    vals[v] = (int32_t)v;
+  }
+}
+
+// The rows a launch covers: ranks [r0, r1), or (row-list mode, rows !=
+// nullptr) the entries of degree class `cls` in `rows`, whose size the
+// device counters hold.
+struct RowSet {
+  int32_t r0, r1;
+  const int32_t* rows;
+  const int32_t* counters;
+  int cls;
+  __device__ __forceinline__ void bounds(int64_t* total, int64_t* base) const {
+    if (!rows) {
+      *total = r1 - r0;
+      *base = r0;
+      return;
+    }
+    int64_t b = 0;
+    for (int q = 0; q < cls; ++q) b += counters[kCRowCount + q];
+    *total = counters[kCRowCount + cls];
+    *base = b;
+  }
+  __device__ __forceinline__ int64_t at(int64_t base, int64_t t) const {
+    return rows ? (int64_t)rows[base + t] : base + t;
+  }
+};
+
+// deg+(r) and deg-(r) for the rows of a RowSet; G lanes per row (G = kBlock:
+// one row per workgroup).
 template <int G>
-__global__ __launch_bounds__(kBlock) void k_orient_count(int32_t r0, int32_t r1,
+__global__ __launch_bounds__(kBlock) void k_orient_count(RowSet rs,
                                                          const int64_t* __restrict__ rowptr,
                                                          const int32_t* __restrict__ col,
                                                          const int32_t* __restrict__ perm,
@@ -141,12 +187,15 @@ __global__ __launch_bounds__(kBlock) void k_orient_count(int32_t r0, int32_t r1,
   constexpr int kGroups = kBlock / G;
   __shared__ int32_t red[kWavesPerBlock];
   const int gi = threadIdx.x / G, li = threadIdx.x % G;
-  for (int64_t rb = r0 + (int64_t)blockIdx.x * kGroups; rb < r1;
-       rb += (int64_t)gridDim.x * kGroups) {
-    const int64_t r = rb + gi;
+  int64_t total, base;
+  rs.bounds(&total, &base);
+  for (int64_t tb = (int64_t)blockIdx.x * kGroups; tb < total;
+       tb += (int64_t)gridDim.x * kGroups) {
+    const bool live = tb + gi < total;
+    const int64_t r = live ? rs.at(base, tb + gi) : 0;
     int32_t cnt = 0;
     int64_t deg = 0;
-    if (r < r1) {
+    if (live) {
       const int32_t u = perm[r];
       const int64_t beg = rowptr[u];
       deg = rowptr[u + 1] - beg;
@@ -154,7 +203,7 @@ __global__ __launch_bounds__(kBlock) void k_orient_count(int32_t r0, int32_t r1,
     }
     if constexpr (G <= kWave) {
       cnt = group_sum<G>(cnt);
-      if (li == 0 && r < r1) {
+      if (li == 0 && live) {
         dplus[r] = cnt;
         dminus[r] = (int32_t)(deg - cnt);
       }
@@ -172,7 +221,7 @@ __global__ __launch_bounds__(kBlock) void k_orient_count(int32_t r0, int32_t r1,
 // (original order), and records each out-edge's tail.
 template <int G>
 __global__ __launch_bounds__(kBlock) void k_orient_write(
-    int32_t r0, int32_t r1, const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+    RowSet rs, const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
     const int32_t* __restrict__ perm, const int32_t* __restrict__ rank,
     const int64_t* __restrict__ orow, const int64_t* __restrict__ irow,
     int32_t* __restrict__ unsorted, int32_t* __restrict__ otail, int32_t* __restrict__ icol) {
@@ -180,11 +229,14 @@ __global__ __launch_bounds__(kBlock) void k_orient_write(
   __shared__ int32_t so[kWavesPerBlock], si[kWavesPerBlock];
   const int gi = threadIdx.x / G, li = threadIdx.x % G;
   const int w = threadIdx.x / kWave;
-  for (int64_t rb = r0 + (int64_t)blockIdx.x * kGroups; rb < r1;
-       rb += (int64_t)gridDim.x * kGroups) {
-    const int64_t r = rb + gi;
+  int64_t total, base;
+  rs.bounds(&total, &base);
+  for (int64_t tb = (int64_t)blockIdx.x * kGroups; tb < total;
+       tb += (int64_t)gridDim.x * kGroups) {
+    const bool live = tb + gi < total;
+    const int64_t r = live ? rs.at(base, tb + gi) : 0;
     int64_t beg = 0, deg = 0, op = 0, ip = 0;
-    if (r < r1) {
+    if (live) {
       const int32_t u = perm[r];
       beg = rowptr[u];
       deg = rowptr[u + 1] - beg;
@@ -232,51 +284,70 @@ __device__ __forceinline__ int sort_class(int64_t len) {
   return len <= 16 ? 0 : len <= 64 ? 1 : len <= 4096 ? 2 : 3;
 }
 
-__global__ __launch_bounds__(kBlock) void k_count_sort_classes(int32_t n,
-                                                               const int32_t* __restrict__ dplus,
-                                                               int32_t* __restrict__ counters) {
+// Class of rank r's row, or -1 for an empty row.  kDeg: the orientation's
+// degree classes (row-group width 4, 16, 64, kBlock) of the full row;
+// otherwise the sort classes of the out-list.
+template <bool kDeg>
+__device__ __forceinline__ int row_class(int64_t r, const int32_t* __restrict__ dplus,
+                                         const int32_t* __restrict__ perm,
+                                         const int64_t* __restrict__ rowptr) {
+  if constexpr (kDeg) {
+    const int32_t u = perm[r];
+    const int64_t d = rowptr[u + 1] - rowptr[u];
+    return d == 0 ? -1 : d <= 4 ? 0 : d <= 16 ? 1 : d <= 64 ? 2 : 3;
+  } else {
+    const int32_t len = dplus[r];
+    return len > 0 ? sort_class(len) : -1;
+  }
+}
+
+template <bool kDeg>
+__global__ __launch_bounds__(kBlock) void k_count_classes(int32_t n,
+                                                          const int32_t* __restrict__ dplus,
+                                                          const int32_t* __restrict__ perm,
+                                                          const int64_t* __restrict__ rowptr,
+                                                          int32_t* __restrict__ counters) {
+  constexpr int kOff = kDeg ? kCRowCount : kCSortCount;
   int32_t h[kSortClasses] = {0, 0, 0, 0};
   for (int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x; r < n;
        r += (int64_t)gridDim.x * kBlock) {
-    const int32_t len = dplus[r];
-    if (len > 0) {
-      const int c = sort_class(len);
+    const int c = row_class<kDeg>(r, dplus, perm, rowptr);
 #pragma unroll
-      for (int q = 0; q < kSortClasses; ++q) h[q] += c == q;
-    }
+    for (int q = 0; q < kSortClasses; ++q) h[q] += c == q;
   }
   __shared__ int32_t red[kWavesPerBlock];
 #pragma unroll
   for (int q = 0; q < kSortClasses; ++q) {
     const int32_t t = block_sum(h[q], red);
-    if (threadIdx.x == 0 && t) atomicAdd(&counters[kCSortCount + q], t);
+    if (threadIdx.x == 0 && t) atomicAdd(&counters[kOff + q], t);
   }
 }
 
-// Rows into their length classes; one global atomic per wave and class.
-__global__ __launch_bounds__(kBlock) void k_scatter_sort_classes(int32_t n,
-                                                                 const int32_t* __restrict__ dplus,
-                                                                 int32_t* __restrict__ counters,
-                                                                 int32_t* __restrict__ rows) {
+// Rows into their classes; one global atomic per wave and class.
+template <bool kDeg>
+__global__ __launch_bounds__(kBlock) void k_scatter_classes(int32_t n,
+                                                            const int32_t* __restrict__ dplus,
+                                                            const int32_t* __restrict__ perm,
+                                                            const int64_t* __restrict__ rowptr,
+                                                            int32_t* __restrict__ counters,
+                                                            int32_t* __restrict__ rows) {
+  constexpr int kOff = kDeg ? kCRowCount : kCSortCount;
+  constexpr int kCur = kDeg ? kCRowCursor : kCSortCursor;
   __shared__ int32_t base[kSortClasses];
   if (threadIdx.x == 0) {
     int32_t run = 0;
-    for (int q = 0; q < kSortClasses; ++q) { base[q] = run; run += counters[kCSortCount + q]; }
+    for (int q = 0; q < kSortClasses; ++q) { base[q] = run; run += counters[kOff + q]; }
   }
   __syncthreads();
   for (int64_t r0 = (int64_t)blockIdx.x * kBlock; r0 < n; r0 += (int64_t)gridDim.x * kBlock) {
     const int64_t r = r0 + threadIdx.x;
-    int c = -1;
-    if (r < n) {
-      const int32_t len = dplus[r];
-      if (len > 0) c = sort_class(len);
-    }
+    const int c = r < n ? row_class<kDeg>(r, dplus, perm, rowptr) : -1;
     for (int q = 0; q < kSortClasses; ++q) {
       const uint64_t mask = ballot(c == q);
       if (!mask) continue;
       const int leader = __ffsll((long long)mask) - 1;
       int32_t at = 0;
-      if (lane_id() == leader) at = atomicAdd(&counters[kCSortCursor + q], (int32_t)__popcll(mask));
+      if (lane_id() == leader) at = atomicAdd(&counters[kCur + q], (int32_t)__popcll(mask));
       at = __shfl(at, leader, kWave);
       if (c == q) rows[base[q] + at + popc_below(mask)] = (int32_t)r;
     }
@@ -421,9 +492,9 @@ unsigned grid_for(int64_t items, int per_block) {
 }
 
 template <int G, typename F>
-hipError_t launch_rows(int32_t r0, int32_t r1, hipStream_t s, F f) {
-  if (r1 <= r0) return hipSuccess;
-  f(grid_for(r1 - r0, kBlock / G), s);
+hipError_t launch_rows(const RowSet& rs, int64_t bound, hipStream_t s, F f) {
+  if (bound <= 0) return hipSuccess;
+  f(rs, grid_for(bound, kBlock / G), s);
   return hipGetLastError();
 }
 
@@ -452,10 +523,20 @@ size_t orient_workspace_bytes(int32_t n, int64_t nnz) {
   return c.used;
 }
 
-int orient_run(int32_t n, int64_t nnz, const int64_t* rowptr, const int32_t* col, bool validate,
-               int64_t* orow, int32_t* ocol, int32_t* otail, int32_t* perm, int32_t* rank,
-               int64_t* irow, int32_t* icol, void* ws, size_t ws_bytes, hipStream_t s,
-               const char** err) {
+namespace {
+
+// Batch mode: sort keys (graph, degree) with `bits` key bits, and row lists
+// instead of rank ranges, so that nothing is read back to the host.
+struct BatchKeys {
+  const int64_t* voff;   // device [count+1]
+  int32_t count;
+  int dbits, bits;
+};
+
+int orient_impl(int32_t n, int64_t nnz, const int64_t* rowptr, const int32_t* col, bool validate,
+                const BatchKeys* bk, int64_t* orow, int32_t* ocol, int32_t* otail,
+                int32_t* perm, int32_t* rank, int64_t* irow, int32_t* icol, void* ws,
+                size_t ws_bytes, hipStream_t s, const char** err) {
   const int64_t m = nnz / 2;
   Carve c(ws, ws_bytes);
   int32_t* key_a = c.take<int32_t>(n);
@@ -502,42 +583,78 @@ int orient_run(int32_t n, int64_t nnz, const int64_t* rowptr, const int32_t* col
     AOT_TRY(fill_i64(irow, 1, 0, s));
     return 0;
   }
-  k_degree<<<std::min(grid_for(n, kBlock), 1024u), kBlock, 0, s>>>(n, rowptr, key_a, val_a,
-                                                                   counters);
-  AOT_TRY(hipGetLastError());
-  int32_t hc[kCounters];
-  AOT_TRY(hipMemcpyAsync(hc, counters, sizeof(hc), hipMemcpyDeviceToHost, s));
-  AOT_TRY(hipStreamSynchronize(s));
-  const int bits = ceil_log2((int64_t)hc[kCMaxDeg] + 1);
+  int bits;
+  int32_t c0 = 0, c4 = 0, c16 = 0, c64 = 0;
+  if (!bk) {
+    k_degree<<<std::min(grid_for(n, kBlock), 1024u), kBlock, 0, s>>>(n, rowptr, key_a, val_a,
+                                                                     counters);
+    AOT_TRY(hipGetLastError());
+    int32_t hc[kCounters];
+    AOT_TRY(hipMemcpyAsync(hc, counters, sizeof(hc), hipMemcpyDeviceToHost, s));
+    AOT_TRY(hipStreamSynchronize(s));
+    bits = ceil_log2((int64_t)hc[kCMaxDeg] + 1);
+    c0 = hc[kCDeg0]; c4 = hc[kCDeg4]; c16 = hc[kCDeg16]; c64 = hc[kCDeg64];
+  } else {
+    k_batch_keys<<<grid_for(n, kBlock), kBlock, 0, s>>>(n, bk->voff, bk->count, bk->dbits,
+                                                         rowptr, key_a, val_a);
+    AOT_TRY(hipGetLastError());
+    bits = bk->bits;
+  }
   int32_t *sk, *sv;
   AOT_TRY(radix_sort_pairs(key_a, val_a, key_b, val_b, n, bits, radix_tmp, s, &sk, &sv));
   k_perm_rank<<<grid_for(n, kBlock), kBlock, 0, s>>>(n, sv, perm, rank);
   AOT_TRY(hipGetLastError());
 
-  // rank ranges with the same row-group width (rows are in degree order)
-  const int32_t c0 = hc[kCDeg0], c4 = hc[kCDeg4], c16 = hc[kCDeg16], c64 = hc[kCDeg64];
-  AOT_TRY(fill_i32(dplus, c0, 0, s));
-  AOT_TRY(fill_i32(dminus, c0, 0, s));
-#define ROWS(G, a, b, KERNEL, ...)                                                      \
-  AOT_TRY(launch_rows<G>(a, b, s, [&](unsigned grid, hipStream_t st) {                  \
-    KERNEL<G><<<grid, kBlock, 0, st>>>(a, b, __VA_ARGS__);                              \
-  }))
-  ROWS(4, c0, c4, k_orient_count, rowptr, col, perm, rank, dplus, dminus);
-  ROWS(16, c4, c16, k_orient_count, rowptr, col, perm, rank, dplus, dminus);
-  ROWS(64, c16, c64, k_orient_count, rowptr, col, perm, rank, dplus, dminus);
-  ROWS(256, c64, n, k_orient_count, rowptr, col, perm, rank, dplus, dminus);
+  // Row sets of the four row-group widths.  Single graph: rank order is
+  // degree order, so each is a rank range.  Batch: ranks go graph by graph,
+  // so each is a list built on the device.
+  RowSet sets[4];
+  int64_t bound[4];
+  const int32_t cuts[5] = {c0, c4, c16, c64, n};
+  for (int q = 0; q < 4; ++q) {
+    sets[q].r0 = cuts[q];
+    sets[q].r1 = cuts[q + 1];
+    sets[q].rows = bk ? rows : nullptr;
+    sets[q].counters = counters;
+    sets[q].cls = q;
+    bound[q] = bk ? (int64_t)n : (int64_t)cuts[q + 1] - cuts[q];
+  }
+  if (bk) {
+    AOT_TRY(fill_i32(dplus, n, 0, s));
+    AOT_TRY(fill_i32(dminus, n, 0, s));
+    k_count_classes<true><<<std::min(grid_for(n, kBlock), 1024u), kBlock, 0, s>>>(
+        n, dplus, perm, rowptr, counters);
+    AOT_TRY(hipGetLastError());
+    k_scatter_classes<true><<<grid_for(n, kBlock), kBlock, 0, s>>>(n, dplus, perm, rowptr,
+                                                                   counters, rows);
+    AOT_TRY(hipGetLastError());
+  } else {
+    AOT_TRY(fill_i32(dplus, c0, 0, s));
+    AOT_TRY(fill_i32(dminus, c0, 0, s));
+  }
+#define ROWS(q, G, KERNEL, ...)                                                          \
+  AOT_TRY(launch_rows<G>(sets[q], bound[q], s,                                          \
+                         [&](const RowSet& rs, unsigned grid, hipStream_t st) {          \
+                           KERNEL<G><<<grid, kBlock, 0, st>>>(rs, __VA_ARGS__);          \
+                         }))
+  ROWS(0, 4, k_orient_count, rowptr, col, perm, rank, dplus, dminus);
+  ROWS(1, 16, k_orient_count, rowptr, col, perm, rank, dplus, dminus);
+  ROWS(2, 64, k_orient_count, rowptr, col, perm, rank, dplus, dminus);
+  ROWS(3, 256, k_orient_count, rowptr, col, perm, rank, dplus, dminus);
   AOT_TRY(exclusive_scan(dplus, orow, n, scan_tmp, s));
   AOT_TRY(exclusive_scan(dminus, irow, n, scan_tmp, s));
-  ROWS(4, c0, c4, k_orient_write, rowptr, col, perm, rank, orow, irow, unsorted, otail, icol);
-  ROWS(16, c4, c16, k_orient_write, rowptr, col, perm, rank, orow, irow, unsorted, otail, icol);
-  ROWS(64, c16, c64, k_orient_write, rowptr, col, perm, rank, orow, irow, unsorted, otail, icol);
-  ROWS(256, c64, n, k_orient_write, rowptr, col, perm, rank, orow, irow, unsorted, otail, icol);
+  ROWS(0, 4, k_orient_write, rowptr, col, perm, rank, orow, irow, unsorted, otail, icol);
+  ROWS(1, 16, k_orient_write, rowptr, col, perm, rank, orow, irow, unsorted, otail, icol);
+  ROWS(2, 64, k_orient_write, rowptr, col, perm, rank, orow, irow, unsorted, otail, icol);
+  ROWS(3, 256, k_orient_write, rowptr, col, perm, rank, orow, irow, unsorted, otail, icol);
+#undef ROWS
 
   // sort each out-list into ocol
-  k_count_sort_classes<<<std::min(grid_for(n, kBlock), 1024u), kBlock, 0, s>>>(n, dplus,
-                                                                               counters);
+  k_count_classes<false><<<std::min(grid_for(n, kBlock), 1024u), kBlock, 0, s>>>(
+      n, dplus, perm, rowptr, counters);
   AOT_TRY(hipGetLastError());
-  k_scatter_sort_classes<<<grid_for(n, kBlock), kBlock, 0, s>>>(n, dplus, counters, rows);
+  k_scatter_classes<false><<<grid_for(n, kBlock), kBlock, 0, s>>>(n, dplus, perm, rowptr,
+                                                                  counters, rows);
   AOT_TRY(hipGetLastError());
   const unsigned g_small = (unsigned)std::min<int64_t>(kGrid, cdiv(n, kBlock / 16) + 1);
   k_sort_lanes<16><<<g_small, kBlock, 0, s>>>(0, counters, rows, orow, unsorted, ocol);
@@ -548,9 +665,26 @@ int orient_run(int32_t n, int64_t nnz, const int64_t* rowptr, const int32_t* col
   AOT_TRY(hipGetLastError());
   k_sort_bitmap<<<512, kBlock, 0, s>>>(3, counters, rows, orow, unsorted, ocol);
   AOT_TRY(hipGetLastError());
-
-#undef ROWS
   return 0;
+}
+
+}  // namespace
+
+int orient_run(int32_t n, int64_t nnz, const int64_t* rowptr, const int32_t* col, bool validate,
+               int64_t* orow, int32_t* ocol, int32_t* otail, int32_t* perm, int32_t* rank,
+               int64_t* irow, int32_t* icol, void* ws, size_t ws_bytes, hipStream_t s,
+               const char** err) {
+  return orient_impl(n, nnz, rowptr, col, validate, nullptr, orow, ocol, otail, perm, rank, irow,
+                     icol, ws, ws_bytes, s, err);
+}
+
+int orient_batch_run(int32_t n, int64_t nnz, const int64_t* rowptr, const int32_t* col,
+                     const int64_t* voff, int32_t count, int dbits, int gbits, int64_t* orow,
+                     int32_t* ocol, int32_t* otail, int32_t* perm, int32_t* rank, int64_t* irow,
+                     int32_t* icol, void* ws, size_t ws_bytes, hipStream_t s, const char** err) {
+  BatchKeys bk{voff, count, dbits, dbits + gbits};
+  return orient_impl(n, nnz, rowptr, col, false, &bk, orow, ocol, otail, perm, rank, irow, icol,
+                     ws, ws_bytes, s, err);
 }
 
 }  // namespace aot

@@ -314,3 +314,24 @@ def batch_member(spec, device="cpu") -> Csr:
     if fam == "rmat":
         return rmat(a, b, s, device=device)
     return random_geometric(a, b, s, device)
+
+
+def arena(csrs, device=None):
+    """The block-diagonal union of several CSRs (a batch's arena): graph g's
+    vertices become [voff[g], voff[g+1]).  Returns (voff int64 [count+1] on
+    the host, rowptr, col) with rowptr/col on `device` (default: the first
+    graph's)."""
+    device = device if device is not None else (csrs[0].rowptr.device if csrs else "cpu")
+    ns = [c.n for c in csrs]
+    nnzs = [c.nnz for c in csrs]
+    voff = torch.zeros(len(csrs) + 1, dtype=torch.int64)
+    voff[1:] = torch.cumsum(torch.tensor(ns, dtype=torch.int64), 0)
+    eoff = [0]
+    for z in nnzs:
+        eoff.append(eoff[-1] + z)
+    rows = [c.rowptr[:-1].to(device) + eoff[g] for g, c in enumerate(csrs)]
+    rows.append(torch.tensor([eoff[-1]], dtype=torch.int64, device=device))
+    cols = [c.col.to(device) + int(voff[g]) for g, c in enumerate(csrs)]
+    rowptr = torch.cat(rows)
+    col = torch.cat(cols).to(torch.int32) if cols else torch.zeros(0, dtype=torch.int32, device=device)
+    return voff, rowptr, col

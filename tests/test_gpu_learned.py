@@ -92,7 +92,7 @@ def test_learned_dispatch_is_bit_exact_and_falls_back():
     (dg0, vc0), (dg1, vc1) = aot.digest(o, c0), aot.digest(o, c1)
     assert dg0 == dg1 and torch.equal(vc0, vc1)
     # a model with a non-finite parameter is ignored: plain rule, same bytes
-    bad = aot.Mlp(8, 32, 9, params=net.params.clone())
+    bad = aot.Mlp(net.n_in, net.n_hidden, net.n_out, params=net.params.clone())
     bad.params[100] = float("nan")
     c2 = aot.count(o, aot.Dispatch(aot.AOT_DISPATCH_LEARNED, 0, None, bad))
     table2, learned2 = aot.count_plan(o, c2)
