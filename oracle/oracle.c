@@ -14,6 +14,12 @@
  *                     (u,v) kept as <u,v> iff eta(u) < eta(v).  The result is
  *                     returned relabelled by eta ("rank space") with every
  *                     out-list sorted ascending, together with perm/rank.
+ *                     Its three steps are also exported (orc_rank,
+ *                     orc_orient_count, orc_orient_write over rank ranges) so
+ *                     that very large graphs can be oriented range by range.
+ *  orc_vertex_triangles -- t(v), the triangles through v, as the number of
+ *                     edges among the neighbours of v (definition of a
+ *                     triangle, Section 2.1), by merging sorted rows.
  *  orc_edge_counts -- per directed edge <u,v>: |N+(u) n N+(v)| by the
  *                     merge-based intersection of Algorithm 1 (CF), Sec. 2.2.
  *  orc_list        -- Algorithm 1 (CF): for each u, each v in N+(u), every w in
@@ -22,7 +28,7 @@
  *                     ascending w.
  *  orc_sum_min     -- sum over <u,v> of min(deg+(u), deg+(v)): the look-up
  *                     count of the adaptive orientation (Section 3.2, "Time
- *                     Complexity").
+ *                     Complexity"); orc_sum_min_range over a rank range.
  *  orc_sum_head    -- sum over <u,v> of deg+(v): the kClist cost that
  *                     Example 1 compares against (Sections 2.3 and 3.2).
  *  orc_aot_ref     -- Algorithm 3 (AOT) as written: a |V|-entry bitmap H of
@@ -56,10 +62,10 @@ static int cmp_i32(const void* a, const void* b) {
   return (x > y) - (x < y);
 }
 
-/* Orientation.  Outputs: perm[r] = original id of rank r, rank[v] = eta(v),
- * orow[n+1], ocol[m] in rank space, each row ascending.  Returns m or -1. */
-int64_t orc_orient(int32_t n, const int64_t* rowptr, const int32_t* col,
-                   int32_t* perm, int32_t* rank, int64_t* orow, int32_t* ocol) {
+/* The order eta: perm[r] = original id of rank r, rank[v] = eta(v); degree
+ * ascending, ties by smaller id (Section 2.2, with the degree order of
+ * Algorithm 3's first step).  Returns 0, or -1 if out of memory. */
+int orc_rank(int32_t n, const int64_t* rowptr, int32_t* perm, int32_t* rank) {
   deg_id* order = (deg_id*)malloc(sizeof(deg_id) * (size_t)(n > 0 ? n : 1));
   if (!order) return -1;
   for (int32_t v = 0; v < n; ++v) {
@@ -72,19 +78,50 @@ int64_t orc_orient(int32_t n, const int64_t* rowptr, const int32_t* col,
     rank[order[r].id] = r;
   }
   free(order);
-  int64_t m = 0;
-  orow[0] = 0;
-  for (int32_t r = 0; r < n; ++r) {
+  return 0;
+}
+
+/* deg+(r) for ranks r in [r_lo, r_hi): neighbours of perm[r] ranked above r. */
+void orc_orient_count(const int64_t* rowptr, const int32_t* col, const int32_t* perm,
+                      const int32_t* rank, int32_t r_lo, int32_t r_hi, int64_t* dplus) {
+  for (int32_t r = r_lo; r < r_hi; ++r) {
     int32_t u = perm[r];
-    int64_t start = m;
+    int64_t c = 0;
+    for (int64_t k = rowptr[u]; k < rowptr[u + 1]; ++k) c += rank[col[k]] > r;
+    dplus[r - r_lo] = c;
+  }
+}
+
+/* Out-lists of ranks [r_lo, r_hi) into ocol at orow[r], each sorted
+ * ascending (ranks above r, relabelled by eta). */
+void orc_orient_write(const int64_t* rowptr, const int32_t* col, const int32_t* perm,
+                      const int32_t* rank, const int64_t* orow, int32_t r_lo, int32_t r_hi,
+                      int32_t* ocol) {
+  for (int32_t r = r_lo; r < r_hi; ++r) {
+    int32_t u = perm[r];
+    int64_t at = orow[r];
     for (int64_t k = rowptr[u]; k < rowptr[u + 1]; ++k) {
       int32_t rv = rank[col[k]];
-      if (rv > r) ocol[m++] = rv;
+      if (rv > r) ocol[at++] = rv;
     }
-    qsort(ocol + start, (size_t)(m - start), sizeof(int32_t), cmp_i32);
-    orow[r + 1] = m;
+    qsort(ocol + orow[r], (size_t)(at - orow[r]), sizeof(int32_t), cmp_i32);
   }
-  return m;
+}
+
+/* Orientation: orc_rank, then keep <u,v> iff eta(u) < eta(v).  Outputs
+ * perm, rank, orow[n+1], ocol[m] in rank space, each row ascending.
+ * Returns m or -1. */
+int64_t orc_orient(int32_t n, const int64_t* rowptr, const int32_t* col,
+                   int32_t* perm, int32_t* rank, int64_t* orow, int32_t* ocol) {
+  if (orc_rank(n, rowptr, perm, rank)) return -1;
+  int64_t* dplus = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+  if (!dplus) return -1;
+  orc_orient_count(rowptr, col, perm, rank, 0, n, dplus);
+  orow[0] = 0;
+  for (int32_t r = 0; r < n; ++r) orow[r + 1] = orow[r] + dplus[r];
+  free(dplus);
+  orc_orient_write(rowptr, col, perm, rank, orow, 0, n, ocol);
+  return orow[n];
 }
 
 /* In-lists of the oriented graph (Algorithm 3's second loop walks them): for
@@ -205,6 +242,20 @@ int64_t orc_list(int32_t n, const int64_t* orow, const int32_t* ocol, const int3
 }
 
 /* sum over <u,v> of min(deg+(u), deg+(v)), rank space. */
+/* sum over <u,v> with u in [r_lo, r_hi) of min(deg+(u), deg+(v)). */
+uint64_t orc_sum_min_range(const int64_t* orow, const int32_t* ocol, int32_t r_lo, int32_t r_hi) {
+  uint64_t s = 0;
+  for (int32_t u = r_lo; u < r_hi; ++u) {
+    int64_t du = orow[u + 1] - orow[u];
+    for (int64_t e = orow[u]; e < orow[u + 1]; ++e) {
+      int32_t v = ocol[e];
+      int64_t dv = orow[v + 1] - orow[v];
+      s += (uint64_t)(du < dv ? du : dv);
+    }
+  }
+  return s;
+}
+
 uint64_t orc_sum_min(int32_t n, const int64_t* orow, const int32_t* ocol) {
   uint64_t s = 0;
   for (int32_t u = 0; u < n; ++u) {
@@ -375,4 +426,23 @@ int64_t orc_list_digest(int32_t n, const int64_t* orow, const int32_t* ocol, con
   }
   fp[0] = s; fp[1] = x;
   return t;
+}
+
+/* Triangles through vertex v of the input graph (original ids), from the
+ * plain definition: t(v) = number of edges {x, y} with x, y both neighbours of
+ * v, i.e. half of the sum over x in N(v) of |N(v) n N(x)| (sorted rows,
+ * merged).  out[i] = t(vs[i]). */
+void orc_vertex_triangles(const int64_t* rowptr, const int32_t* col, const int32_t* vs, int64_t k,
+                          int64_t* out) {
+  for (int64_t i = 0; i < k; ++i) {
+    int32_t v = vs[i];
+    const int32_t* nv = col + rowptr[v];
+    int64_t dv = rowptr[v + 1] - rowptr[v];
+    int64_t twice = 0;
+    for (int64_t j = 0; j < dv; ++j) {
+      int32_t x = nv[j];
+      twice += merge_count(nv, dv, col + rowptr[x], rowptr[x + 1] - rowptr[x]);
+    }
+    out[i] = twice / 2;
+  }
 }

@@ -117,6 +117,36 @@ def csr_from_pairs(n: int, u: torch.Tensor, v: torch.Tensor, name: str = "") -> 
     return Csr(n, rowptr, cols.to(torch.int32), name)
 
 
+def csr_from_pairs_partitioned(n: int, u: torch.Tensor, v: torch.Tensor, name: str = "",
+                               parts: int = 32) -> Csr:
+    """The same CSR as csr_from_pairs, built one range of rows at a time so
+    that no sort ever holds more than about 2 * len(u) / parts keys (graphs
+    with billions of entries).  u, v may be int32; they are not modified."""
+    dev = u.device
+    counts = torch.zeros(n, dtype=torch.int64, device=dev)
+    cols = []
+    bounds = [n * p // parts for p in range(parts + 1)]
+    for p in range(parts):
+        lo, hi = bounds[p], bounds[p + 1]
+        if hi <= lo:
+            continue
+        keys = []
+        for x, y in ((u, v), (v, u)):
+            sel = (x >= lo) & (x < hi) & (x != y)
+            keys.append((x[sel].to(torch.int64) - lo) * n + y[sel].to(torch.int64))
+            del sel
+        key = torch.unique(torch.cat(keys))          # sorted, deduplicated (row, col)
+        del keys
+        rows = key // n
+        counts[lo:hi] = torch.bincount(rows, minlength=hi - lo)
+        cols.append((key - rows * n).to(torch.int32))
+        del key, rows
+    rowptr = torch.zeros(n + 1, dtype=torch.int64, device=dev)
+    rowptr[1:] = torch.cumsum(counts, 0)
+    col = torch.cat(cols) if cols else torch.zeros(0, dtype=torch.int32, device=dev)
+    return Csr(n, rowptr, col, name)
+
+
 def csr_from_edges_np(n: int, edges) -> Csr:
     """Small hand-written graphs: ``edges`` is an iterable of (u, v) pairs."""
     e = np.asarray(list(edges), dtype=np.int64).reshape(-1, 2)
@@ -160,9 +190,11 @@ def erdos_renyi_m(n: int, mean_degree: float, seed: int, device="cpu") -> Csr:
 
 
 def rmat(scale: int, edge_factor: int, seed: int, a=0.57, b=0.19, c=0.19,
-         device="cpu", chunk: int = 1 << 24) -> Csr:
+         device="cpu", chunk: int = 1 << 24, parts: int | None = None) -> Csr:
     """R-MAT: edge_factor * 2^scale tuples, one quadrant draw per bit level
-    (16-bit resolution, no per-level noise), then a seeded vertex relabelling."""
+    (16-bit resolution, no per-level noise), then a seeded vertex relabelling.
+    From 2^27 tuples on (or when parts is given) the CSR is built by row
+    ranges (csr_from_pairs_partitioned): the same graph, less memory."""
     n = 1 << scale
     ntup = edge_factor * n
     ta = int(round(a * 65536))
@@ -184,10 +216,15 @@ def rmat(scale: int, edge_factor: int, seed: int, a=0.57, b=0.19, c=0.19,
             vbit = ((x >= ta) & (x < tab) | (x >= tabc)).to(torch.int64)
             u = u | (ubit << lvl)
             v = v | (vbit << lvl)
-        us.append(perm[u])
-        vs.append(perm[v])
-    return csr_from_pairs(n, torch.cat(us), torch.cat(vs),
-                          f"rmat(scale={scale},ef={edge_factor},seed={seed})")
+        us.append(perm[u].to(torch.int32))
+        vs.append(perm[v].to(torch.int32))
+        del t, u, v
+    name = f"rmat(scale={scale},ef={edge_factor},seed={seed})"
+    u, v = torch.cat(us), torch.cat(vs)
+    del us, vs
+    if parts is None and ntup < (1 << 27):
+        return csr_from_pairs(n, u, v, name)
+    return csr_from_pairs_partitioned(n, u, v, name, parts or max(8, ntup >> 26))
 
 
 def chung_lu(n: int, mean_degree: float, gamma: float, max_degree: float, seed: int,

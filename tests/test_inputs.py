@@ -78,3 +78,15 @@ def test_batch_spec():
             assert 1000 <= a <= 200000 and 8 <= b <= 64
         else:
             assert 1000 <= a <= 200000
+
+
+@pytest.mark.parametrize("scale,ef,parts", [(9, 16, 2), (11, 32, 5), (12, 8, 32), (6, 4, 100)])
+def test_partitioned_csr_build_is_the_same_graph(scale, ef, parts):
+    a = inputs.rmat(scale, ef, 17)
+    b = inputs.rmat(scale, ef, 17, parts=parts)
+    assert torch.equal(a.rowptr, b.rowptr) and torch.equal(a.col, b.col)
+    u = inputs.rand32(3, 1, torch.arange(5000)) % 300
+    v = inputs.rand32(3, 2, torch.arange(5000)) % 300
+    x = inputs.csr_from_pairs(300, u, v)
+    y = inputs.csr_from_pairs_partitioned(300, u.to(torch.int32), v.to(torch.int32), parts=parts)
+    assert torch.equal(x.rowptr, y.rowptr) and torch.equal(x.col, y.col)

@@ -346,3 +346,49 @@ def test_in_lists_transpose_the_out_lists(n, p, seed):
         assert np.all(np.diff(o.perm[ins]) > 0)
         for x, e in zip(ins.tolist(), ieid[irow[r]:irow[r + 1]].tolist()):
             assert tail[e] == x and o.ocol[e] == r
+
+
+# ---------------------------------------------------------------- large-graph helpers
+
+@pytest.mark.parametrize("n,p,seed", SMALL)
+def test_vertex_triangles_equal_a3_diagonal(n, p, seed):
+    """t(v) = (A^3)_vv / 2 (closed walks of length 3 through v, each triangle
+    walked in two directions)."""
+    g = random_graph(n, p, seed)
+    rp, col = g.numpy()
+    A = dense(g)
+    want = np.diag(A @ A @ A) // 2
+    got = oracle.vertex_triangles(rp, col, np.arange(n))
+    assert np.array_equal(got, want)
+    assert got.sum() == 3 * len(brute_force(g))
+
+
+@pytest.mark.parametrize("n", [5, 6, 9, 20])
+def test_vertex_triangles_closed_forms(n):
+    # wheel: hub in n-1 triangles, every rim vertex in 2
+    rp, col = wheel(n).numpy()
+    t = oracle.vertex_triangles(rp, col, np.arange(n))
+    assert t[0] == n - 1 and np.all(t[1:] == 2)
+    # K_n: every vertex in C(n-1, 2)
+    rp, col = graph(n, itertools.combinations(range(n), 2)).numpy()
+    assert np.all(oracle.vertex_triangles(rp, col, np.arange(n)) == math.comb(n - 1, 2))
+    # a tree has none
+    rp, col = graph(n, [(i, (i - 1) // 2) for i in range(1, n)]).numpy()
+    assert np.all(oracle.vertex_triangles(rp, col, np.arange(n)) == 0)
+
+
+@pytest.mark.parametrize("g", [
+    lambda: inputs.rmat(13, 16, 3), lambda: inputs.erdos_renyi(2000, 0.01, 1),
+    lambda: inputs.chung_lu(20000, 20.0, 2.1, 2000.0, 5), lambda: graph(0, []),
+    lambda: graph(7, []), lambda: random_graph(40, 0.5, 9)])
+@pytest.mark.parametrize("threads", [1, 3, 8])
+def test_threaded_orientation_and_sum_min(g, threads):
+    """Range-by-range orientation on threads equals the one-pass orientation;
+    the ranged sum of minima equals the one-pass sum."""
+    csr = g()
+    rp, col = csr.numpy()
+    a = oracle.orient(rp, col)
+    b = oracle.orient_threaded(rp, col, threads=threads)
+    assert np.array_equal(a.perm, b.perm) and np.array_equal(a.rank, b.rank)
+    assert np.array_equal(a.orow, b.orow) and np.array_equal(a.ocol, b.ocol)
+    assert oracle.sum_min_threaded(b, threads=threads) == oracle.sum_min(a)
