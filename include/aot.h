@@ -188,7 +188,11 @@ int aot_bucket_features(const void* ws, size_t ws_bytes, int32_t n, int64_t m, f
  * int32[3*count]): each triangle as its three ORIGINAL ids ascending; the
  * global order is edge order, then ascending third vertex (in rank space).
  * Requires the tri_off and workspace of a prior aot_count on the same graph.
- * count may run past T (only T - first are written).  Does not synchronise.
+ * count may run past T (only T - first are written).  A window costs about
+ * its own triangles: light edges are visited only over the run of the edge
+ * order the window covers, heavy work items whose owned edges miss it are
+ * skipped whole.  Synchronises `stream` once at the start (to size its
+ * launches); the writes themselves are left enqueued.
  *   written  host, optional: number of triangles written. */
 int aot_list(const aot_oriented* g, const aot_dispatch* d, const int64_t* tri_off,
              void* ws, size_t ws_bytes, int64_t first, int64_t count,
@@ -341,9 +345,10 @@ typedef struct aot_timing {
                          2 global binary search, 3 LDS sorted copy); light: 0 */
   int32_t tile;       /* lanes per edge (light) or workgroup size (heavy)    */
   int64_t edges;      /* directed edges in the bucket                        */
-  int64_t probes;     /* their sum of min(deg+): look-ups made               */
+  int64_t probes;     /* their sum of min(deg+): look-ups made (-1 for a
+                         write-pass launch over part of a light bin)          */
   int64_t staged;     /* owner out-list entries staged into LDS (heavy)      */
-  int64_t triangles;  /* triangles the bucket's edges hold                   */
+  int64_t triangles;  /* triangles the bucket's edges hold (-1 as probes)    */
   double ms;          /* launch time from HIP events on the launch stream    */
 } aot_timing;
 int aot_timing_start(void);

@@ -91,6 +91,26 @@ __device__ __forceinline__ unsigned long long* u64p(int64_t* p) {
   return reinterpret_cast<unsigned long long*>(p);
 }
 
+__device__ __forceinline__ int32_t block_min(int32_t x, int32_t* tmp) {
+  for (int o = kWave / 2; o > 0; o >>= 1) x = min(x, __shfl_xor(x, o, kWave));
+  if (lane_id() == 0) tmp[threadIdx.x / kWave] = x;
+  __syncthreads();
+  int32_t r = tmp[0];
+  for (int q = 1; q < kWavesPerBlock; ++q) r = min(r, tmp[q]);
+  __syncthreads();
+  return r;
+}
+
+__device__ __forceinline__ int32_t block_max(int32_t x, int32_t* tmp) {
+  for (int o = kWave / 2; o > 0; o >>= 1) x = max(x, __shfl_xor(x, o, kWave));
+  if (lane_id() == 0) tmp[threadIdx.x / kWave] = x;
+  __syncthreads();
+  int32_t r = tmp[0];
+  for (int q = 1; q < kWavesPerBlock; ++q) r = max(r, tmp[q]);
+  __syncthreads();
+  return r;
+}
+
 // ---------------------------------------------------------------- binning
 
 // Per-bucket edge and probe counts, and the probe total.
@@ -127,39 +147,73 @@ __global__ __launch_bounds__(kBlock) void k_bin_count(int64_t m, const int64_t* 
   }
 }
 
-// Light edges into their bins.  A block takes a contiguous chunk of edges,
-// counts its bins in LDS, reserves its ranges with one global atomic per bin,
-// then scatters with LDS cursors.
+// Light edges into their bins, in edge order inside every bin, so that a
+// window of the edge order is one contiguous run of each bin.  k_bin_hist
+// counts every chunk's edges per bin; an exclusive scan over (bin, chunk)
+// gives each chunk's first slot in each bin; k_bin_place writes each chunk's
+// edges in order, ranked with per-wave ballots.
 constexpr int kScatterChunk = 8192;
-__global__ __launch_bounds__(kBlock) void k_bin_scatter(int64_t m, const uint8_t* __restrict__ code,
-                                                        int64_t* __restrict__ stats,
-                                                        int32_t* __restrict__ elist) {
-  __shared__ int64_t base[kLightBins];
-  __shared__ int32_t cnt[kLightBins], cur[kLightBins];
-  for (int64_t c0 = (int64_t)blockIdx.x * kScatterChunk; c0 < m;
-       c0 += (int64_t)gridDim.x * kScatterChunk) {
-    const int64_t c1 = min(m, c0 + kScatterChunk);
-    if (threadIdx.x < kLightBins) { cnt[threadIdx.x] = 0; cur[threadIdx.x] = 0; }
+
+__global__ __launch_bounds__(kBlock) void k_bin_hist(int64_t m, const uint8_t* __restrict__ code,
+                                                     int64_t nchunks, int32_t* __restrict__ hist) {
+  __shared__ int32_t cnt[kLightBins];
+  int32_t mine[kLightBins];
+  for (int64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+    if (threadIdx.x < kLightBins) cnt[threadIdx.x] = 0;
+#pragma unroll
+    for (int q = 0; q < kLightBins; ++q) mine[q] = 0;
     __syncthreads();
+    const int64_t c0 = c * kScatterChunk, c1 = min(m, c0 + kScatterChunk);
     for (int64_t e = c0 + threadIdx.x; e < c1; e += kBlock) {
-      const int c = code[e];
-      if (c != 0xFF) atomicAdd(&cnt[c], 1);
+      const int bin = code[e];
+#pragma unroll
+      for (int q = 0; q < kLightBins; ++q) mine[q] += (int32_t)__popcll(ballot(bin == q));
     }
+    if (lane_id() == 0)
+#pragma unroll
+      for (int q = 0; q < kLightBins; ++q)
+        if (mine[q]) atomicAdd(&cnt[q], mine[q]);
     __syncthreads();
-    if (threadIdx.x < kLightBins) {
-      int64_t bin_base = 0;
-      for (int q = 0; q < (int)threadIdx.x; ++q) bin_base += stats[q * kStats + kSEdges];
-      const int32_t k = cnt[threadIdx.x];
-      base[threadIdx.x] = bin_base + (k ? (int64_t)atomicAdd(u64p(&stats[threadIdx.x * kStats + kSCursor]),
-                                                             (unsigned long long)k)
-                                        : 0);
+    if (threadIdx.x < kLightBins) hist[threadIdx.x * nchunks + c] = cnt[threadIdx.x];
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_bin_place(int64_t m, const uint8_t* __restrict__ code,
+                                                      int64_t nchunks,
+                                                      const int64_t* __restrict__ hoff,
+                                                      int32_t* __restrict__ elist) {
+  __shared__ int64_t run[kLightBins];
+  __shared__ int32_t wc[kWavesPerBlock][kLightBins];
+  const int w = threadIdx.x / kWave;
+  for (int64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+    if (threadIdx.x < kLightBins) run[threadIdx.x] = hoff[threadIdx.x * nchunks + c];
+    __syncthreads();
+    const int64_t c0 = c * kScatterChunk, c1 = min(m, c0 + kScatterChunk);
+    for (int64_t r0 = c0; r0 < c1; r0 += kBlock) {
+      const int64_t e = r0 + threadIdx.x;
+      const int bin = e < c1 ? code[e] : 0xFF;
+      uint64_t same = 0;
+#pragma unroll
+      for (int q = 0; q < kLightBins; ++q) {
+        const uint64_t mask = ballot(bin == q);
+        if (lane_id() == 0) wc[w][q] = (int32_t)__popcll(mask);
+        if (bin == q) same = mask;
+      }
+      __syncthreads();
+      if (bin < kLightBins) {
+        int64_t pos = run[bin] + popc_below(same);
+        for (int x = 0; x < w; ++x) pos += wc[x][bin];
+        elist[pos] = (int32_t)e;
+      }
+      __syncthreads();
+      if (threadIdx.x < kLightBins) {
+        int32_t t = 0;
+        for (int x = 0; x < kWavesPerBlock; ++x) t += wc[x][threadIdx.x];
+        run[threadIdx.x] += t;
+      }
+      __syncthreads();
     }
-    __syncthreads();
-    for (int64_t e = c0 + threadIdx.x; e < c1; e += kBlock) {
-      const int c = code[e];
-      if (c != 0xFF) elist[base[c] + atomicAdd(&cur[c], 1)] = (int32_t)e;
-    }
-    __syncthreads();
   }
 }
 
@@ -362,6 +416,8 @@ struct HeavyArgs {
   int32_t arms[kHeavyClasses];  // requested arm of each heavy class
   int idx_words;                // LDS words of the index (dynamic shared memory)
   const int2* items;
+  int2* item_e;                 // per item: smallest and largest owned edge id with
+                                // probes (count pass writes, write pass reads)
   int64_t item_base, item_count;
   const int64_t* orow;
   const int32_t* ocol;
@@ -448,6 +504,7 @@ struct HeavyShared {
   int32_t nb_py[kEmit ? kItemSpan : 1];
   int32_t wave_k[kWavesPerBlock + 1];
   int64_t scan_tmp[kWavesPerBlock + 1];
+  int32_t red[kWavesPerBlock + 1];
 };
 
 // Per-lane hits of one 64-probe window, reduced per neighbour segment (lanes
@@ -636,6 +693,17 @@ template <bool kEmit>
 __device__ void heavy_item(HeavyShared<kEmit>& sh, uint32_t* lds, const HeavyArgs& a, int64_t it,
                            int64_t& tri_block, Digest& dg) {
   const int tid = threadIdx.x;
+  if constexpr (kEmit) {
+    // an item whose owned edges hold no slot in the window is skipped whole
+    if (a.item_e) {
+      const int2 r = a.item_e[it];
+      if (r.y < r.x) return;
+      if (!a.digest) {
+        const int64_t lo = a.tri_off[r.x], hi = a.tri_off[r.y + 1];
+        if (hi <= a.first || lo >= a.first + a.count) return;
+      }
+    }
+  }
   const int2 item = a.items[it];
   const int32_t b = item.x;
   const int64_t ob = a.orow[b];
@@ -680,6 +748,17 @@ __device__ void heavy_item(HeavyShared<kEmit>& sh, uint32_t* lds, const HeavyArg
       }
     }
     if (keep[i]) packed += (int64_t(1) << 32) + nd[i];
+  }
+  if constexpr (!kEmit) {
+    if (a.item_e) {
+      int32_t lo = INT_MAX, hi = -1;
+#pragma unroll
+      for (int i = 0; i < kPer; ++i)
+        if (keep[i]) { lo = min(lo, ne[i]); hi = max(hi, ne[i]); }
+      lo = block_min(lo, sh.red);
+      hi = block_max(hi, sh.red);
+      if (tid == 0) a.item_e[it] = make_int2(lo, hi);
+    }
   }
   int64_t total;
   int64_t at = block_exclusive_scan(packed, sh.scan_tmp, &total);
@@ -932,6 +1011,57 @@ __global__ __launch_bounds__(kBlock) void k_light_drain(LightArgs a, LightPlan p
   light_finish<kEmit>(a, tri, dg, nullptr);
 }
 
+// The part of the edge order a triangle window [first, first + count)
+// touches, and each light bin's run of it: win[0..1] = [e_lo, e_hi), the
+// edges whose slots can meet the window; win[2 + 2k .. 3 + 2k] = the elist
+// indices of bin k's edges in [e_lo, e_hi) (bins are in edge order).
+constexpr int kWinWords = 2 + 2 * kLightBins;
+
+__global__ void k_window(int64_t m, const int64_t* __restrict__ tri_off, int64_t first,
+                         int64_t count, const int64_t* __restrict__ stats,
+                         const int32_t* __restrict__ elist, int64_t* __restrict__ win) {
+  __shared__ int64_t range[2];
+  if (threadIdx.x == 0) {
+    int64_t lo = 0, hi = m;           // first e with tri_off[e + 1] > first
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (tri_off[mid + 1] > first) hi = mid; else lo = mid + 1;
+    }
+    range[0] = lo;
+    const int64_t end = first + count;
+    lo = 0; hi = m;                   // first e with tri_off[e] >= end (m if none)
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (tri_off[mid] >= end) hi = mid; else lo = mid + 1;
+    }
+    range[1] = lo;
+    if (first <= 0 && end >= tri_off[m]) {   // the whole list: whole bins
+      range[0] = 0;
+      range[1] = m;
+    }
+    win[0] = range[0];
+    win[1] = range[1];
+  }
+  __syncthreads();
+  if (threadIdx.x < kLightBins) {
+    const int k = threadIdx.x;
+    int64_t base = 0;
+    for (int q = 0; q < k; ++q) base += stats[q * kStats + kSEdges];
+    const int64_t len = stats[k * kStats + kSEdges];
+    int64_t at[2];
+    for (int z = 0; z < 2; ++z) {
+      int64_t lo = 0, hi = len;
+      while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (elist[base + mid] < range[z]) lo = mid + 1; else hi = mid;
+      }
+      at[z] = base + lo;
+    }
+    win[2 + 2 * k] = at[0];
+    win[3 + 2 * k] = at[1];
+  }
+}
+
 // ---------------------------------------------------------------- host side
 
 // Per-bucket choices: lanes per edge of each light bin, index arm of each
@@ -1034,6 +1164,10 @@ struct CountWs {
   uint8_t* code;
   int32_t* elist;
   int2* items;
+  int2* item_e;                      // per item: owned edge-id bounds
+  int32_t* hist;                     // [kLightBins][chunks] light edges per chunk
+  int64_t* hoff;                     // its exclusive scan
+  int64_t* win;                      // window: edge range, then each bin's elist run
   int64_t* stats;
   unsigned long long* probes;
   void* scan_tmp;
@@ -1049,6 +1183,11 @@ CountWs carve_count(Carve& c, int32_t n, int64_t m) {
   w.code = c.take<uint8_t>(m);
   w.elist = c.take<int32_t>(m);
   w.items = c.take<int2>(max_items(n, m));
+  w.item_e = c.take<int2>(max_items(n, m));
+  const int64_t cells = kLightBins * cdiv(m, kScatterChunk);
+  w.hist = c.take<int32_t>(cells);
+  w.hoff = c.take<int64_t>(cells + 1);
+  w.win = c.take<int64_t>(kWinWords);
   w.stats = c.take<int64_t>(kStatWords);
   w.probes = c.take<unsigned long long>(8);   // [0] probes, [4..7] drain cursors
   w.scan_tmp = c.take<char>((int64_t)scan_workspace(m));
@@ -1105,6 +1244,18 @@ unsigned grid_cap(int64_t work_units) {
   return (unsigned)std::max<int64_t>(1, std::min<int64_t>(kGrid * 4, work_units));
 }
 
+hipError_t bin_scatter(int64_t m, const CountWs& w, hipStream_t s) {
+  const int64_t nchunks = cdiv(m, kScatterChunk);
+  const unsigned g = grid_cap(std::min<int64_t>(nchunks, 4096));
+  k_bin_hist<<<g, kBlock, 0, s>>>(m, w.code, nchunks, w.hist);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = exclusive_scan(w.hist, w.hoff, kLightBins * nchunks, w.scan_tmp, s);
+  if (e != hipSuccess) return e;
+  k_bin_place<<<g, kBlock, 0, s>>>(m, w.code, nchunks, w.hoff, w.elist);
+  return hipGetLastError();
+}
+
 // The learned plan: features of every bucket -> cost model -> argmin.  A
 // model of the wrong shape or with non-finite parameters or predictions
 // leaves the plain rule in place (*learned = 0).
@@ -1144,30 +1295,34 @@ int run_buckets(bool emit, const Plan& plan, const int64_t* hs, const CountWs& w
                 const int64_t* orow, const int32_t* ocol, const int32_t* otail,
                 const int32_t* perm, const int64_t* irow, const int32_t* icol,
                 const int64_t* tri_off, int64_t first, int64_t count, int32_t* out,
-                unsigned long long* digest, unsigned long long* vcount, hipStream_t s,
-                const char** err) {
+                unsigned long long* digest, unsigned long long* vcount, const int64_t* win,
+                hipStream_t s, const char** err) {
   int64_t lbase = 0;
   for (int k = 0; k < kLightBins; ++k) {
     const int64_t* st = hs + k * kStats;
-    const int64_t edges = st[kSEdges];
+    const int64_t all = st[kSEdges];
+    // a write window covers one run of the bin (bins are in edge order)
+    const int64_t b0 = win ? win[2 + 2 * k] : lbase;
+    const int64_t edges = win ? win[3 + 2 * k] - win[2 + 2 * k] : all;
     if (edges > 0) {
       const int tile = plan.light_tile[k];
       const unsigned grid = grid_cap(cdiv(edges, kBlock / tile));
-      const int rec = timing_begin(emit ? 1 : 0, k, 0, tile, edges, st[kSProbes], 0,
-                                   st[kSTriangles], s);
+      const int rec = timing_begin(emit ? 1 : 0, k, 0, tile, edges,
+                                   edges == all ? st[kSProbes] : -1, 0,
+                                   edges == all ? st[kSTriangles] : -1, s);
       LightArgs la;
       la.elist = w.elist; la.orow = orow; la.ocol = ocol; la.otail = otail;
       la.cnt = emit ? nullptr : w.cnt;
       la.tri_off = tri_off; la.perm = perm; la.first = first; la.count = count; la.out = out;
       la.digest = digest; la.vcount = vcount;
       const hipError_t e =
-          emit ? launch_light<true>(tile, grid, la, lbase, edges, nullptr, s)
-               : launch_light<false>(tile, grid, la, lbase, edges,
+          emit ? launch_light<true>(tile, grid, la, b0, edges, nullptr, s)
+               : launch_light<false>(tile, grid, la, b0, edges,
                                      w.stats + k * kStats + kSTriangles, s);
       AOT_TRY(e);
       timing_end(rec, s);
     }
-    lbase += edges;
+    lbase += all;
   }
   for (int h = 0; h < kHeavyClasses; ++h) {
     const int64_t* st = hs + (kHeavyBase + h) * kStats;
@@ -1178,6 +1333,7 @@ int run_buckets(bool emit, const Plan& plan, const int64_t* hs, const CountWs& w
     for (int q = 0; q < kHeavyClasses; ++q) a.arms[q] = arm;
     a.idx_words = index_words(arm, h, st[kSSpan]);
     a.items = w.items;
+    a.item_e = w.item_e;
     a.item_base = st[kSItemBase];
     a.item_count = items;
     a.orow = orow; a.ocol = ocol; a.irow = irow; a.icol = icol;
@@ -1233,9 +1389,7 @@ int count_run(int32_t n, int64_t m, const int64_t* orow, const int32_t* ocol, co
     k_bin_count<<<ge, kBlock, 0, s>>>(m, orow, ocol, otail, heavy_min, w.cnt, w.code, w.stats,
                                       w.probes);
     AOT_TRY(hipGetLastError());
-    k_bin_scatter<<<grid_cap(std::min<int64_t>(cdiv(m, kScatterChunk), 4096)), kBlock, 0, s>>>(
-        m, w.code, w.stats, w.elist);
-    AOT_TRY(hipGetLastError());
+    AOT_TRY(bin_scatter(m, w, s));
     const unsigned gv = grid_cap(std::min<int64_t>(cdiv(n, kBlock), 1024));
     k_item_count<<<gv, kBlock, 0, s>>>(n, orow, ocol, irow, heavy_min, w.stats);
     AOT_TRY(hipGetLastError());
@@ -1252,7 +1406,7 @@ int count_run(int32_t n, int64_t m, const int64_t* orow, const int32_t* ocol, co
       }
     }
     const int rc = run_buckets(false, plan, hs.data(), w, orow, ocol, otail, nullptr, irow, icol,
-                               nullptr, 0, 0, nullptr, nullptr, nullptr, s, err);
+                               nullptr, 0, 0, nullptr, nullptr, nullptr, nullptr, s, err);
     if (rc) return rc;
   }
   {
@@ -1358,6 +1512,7 @@ int drain_run(int32_t n, int64_t m, const int64_t* orow, const int32_t* ocol,
   for (int h = 0; h < kHeavyClasses; ++h) ha.arms[h] = plan.heavy_arm[h];
   ha.idx_words = idx_words;
   ha.items = w.items;
+  ha.item_e = w.item_e;
   ha.item_base = 0;
   ha.item_count = 0;
   ha.orow = orow; ha.ocol = ocol; ha.irow = irow; ha.icol = icol;
@@ -1386,9 +1541,7 @@ int drain_run(int32_t n, int64_t m, const int64_t* orow, const int32_t* ocol,
     k_bin_count<<<ge, kBlock, 0, s>>>(m, orow, ocol, otail, heavy_min, w.cnt, w.code, w.stats,
                                       w.probes);
     AOT_TRY(hipGetLastError());
-    k_bin_scatter<<<grid_cap(std::min<int64_t>(cdiv(m, kScatterChunk), 4096)), kBlock, 0, s>>>(
-        m, w.code, w.stats, w.elist);
-    AOT_TRY(hipGetLastError());
+    AOT_TRY(bin_scatter(m, w, s));
     const unsigned gv = grid_cap(std::min<int64_t>(cdiv(n, kBlock), 1024));
     k_item_count<<<gv, kBlock, 0, s>>>(n, orow, ocol, irow, heavy_min, w.stats);
     AOT_TRY(hipGetLastError());
@@ -1444,6 +1597,12 @@ int emit_run(int32_t n, int64_t m, const int64_t* orow, const int32_t* ocol, con
   if (m > 0 && (digest_mode || count > 0)) {
     std::vector<int64_t> hs(kStatWords, 0);
     int32_t words[kPlanWords];
+    int64_t win[kWinWords];
+    if (!digest_mode) {
+      k_window<<<1, 64, 0, s>>>(m, tri_off, first, count, w.stats, w.elist, w.win);
+      AOT_TRY(hipGetLastError());
+      AOT_TRY(hipMemcpyAsync(win, w.win, sizeof(win), hipMemcpyDeviceToHost, s));
+    }
     AOT_TRY(hipMemcpyAsync(hs.data(), w.stats, sizeof(int64_t) * kStatWords,
                            hipMemcpyDeviceToHost, s));
     AOT_TRY(hipMemcpyAsync(words, w.plan, sizeof(words), hipMemcpyDeviceToHost, s));
@@ -1454,7 +1613,8 @@ int emit_run(int32_t n, int64_t m, const int64_t* orow, const int32_t* ocol, con
       if (!plan_from(t, &plan)) plan = plain_plan();
     }
     const int rc = run_buckets(true, plan, hs.data(), w, orow, ocol, otail, perm, irow, icol,
-                               tri_off, first, count, out, dg, vc, s, err);
+                               tri_off, first, count, out, dg, vc, digest_mode ? nullptr : win,
+                               s, err);
     if (rc) return rc;
   }
   if (digest_mode) {

@@ -54,7 +54,8 @@ def plain_table() -> list[int]:
 
 def _timed(o, d, repeats: int, out):
     """Per-bucket milliseconds (count + write launch) averaged over repeats,
-    after one untimed warm-up, and the bucket's probe counts."""
+    after one untimed warm-up, and the bucket's probe counts (from the count
+    pass's records)."""
     ms: dict[int, float] = {}
     probes: dict[int, int] = {}
     for r in range(repeats + 1):
@@ -66,7 +67,8 @@ def _timed(o, d, repeats: int, out):
             continue
         for rec in recs:
             ms[rec["bucket"]] = ms.get(rec["bucket"], 0.0) + rec["ms"] / repeats
-            probes[rec["bucket"]] = rec["probes"]
+            if rec["pass"] == 0:          # the count pass covers every bucket whole
+                probes[rec["bucket"]] = rec["probes"]
     return ms, probes
 
 
