@@ -57,6 +57,10 @@ extern "C" {
 
 /* Flags for aot_orient. */
 #define AOT_VALIDATE 1u       /* check the CSR on the device first (syncs)   */
+#define AOT_IN_LISTS_BY_RANK 2u  /* sort every in-list into ascending rank;
+                                    costs a segmented sort of m entries, and
+                                    makes windows of a very large triangle
+                                    list cost about their own triangles     */
 
 /* Text for a status code; never NULL. */
 const char* aot_status_str(int status);
@@ -85,7 +89,8 @@ typedef struct aot_oriented {
   int32_t* perm;       /* [n]   rank -> original id                                 */
   int32_t* rank;       /* [n]   original id -> rank                                 */
   int64_t* in_rowptr;  /* [n+1] in-list offsets                                     */
-  int32_t* in_col;     /* [m]   in-neighbour ranks, in ascending ORIGINAL id        */
+  int32_t* in_col;     /* [m]   in-neighbour ranks; per row in ascending ORIGINAL
+                                id, or ascending rank with AOT_IN_LISTS_BY_RANK         */
 } aot_oriented;
 
 /* ------------------------------------------------------------------------
@@ -96,7 +101,7 @@ typedef struct aot_oriented {
  * taken ascending in rank space).  Also builds the in-lists that Algorithm 3's
  * second loop walks.
  *   g       input graph (device arrays).
- *   flags   0 or AOT_VALIDATE.
+ *   flags   0 or AOT_VALIDATE | AOT_IN_LISTS_BY_RANK.
  *   out     caller-allocated arrays of the sizes listed in aot_oriented;
  *           out->n and out->m are written.
  *   ws      device workspace of at least aot_orient_workspace() bytes.
@@ -188,10 +193,12 @@ int aot_bucket_features(const void* ws, size_t ws_bytes, int32_t n, int64_t m, f
  * int32[3*count]): each triangle as its three ORIGINAL ids ascending; the
  * global order is edge order, then ascending third vertex (in rank space).
  * Requires the tri_off and workspace of a prior aot_count on the same graph.
- * count may run past T (only T - first are written).  A window costs about
- * its own triangles: light edges are visited only over the run of the edge
- * order the window covers, heavy work items whose owned edges miss it are
- * skipped whole.  Synchronises `stream` once at the start (to size its
+ * count may run past T (only T - first are written).  Light edges are
+ * visited only over the run of the edge order the window covers, and heavy
+ * work items whose owned edges miss the window are skipped whole; with
+ * in-lists in rank order (AOT_IN_LISTS_BY_RANK) the in-neighbour items of
+ * long rows are narrow runs of the edge order, so a window of a very large
+ * list costs about its own triangles.  Synchronises `stream` once at the start (to size its
  * launches); the writes themselves are left enqueued.
  *   written  host, optional: number of triangles written. */
 int aot_list(const aot_oriented* g, const aot_dispatch* d, const int64_t* tri_off,

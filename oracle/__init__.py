@@ -62,7 +62,7 @@ def _load():
     lib.orc_fingerprint.restype = None
     lib.orc_list_digest.argtypes = [i32, _i64p, _i32p, _i32p, i32, i32, _u64p, ctypes.c_void_p]
     lib.orc_list_digest.restype = i64
-    lib.orc_in_lists.argtypes = [i32, _i64p, _i32p, _i32p, _i32p, _i64p, _i32p, _i64p, _i32p, _i32p]
+    lib.orc_in_lists.argtypes = [i32, _i64p, _i32p, _i64p, _i32p, _i32p]
     lib.orc_in_lists.restype = i64
     lib.orc_rank.argtypes = [i32, _i64p, _i32p, _i32p]
     lib.orc_rank.restype = ctypes.c_int
@@ -200,17 +200,15 @@ def vertex_triangles(rowptr, col, vs) -> np.ndarray:
     return out[: vs.size]
 
 
-def in_lists(rowptr, col, o: Oriented):
-    """In-lists in input-row order and the edge id of each in-edge <x, r>."""
+def in_lists(o: Oriented):
+    """In-lists in ascending rank and the edge id of each in-edge <x, r>."""
     lib = _load()
-    rowptr, col = _arrays(rowptr, col)
     irow = np.empty(o.n + 1, np.int64)
     icol = np.empty(max(o.m, 1), np.int32)
     ieid = np.empty(max(o.m, 1), np.int32)
-    k = lib.orc_in_lists(o.n, rowptr, _nonempty(col), _nonempty(o.perm), _nonempty(o.rank), o.orow,
-                         _nonempty(o.ocol), irow, icol, ieid)
+    k = lib.orc_in_lists(o.n, o.orow, _nonempty(o.ocol), irow, icol, ieid)
     if k < 0:
-        raise ValueError("input is not symmetric")
+        raise MemoryError("oracle in-lists failed")
     return irow, icol[:k].copy(), ieid[:k].copy()
 
 

@@ -125,34 +125,27 @@ int64_t orc_orient(int32_t n, const int64_t* rowptr, const int32_t* col,
 }
 
 /* In-lists of the oriented graph (Algorithm 3's second loop walks them): for
- * rank r, the ranks of the neighbours of perm[r] ranked below r, in the
- * order they appear in the input row (ascending original id); ieid[j] is the
- * index in ocol of the edge <icol[j], r>, found by binary search in N+(icol[j]). */
-int64_t orc_in_lists(int32_t n, const int64_t* rowptr, const int32_t* col, const int32_t* perm,
-                     const int32_t* rank, const int64_t* orow, const int32_t* ocol,
-                     int64_t* irow, int32_t* icol, int32_t* ieid) {
-  int64_t k = 0;
-  irow[0] = 0;
-  for (int32_t r = 0; r < n; ++r) {
-    int32_t u = perm[r];
-    for (int64_t j = rowptr[u]; j < rowptr[u + 1]; ++j) {
-      int32_t x = rank[col[j]];
-      if (x < r) {
-        int64_t lo = orow[x], hi = orow[x + 1];  /* binary search: N+(x) ascending */
-        while (lo < hi) {
-          int64_t mid = lo + (hi - lo) / 2;
-          if (ocol[mid] < r) lo = mid + 1; else hi = mid;
-        }
-        int64_t e = lo;
-        if (e == orow[x + 1] || ocol[e] != r) return -1;   /* not an edge: asymmetric input */
-        icol[k] = x;
-        ieid[k] = (int32_t)e;
-        ++k;
-      }
+ * rank r, every x with r in N+(x), in ascending rank x; ieid[j] is the index
+ * in ocol of the edge <icol[j], r>.  Built as the transpose of the out-lists,
+ * visiting the edges in order.  Returns m. */
+int64_t orc_in_lists(int32_t n, const int64_t* orow, const int32_t* ocol, int64_t* irow,
+                     int32_t* icol, int32_t* ieid) {
+  const int64_t m = orow[n];
+  for (int32_t r = 0; r <= n; ++r) irow[r] = 0;
+  for (int64_t e = 0; e < m; ++e) irow[ocol[e] + 1] += 1;
+  for (int32_t r = 0; r < n; ++r) irow[r + 1] += irow[r];
+  int64_t* fill = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+  if (!fill) return -1;
+  for (int32_t r = 0; r < n; ++r) fill[r] = irow[r];
+  for (int32_t x = 0; x < n; ++x)
+    for (int64_t e = orow[x]; e < orow[x + 1]; ++e) {
+      const int32_t r = ocol[e];
+      icol[fill[r]] = x;
+      ieid[fill[r]] = (int32_t)e;
+      fill[r] += 1;
     }
-    irow[r + 1] = k;
-  }
-  return k;
+  free(fill);
+  return m;
 }
 
 /* |A n B| for two ascending lists, by merging. */

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libaot.so")
 
 AOT_OK = 0
 AOT_VALIDATE = 1
+AOT_IN_LISTS_BY_RANK = 2
 AOT_DISPATCH_PLAIN = 0
 AOT_DISPATCH_TABLE = 1
 AOT_DISPATCH_LEARNED = 2
@@ -300,7 +301,8 @@ def alloc_oriented(n: int, m: int, device) -> Oriented:
 
 
 def orient(rowptr: torch.Tensor, col: torch.Tensor, validate: bool = False, stream=None,
-           ws: torch.Tensor | None = None, out: Oriented | None = None) -> Oriented:
+           ws: torch.Tensor | None = None, out: Oriented | None = None,
+           in_by_rank: bool = False) -> Oriented:
     """aot_orient on a symmetric device CSR (rowptr int64[n+1], col int32[nnz])."""
     assert rowptr.dtype == torch.int64 and col.dtype == torch.int32
     assert rowptr.is_contiguous() and col.is_contiguous()
@@ -315,7 +317,8 @@ def orient(rowptr: torch.Tensor, col: torch.Tensor, validate: bool = False, stre
         ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
     g = Graph(n, nnz, _ptr(rowptr) or ctypes.c_void_p(rowptr.data_ptr()), _ptr(col))
     oc = o.cstruct()
-    _check(load().aot_orient(ctypes.byref(g), AOT_VALIDATE if validate else 0, ctypes.byref(oc),
+    flags = (AOT_VALIDATE if validate else 0) | (AOT_IN_LISTS_BY_RANK if in_by_rank else 0)
+    _check(load().aot_orient(ctypes.byref(g), flags, ctypes.byref(oc),
                              _ptr(ws), ws.numel(), _stream(stream)), "aot_orient")
     return o
 
@@ -521,3 +524,59 @@ class BatchGraph:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------- streaming
+
+def stream_list(o: Oriented, c: Counted, chunk: int, consume=None, first: int = 0,
+                last: int | None = None, dispatch: Dispatch | None = None,
+                to_host: bool = True, stream=None):
+    """Lists triangles [first, last) window by window (aot_list into one of
+    two device buffers of `chunk` triangles) and, with to_host, copies each
+    window to one of two pinned host buffers on a second stream while the
+    next window is being listed.  consume(first_index, host_view) is called
+    for each window in order; the view stays valid until the call returns.
+    Returns the number of windows."""
+    last = c.T if last is None else min(last, c.T)
+    if last <= first:
+        return 0
+    dev = o.rowptr.device
+    k = max(1, min(chunk, last - first))
+    cs = stream if stream is not None else torch.cuda.current_stream()
+    dbuf = [torch.empty((k, 3), dtype=torch.int32, device=dev) for _ in range(2)]
+    hbuf, xs = None, None
+    if to_host:
+        hbuf = [torch.empty((k, 3), dtype=torch.int32, pin_memory=True) for _ in range(2)]
+        xs = torch.cuda.Stream(device=dev)          # default priority
+    pending = [None, None]       # per slot: (event, first index, count)
+
+    def finish(slot):
+        ev, f, n = pending[slot]
+        ev.synchronize()
+        if consume is not None:
+            consume(f, hbuf[slot][:n] if to_host else dbuf[slot][:n])
+        pending[slot] = None
+
+    windows = 0
+    for i, f in enumerate(range(first, last, k)):
+        slot = i % 2
+        n = min(k, last - f)
+        if pending[slot] is not None:
+            finish(slot)          # the copy out of this slot is done and consumed
+        list_triangles(o, c, first=f, count=n, out=dbuf[slot], dispatch=dispatch, stream=cs)
+        done = torch.cuda.Event()
+        done.record(cs)
+        if to_host:
+            xs.wait_event(done)
+            with torch.cuda.stream(xs):
+                hbuf[slot][:n].copy_(dbuf[slot][:n], non_blocking=True)
+                copied = torch.cuda.Event()
+                copied.record(xs)
+            pending[slot] = (copied, f, n)
+        else:
+            pending[slot] = (done, f, n)
+        windows += 1
+    for j in range(windows, windows + 2):
+        if pending[j % 2] is not None:
+            finish(j % 2)
+    return windows

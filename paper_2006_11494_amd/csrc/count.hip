@@ -10,8 +10,11 @@
 //  * heavy owner classes (deg+(b) >= heavy_min), one per ceil(log2 deg+(b)):
 //    owner-grouped as in Algorithm 3, where a pivot builds its index once
 //    (Section 3.2, the remark on the bitmap).  A workgroup takes a work item
-//    = an owner and a window of up to kItemSpan of its neighbours (out-list,
-//    then in-list), compacts the neighbours it owns into LDS with a prefix sum
+//    = an owner and its whole row if that holds at most kItemSpan
+//    neighbours, else a window of up to kItemSpan of its out-neighbours or of
+//    its in-neighbours (in-lists are in rank order, so the in-items of a long
+//    in-list each hold a narrow run of the edge order), compacts the
+//    neighbours it owns into LDS with a prefix sum
 //    of their out-degrees, stages N+(b) in LDS (bitmap over [min, max] of the
 //    list, open-addressing hash, or a sorted copy), and then spreads the
 //    flattened probes over all its lanes: each lane takes consecutive probes,
@@ -47,6 +50,11 @@ constexpr int kMaxIndexWords = 12288;  // LDS index cap: 48 KiB (bitmap window o
 constexpr int kUnroll = AOT_PROBE_UNROLL;   // 64-probe windows a wave keeps in flight
 constexpr int kGrid = 4096;
 constexpr int kDefaultHeavyMin = 32;
+#ifndef AOT_SPLIT_ITEMS
+#define AOT_SPLIT_ITEMS 1
+#endif
+// rows longer than this are windowed separately over out- and in-list
+constexpr int kSplitAbove = AOT_SPLIT_ITEMS ? kItemSpan : (1 << 30);
 constexpr int kPlanWords = 64;      // resolved table [32], learned flag, valid flag
 constexpr int kFeatures = AOT_NUM_FEATURES;
 constexpr int kOptions = AOT_NUM_OPTIONS;
@@ -232,8 +240,10 @@ __global__ __launch_bounds__(kBlock) void k_item_count(int32_t n, const int64_t*
     const int64_t ob = orow[b];
     const int64_t db = orow[b + 1] - ob;
     if (db < heavy_min) continue;
-    const int64_t deg = db + irow[b + 1] - irow[b];
-    const int64_t k = (deg + kItemSpan - 1) / kItemSpan;
+    const int64_t din = irow[b + 1] - irow[b];
+    const int64_t k = db + din <= kSplitAbove
+                          ? (db + din + kItemSpan - 1) / kItemSpan
+                          : (db + kItemSpan - 1) / kItemSpan + (din + kItemSpan - 1) / kItemSpan;
     const int h = heavy_class((int32_t)db);
     const unsigned long long span = (unsigned long long)(ocol[ob + db - 1] - ocol[ob] + 1);
     atomicAdd(&si[h], (unsigned long long)k);
@@ -269,13 +279,21 @@ __global__ __launch_bounds__(kBlock) void k_item_scatter(int32_t n, const int64_
   for (int64_t b0 = (int64_t)blockIdx.x * kBlock; b0 < n; b0 += (int64_t)gridDim.x * kBlock) {
     const int64_t b = b0 + threadIdx.x;
     int h = -1;
-    int32_t k = 0;
+    int32_t k = 0, kout = 0;
+    int32_t dbo = 0;
     if (b < n) {
       const int64_t db = orow[b + 1] - orow[b];
       if (db >= heavy_min) {
-        const int64_t deg = db + irow[b + 1] - irow[b];
-        k = (int32_t)((deg + kItemSpan - 1) / kItemSpan);
+        const int64_t din = irow[b + 1] - irow[b];
+        if (db + din <= kSplitAbove) {        // windows over the whole row
+          k = (int32_t)((db + din + kItemSpan - 1) / kItemSpan);
+          kout = k;
+        } else {
+          kout = (int32_t)((db + kItemSpan - 1) / kItemSpan);
+          k = kout + (int32_t)((din + kItemSpan - 1) / kItemSpan);
+        }
         h = heavy_class((int32_t)db);
+        dbo = (int32_t)db;
       }
     }
     if (!ballot(h >= 0)) continue;
@@ -294,7 +312,12 @@ __global__ __launch_bounds__(kBlock) void k_item_scatter(int32_t n, const int64_
       at = __shfl(at, leader, kWave);
       if (h == q) {
         const int64_t first = base[q] + at + (inc - kin);
-        for (int32_t r = 0; r < k; ++r) items[first + r] = make_int2((int32_t)b, r * kItemSpan);
+        // out-list windows, then in-list windows: an item of a longer row
+        // never mixes the two
+        for (int32_t r = 0; r < k; ++r)
+          items[first + r] = make_int2((int32_t)b, r < kout ? r * kItemSpan
+                                                            : dbo + (r - kout) * kItemSpan);
+        (void)dbo;
       }
     }
   }
@@ -711,7 +734,9 @@ __device__ void heavy_item(HeavyShared<kEmit>& sh, uint32_t* lds, const HeavyArg
   const int64_t ib = a.irow[b];
   const int32_t deg = db + (int32_t)(a.irow[b + 1] - ib);
   const int32_t j0 = item.y;
-  const int32_t j1 = min(deg, j0 + kItemSpan);
+  // the whole row, or one window of the out-list or of the in-list
+  const int32_t j1 = deg <= kSplitAbove ? min(deg, j0 + kItemSpan)
+                                        : min(j0 < db ? db : deg, j0 + kItemSpan);
 
   // owned neighbours of this window, compacted with a prefix of their probe counts
   constexpr int kPer = kItemSpan / kBlock;
@@ -1153,7 +1178,9 @@ bool plan_from_predictions(const float* pred, int stride, const uint8_t* present
   return true;
 }
 
-int64_t max_items(int32_t n, int64_t m) { return (int64_t)n + cdiv(2 * m, kItemSpan) + 16; }
+// Work items: per heavy owner ceil(deg+/kItemSpan) + ceil(deg-/kItemSpan)
+// <= (deg+ + deg-)/kItemSpan + 2, so at most 2n + 2m/kItemSpan in all.
+int64_t max_items(int32_t n, int64_t m) { return 2 * (int64_t)n + cdiv(2 * m, kItemSpan) + 16; }
 
 struct CountWs {
   int32_t* plan;

@@ -7,7 +7,9 @@
 // similar row lengths: rows are processed in rank ranges with a row-group
 // width G matched to the degree range (4, 16 or 64 lanes, or a whole
 // workgroup for rows longer than 64).  Out-list lengths are not monotone in
-// rank, so the sort step first bins rows by length.
+// rank, so the sort step first bins rows by length.  On request, in-lists are
+// sorted the same way into ascending rank, which is the order of their edges'
+// ids (this makes windows of a huge triangle list cheap; see aot_list).
 #include <algorithm>
 #include <climits>
 
@@ -29,7 +31,9 @@ enum : int {
   kCSortCursor = 12,  // [12..15]
   kCRowCount = 16,    // [16..19] rows per degree class (row-list mode)
   kCRowCursor = 20,   // [20..23]
-  kCounters = 24,
+  kCInCount = 24,     // [24..27] in-lists per sort class
+  kCInCursor = 28,    // [28..31]
+  kCounters = 32,
 };
 
 constexpr int kSortClasses = 4;     // len <= 16, <= 64, <= 4096, longer
@@ -284,34 +288,53 @@ __device__ __forceinline__ int sort_class(int64_t len) {
   return len <= 16 ? 0 : len <= 64 ? 1 : len <= 4096 ? 2 : 3;
 }
 
-// Class of rank r's row, or -1 for an empty row.  kDeg: the orientation's
-// degree classes (row-group width 4, 16, 64, kBlock) of the full row;
-// otherwise the sort classes of the out-list.
-template <bool kDeg>
-__device__ __forceinline__ int row_class(int64_t r, const int32_t* __restrict__ dplus,
+__global__ __launch_bounds__(kBlock) void k_copy(const int32_t* __restrict__ src, int64_t n,
+                                                 int32_t* __restrict__ dst) {
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kBlock)
+    dst[i] = src[i];
+}
+
+// What a class pass bins: the out-lists (by length, for sorting), the full
+// rows (by degree, the orientation's row-group widths 4, 16, 64, kBlock), or
+// the in-lists (by length, for sorting).
+enum ClassMode : int { kOutLists = 0, kRowsByDegree = 1, kInLists = 2 };
+
+template <int kMode>
+struct ClassSlots {
+  static constexpr int count = kMode == kOutLists ? kCSortCount
+                               : kMode == kRowsByDegree ? kCRowCount : kCInCount;
+  static constexpr int cursor = kMode == kOutLists ? kCSortCursor
+                                : kMode == kRowsByDegree ? kCRowCursor : kCInCursor;
+};
+
+// Class of rank r's row, or -1 for an empty one.  len: deg+ (out-lists) or
+// deg- (in-lists) per rank.
+template <int kMode>
+__device__ __forceinline__ int row_class(int64_t r, const int32_t* __restrict__ len,
                                          const int32_t* __restrict__ perm,
                                          const int64_t* __restrict__ rowptr) {
-  if constexpr (kDeg) {
+  if constexpr (kMode == kRowsByDegree) {
     const int32_t u = perm[r];
     const int64_t d = rowptr[u + 1] - rowptr[u];
     return d == 0 ? -1 : d <= 4 ? 0 : d <= 16 ? 1 : d <= 64 ? 2 : 3;
   } else {
-    const int32_t len = dplus[r];
-    return len > 0 ? sort_class(len) : -1;
+    const int32_t l = len[r];
+    return l > 0 ? sort_class(l) : -1;
   }
 }
 
-template <bool kDeg>
+template <int kMode>
 __global__ __launch_bounds__(kBlock) void k_count_classes(int32_t n,
-                                                          const int32_t* __restrict__ dplus,
+                                                          const int32_t* __restrict__ len,
                                                           const int32_t* __restrict__ perm,
                                                           const int64_t* __restrict__ rowptr,
                                                           int32_t* __restrict__ counters) {
-  constexpr int kOff = kDeg ? kCRowCount : kCSortCount;
+  constexpr int kOff = ClassSlots<kMode>::count;
   int32_t h[kSortClasses] = {0, 0, 0, 0};
   for (int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x; r < n;
        r += (int64_t)gridDim.x * kBlock) {
-    const int c = row_class<kDeg>(r, dplus, perm, rowptr);
+    const int c = row_class<kMode>(r, len, perm, rowptr);
 #pragma unroll
     for (int q = 0; q < kSortClasses; ++q) h[q] += c == q;
   }
@@ -324,15 +347,15 @@ __global__ __launch_bounds__(kBlock) void k_count_classes(int32_t n,
 }
 
 // Rows into their classes; one global atomic per wave and class.
-template <bool kDeg>
+template <int kMode>
 __global__ __launch_bounds__(kBlock) void k_scatter_classes(int32_t n,
-                                                            const int32_t* __restrict__ dplus,
+                                                            const int32_t* __restrict__ len,
                                                             const int32_t* __restrict__ perm,
                                                             const int64_t* __restrict__ rowptr,
                                                             int32_t* __restrict__ counters,
                                                             int32_t* __restrict__ rows) {
-  constexpr int kOff = kDeg ? kCRowCount : kCSortCount;
-  constexpr int kCur = kDeg ? kCRowCursor : kCSortCursor;
+  constexpr int kOff = ClassSlots<kMode>::count;
+  constexpr int kCur = ClassSlots<kMode>::cursor;
   __shared__ int32_t base[kSortClasses];
   if (threadIdx.x == 0) {
     int32_t run = 0;
@@ -341,7 +364,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter_classes(int32_t n,
   __syncthreads();
   for (int64_t r0 = (int64_t)blockIdx.x * kBlock; r0 < n; r0 += (int64_t)gridDim.x * kBlock) {
     const int64_t r = r0 + threadIdx.x;
-    const int c = r < n ? row_class<kDeg>(r, dplus, perm, rowptr) : -1;
+    const int c = r < n ? row_class<kMode>(r, len, perm, rowptr) : -1;
     for (int q = 0; q < kSortClasses; ++q) {
       const uint64_t mask = ballot(c == q);
       if (!mask) continue;
@@ -356,15 +379,15 @@ __global__ __launch_bounds__(kBlock) void k_scatter_classes(int32_t n,
 
 // Bitonic sort of one row per G-lane group, one element per lane.
 template <int G>
-__global__ __launch_bounds__(kBlock) void k_sort_lanes(int cls, const int32_t* __restrict__ counters,
+__global__ __launch_bounds__(kBlock) void k_sort_lanes(int cbase, int cls, const int32_t* __restrict__ counters,
                                                        const int32_t* __restrict__ rows,
                                                        const int64_t* __restrict__ orow,
                                                        const int32_t* __restrict__ src,
                                                        int32_t* __restrict__ dst) {
   constexpr int kGroups = kBlock / G;
   int32_t base = 0;
-  for (int q = 0; q < cls; ++q) base += counters[kCSortCount + q];
-  const int32_t count = counters[kCSortCount + cls];
+  for (int q = 0; q < cls; ++q) base += counters[cbase + q];
+  const int32_t count = counters[cbase + cls];
   const int gi = threadIdx.x / G, li = threadIdx.x % G;
   for (int64_t t = (int64_t)blockIdx.x * kGroups + gi; t < count;
        t += (int64_t)gridDim.x * kGroups) {
@@ -387,15 +410,15 @@ __global__ __launch_bounds__(kBlock) void k_sort_lanes(int cls, const int32_t* _
 }
 
 // Bitonic sort in LDS, one row (64 < len <= 4096) per workgroup.
-__global__ __launch_bounds__(kBlock) void k_sort_block(int cls, const int32_t* __restrict__ counters,
+__global__ __launch_bounds__(kBlock) void k_sort_block(int cbase, int cls, const int32_t* __restrict__ counters,
                                                        const int32_t* __restrict__ rows,
                                                        const int64_t* __restrict__ orow,
                                                        const int32_t* __restrict__ src,
                                                        int32_t* __restrict__ dst) {
   __shared__ int32_t s[4096];
   int32_t base = 0;
-  for (int q = 0; q < cls; ++q) base += counters[kCSortCount + q];
-  const int32_t count = counters[kCSortCount + cls];
+  for (int q = 0; q < cls; ++q) base += counters[cbase + q];
+  const int32_t count = counters[cbase + cls];
   for (int64_t t = blockIdx.x; t < count; t += gridDim.x) {
     const int32_t r = rows[base + t];
     const int64_t beg = orow[r];
@@ -424,7 +447,7 @@ __global__ __launch_bounds__(kBlock) void k_sort_block(int cls, const int32_t* _
 // Long rows: values are distinct ranks, so a bitmap over [min, max] in LDS
 // (one 524288-id window at a time) sorts them; set bits are written out in
 // order after a block-wide prefix count.
-__global__ __launch_bounds__(kBlock) void k_sort_bitmap(int cls, const int32_t* __restrict__ counters,
+__global__ __launch_bounds__(kBlock) void k_sort_bitmap(int cbase, int cls, const int32_t* __restrict__ counters,
                                                         const int32_t* __restrict__ rows,
                                                         const int64_t* __restrict__ orow,
                                                         const int32_t* __restrict__ src,
@@ -435,8 +458,8 @@ __global__ __launch_bounds__(kBlock) void k_sort_bitmap(int cls, const int32_t* 
   constexpr int64_t kBits = (int64_t)kBitmapWords * 32;
   constexpr int kWordsPerThread = kBitmapWords / kBlock;
   int32_t base = 0;
-  for (int q = 0; q < cls; ++q) base += counters[kCSortCount + q];
-  const int32_t count = counters[kCSortCount + cls];
+  for (int q = 0; q < cls; ++q) base += counters[cbase + q];
+  const int32_t count = counters[cbase + cls];
   for (int64_t t = blockIdx.x; t < count; t += gridDim.x) {
     const int32_t r = rows[base + t];
     const int64_t beg = orow[r];
@@ -525,6 +548,21 @@ size_t orient_workspace_bytes(int32_t n, int64_t nnz) {
 
 namespace {
 
+// Sorts every list of (offsets, src) into dst by its length class; cbase:
+// the counter slots holding the class sizes.
+hipError_t sort_lists(int cbase, unsigned g_small, const int32_t* counters, const int32_t* rows,
+                      const int64_t* offsets, const int32_t* src, int32_t* dst, hipStream_t s) {
+  k_sort_lanes<16><<<g_small, kBlock, 0, s>>>(cbase, 0, counters, rows, offsets, src, dst);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_sort_lanes<64><<<g_small, kBlock, 0, s>>>(cbase, 1, counters, rows, offsets, src, dst);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  k_sort_block<<<kGrid, kBlock, 0, s>>>(cbase, 2, counters, rows, offsets, src, dst);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  k_sort_bitmap<<<512, kBlock, 0, s>>>(cbase, 3, counters, rows, offsets, src, dst);
+  return hipGetLastError();
+}
+
 // Batch mode: sort keys (graph, degree) with `bits` key bits, and row lists
 // instead of rank ranges, so that nothing is read back to the host.
 struct BatchKeys {
@@ -534,7 +572,7 @@ struct BatchKeys {
 };
 
 int orient_impl(int32_t n, int64_t nnz, const int64_t* rowptr, const int32_t* col, bool validate,
-                const BatchKeys* bk, int64_t* orow, int32_t* ocol, int32_t* otail,
+                bool in_by_rank, const BatchKeys* bk, int64_t* orow, int32_t* ocol, int32_t* otail,
                 int32_t* perm, int32_t* rank, int64_t* irow, int32_t* icol, void* ws,
                 size_t ws_bytes, hipStream_t s, const char** err) {
   const int64_t m = nnz / 2;
@@ -622,10 +660,10 @@ int orient_impl(int32_t n, int64_t nnz, const int64_t* rowptr, const int32_t* co
   if (bk) {
     AOT_TRY(fill_i32(dplus, n, 0, s));
     AOT_TRY(fill_i32(dminus, n, 0, s));
-    k_count_classes<true><<<std::min(grid_for(n, kBlock), 1024u), kBlock, 0, s>>>(
+    k_count_classes<kRowsByDegree><<<std::min(grid_for(n, kBlock), 1024u), kBlock, 0, s>>>(
         n, dplus, perm, rowptr, counters);
     AOT_TRY(hipGetLastError());
-    k_scatter_classes<true><<<grid_for(n, kBlock), kBlock, 0, s>>>(n, dplus, perm, rowptr,
+    k_scatter_classes<kRowsByDegree><<<grid_for(n, kBlock), kBlock, 0, s>>>(n, dplus, perm, rowptr,
                                                                    counters, rows);
     AOT_TRY(hipGetLastError());
   } else {
@@ -650,31 +688,38 @@ int orient_impl(int32_t n, int64_t nnz, const int64_t* rowptr, const int32_t* co
 #undef ROWS
 
   // sort each out-list into ocol
-  k_count_classes<false><<<std::min(grid_for(n, kBlock), 1024u), kBlock, 0, s>>>(
+  k_count_classes<kOutLists><<<std::min(grid_for(n, kBlock), 1024u), kBlock, 0, s>>>(
       n, dplus, perm, rowptr, counters);
   AOT_TRY(hipGetLastError());
-  k_scatter_classes<false><<<grid_for(n, kBlock), kBlock, 0, s>>>(n, dplus, perm, rowptr,
+  k_scatter_classes<kOutLists><<<grid_for(n, kBlock), kBlock, 0, s>>>(n, dplus, perm, rowptr,
                                                                   counters, rows);
   AOT_TRY(hipGetLastError());
   const unsigned g_small = (unsigned)std::min<int64_t>(kGrid, cdiv(n, kBlock / 16) + 1);
-  k_sort_lanes<16><<<g_small, kBlock, 0, s>>>(0, counters, rows, orow, unsorted, ocol);
+  AOT_TRY(sort_lists(kCSortCount, g_small, counters, rows, orow, unsorted, ocol, s));
+
+  if (!in_by_rank) return 0;
+  // sort each in-list into ascending rank (= edge order of the in-edges): the
+  // in-lists were written to icol; move them to the now free scratch first
+  AOT_TRY(fill_i32(counters + kCInCount, 8, 0, s));
+  k_copy<<<grid_for(m, kBlock), kBlock, 0, s>>>(icol, m, unsorted);
   AOT_TRY(hipGetLastError());
-  k_sort_lanes<64><<<g_small, kBlock, 0, s>>>(1, counters, rows, orow, unsorted, ocol);
+  k_count_classes<kInLists><<<std::min(grid_for(n, kBlock), 1024u), kBlock, 0, s>>>(
+      n, dminus, perm, rowptr, counters);
   AOT_TRY(hipGetLastError());
-  k_sort_block<<<kGrid, kBlock, 0, s>>>(2, counters, rows, orow, unsorted, ocol);
+  k_scatter_classes<kInLists><<<grid_for(n, kBlock), kBlock, 0, s>>>(n, dminus, perm, rowptr,
+                                                                     counters, rows);
   AOT_TRY(hipGetLastError());
-  k_sort_bitmap<<<512, kBlock, 0, s>>>(3, counters, rows, orow, unsorted, ocol);
-  AOT_TRY(hipGetLastError());
+  AOT_TRY(sort_lists(kCInCount, g_small, counters, rows, irow, unsorted, icol, s));
   return 0;
 }
 
 }  // namespace
 
 int orient_run(int32_t n, int64_t nnz, const int64_t* rowptr, const int32_t* col, bool validate,
-               int64_t* orow, int32_t* ocol, int32_t* otail, int32_t* perm, int32_t* rank,
-               int64_t* irow, int32_t* icol, void* ws, size_t ws_bytes, hipStream_t s,
-               const char** err) {
-  return orient_impl(n, nnz, rowptr, col, validate, nullptr, orow, ocol, otail, perm, rank, irow,
+               bool in_by_rank, int64_t* orow, int32_t* ocol, int32_t* otail, int32_t* perm,
+               int32_t* rank, int64_t* irow, int32_t* icol, void* ws, size_t ws_bytes,
+               hipStream_t s, const char** err) {
+  return orient_impl(n, nnz, rowptr, col, validate, in_by_rank, nullptr, orow, ocol, otail, perm, rank, irow,
                      icol, ws, ws_bytes, s, err);
 }
 
@@ -683,7 +728,8 @@ int orient_batch_run(int32_t n, int64_t nnz, const int64_t* rowptr, const int32_
                      int32_t* ocol, int32_t* otail, int32_t* perm, int32_t* rank, int64_t* irow,
                      int32_t* icol, void* ws, size_t ws_bytes, hipStream_t s, const char** err) {
   BatchKeys bk{voff, count, dbits, dbits + gbits};
-  return orient_impl(n, nnz, rowptr, col, false, &bk, orow, ocol, otail, perm, rank, irow, icol,
+  return orient_impl(n, nnz, rowptr, col, false, false, &bk, orow, ocol, otail, perm, rank, irow,
+                     icol,
                      ws, ws_bytes, s, err);
 }
 

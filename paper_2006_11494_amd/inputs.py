@@ -117,12 +117,14 @@ def csr_from_pairs(n: int, u: torch.Tensor, v: torch.Tensor, name: str = "") -> 
     return Csr(n, rowptr, cols.to(torch.int32), name)
 
 
-def csr_from_pairs_partitioned(n: int, u: torch.Tensor, v: torch.Tensor, name: str = "",
-                               parts: int = 32) -> Csr:
+def csr_from_pairs_partitioned(n: int, u, v, name: str = "", parts: int = 32) -> Csr:
     """The same CSR as csr_from_pairs, built one range of rows at a time so
-    that no sort ever holds more than about 2 * len(u) / parts keys (graphs
-    with billions of entries).  u, v may be int32; they are not modified."""
-    dev = u.device
+    that no sort ever holds more than about 2 * pairs / parts keys (graphs
+    with billions of entries).  u, v: tensors (int32 or int64), or equally
+    chunked lists of them, so that no single operation sees all pairs."""
+    us = list(u) if isinstance(u, (list, tuple)) else [u]
+    vs = list(v) if isinstance(v, (list, tuple)) else [v]
+    dev = us[0].device if us else torch.device("cpu")
     counts = torch.zeros(n, dtype=torch.int64, device=dev)
     cols = []
     bounds = [n * p // parts for p in range(parts + 1)]
@@ -131,13 +133,15 @@ def csr_from_pairs_partitioned(n: int, u: torch.Tensor, v: torch.Tensor, name: s
         if hi <= lo:
             continue
         keys = []
-        for x, y in ((u, v), (v, u)):
-            sel = (x >= lo) & (x < hi) & (x != y)
-            keys.append((x[sel].to(torch.int64) - lo) * n + y[sel].to(torch.int64))
-            del sel
-        key = torch.unique(torch.cat(keys))          # sorted, deduplicated (row, col)
+        for cu, cv in zip(us, vs):
+            for x, y in ((cu, cv), (cv, cu)):
+                sel = (x >= lo) & (x < hi) & (x != y)
+                keys.append((x[sel].to(torch.int64) - lo) * n + y[sel].to(torch.int64))
+                del sel
+        key = torch.unique(torch.cat(keys)) if keys else torch.zeros(0, dtype=torch.int64,
+                                                                     device=dev)
         del keys
-        rows = key // n
+        rows = key // n                                  # sorted, deduplicated (row, col)
         counts[lo:hi] = torch.bincount(rows, minlength=hi - lo)
         cols.append((key - rows * n).to(torch.int32))
         del key, rows
@@ -220,11 +224,9 @@ def rmat(scale: int, edge_factor: int, seed: int, a=0.57, b=0.19, c=0.19,
         vs.append(perm[v].to(torch.int32))
         del t, u, v
     name = f"rmat(scale={scale},ef={edge_factor},seed={seed})"
-    u, v = torch.cat(us), torch.cat(vs)
-    del us, vs
     if parts is None and ntup < (1 << 27):
-        return csr_from_pairs(n, u, v, name)
-    return csr_from_pairs_partitioned(n, u, v, name, parts or max(8, ntup >> 26))
+        return csr_from_pairs(n, torch.cat(us), torch.cat(vs), name)
+    return csr_from_pairs_partitioned(n, us, vs, name, parts or max(8, ntup >> 26))
 
 
 def chung_lu(n: int, mean_degree: float, gamma: float, max_degree: float, seed: int,
@@ -309,7 +311,8 @@ def workload(name: str, seed: int | None = None, device="cpu") -> Csr:
     """The synthetic stand-ins for the paper's real graphs (Table 2):
     er2000 (ER n=2000 p=0.01), rmat20 (scale 20, edge factor 16),
     chunglu4m (n=4M, mean degree 40, exponent 2.1, cap 100k),
-    rmat26 (scale 26, edge factor 32); small variants for quick runs."""
+    rmat26 (scale 26, edge factor 32); rmatS / rmatSxE: R-MAT of scale S and
+    edge factor 16 / E (smaller variants and proxies)."""
     if name == "er2000":
         return erdos_renyi(2000, 0.01, 1 if seed is None else seed, device)
     if name == "rmat20":
@@ -318,9 +321,10 @@ def workload(name: str, seed: int | None = None, device="cpu") -> Csr:
         return chung_lu(4_000_000, 40.0, 2.1, 100_000.0, 3 if seed is None else seed, device)
     if name == "rmat26":
         return rmat(26, 32, 5 if seed is None else seed, device=device)
-    if name.startswith("rmat"):
-        scale = int(name[4:])
-        return rmat(scale, 16, 2 if seed is None else seed, device=device)
+    if name.startswith("rmat"):           # rmatS (edge factor 16) or rmatSxE
+        spec = name[4:].split("x")
+        scale, ef = int(spec[0]), int(spec[1]) if len(spec) > 1 else 16
+        return rmat(scale, ef, 2 if seed is None else seed, device=device)
     raise ValueError(f"unknown workload {name!r}")
 
 

@@ -52,6 +52,23 @@ def plain_table() -> list[int]:
     return t
 
 
+RESIDENT = 1 << 28     # lists up to this many triangles go into one buffer
+
+
+def out_buffer(c, device):
+    """Output buffer for timing runs: the whole list, or one window of it."""
+    return torch.empty((max(1, min(c.T, RESIDENT)), 3), dtype=torch.int32, device=device)
+
+
+def list_all(o, c, d, out):
+    """The whole write pass: into `out` if it holds the list, else window by
+    window (device windows, nothing copied to the host)."""
+    if c.T <= out.shape[0]:
+        aot.list_triangles(o, c, out=out, dispatch=d)
+    else:
+        aot.stream_list(o, c, out.shape[0], None, dispatch=d, to_host=False)
+
+
 def _timed(o, d, repeats: int, out):
     """Per-bucket milliseconds (count + write launch) averaged over repeats,
     after one untimed warm-up, and the bucket's probe counts (from the count
@@ -61,8 +78,8 @@ def _timed(o, d, repeats: int, out):
     for r in range(repeats + 1):
         aot.timing_start()
         c = aot.count(o, d)
-        aot.list_triangles(o, c, out=out, dispatch=d)
-        recs = aot.timing_stop()
+        list_all(o, c, d, out)
+        recs = aot.timing_stop(cap=1 << 17)
         if r == 0:
             continue
         for rec in recs:
@@ -77,7 +94,7 @@ def record(csr, repeats: int = 3):
     o = aot.orient(csr.rowptr, csr.col)
     c = aot.count(o)
     feats, present = aot.bucket_features(o, c)
-    out = torch.empty((max(c.T, 1), 3), dtype=torch.int32, device=csr.rowptr.device)
+    out = out_buffer(c, csr.rowptr.device)
     rows = []
     for i in range(N_EXPLORE):
         d = aot.Dispatch(aot.AOT_DISPATCH_TABLE, 0, exploration_table(i))
@@ -126,7 +143,7 @@ def step_ms(o, d, repeats: int, out) -> float:
         b = torch.cuda.Event(enable_timing=True)
         a.record()
         c = aot.count(o, d)
-        aot.list_triangles(o, c, out=out, dispatch=d)
+        list_all(o, c, d, out)
         b.record()
         torch.cuda.synchronize()
         if r:
@@ -142,7 +159,7 @@ def judge(net: aot.Mlp, graphs, repeats: int = 5):
     for csr in graphs:
         o = aot.orient(csr.rowptr, csr.col)
         c = aot.count(o)
-        out = torch.empty((max(c.T, 1), 3), dtype=torch.int32, device=csr.rowptr.device)
+        out = out_buffer(c, csr.rowptr.device)
         plain += step_ms(o, None, repeats, out)
         learned += step_ms(o, d_learned, repeats, out)
     return plain, learned, learned < plain

@@ -51,11 +51,13 @@ DISPATCHES = {
 def reference(csr):
     rp, col = csr.numpy()
     o = oracle.orient(rp, col)
-    irow, icol, ieid = oracle.in_lists(rp, col, o)
+    irow, icol, ieid = oracle.in_lists(o)
     return o, irow, icol, ieid
 
 
-def check_orientation(o_gpu, ref):
+def check_orientation(o_gpu, ref, in_by_rank=False):
+    """Exact equality; in-lists in the oracle's (rank) order when they were
+    sorted by rank, else per row the same set in ascending original id."""
     o, irow, icol, ieid = ref
     h = lambda t: t.cpu().numpy()
     assert np.array_equal(h(o_gpu.perm), o.perm)
@@ -64,7 +66,17 @@ def check_orientation(o_gpu, ref):
     assert np.array_equal(h(o_gpu.col), o.ocol)
     assert np.array_equal(h(o_gpu.tail), o.tail())
     assert np.array_equal(h(o_gpu.in_rowptr), irow)
-    assert np.array_equal(h(o_gpu.in_col), icol)
+    gi = h(o_gpu.in_col)
+    if in_by_rank:
+        assert np.array_equal(gi, icol)
+        return
+    rows = np.repeat(np.arange(o.n), np.diff(irow))
+    # same set per row: sort both by (row, rank)
+    assert np.array_equal(gi[np.lexsort((gi, rows))], icol[np.lexsort((icol, rows))])
+    # documented order: ascending original id inside each row
+    ids = o.perm[gi] if gi.size else gi
+    same_row = rows[1:] == rows[:-1]
+    assert np.all(ids[1:][same_row] > ids[:-1][same_row])
 
 
 def check_all(csr, name, dispatches=DISPATCHES, windows=True):
@@ -80,6 +92,9 @@ def check_all(csr, name, dispatches=DISPATCHES, windows=True):
     o = aot.orient(g.rowptr, g.col, validate=True)
     torch.cuda.synchronize()
     check_orientation(o, ref)
+    ob = aot.orient(g.rowptr, g.col, in_by_rank=True)
+    torch.cuda.synchronize()
+    check_orientation(ob, ref, in_by_rank=True)
     for dname, d in dispatches.items():
         say(f"[gpu] count+list {name} dispatch={dname}")
         c = aot.count(o, d)
@@ -87,6 +102,12 @@ def check_all(csr, name, dispatches=DISPATCHES, windows=True):
         assert np.array_equal(np.diff(c.tri_off.cpu().numpy()), cnt_ref), dname
         tri = aot.list_triangles(o, c, dispatch=d).cpu().numpy()
         assert np.array_equal(tri, tri_ref), dname
+    # in-lists in rank order: same counts and list for every dispatch
+    for dname in ("plain", "all_heavy_hash", "mixed"):
+        d = dispatches.get(dname, None) if dname in dispatches else None
+        c = aot.count(ob, d)
+        assert np.array_equal(np.diff(c.tri_off.cpu().numpy()), cnt_ref), dname
+        assert np.array_equal(aot.list_triangles(ob, c, dispatch=d).cpu().numpy(), tri_ref)
     if windows and T > 0:
         say(f"[gpu] windows {name}")
         c = aot.count(o)
