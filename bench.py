@@ -53,8 +53,11 @@ def parse():
     p.add_argument("--batch-count", type=int, default=512)
     p.add_argument("--resident-gb", type=float, default=48.0,
                    help="list into one device buffer up to this size, else in windows")
-    p.add_argument("--chunk", type=int, default=1 << 29,
-                   help="triangles per window when the list is not resident")
+    p.add_argument("--chunk", type=int, default=1 << 33,
+                   help="triangles per device window when the list is not resident "
+                        "(capped at 40%% of the free device memory)")
+    p.add_argument("--stream-chunk", type=int, default=1 << 29,
+                   help="triangles per window streamed to pinned host memory")
     p.add_argument("--no-stream", action="store_true",
                    help="skip the pass that streams every window to pinned host memory")
     p.add_argument("--copy-calibration", action="store_true",
@@ -367,6 +370,9 @@ def main():
     c = aot.count(o, dispatch, ws=cws, tri_off=tri_off)
     T, probes = c.T, c.probes
     windowed = T * 12 > args.resident_gb * 1e9
+    if windowed:
+        free, _ = torch.cuda.mem_get_info(dev)
+        args.chunk = int(min(args.chunk, T, 0.4 * free // 12))
     out = None if windowed else torch.empty((max(T, 1), 3), dtype=torch.int32, device=dev)
     log(f"[bench] T={T} probes={probes}; output {T * 12 / 1e9:.2f} GB"
         + (f", listed in windows of {args.chunk} triangles" if windowed else ""))
@@ -429,11 +435,11 @@ def main():
         torch.cuda.synchronize()
         t = time.perf_counter()
         cc = aot.count(o, dispatch, ws=cws, tri_off=tri_off)
-        aot.stream_list(o, cc, args.chunk, consume, dispatch=dispatch, to_host=True)
+        aot.stream_list(o, cc, args.stream_chunk, consume, dispatch=dispatch, to_host=True)
         torch.cuda.synchronize()
         s_ms = (time.perf_counter() - t) * 1000.0
         streamed = {"ms_count_and_list": s_ms, "windows": state["windows"],
-                    "window_triangles": args.chunk, "bytes_to_host": 12 * T,
+                    "window_triangles": args.stream_chunk, "bytes_to_host": 12 * T,
                     "host_GB_per_s": 12 * T / (s_ms / 1000.0) / 1e9,
                     "triangles_per_s": T / (s_ms / 1000.0),
                     "note": "count + every window copied to pinned host memory (PCIe-inclusive)"}

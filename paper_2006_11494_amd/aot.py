@@ -531,10 +531,10 @@ class BatchGraph:
 def stream_list(o: Oriented, c: Counted, chunk: int, consume=None, first: int = 0,
                 last: int | None = None, dispatch: Dispatch | None = None,
                 to_host: bool = True, stream=None):
-    """Lists triangles [first, last) window by window (aot_list into one of
-    two device buffers of `chunk` triangles) and, with to_host, copies each
-    window to one of two pinned host buffers on a second stream while the
-    next window is being listed.  consume(first_index, host_view) is called
+    """Lists triangles [first, last) window by window (aot_list into a device
+    buffer of `chunk` triangles) and, with to_host, copies each window to
+    one of two pinned host buffers on a second stream while the next window
+    is being listed into the other of two device buffers.  consume(first_index, host_view) is called
     for each window in order; the view stays valid until the call returns.
     Returns the number of windows."""
     last = c.T if last is None else min(last, c.T)
@@ -543,7 +543,10 @@ def stream_list(o: Oriented, c: Counted, chunk: int, consume=None, first: int = 
     dev = o.rowptr.device
     k = max(1, min(chunk, last - first))
     cs = stream if stream is not None else torch.cuda.current_stream()
-    dbuf = [torch.empty((k, 3), dtype=torch.int32, device=dev) for _ in range(2)]
+    # without host copies one device buffer suffices (the windows are
+    # listed one after another on one stream)
+    one = torch.empty((k, 3), dtype=torch.int32, device=dev)
+    dbuf = [one, torch.empty((k, 3), dtype=torch.int32, device=dev) if to_host else one]
     hbuf, xs = None, None
     if to_host:
         hbuf = [torch.empty((k, 3), dtype=torch.int32, pin_memory=True) for _ in range(2)]
@@ -574,7 +577,10 @@ def stream_list(o: Oriented, c: Counted, chunk: int, consume=None, first: int = 
                 copied.record(xs)
             pending[slot] = (copied, f, n)
         else:
+            # one shared device buffer: hand the window over before the next
+            # one overwrites it
             pending[slot] = (done, f, n)
+            finish(slot)
         windows += 1
     for j in range(windows, windows + 2):
         if pending[j % 2] is not None:

@@ -40,7 +40,11 @@ constexpr int kLightBins = 8;       // c in {1}, {2}, (2,4], (4,8], ..., last bi
 constexpr int kHeavyClasses = 16;   // owner classes by ceil(log2 deg+(b))
 constexpr int kHeavyBase = 16;      // bucket id of heavy class 0
 constexpr int kItemSpan = 512;      // neighbours of one owner per work item
-constexpr int kMaxIndexWords = 12288;  // LDS index cap: 48 KiB (bitmap window of 393216 ids)
+#ifndef AOT_MAX_INDEX_WORDS
+#define AOT_MAX_INDEX_WORDS 12288
+#endif
+constexpr int kMaxIndexWords = AOT_MAX_INDEX_WORDS;  // LDS index cap (12288: 48 KiB, a bitmap
+                                                     // window of 393216 ids)
 #ifndef AOT_PROBE_UNROLL
 #define AOT_PROBE_UNROLL 4
 #endif
