@@ -196,8 +196,8 @@ def cpu_baseline(csr, frac: float, threads: int = 1):
 
 # Graphs the cost model trains and is judged on when the workload itself is
 # too large to hold twice: same recipe, smaller scale, other seeds.
-PROXY = {"rmat26": "rmat23x32"}
-JUDGE_PROXY = {"rmat26": "rmat24x32"}
+PROXY = {"rmat26": ("rmat23x32", "rmat24x32")}
+JUDGE_PROXY = {"rmat26": "rmat25x32"}
 
 
 def learned_leg(aot, o, csr, cws, tri_off, list_all, T, probes, args):
@@ -210,8 +210,9 @@ def learned_leg(aot, o, csr, cws, tri_off, list_all, T, probes, args):
     t0 = time.time()
     # training: the standard family mix plus two graphs of this workload's own
     # recipe; judge: a third graph of the recipe (all seeds >= 1000)
-    name = PROXY.get(args.workload, args.workload)
-    training = learn.training_graphs(scale=2) + learn.workload_graphs(name, (1021, 1022))
+    names = PROXY.get(args.workload, (args.workload, args.workload))
+    training = learn.training_graphs(scale=2) + [
+        learn.workload_graphs(name, (seed,))[0] for name, seed in zip(names, (1021, 1022))]
     calibration = learn.workload_graphs(JUDGE_PROXY.get(args.workload, args.workload), (1020,))
     net, report = learn.learn(training, calibration, epochs=1000, repeats=2, log=log)
     del training, calibration

@@ -573,11 +573,21 @@ __device__ __forceinline__ void load_windows(Windows& W, const int32_t* pre, con
                                              const int32_t* __restrict__ ocol, int& kc, int kend,
                                              int32_t w0, int32_t end) {
   const int lane = lane_id();
+  // where the neighbour after kc starts: one LDS read serves every window
+  // until a probe crosses it (kc < kend while probes remain)
+  int32_t nxt = pre[kc + 1];
 #pragma unroll
   for (int u = 0; u < kUnroll; ++u) {
     const int32_t p = w0 + u * kWave + lane;
-    W.kk[u] = p < end ? advance(pre, kc, kend, p) : -1;
-    if (W.kk[u] >= 0) kc = W.kk[u];
+    int k = -1;
+    if (p < end) {
+      if (p >= nxt) {
+        kc = advance(pre, kc + 1, kend, p);
+        nxt = pre[kc + 1];
+      }
+      k = kc;
+    }
+    W.kk[u] = k;
   }
 #pragma unroll
   for (int u = 0; u < kUnroll; ++u) {

@@ -151,9 +151,9 @@ def step_ms(o, d, repeats: int, out) -> float:
     return float(np.median(ts))
 
 
-def judge(net: aot.Mlp, graphs, repeats: int = 5):
+def judge(net: aot.Mlp, graphs, repeats: int = 5, margin: float = 0.02):
     """Plain vs learned time (ms) summed over calibration graphs; the model is
-    accepted only if it is faster."""
+    accepted only if it is faster by more than `margin` (timing noise)."""
     plain = learned = 0.0
     d_learned = aot.Dispatch(aot.AOT_DISPATCH_LEARNED, 0, None, net)
     for csr in graphs:
@@ -162,7 +162,7 @@ def judge(net: aot.Mlp, graphs, repeats: int = 5):
         out = out_buffer(c, csr.rowptr.device)
         plain += step_ms(o, None, repeats, out)
         learned += step_ms(o, d_learned, repeats, out)
-    return plain, learned, learned < plain
+    return plain, learned, learned < plain * (1.0 - margin)
 
 
 def training_graphs(device="cuda", scale: int = 1):
