@@ -395,9 +395,11 @@ __device__ __forceinline__ Index build_index(const int32_t* __restrict__ a, int3
 template <int ARM>
 __device__ __forceinline__ bool index_has(const Index& ix, const uint32_t* lds, int32_t w) {
   if constexpr (ARM == kArmBitmap) {
+    // branchless: an id outside the window reads word 0 and is masked off
     const uint32_t off = (uint32_t)(w - ix.lo);
-    if (off >= (uint32_t)ix.span) return false;
-    return (lds[off >> 5] >> (off & 31)) & 1u;
+    const bool in = off < (uint32_t)ix.span;
+    const uint32_t word = lds[(in ? off : 0u) >> 5];
+    return in & ((word >> (off & 31)) & 1u);
   } else if constexpr (ARM == kArmHash) {
     uint32_t h = hash_slot(w) >> ix.shift;
     while (true) {
@@ -506,9 +508,10 @@ __device__ void flush_digest(const Digest& d, unsigned long long* out) {
 }
 
 // Where an emitted triangle goes: the output window, or the digest.
+template <bool kDigest>
 __device__ __forceinline__ void sink(const HeavyArgs& a, Digest& dg, int64_t pos, int32_t t0,
                                      int32_t t1, int32_t t2) {
-  if (a.digest) {
+  if constexpr (kDigest) {
     dg.add(t0, t1, t2);
     if (a.vcount) {
       atomicAdd(&a.vcount[t0], 1ull);
@@ -579,20 +582,22 @@ __device__ __forceinline__ void load_windows(Windows& W, const int32_t* pre, con
 #pragma unroll
   for (int u = 0; u < kUnroll; ++u) {
     const int32_t p = w0 + u * kWave + lane;
-    int k = -1;
-    if (p < end) {
-      if (p >= nxt) {
+    const bool live = p < end;
+    // search only when some lane's probe crosses into a later neighbour
+    if (ballot(live && p >= nxt)) {
+      if (live && p >= nxt) {
         kc = advance(pre, kc + 1, kend, p);
         nxt = pre[kc + 1];
       }
-      k = kc;
     }
-    W.kk[u] = k;
+    W.kk[u] = live ? kc : -1;
   }
 #pragma unroll
   for (int u = 0; u < kUnroll; ++u) {
+    // every lane loads; a lane past the end reads ocol[0] and is ignored
     const int32_t p = w0 + u * kWave + lane;
-    W.wv[u] = W.kk[u] >= 0 ? ocol[src[W.kk[u]] + p] : 0;
+    const int32_t at = W.kk[u] >= 0 ? src[W.kk[u]] + p : 0;
+    W.wv[u] = ocol[at];
   }
 }
 
@@ -617,7 +622,7 @@ __device__ int64_t probe_count(HeavyShared<false>& sh, const uint32_t* lds, cons
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
       const bool valid = cur.kk[u] >= 0;
-      const bool hit = valid && index_has<ARM>(ix, lds, cur.wv[u]);
+      const bool hit = valid & index_has<ARM>(ix, lds, cur.wv[u]);
       const uint64_t hm = ballot(hit);
       if (!hm) continue;
       const int c = (int)__popcll(hm);
@@ -655,7 +660,7 @@ __device__ int64_t probe_count(HeavyShared<false>& sh, const uint32_t* lds, cons
 // current edge in a wave-uniform register.  In a window inside one out-list
 // a hit's rank is its count of hitting lanes below it; a window across a
 // boundary ranks hits per segment.
-template <int ARM>
+template <int ARM, bool kDigest>
 __device__ void probe_emit(HeavyShared<true>& sh, const uint32_t* lds, const HeavyArgs& a,
                            const Index& ix, int K, int32_t P, int32_t pb, Digest& dg) {
   const int wave = threadIdx.x / kWave;
@@ -674,8 +679,8 @@ __device__ void probe_emit(HeavyShared<true>& sh, const uint32_t* lds, const Hea
     int32_t third[kUnroll];
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
-      hit[u] = cur.kk[u] >= 0 && index_has<ARM>(ix, lds, cur.wv[u]);
-      third[u] = hit[u] ? perm[cur.wv[u]] : 0;      // gathers issued before any store
+      hit[u] = (cur.kk[u] >= 0) & index_has<ARM>(ix, lds, cur.wv[u]);
+      third[u] = perm[hit[u] ? cur.wv[u] : 0];      // gathers issued before any store
     }
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
@@ -705,13 +710,13 @@ __device__ void probe_emit(HeavyShared<true>& sh, const uint32_t* lds, const Hea
       if (hit[u]) {
         int32_t t0 = pb, t1 = sh.nb_py[k], t2 = third[u];
         sort3(t0, t1, t2);
-        sink(a, dg, pos, t0, t1, t2);
+        sink<kDigest>(a, dg, pos, t0, t1, t2);
       }
     }
   }
 }
 
-template <int ARM, bool kEmit>
+template <int ARM, bool kEmit, bool kDigest>
 __device__ int64_t run_item(HeavyShared<kEmit>& sh, uint32_t* lds, const HeavyArgs& a,
                             const int32_t* list, int32_t db, int K, int32_t P, int32_t pb,
                             Digest& dg) {
@@ -719,14 +724,14 @@ __device__ int64_t run_item(HeavyShared<kEmit>& sh, uint32_t* lds, const HeavyAr
   if constexpr (!kEmit) {
     return probe_count<ARM>(sh, lds, a, ix, K, P);
   } else {
-    probe_emit<ARM>(sh, lds, a, ix, K, P, pb, dg);
+    probe_emit<ARM, kDigest>(sh, lds, a, ix, K, P, pb, dg);
     return 0;
   }
 }
 
 // One work item: owner b and a window of up to kItemSpan of its neighbours
 // (out-list, then in-list).  Ends with a barrier.
-template <bool kEmit>
+template <bool kEmit, bool kDigest>
 __device__ void heavy_item(HeavyShared<kEmit>& sh, uint32_t* lds, const HeavyArgs& a, int64_t it,
                            int64_t& tri_block, Digest& dg) {
   const int tid = threadIdx.x;
@@ -735,7 +740,7 @@ __device__ void heavy_item(HeavyShared<kEmit>& sh, uint32_t* lds, const HeavyArg
     if (a.item_e) {
       const int2 r = a.item_e[it];
       if (r.y < r.x) return;
-      if (!a.digest) {
+      if constexpr (!kDigest) {
         const int64_t lo = a.tri_off[r.x], hi = a.tri_off[r.y + 1];
         if (hi <= a.first || lo >= a.first + a.count) return;
       }
@@ -782,7 +787,7 @@ __device__ void heavy_item(HeavyShared<kEmit>& sh, uint32_t* lds, const HeavyArg
         if (owned) {
           const int64_t lo = a.tri_off[e], hi = a.tri_off[e + 1];
           nbase[i] = lo;
-          keep[i] = hi > lo && (a.digest || (hi > a.first && lo < a.first + a.count));
+          keep[i] = hi > lo && (kDigest || (hi > a.first && lo < a.first + a.count));
         }
       }
     }
@@ -840,10 +845,10 @@ __device__ void heavy_item(HeavyShared<kEmit>& sh, uint32_t* lds, const HeavyArg
   const int32_t pb = kEmit ? a.perm[b] : 0;
   int64_t t = 0;
   switch (arm) {
-    case kArmBitmap: t = run_item<kArmBitmap, kEmit>(sh, lds, a, list, db, K, P, pb, dg); break;
-    case kArmHash: t = run_item<kArmHash, kEmit>(sh, lds, a, list, db, K, P, pb, dg); break;
-    case kArmSorted: t = run_item<kArmSorted, kEmit>(sh, lds, a, list, db, K, P, pb, dg); break;
-    default: t = run_item<kArmGlobal, kEmit>(sh, lds, a, list, db, K, P, pb, dg); break;
+    case kArmBitmap: t = run_item<kArmBitmap, kEmit, kDigest>(sh, lds, a, list, db, K, P, pb, dg); break;
+    case kArmHash: t = run_item<kArmHash, kEmit, kDigest>(sh, lds, a, list, db, K, P, pb, dg); break;
+    case kArmSorted: t = run_item<kArmSorted, kEmit, kDigest>(sh, lds, a, list, db, K, P, pb, dg); break;
+    default: t = run_item<kArmGlobal, kEmit, kDigest>(sh, lds, a, list, db, K, P, pb, dg); break;
   }
   if constexpr (!kEmit) tri_block += t;
   __syncthreads();
@@ -852,28 +857,28 @@ __device__ void heavy_item(HeavyShared<kEmit>& sh, uint32_t* lds, const HeavyArg
   __syncthreads();
 }
 
-template <bool kEmit>
+template <bool kEmit, bool kDigest>
 __device__ void heavy_finish(HeavyShared<kEmit>& sh, const HeavyArgs& a, int64_t tri_block,
                              const Digest& dg) {
   if constexpr (!kEmit) {
     const int64_t t = block_sum(tri_block, sh.scan_tmp);
     if (a.tri_stat && threadIdx.x == 0 && t) atomicAdd(u64p(a.tri_stat), (unsigned long long)t);
   } else {
-    if (a.digest) flush_digest(dg, a.digest);
+    if constexpr (kDigest) flush_digest(dg, a.digest);
   }
 }
 
 // A launch covers the work items of one heavy class; the LDS index lives in
 // dynamic shared memory of a.idx_words words.
-template <bool kEmit>
+template <bool kEmit, bool kDigest = false>
 __global__ __launch_bounds__(kBlock) void k_heavy(HeavyArgs a) {
   __shared__ HeavyShared<kEmit> sh;
   extern __shared__ uint32_t lds[];
   int64_t tri_block = 0;
   Digest dg;
   for (int64_t it = blockIdx.x; it < a.item_count; it += gridDim.x)
-    heavy_item<kEmit>(sh, lds, a, a.item_base + it, tri_block, dg);
-  heavy_finish<kEmit>(sh, a, tri_block, dg);
+    heavy_item<kEmit, kDigest>(sh, lds, a, a.item_base + it, tri_block, dg);
+  heavy_finish<kEmit, kDigest>(sh, a, tri_block, dg);
 }
 
 // Persistent form: one launch drains the work items of every heavy class
@@ -897,9 +902,9 @@ __global__ __launch_bounds__(kBlock) void k_heavy_drain(HeavyArgs a,
     const int64_t t = next;
     __syncthreads();
     if (t >= total) break;
-    heavy_item<kEmit>(sh, lds, a, total - 1 - t, tri_block, dg);
+    heavy_item<kEmit, false>(sh, lds, a, total - 1 - t, tri_block, dg);
   }
-  heavy_finish<kEmit>(sh, a, tri_block, dg);
+  heavy_finish<kEmit, false>(sh, a, tri_block, dg);
 }
 
 // ---------------------------------------------------------------- light path
@@ -920,7 +925,7 @@ struct LightArgs {
 
 // Binned light edges elist[t0 .. t1), G lanes per edge: each lane binary-
 // searches N+(b) for its share of N+(s).
-template <int G, bool kEmit>
+template <int G, bool kEmit, bool kDigest>
 __device__ __forceinline__ void light_range(const LightArgs& a, int64_t t0, int64_t t1,
                                             int64_t& tri, Digest& dg) {
   constexpr int kGroups = kBlock / G;
@@ -940,7 +945,7 @@ __device__ __forceinline__ void light_range(const LightArgs& a, int64_t t0, int6
     } else {
       int64_t pos = a.tri_off[e];
       const int64_t end = a.tri_off[e + 1];
-      if (pos == end || (!a.digest && (end <= a.first || pos >= a.first + a.count))) continue;
+      if (pos == end || (!kDigest && (end <= a.first || pos >= a.first + a.count))) continue;
       const int32_t pu = a.perm[u], pv = a.perm[v];
       for (int32_t q0 = 0; q0 < x.c; q0 += G) {
         const int32_t q = q0 + li;
@@ -951,7 +956,7 @@ __device__ __forceinline__ void light_range(const LightArgs& a, int64_t t0, int6
         if (hit) {
           int32_t t0_ = pu, t1_ = pv, t2_ = a.perm[w];
           sort3(t0_, t1_, t2_);
-          if (a.digest) {
+          if constexpr (kDigest) {
             dg.add(t0_, t1_, t2_);
             if (a.vcount) {
               atomicAdd(&a.vcount[t0_], 1ull);
@@ -969,7 +974,7 @@ __device__ __forceinline__ void light_range(const LightArgs& a, int64_t t0, int6
   }
 }
 
-template <bool kEmit>
+template <bool kEmit, bool kDigest>
 __device__ void light_finish(const LightArgs& a, int64_t tri, const Digest& dg,
                              int64_t* tri_stat) {
   if constexpr (!kEmit) {
@@ -977,20 +982,20 @@ __device__ void light_finish(const LightArgs& a, int64_t tri, const Digest& dg,
     const int64_t s = block_sum(tri, red);
     if (tri_stat && threadIdx.x == 0 && s) atomicAdd(u64p(tri_stat), (unsigned long long)s);
   } else {
-    if (a.digest) flush_digest(dg, a.digest);
+    if constexpr (kDigest) flush_digest(dg, a.digest);
   }
 }
 
 // A launch covers one light bin, elist[base .. base + total).
-template <int G, bool kEmit>
+template <int G, bool kEmit, bool kDigest = false>
 __global__ __launch_bounds__(kBlock) void k_light(LightArgs a, int64_t base, int64_t total,
                                                   int64_t* tri_stat) {
   constexpr int kGroups = kBlock / G;
   int64_t tri = 0;
   Digest dg;
   for (int64_t c = (int64_t)blockIdx.x * kGroups; c < total; c += (int64_t)gridDim.x * kGroups)
-    light_range<G, kEmit>(a, base + c, base + min(c + kGroups, total), tri, dg);
-  light_finish<kEmit>(a, tri, dg, tri_stat);
+    light_range<G, kEmit, kDigest>(a, base + c, base + min(c + kGroups, total), tri, dg);
+  light_finish<kEmit, kDigest>(a, tri, dg, tri_stat);
 }
 
 // Lanes per edge of every light bin and the group-rounds of one task.
@@ -1040,14 +1045,14 @@ __global__ __launch_bounds__(kBlock) void k_light_drain(LightArgs a, LightPlan p
     const int64_t hi = min(lo + eper[k], ecnt[k]);
     const int64_t t0 = ebase[k] + lo, t1 = ebase[k] + hi;
     switch (p.tile[k]) {
-      case 4: light_range<4, kEmit>(a, t0, t1, tri, dg); break;
-      case 8: light_range<8, kEmit>(a, t0, t1, tri, dg); break;
-      case 16: light_range<16, kEmit>(a, t0, t1, tri, dg); break;
-      case 32: light_range<32, kEmit>(a, t0, t1, tri, dg); break;
-      default: light_range<64, kEmit>(a, t0, t1, tri, dg); break;
+      case 4: light_range<4, kEmit, false>(a, t0, t1, tri, dg); break;
+      case 8: light_range<8, kEmit, false>(a, t0, t1, tri, dg); break;
+      case 16: light_range<16, kEmit, false>(a, t0, t1, tri, dg); break;
+      case 32: light_range<32, kEmit, false>(a, t0, t1, tri, dg); break;
+      default: light_range<64, kEmit, false>(a, t0, t1, tri, dg); break;
     }
   }
-  light_finish<kEmit>(a, tri, dg, nullptr);
+  light_finish<kEmit, false>(a, tri, dg, nullptr);
 }
 
 // The part of the edge order a triangle window [first, first + count)
@@ -1244,10 +1249,10 @@ CountWs carve_count(Carve& c, int32_t n, int64_t m) {
     }                                       \
   } while (0)
 
-template <bool kEmit>
+template <bool kEmit, bool kDigest = false>
 hipError_t launch_light(int tile, unsigned grid, const LightArgs& a, int64_t base, int64_t total,
                         int64_t* tri_stat, hipStream_t s) {
-#define L(G) k_light<G, kEmit><<<grid, kBlock, 0, s>>>(a, base, total, tri_stat)
+#define L(G) k_light<G, kEmit, kDigest><<<grid, kBlock, 0, s>>>(a, base, total, tri_stat)
   switch (tile) {
     case 4: L(4); break;
     case 8: L(8); break;
@@ -1357,7 +1362,8 @@ int run_buckets(bool emit, const Plan& plan, const int64_t* hs, const CountWs& w
       la.tri_off = tri_off; la.perm = perm; la.first = first; la.count = count; la.out = out;
       la.digest = digest; la.vcount = vcount;
       const hipError_t e =
-          emit ? launch_light<true>(tile, grid, la, b0, edges, nullptr, s)
+          emit ? (digest ? launch_light<true, true>(tile, grid, la, b0, edges, nullptr, s)
+                         : launch_light<true>(tile, grid, la, b0, edges, nullptr, s))
                : launch_light<false>(tile, grid, la, b0, edges,
                                      w.stats + k * kStats + kSTriangles, s);
       AOT_TRY(e);
@@ -1390,7 +1396,8 @@ int run_buckets(bool emit, const Plan& plan, const int64_t* hs, const CountWs& w
     const int rec = timing_begin(emit ? 1 : 0, kHeavyBase + h, arm, kBlock, st[kSEdges],
                                  st[kSProbes], st[kSStaged], st[kSTriangles], s);
     const size_t dyn = sizeof(uint32_t) * (size_t)std::max(a.idx_words, 1);
-    if (emit) k_heavy<true><<<grid_cap(items), kBlock, dyn, s>>>(a);
+    if (emit && digest) k_heavy<true, true><<<grid_cap(items), kBlock, dyn, s>>>(a);
+    else if (emit) k_heavy<true><<<grid_cap(items), kBlock, dyn, s>>>(a);
     else k_heavy<false><<<grid_cap(items), kBlock, dyn, s>>>(a);
     AOT_TRY(hipGetLastError());
     timing_end(rec, s);
