@@ -55,7 +55,7 @@ def parse():
                    help="list into one device buffer up to this size, else in windows")
     p.add_argument("--chunk", type=int, default=1 << 33,
                    help="triangles per device window when the list is not resident "
-                        "(capped at 40%% of the free device memory)")
+                        "(capped at 60%% of the free device memory)")
     p.add_argument("--stream-chunk", type=int, default=1 << 29,
                    help="triangles per window streamed to pinned host memory")
     p.add_argument("--no-stream", action="store_true",
@@ -373,7 +373,7 @@ def main():
     windowed = T * 12 > args.resident_gb * 1e9
     if windowed:
         free, _ = torch.cuda.mem_get_info(dev)
-        args.chunk = int(min(args.chunk, T, 0.4 * free // 12))
+        args.chunk = int(min(args.chunk, T, 0.6 * free // 12))
     out = None if windowed else torch.empty((max(T, 1), 3), dtype=torch.int32, device=dev)
     log(f"[bench] T={T} probes={probes}; output {T * 12 / 1e9:.2f} GB"
         + (f", listed in windows of {args.chunk} triangles" if windowed else ""))
@@ -447,6 +447,7 @@ def main():
         log(f"[bench] streamed to host: {s_ms:.1f} ms for {12 * T / 1e9:.1f} GB "
             f"({streamed['host_GB_per_s']:.1f} GB/s)")
 
+    torch.cuda.empty_cache()        # return cached window buffers before the next legs
     learned = None
     if not args.no_learned and not args.heavy_arm:
         learned = learned_leg(aot, o, csr, cws, tri_off, list_all, T, probes, args)

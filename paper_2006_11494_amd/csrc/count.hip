@@ -447,6 +447,8 @@ struct HeavyArgs {
   const int2* items;
   int2* item_e;                 // per item: smallest and largest owned edge id with
                                 // probes (count pass writes, write pass reads)
+  int32_t* ieid;                // per in-list entry: the id of an owned in-edge
+                                // (count pass writes, write pass reads)
   int64_t item_base, item_count;
   const int64_t* orow;
   const int32_t* ocol;
@@ -777,8 +779,17 @@ __device__ void heavy_item(HeavyShared<kEmit>& sh, uint32_t* lds, const HeavyArg
       const int64_t oy = a.orow[y];
       const int32_t dy = (int32_t)(a.orow[y + 1] - oy);
       const bool owned = dy < db || (dy == db && y < b);
-      // an owned in-edge <y, b>: its id is b's place in N+(y), the list probed next
-      if (owned && !out_edge) e = (int32_t)(oy + lower_bound(a.ocol + oy, dy, b));
+      // an owned in-edge <y, b>: its id is b's place in N+(y), the list probed
+      // next; the count pass finds it and keeps it for the write pass
+      if (owned && !out_edge) {
+        int32_t* slot = a.ieid + ib + (j - db);
+        if constexpr (!kEmit) {
+          e = (int32_t)(oy + lower_bound(a.ocol + oy, dy, b));
+          *slot = e;
+        } else {
+          e = *slot;
+        }
+      }
       ny[i] = y; ne[i] = e; noy[i] = oy; nd[i] = dy;
       if constexpr (!kEmit) {
         if (owned && dy == 0) a.cnt[e] = 0;
@@ -1211,6 +1222,7 @@ struct CountWs {
   int32_t* elist;
   int2* items;
   int2* item_e;                      // per item: owned edge-id bounds
+  int32_t* ieid;                     // [m] per in-list entry: owned in-edge id
   int32_t* hist;                     // [kLightBins][chunks] light edges per chunk
   int64_t* hoff;                     // its exclusive scan
   int64_t* win;                      // window: edge range, then each bin's elist run
@@ -1230,6 +1242,7 @@ CountWs carve_count(Carve& c, int32_t n, int64_t m) {
   w.elist = c.take<int32_t>(m);
   w.items = c.take<int2>(max_items(n, m));
   w.item_e = c.take<int2>(max_items(n, m));
+  w.ieid = c.take<int32_t>(m);
   const int64_t cells = kLightBins * cdiv(m, kScatterChunk);
   w.hist = c.take<int32_t>(cells);
   w.hoff = c.take<int64_t>(cells + 1);
@@ -1381,6 +1394,7 @@ int run_buckets(bool emit, const Plan& plan, const int64_t* hs, const CountWs& w
     a.idx_words = index_words(arm, h, st[kSSpan]);
     a.items = w.items;
     a.item_e = w.item_e;
+    a.ieid = w.ieid;
     a.item_base = st[kSItemBase];
     a.item_count = items;
     a.orow = orow; a.ocol = ocol; a.irow = irow; a.icol = icol;
@@ -1561,6 +1575,7 @@ int drain_run(int32_t n, int64_t m, const int64_t* orow, const int32_t* ocol,
   ha.idx_words = idx_words;
   ha.items = w.items;
   ha.item_e = w.item_e;
+  ha.ieid = w.ieid;
   ha.item_base = 0;
   ha.item_count = 0;
   ha.orow = orow; ha.ocol = ocol; ha.irow = irow; ha.icol = icol;
