@@ -621,11 +621,33 @@ __device__ int64_t probe_count(HeavyShared<false>& sh, const uint32_t* lds, cons
   for (int32_t w0 = wave * kWave * kUnroll; w0 < P; w0 += kStride) {
     Windows cur;
     load_windows(cur, sh.nb_pre, sh.nb_src, a.ocol, kc, K, w0, P);
+    uint64_t hms[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u)
+      hms[u] = ballot((cur.kk[u] >= 0) & index_has<ARM>(ix, lds, cur.wv[u]));
+    // a full run inside one out-list: one accumulator update for all windows
+    const int ka = __builtin_amdgcn_readfirstlane(cur.kk[0]);
+    const int kb = __builtin_amdgcn_readlane(cur.kk[kUnroll - 1], kWave - 1);
+    if (w0 + kWave * kUnroll <= P && ka == kb) {
+      int c = 0;
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) c += (int)__popcll(hms[u]);
+      if (c) {
+        hits_wave += c;
+        if (ka == acc_k) {
+          acc += c;
+        } else {
+          if (acc_k >= 0 && lane == 0) atomicAdd(&sh.nb_acc[acc_k], acc);
+          acc_k = ka;
+          acc = c;
+        }
+      }
+      continue;
+    }
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
       const bool valid = cur.kk[u] >= 0;
-      const bool hit = valid & index_has<ARM>(ix, lds, cur.wv[u]);
-      const uint64_t hm = ballot(hit);
+      const uint64_t hm = hms[u];
       if (!hm) continue;
       const int c = (int)__popcll(hm);
       hits_wave += c;
@@ -683,6 +705,28 @@ __device__ void probe_emit(HeavyShared<true>& sh, const uint32_t* lds, const Hea
     for (int u = 0; u < kUnroll; ++u) {
       hit[u] = (cur.kk[u] >= 0) & index_has<ARM>(ix, lds, cur.wv[u]);
       third[u] = perm[hit[u] ? cur.wv[u] : 0];      // gathers issued before any store
+    }
+    // a full run inside one out-list: one base and one neighbour for all windows
+    const int ka = __builtin_amdgcn_readfirstlane(cur.kk[0]);
+    const int kb = __builtin_amdgcn_readlane(cur.kk[kUnroll - 1], kWave - 1);
+    if (w0 + kStride <= p_hi && ka == kb) {
+      if (ka != run_k) { run_k = ka; run = 0; }
+      const int64_t base = sh.nb_base[ka] + run;
+      const int32_t py = sh.nb_py[ka];
+      const int32_t lo = min(pb, py), hi = max(pb, py);
+      int before = 0;
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const uint64_t hm = ballot(hit[u]);
+        if (hit[u]) {
+          const int32_t t = third[u];
+          sink<kDigest>(a, dg, base + before + popc_below(hm), min(lo, t), max(lo, min(hi, t)),
+                        max(hi, t));
+        }
+        before += (int)__popcll(hm);
+      }
+      run += before;
+      continue;
     }
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
