@@ -459,6 +459,8 @@ struct HeavyArgs {
   const int64_t* tri_off;       // write pass
   const int32_t* perm;
   int64_t first, count;
+  int64_t e_lo, e_hi;           // write pass: the edge range the window can touch, and
+  int32_t y_lo, y_hi;           // the rows of its first and last edge
   int32_t* out;
   unsigned long long* digest;   // write pass in digest mode: {triangles, hash sum, hash xor}
   unsigned long long* vcount;   // digest mode, optional: per-vertex triangle counts
@@ -815,11 +817,22 @@ __device__ void heavy_item(HeavyShared<kEmit>& sh, uint32_t* lds, const HeavyArg
     keep[i] = false;
     nd[i] = 0;
     ny[i] = 0; ne[i] = 0; noy[i] = 0; nbase[i] = 0;
-    if (j < j1) {
-      int32_t y, e = 0;
-      const bool out_edge = j < db;
-      if (out_edge) { y = a.ocol[ob + j]; e = (int32_t)(ob + j); }
-      else y = a.icol[ib + (j - db)];
+    bool near = j < j1;
+    int32_t y = 0, e = 0;
+    const bool out_edge = j < db;
+    if (near) {
+      if (out_edge) {
+        e = (int32_t)(ob + j);
+        // write pass: an edge outside the window's edge range is dropped before any load
+        if constexpr (kEmit) near = e >= a.e_lo && e < a.e_hi;
+        if (near) y = a.ocol[ob + j];
+      } else {
+        y = a.icol[ib + (j - db)];
+        // an in-edge <y, b> lies in row y: rows outside the window's rows are dropped
+        if constexpr (kEmit) near = y >= a.y_lo && y <= a.y_hi;
+      }
+    }
+    if (near) {
       const int64_t oy = a.orow[y];
       const int32_t dy = (int32_t)(a.orow[y + 1] - oy);
       const bool owned = dy < db || (dy == db && y < b);
@@ -1114,11 +1127,12 @@ __global__ __launch_bounds__(kBlock) void k_light_drain(LightArgs a, LightPlan p
 // touches, and each light bin's run of it: win[0..1] = [e_lo, e_hi), the
 // edges whose slots can meet the window; win[2 + 2k .. 3 + 2k] = the elist
 // indices of bin k's edges in [e_lo, e_hi) (bins are in edge order).
-constexpr int kWinWords = 2 + 2 * kLightBins;
+constexpr int kWinWords = 2 + 2 * kLightBins + 2;   // + tail ranks of e_lo and e_hi - 1
 
 __global__ void k_window(int64_t m, const int64_t* __restrict__ tri_off, int64_t first,
                          int64_t count, const int64_t* __restrict__ stats,
-                         const int32_t* __restrict__ elist, int64_t* __restrict__ win) {
+                         const int32_t* __restrict__ elist, const int32_t* __restrict__ otail,
+                         int32_t n, int64_t* __restrict__ win) {
   __shared__ int64_t range[2];
   if (threadIdx.x == 0) {
     int64_t lo = 0, hi = m;           // first e with tri_off[e + 1] > first
@@ -1140,6 +1154,10 @@ __global__ void k_window(int64_t m, const int64_t* __restrict__ tri_off, int64_t
     }
     win[0] = range[0];
     win[1] = range[1];
+    // the rows the window's edges come from (tails ascend with the edge id)
+    const bool any = range[1] > range[0];
+    win[kWinWords - 2] = any ? otail[range[0]] : n;
+    win[kWinWords - 1] = any ? otail[range[1] - 1] : -1;
   }
   __syncthreads();
   if (threadIdx.x < kLightBins) {
@@ -1448,6 +1466,10 @@ int run_buckets(bool emit, const Plan& plan, const int64_t* hs, const CountWs& w
     a.perm = perm;
     a.first = first;
     a.count = count;
+    a.e_lo = win ? win[0] : 0;                         // no window: every edge
+    a.e_hi = win ? win[1] : INT64_MAX;
+    a.y_lo = win ? (int32_t)win[kWinWords - 2] : 0;
+    a.y_hi = win ? (int32_t)win[kWinWords - 1] : INT32_MAX;
     a.out = out;
     a.digest = digest;
     a.vcount = vcount;
@@ -1629,6 +1651,10 @@ int drain_run(int32_t n, int64_t m, const int64_t* orow, const int32_t* ocol,
   ha.perm = perm;
   ha.first = first;
   ha.count = count;
+  ha.e_lo = 0;
+  ha.e_hi = INT64_MAX;
+  ha.y_lo = 0;
+  ha.y_hi = INT32_MAX;
   ha.out = out;
   ha.digest = nullptr;
   ha.vcount = nullptr;
@@ -1706,7 +1732,7 @@ int emit_run(int32_t n, int64_t m, const int64_t* orow, const int32_t* ocol, con
     int32_t words[kPlanWords];
     int64_t win[kWinWords];
     if (!digest_mode) {
-      k_window<<<1, 64, 0, s>>>(m, tri_off, first, count, w.stats, w.elist, w.win);
+      k_window<<<1, 64, 0, s>>>(m, tri_off, first, count, w.stats, w.elist, otail, n, w.win);
       AOT_TRY(hipGetLastError());
       AOT_TRY(hipMemcpyAsync(win, w.win, sizeof(win), hipMemcpyDeviceToHost, s));
     }
