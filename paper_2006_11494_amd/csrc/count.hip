@@ -48,10 +48,14 @@ constexpr int kMaxIndexWords = AOT_MAX_INDEX_WORDS;  // LDS index cap (12288: 48
 #ifndef AOT_PROBE_UNROLL
 #define AOT_PROBE_UNROLL 4
 #endif
+#ifndef AOT_EMIT_UNROLL
+#define AOT_EMIT_UNROLL 8
+#endif
 #ifndef AOT_CHAINED_CURSOR
 #define AOT_CHAINED_CURSOR 1
 #endif
-constexpr int kUnroll = AOT_PROBE_UNROLL;   // 64-probe windows a wave keeps in flight
+constexpr int kUnroll = AOT_PROBE_UNROLL;       // 64-probe windows in flight per wave: count pass
+constexpr int kEmitUnroll = AOT_EMIT_UNROLL;    // and write pass
 constexpr int kGrid = 4096;
 constexpr int kDefaultHeavyMin = 32;
 #ifndef AOT_SPLIT_ITEMS
@@ -571,12 +575,14 @@ __device__ __forceinline__ int segment_rank(bool valid, int k, uint64_t hm, int*
 // windows (usually one LDS read: the probe lies in the same out-list as the
 // previous one) and issues the load of the probed id.  kk = -1 marks lanes
 // at or past `end`.
+template <int U>
 struct Windows {
-  int kk[kUnroll];
-  int32_t wv[kUnroll];
+  int kk[U];
+  int32_t wv[U];
 };
 
-__device__ __forceinline__ void load_windows(Windows& W, const int32_t* pre, const int32_t* src,
+template <int U>
+__device__ __forceinline__ void load_windows(Windows<U>& W, const int32_t* pre, const int32_t* src,
                                              const int32_t* __restrict__ ocol, int& kc, int kend,
                                              int32_t w0, int32_t end) {
   const int lane = lane_id();
@@ -584,7 +590,7 @@ __device__ __forceinline__ void load_windows(Windows& W, const int32_t* pre, con
   // until a probe crosses it (kc < kend while probes remain)
   int32_t nxt = pre[kc + 1];
 #pragma unroll
-  for (int u = 0; u < kUnroll; ++u) {
+  for (int u = 0; u < U; ++u) {
     const int32_t p = w0 + u * kWave + lane;
     const bool live = p < end;
     // search only when some lane's probe crosses into a later neighbour
@@ -597,7 +603,7 @@ __device__ __forceinline__ void load_windows(Windows& W, const int32_t* pre, con
     W.kk[u] = live ? kc : -1;
   }
 #pragma unroll
-  for (int u = 0; u < kUnroll; ++u) {
+  for (int u = 0; u < U; ++u) {
     // every lane loads; a lane past the end reads ocol[0] and is ignored
     const int32_t p = w0 + u * kWave + lane;
     const int32_t at = W.kk[u] >= 0 ? src[W.kk[u]] + p : 0;
@@ -621,7 +627,7 @@ __device__ int64_t probe_count(HeavyShared<false>& sh, const uint32_t* lds, cons
   int acc_k = -1;     // wave-uniform: neighbour being accumulated
   int acc = 0;        // and its hits so far
   for (int32_t w0 = wave * kWave * kUnroll; w0 < P; w0 += kStride) {
-    Windows cur;
+    Windows<kUnroll> cur;
     load_windows(cur, sh.nb_pre, sh.nb_src, a.ocol, kc, K, w0, P);
     uint64_t hms[kUnroll];
 #pragma unroll
@@ -694,23 +700,23 @@ __device__ void probe_emit(HeavyShared<true>& sh, const uint32_t* lds, const Hea
   if (k_lo >= k_hi) return;
   const int32_t p_lo = sh.nb_pre[k_lo], p_hi = sh.nb_pre[k_hi];
   const int32_t* __restrict__ perm = a.perm;
-  constexpr int32_t kStride = kWave * kUnroll;
+  constexpr int32_t kStride = kWave * kEmitUnroll;
   int kc = k_lo;
   int run_k = -1;     // wave-uniform: edge whose hits are being ranked
   int run = 0;        // hits of run_k emitted so far
   for (int32_t w0 = p_lo; w0 < p_hi; w0 += kStride) {
-    Windows cur;
+    Windows<kEmitUnroll> cur;
     load_windows(cur, sh.nb_pre, sh.nb_src, a.ocol, kc, k_hi, w0, p_hi);
-    bool hit[kUnroll];
-    int32_t third[kUnroll];
+    bool hit[kEmitUnroll];
+    int32_t third[kEmitUnroll];
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
+    for (int u = 0; u < kEmitUnroll; ++u) {
       hit[u] = (cur.kk[u] >= 0) & index_has<ARM>(ix, lds, cur.wv[u]);
       third[u] = perm[hit[u] ? cur.wv[u] : 0];      // gathers issued before any store
     }
     // a full run inside one out-list: one base and one neighbour for all windows
     const int ka = __builtin_amdgcn_readfirstlane(cur.kk[0]);
-    const int kb = __builtin_amdgcn_readlane(cur.kk[kUnroll - 1], kWave - 1);
+    const int kb = __builtin_amdgcn_readlane(cur.kk[kEmitUnroll - 1], kWave - 1);
     if (w0 + kStride <= p_hi && ka == kb) {
       if (ka != run_k) { run_k = ka; run = 0; }
       const int64_t base = sh.nb_base[ka] + run;
@@ -718,7 +724,7 @@ __device__ void probe_emit(HeavyShared<true>& sh, const uint32_t* lds, const Hea
       const int32_t lo = min(pb, py), hi = max(pb, py);
       int before = 0;
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u) {
+      for (int u = 0; u < kEmitUnroll; ++u) {
         const uint64_t hm = ballot(hit[u]);
         if (hit[u]) {
           const int32_t t = third[u];
@@ -731,7 +737,7 @@ __device__ void probe_emit(HeavyShared<true>& sh, const uint32_t* lds, const Hea
       continue;
     }
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
+    for (int u = 0; u < kEmitUnroll; ++u) {
       const bool valid = cur.kk[u] >= 0;
       const uint64_t hm = ballot(hit[u]);
       if (!hm) continue;
