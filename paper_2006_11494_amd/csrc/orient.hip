@@ -25,18 +25,18 @@ enum : int {
   kCDeg0 = 1,   // #vertices with degree 0
   kCDeg4 = 2,   // #vertices with degree <= 4
   kCDeg16 = 3,  // <= 16
-  kCDeg64 = 4,  // <= 64
+  kCDeg512 = 4, // <= 512 (one wave per row up to here)
   kCError = 5,
-  kCSortCount = 8,    // [8..11] rows per sort class
-  kCSortCursor = 12,  // [12..15]
-  kCRowCount = 16,    // [16..19] rows per degree class (row-list mode)
-  kCRowCursor = 20,   // [20..23]
-  kCInCount = 24,     // [24..27] in-lists per sort class
-  kCInCursor = 28,    // [28..31]
-  kCounters = 32,
+  kCSortCount = 8,    // [8..12] rows per sort class
+  kCSortCursor = 13,  // [13..17]
+  kCRowCount = 18,    // [18..22] rows per degree class (row-list mode; 4 used)
+  kCRowCursor = 23,   // [23..27]
+  kCInCount = 28,     // [28..32] in-lists per sort class
+  kCInCursor = 33,    // [33..37]
+  kCounters = 38,
 };
 
-constexpr int kSortClasses = 4;     // len <= 16, <= 64, <= 4096, longer
+constexpr int kSortClasses = 5;     // len <= 16, <= 64, <= 256, <= 4096, longer
 constexpr int kBitmapWords = 16384; // 64 KiB window for the long-list sort
 constexpr int kGrid = 4096;         // grid of the grid-stride kernels
 
@@ -87,7 +87,7 @@ __global__ __launch_bounds__(kBlock) void k_degree(int32_t n, const int64_t* __r
                                                    int32_t* __restrict__ vals,
                                                    int32_t* __restrict__ counters) {
   __shared__ int32_t red[kWavesPerBlock];
-  int32_t mx = 0, c0 = 0, c4 = 0, c16 = 0, c64 = 0;
+  int32_t mx = 0, c0 = 0, c4 = 0, c16 = 0, c512 = 0;
   for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < n;
        v += (int64_t)gridDim.x * kBlock) {
     const int32_t d = (int32_t)(rowptr[v + 1] - rowptr[v]);
@@ -97,7 +97,7 @@ __global__ __launch_bounds__(kBlock) void k_degree(int32_t n, const int64_t* __r
     c0 += d == 0;
     c4 += d <= 4;
     c16 += d <= 16;
-    c64 += d <= 64;
+    c512 += d <= 512;
   }
   for (int o = kWave / 2; o > 0; o >>= 1) {
     const int32_t y = __shfl_xor(mx, o, kWave);
@@ -114,12 +114,12 @@ __global__ __launch_bounds__(kBlock) void k_degree(int32_t n, const int64_t* __r
   c0 = block_sum(c0, red);
   c4 = block_sum(c4, red);
   c16 = block_sum(c16, red);
-  c64 = block_sum(c64, red);
+  c512 = block_sum(c512, red);
   if (threadIdx.x == 0) {
     atomicAdd(&counters[kCDeg0], c0);
     atomicAdd(&counters[kCDeg4], c4);
     atomicAdd(&counters[kCDeg16], c16);
-    atomicAdd(&counters[kCDeg64], c64);
+    atomicAdd(&counters[kCDeg512], c512);
   }
 }
 
@@ -285,7 +285,7 @@ __global__ __launch_bounds__(kBlock) void k_orient_write(
 }
 
 __device__ __forceinline__ int sort_class(int64_t len) {
-  return len <= 16 ? 0 : len <= 64 ? 1 : len <= 4096 ? 2 : 3;
+  return len <= 16 ? 0 : len <= 64 ? 1 : len <= 256 ? 2 : len <= 4096 ? 3 : 4;
 }
 
 __global__ __launch_bounds__(kBlock) void k_copy(const int32_t* __restrict__ src, int64_t n,
@@ -317,7 +317,7 @@ __device__ __forceinline__ int row_class(int64_t r, const int32_t* __restrict__ 
   if constexpr (kMode == kRowsByDegree) {
     const int32_t u = perm[r];
     const int64_t d = rowptr[u + 1] - rowptr[u];
-    return d == 0 ? -1 : d <= 4 ? 0 : d <= 16 ? 1 : d <= 64 ? 2 : 3;
+    return d == 0 ? -1 : d <= 4 ? 0 : d <= 16 ? 1 : d <= 512 ? 2 : 3;
   } else {
     const int32_t l = len[r];
     return l > 0 ? sort_class(l) : -1;
@@ -331,7 +331,7 @@ __global__ __launch_bounds__(kBlock) void k_count_classes(int32_t n,
                                                           const int64_t* __restrict__ rowptr,
                                                           int32_t* __restrict__ counters) {
   constexpr int kOff = ClassSlots<kMode>::count;
-  int32_t h[kSortClasses] = {0, 0, 0, 0};
+  int32_t h[kSortClasses] = {0, 0, 0, 0, 0};
   for (int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x; r < n;
        r += (int64_t)gridDim.x * kBlock) {
     const int c = row_class<kMode>(r, len, perm, rowptr);
@@ -409,7 +409,71 @@ __global__ __launch_bounds__(kBlock) void k_sort_lanes(int cbase, int cls, const
   }
 }
 
-// Bitonic sort in LDS, one row (64 < len <= 4096) per workgroup.
+// Bitonic sort of one row (64 < len <= 64 * K) per wave, K elements per lane
+// in registers: element i = lane * K + k; partners within a lane swap in
+// registers, partners across lanes exchange with a shuffle.  No LDS, no
+// barrier.
+template <int K>
+__global__ __launch_bounds__(kBlock) void k_sort_wave(int cbase, int cls,
+                                                      const int32_t* __restrict__ counters,
+                                                      const int32_t* __restrict__ rows,
+                                                      const int64_t* __restrict__ orow,
+                                                      const int32_t* __restrict__ src,
+                                                      int32_t* __restrict__ dst) {
+  constexpr int N = kWave * K;
+  int32_t base = 0;
+  for (int q = 0; q < cls; ++q) base += counters[cbase + q];
+  const int32_t count = counters[cbase + cls];
+  const int lane = lane_id();
+  for (int64_t t = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; t < count;
+       t += (int64_t)gridDim.x * kWavesPerBlock) {
+    const int32_t r = rows[base + t];
+    const int64_t beg = orow[r];
+    const int32_t len = (int32_t)(orow[r + 1] - beg);
+    int32_t x[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int i = lane * K + k;
+      x[k] = i < len ? src[beg + i] : INT_MAX;
+    }
+#pragma unroll
+    for (int sz = 2; sz <= N; sz <<= 1) {
+#pragma unroll
+      for (int j = sz >> 1; j > 0; j >>= 1) {
+        if (j < K) {
+#pragma unroll
+          for (int k = 0; k < K; ++k) {
+            if ((k & j) == 0) {
+              const int i = lane * K + k;
+              const bool up = (i & sz) == 0;
+              const int32_t a = x[k], b = x[k | j];
+              const bool swap = (a > b) == up;
+              x[k] = swap ? b : a;
+              x[k | j] = swap ? a : b;
+            }
+          }
+        } else {
+          const int lj = j / K;
+          const bool lower = (lane & lj) == 0;
+#pragma unroll
+          for (int k = 0; k < K; ++k) {
+            const int i = lane * K + k;
+            const bool up = (i & sz) == 0;
+            const int32_t y = __shfl_xor(x[k], lj, kWave);
+            x[k] = (lower == up) ? min(x[k], y) : max(x[k], y);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int i = lane * K + k;
+      if (i < len) dst[beg + i] = x[k];
+    }
+  }
+}
+
+// Bitonic sort in LDS, one row (256 < len <= 4096) per workgroup.
 __global__ __launch_bounds__(kBlock) void k_sort_block(int cbase, int cls, const int32_t* __restrict__ counters,
                                                        const int32_t* __restrict__ rows,
                                                        const int64_t* __restrict__ orow,
@@ -557,9 +621,11 @@ hipError_t sort_lists(int cbase, unsigned g_small, const int32_t* counters, cons
   if (e != hipSuccess) return e;
   k_sort_lanes<64><<<g_small, kBlock, 0, s>>>(cbase, 1, counters, rows, offsets, src, dst);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  k_sort_block<<<kGrid, kBlock, 0, s>>>(cbase, 2, counters, rows, offsets, src, dst);
+  k_sort_wave<4><<<g_small, kBlock, 0, s>>>(cbase, 2, counters, rows, offsets, src, dst);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  k_sort_bitmap<<<512, kBlock, 0, s>>>(cbase, 3, counters, rows, offsets, src, dst);
+  k_sort_block<<<kGrid, kBlock, 0, s>>>(cbase, 3, counters, rows, offsets, src, dst);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  k_sort_bitmap<<<512, kBlock, 0, s>>>(cbase, 4, counters, rows, offsets, src, dst);
   return hipGetLastError();
 }
 
@@ -622,7 +688,7 @@ int orient_impl(int32_t n, int64_t nnz, const int64_t* rowptr, const int32_t* co
     return 0;
   }
   int bits;
-  int32_t c0 = 0, c4 = 0, c16 = 0, c64 = 0;
+  int32_t c0 = 0, c4 = 0, c16 = 0, c512 = 0;
   if (!bk) {
     k_degree<<<std::min(grid_for(n, kBlock), 1024u), kBlock, 0, s>>>(n, rowptr, key_a, val_a,
                                                                      counters);
@@ -631,7 +697,7 @@ int orient_impl(int32_t n, int64_t nnz, const int64_t* rowptr, const int32_t* co
     AOT_TRY(hipMemcpyAsync(hc, counters, sizeof(hc), hipMemcpyDeviceToHost, s));
     AOT_TRY(hipStreamSynchronize(s));
     bits = ceil_log2((int64_t)hc[kCMaxDeg] + 1);
-    c0 = hc[kCDeg0]; c4 = hc[kCDeg4]; c16 = hc[kCDeg16]; c64 = hc[kCDeg64];
+    c0 = hc[kCDeg0]; c4 = hc[kCDeg4]; c16 = hc[kCDeg16]; c512 = hc[kCDeg512];
   } else {
     k_batch_keys<<<grid_for(n, kBlock), kBlock, 0, s>>>(n, bk->voff, bk->count, bk->dbits,
                                                          rowptr, key_a, val_a);
@@ -648,7 +714,7 @@ int orient_impl(int32_t n, int64_t nnz, const int64_t* rowptr, const int32_t* co
   // so each is a list built on the device.
   RowSet sets[4];
   int64_t bound[4];
-  const int32_t cuts[5] = {c0, c4, c16, c64, n};
+  const int32_t cuts[5] = {c0, c4, c16, c512, n};
   for (int q = 0; q < 4; ++q) {
     sets[q].r0 = cuts[q];
     sets[q].r1 = cuts[q + 1];
@@ -700,7 +766,7 @@ int orient_impl(int32_t n, int64_t nnz, const int64_t* rowptr, const int32_t* co
   if (!in_by_rank) return 0;
   // sort each in-list into ascending rank (= edge order of the in-edges): the
   // in-lists were written to icol; move them to the now free scratch first
-  AOT_TRY(fill_i32(counters + kCInCount, 8, 0, s));
+  AOT_TRY(fill_i32(counters + kCInCount, 2 * kSortClasses, 0, s));
   k_copy<<<grid_for(m, kBlock), kBlock, 0, s>>>(icol, m, unsorted);
   AOT_TRY(hipGetLastError());
   k_count_classes<kInLists><<<std::min(grid_for(n, kBlock), 1024u), kBlock, 0, s>>>(
