@@ -56,6 +56,8 @@ def _load():
     lib.orc_sum_min.restype = u64
     lib.orc_sum_head.argtypes = [i32, _i64p, _i32p]
     lib.orc_sum_head.restype = u64
+    lib.orc_sum_merge.argtypes = [i32, _i64p, _i32p]
+    lib.orc_sum_merge.restype = u64
     lib.orc_aot_ref.argtypes = [i32, _i64p, _i32p, ctypes.c_int, _i32p, i64, ctypes.POINTER(u64)]
     lib.orc_aot_ref.restype = i64
     lib.orc_fingerprint.argtypes = [_i32p, i64, _u64p, ctypes.c_void_p]
@@ -270,6 +272,11 @@ def sum_min(o: Oriented) -> int:
 def sum_head(o: Oriented) -> int:
     """sum over <u,v> of deg+(v) (the kClist cost, Section 2.3)."""
     return int(_load().orc_sum_head(o.n, o.orow, _nonempty(o.ocol)))
+
+
+def sum_merge(o: Oriented) -> int:
+    """sum over <u,v> of deg+(u) + deg+(v) (the CF merge cost, Section 2.2)."""
+    return int(_load().orc_sum_merge(o.n, o.orow, _nonempty(o.ocol)))
 
 
 def aot_ref(rowptr, col, tie_break: bool = True, cap: int | None = None):

@@ -273,6 +273,20 @@ uint64_t orc_sum_head(int32_t n, const int64_t* orow, const int32_t* ocol) {
   return s;
 }
 
+/* sum over <u,v> of deg+(u) + deg+(v): the cost of Algorithm 1's merge
+ * intersections (Section 2.2, Analysis). */
+uint64_t orc_sum_merge(int32_t n, const int64_t* orow, const int32_t* ocol) {
+  uint64_t s = 0;
+  for (int32_t u = 0; u < n; ++u) {
+    int64_t du = orow[u + 1] - orow[u];
+    for (int64_t e = orow[u]; e < orow[u + 1]; ++e) {
+      int32_t v = ocol[e];
+      s += (uint64_t)du + (uint64_t)(orow[v + 1] - orow[v]);
+    }
+  }
+  return s;
+}
+
 /* Algorithm 3 (AOT), literally, on the original ids.
  *  tie_break = 1: a vertex x is "smaller" than the pivot u when
  *                 (deg+(x), x) < (deg+(u), u) lexicographically;

@@ -169,6 +169,22 @@ def test_complete_graph(n):
     # <i,j> costs n-1-j and the total is C(n,3)
     assert oracle.sum_min(o) == math.comb(n, 3)
     assert oracle.sum_head(o) == math.comb(n, 3)
+    # the tails add sum over i of deg+(i) * deg+(i) = 0^2 + 1^2 + ... + (n-1)^2
+    assert oracle.sum_merge(o) == math.comb(n, 3) + (n - 1) * n * (2 * n - 1) // 6
+
+
+@pytest.mark.parametrize("k", [1, 2, 5, 17])
+def test_star_costs(k):
+    # K_{1,k}: every leaf (degree 1) points at the hub (degree k >= 1, or the
+    # larger id when k = 1), which has no out-neighbour: the head never costs
+    # anything and CF still merges each leaf's one-entry list
+    g = graph(k + 1, [(0, i) for i in range(1, k + 1)])
+    rp, col = g.numpy()
+    o = oracle.orient(rp, col)
+    assert len(oracle.list_triangles(o)) == 0
+    assert oracle.sum_min(o) == 0
+    assert oracle.sum_head(o) == 0
+    assert oracle.sum_merge(o) == k
 
 
 def grid(a, b):
