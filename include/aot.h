@@ -134,12 +134,35 @@ int aot_orient(const aot_graph* g, uint32_t flags, aot_oriented* out,
  *               not finite, or of the wrong shape, is not used: the bucket
  *               falls back to the plain rule (the call still succeeds;
  *               aot_count_plan reports which rule ran).
- * aot_count stores the plan it resolved in the workspace; aot_list and
- * aot_digest given d = NULL use that plan.
+ *   strategy    which list each edge probes, and into what.  Every strategy
+ *               gives the same tri_off and byte-identical lists; they differ
+ *               in cost, which aot_count's result[1] reports:
+ *     AOT_STRATEGY_ADAPTIVE  Algorithm 3 (Section 3.2): s probes into an index
+ *                 of N+(b), built once per owner b; cost sum of
+ *                 min(deg+(u), deg+(v)).  The default.
+ *     AOT_STRATEGY_HEAD      the fixed orientation: edge <u,v> probes N+(v)
+ *                 into an index of N+(u), built once per tail u; the cost
+ *                 of kClist's analysis (Section 2.3), sum of deg+(v).
+ *     AOT_STRATEGY_MERGE     Algorithm 1 (CF, Section 2.2): each edge merges
+ *                 N+(u) with N+(v); cost sum of deg+(u) + deg+(v).
+ *     AOT_STRATEGY_PER_EDGE  the CF-Hash remark of Section 2.2: the smaller
+ *                 list probes the larger edge by edge, with no per-owner
+ *                 index (every edge takes the light path's search of the
+ *                 larger list in device memory); cost as ADAPTIVE.
+ *               Non-adaptive strategies take AOT_DISPATCH_PLAIN or TABLE
+ *               (AOT_E_ARG with LEARNED); MERGE and PER_EDGE ignore
+ *               heavy_min and the heavy arms.
+ * aot_count stores the plan and strategy it resolved in the workspace;
+ * aot_list and aot_digest given d = NULL use that plan, and always the
+ * count's strategy.
  */
 #define AOT_DISPATCH_PLAIN 0
 #define AOT_DISPATCH_TABLE 1
 #define AOT_DISPATCH_LEARNED 2
+#define AOT_STRATEGY_ADAPTIVE 0
+#define AOT_STRATEGY_HEAD 1
+#define AOT_STRATEGY_MERGE 2
+#define AOT_STRATEGY_PER_EDGE 3
 #define AOT_NUM_BUCKETS 32
 #define AOT_NUM_OPTIONS 9      /* cost-model outputs, see aot_bucket_features */
 #define AOT_NUM_FEATURES 8
@@ -149,6 +172,7 @@ typedef struct aot_dispatch {
   int32_t heavy_min;
   const int32_t* table;          /* AOT_DISPATCH_TABLE                       */
   const struct aot_mlp* model;   /* AOT_DISPATCH_LEARNED: the cost model      */
+  int32_t strategy;              /* AOT_STRATEGY_*                            */
 } aot_dispatch;
 
 /* ------------------------------------------------------------------------
@@ -162,7 +186,8 @@ typedef struct aot_dispatch {
  *            triangles of edge e are global indices [tri_off[e], tri_off[e+1]).
  *   ws       device workspace of at least aot_count_workspace() bytes; keep it
  *            unchanged until the matching aot_list calls are done.
- *   result   host uint64[2], written: {T, probes}; probes = sum over edges of
+ *   result   host uint64[2], written: {T, probes}; probes = the strategy's
+ *            cost, for the adaptive one the sum over edges of
  *            min(deg+(u), deg+(v)).
  * Synchronises `stream`. */
 int aot_count_workspace(int32_t n, int64_t m, size_t* bytes);

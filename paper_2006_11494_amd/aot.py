@@ -22,6 +22,12 @@ AOT_IN_LISTS_BY_RANK = 2
 AOT_DISPATCH_PLAIN = 0
 AOT_DISPATCH_TABLE = 1
 AOT_DISPATCH_LEARNED = 2
+AOT_STRATEGY_ADAPTIVE = 0
+AOT_STRATEGY_HEAD = 1
+AOT_STRATEGY_MERGE = 2
+AOT_STRATEGY_PER_EDGE = 3
+STRATEGIES = {"aot": AOT_STRATEGY_ADAPTIVE, "head": AOT_STRATEGY_HEAD,
+              "merge": AOT_STRATEGY_MERGE, "per_edge": AOT_STRATEGY_PER_EDGE}
 AOT_NUM_BUCKETS = 32
 AOT_NUM_OPTIONS = 9
 AOT_NUM_FEATURES = 8
@@ -68,7 +74,8 @@ class TimingC(ctypes.Structure):
 
 class DispatchC(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("heavy_min", ctypes.c_int32),
-                ("table", ctypes.c_void_p), ("model", ctypes.c_void_p)]
+                ("table", ctypes.c_void_p), ("model", ctypes.c_void_p),
+                ("strategy", ctypes.c_int32)]
 
 
 class BatchC(ctypes.Structure):
@@ -188,11 +195,13 @@ class Oriented:
 @dataclass
 class Dispatch:
     """Probe-kernel dispatch: the plain rule, a per-bucket code table, or the
-    learned cost model (`model`, an Mlp)."""
+    learned cost model (`model`, an Mlp), and the probe strategy
+    (AOT_STRATEGY_*; the write pass always uses the count's)."""
     mode: int = AOT_DISPATCH_PLAIN
     heavy_min: int = 0
     table: list | None = None
     model: "Mlp | None" = None
+    strategy: int = AOT_STRATEGY_ADAPTIVE
 
     def cstruct(self):
         self._table = None
@@ -204,7 +213,7 @@ class Dispatch:
         if self.model is not None:
             self._model = self.model.cstruct()
             mp = ctypes.cast(ctypes.pointer(self._model), ctypes.c_void_p)
-        return DispatchC(self.mode, self.heavy_min, tp, mp)
+        return DispatchC(self.mode, self.heavy_min, tp, mp, self.strategy)
 
 
 class Mlp:

@@ -47,8 +47,13 @@ int check_dispatch(const aot_dispatch* d, aot::DispatchView* v) {
       d->mode != AOT_DISPATCH_LEARNED)
     return fail(AOT_E_ARG, "unknown dispatch mode");
   if (d->heavy_min < 0) return fail(AOT_E_ARG, "heavy_min < 0");
+  if (d->strategy < AOT_STRATEGY_ADAPTIVE || d->strategy > AOT_STRATEGY_PER_EDGE)
+    return fail(AOT_E_ARG, "unknown strategy");
+  if (d->strategy != AOT_STRATEGY_ADAPTIVE && d->mode == AOT_DISPATCH_LEARNED)
+    return fail(AOT_E_ARG, "the cost model chooses for the adaptive strategy only");
   v->given = true;
   v->heavy_min = d->heavy_min;
+  v->strategy = d->strategy;
   if (d->mode == AOT_DISPATCH_TABLE) {
     if (!d->table) return fail(AOT_E_MODEL, "table dispatch without a table");
     v->table = d->table;

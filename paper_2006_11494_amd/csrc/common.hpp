@@ -44,6 +44,19 @@ __device__ __forceinline__ T group_sum(T x) {
   return x;
 }
 
+// Sum of x over the lanes below this one inside its G-lane group.
+template <int G, typename T>
+__device__ __forceinline__ T group_exclusive_sum(T x) {
+  const int in = lane_id() & (G - 1);
+  T inc = x;
+#pragma unroll
+  for (int o = 1; o < G; o <<= 1) {
+    const T y = __shfl_up(inc, o, G);
+    if (in >= o) inc += y;
+  }
+  return inc - x;
+}
+
 // Inclusive prefix sum across the 64 lanes of a wave.
 template <typename T>
 __device__ __forceinline__ T wave_inclusive_scan(T x) {

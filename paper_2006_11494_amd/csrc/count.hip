@@ -63,7 +63,7 @@ constexpr int kDefaultHeavyMin = 32;
 #endif
 // rows longer than this are windowed separately over out- and in-list
 constexpr int kSplitAbove = AOT_SPLIT_ITEMS ? kItemSpan : (1 << 30);
-constexpr int kPlanWords = 64;      // resolved table [32], learned flag, valid flag
+constexpr int kPlanWords = 64;      // resolved table [32], learned flag, valid flag, strategy
 constexpr int kFeatures = AOT_NUM_FEATURES;
 constexpr int kOptions = AOT_NUM_OPTIONS;
 
@@ -87,18 +87,29 @@ __host__ __device__ __forceinline__ int heavy_class(int32_t db) {
   return h < kHeavyClasses ? h : kHeavyClasses - 1;
 }
 
+// Probe strategies (the ablation of Section 4.3 and the costs of Section 2):
+// which list an edge probes and into what.  All list the same triangles in
+// the same order.
+constexpr int kStratAdaptive = 0;   // Algorithm 3: min side into the owner's index
+constexpr int kStratHead = 1;       // fixed orientation: N+(v) into N+(u) (kClist cost)
+constexpr int kStratMerge = 2;      // Algorithm 1: merge N+(u) with N+(v)
+constexpr int kStratPerEdge = 3;    // min side into the larger list, edge by edge
+constexpr int kNumStrategies = 4;
+
 struct EdgeEnds {
   int32_t s, b;      // probe side, owner
   int32_t c, db;     // deg+(s), deg+(b)
 };
 
+// head = false: the adaptive rule.  head = true: the fixed orientation, where
+// the tail u always owns the edge and its head's list is probed.
 __device__ __forceinline__ EdgeEnds edge_ends(const int64_t* __restrict__ orow, int32_t u,
-                                              int32_t v) {
+                                              int32_t v, bool head) {
   const int32_t du = (int32_t)(orow[u + 1] - orow[u]);
   const int32_t dv = (int32_t)(orow[v + 1] - orow[v]);
   // u < v in rank, so on a tie u has the smaller (deg+, id) and is probed
   EdgeEnds r;
-  if (du <= dv) { r.s = u; r.b = v; r.c = du; r.db = dv; }
+  if (!head && du <= dv) { r.s = u; r.b = v; r.c = du; r.db = dv; }
   else { r.s = v; r.b = u; r.c = dv; r.db = du; }
   return r;
 }
@@ -134,27 +145,37 @@ __device__ __forceinline__ int32_t block_max(int32_t x, int32_t* tmp) {
 __global__ __launch_bounds__(kBlock) void k_bin_count(int64_t m, const int64_t* __restrict__ orow,
                                                       const int32_t* __restrict__ ocol,
                                                       const int32_t* __restrict__ otail,
-                                                      int32_t heavy_min,
+                                                      int32_t heavy_min, int32_t strategy,
                                                       int32_t* __restrict__ cnt,
                                                       uint8_t* __restrict__ code,
                                                       int64_t* __restrict__ stats,
                                                       unsigned long long* __restrict__ probes) {
-  __shared__ unsigned long long se[kNumBuckets], sp[kNumBuckets], sd[kNumBuckets];
+  __shared__ unsigned long long se[kNumBuckets], sp[kNumBuckets], sd[kNumBuckets], sk;
   if (threadIdx.x < kNumBuckets) { se[threadIdx.x] = 0; sp[threadIdx.x] = 0; sd[threadIdx.x] = 0; }
+  if (threadIdx.x == 0) sk = 0;
   __syncthreads();
+  const bool merge = strategy == kStratMerge;
+  unsigned long long skipped = 0;       // merge cost of edges with an empty list
   for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < m;
        e += (int64_t)gridDim.x * kBlock) {
-    const EdgeEnds x = edge_ends(orow, otail[e], ocol[e]);
+    const EdgeEnds x = edge_ends(orow, otail[e], ocol[e], strategy == kStratHead);
+    // the edge's cost: probes of N+(s), or both lists for a merge
+    const int32_t cost = merge ? x.c + x.db : x.c;
     int bucket;
     if (x.db >= heavy_min) bucket = kHeavyBase + heavy_class(x.db);
-    else if (x.c == 0) { cnt[e] = 0; code[e] = 0xFF; continue; }
-    else bucket = light_bin(x.c);
+    else if (x.c == 0) { cnt[e] = 0; code[e] = 0xFF; skipped += (unsigned)cost; continue; }
+    else bucket = light_bin(cost);
     code[e] = bucket < kLightBins ? (uint8_t)bucket : (uint8_t)0xFF;
     atomicAdd(&se[bucket], 1ull);
-    atomicAdd(&sp[bucket], (unsigned long long)x.c);
+    atomicAdd(&sp[bucket], (unsigned long long)cost);
     atomicAdd(&sd[bucket], (unsigned long long)x.db);
   }
+  if (merge) {
+    skipped = wave_sum(skipped);
+    if (lane_id() == 0 && skipped) atomicAdd(&sk, skipped);
+  }
   __syncthreads();
+  if (threadIdx.x == 0 && sk) atomicAdd(probes, sk);
   if (threadIdx.x < kNumBuckets && se[threadIdx.x]) {
     atomicAdd(u64p(&stats[threadIdx.x * kStats + kSEdges]), se[threadIdx.x]);
     atomicAdd(u64p(&stats[threadIdx.x * kStats + kSProbes]), sp[threadIdx.x]);
@@ -238,7 +259,7 @@ __global__ __launch_bounds__(kBlock) void k_bin_place(int64_t m, const uint8_t* 
 __global__ __launch_bounds__(kBlock) void k_item_count(int32_t n, const int64_t* __restrict__ orow,
                                                        const int32_t* __restrict__ ocol,
                                                        const int64_t* __restrict__ irow,
-                                                       int32_t heavy_min,
+                                                       int32_t heavy_min, bool head,
                                                        int64_t* __restrict__ stats) {
   __shared__ unsigned long long si[kHeavyClasses], ss[kHeavyClasses], sx[kHeavyClasses];
   if (threadIdx.x < kHeavyClasses) { si[threadIdx.x] = 0; ss[threadIdx.x] = 0; sx[threadIdx.x] = 0; }
@@ -248,7 +269,7 @@ __global__ __launch_bounds__(kBlock) void k_item_count(int32_t n, const int64_t*
     const int64_t ob = orow[b];
     const int64_t db = orow[b + 1] - ob;
     if (db < heavy_min) continue;
-    const int64_t din = irow[b + 1] - irow[b];
+    const int64_t din = head ? 0 : irow[b + 1] - irow[b];
     const int64_t k = db + din <= kSplitAbove
                           ? (db + din + kItemSpan - 1) / kItemSpan
                           : (db + kItemSpan - 1) / kItemSpan + (din + kItemSpan - 1) / kItemSpan;
@@ -270,7 +291,7 @@ __global__ __launch_bounds__(kBlock) void k_item_count(int32_t n, const int64_t*
 // Work items into their classes; one global atomic per wave and class.
 __global__ __launch_bounds__(kBlock) void k_item_scatter(int32_t n, const int64_t* __restrict__ orow,
                                                          const int64_t* __restrict__ irow,
-                                                         int32_t heavy_min,
+                                                         int32_t heavy_min, bool head,
                                                          int64_t* __restrict__ stats,
                                                          int2* __restrict__ items) {
   __shared__ int64_t base[kHeavyClasses];
@@ -292,7 +313,7 @@ __global__ __launch_bounds__(kBlock) void k_item_scatter(int32_t n, const int64_
     if (b < n) {
       const int64_t db = orow[b + 1] - orow[b];
       if (db >= heavy_min) {
-        const int64_t din = irow[b + 1] - irow[b];
+        const int64_t din = head ? 0 : irow[b + 1] - irow[b];
         if (db + din <= kSplitAbove) {        // windows over the whole row
           k = (int32_t)((db + din + kItemSpan - 1) / kItemSpan);
           kout = k;
@@ -468,6 +489,7 @@ struct HeavyArgs {
   int32_t* out;
   unsigned long long* digest;   // write pass in digest mode: {triangles, hash sum, hash xor}
   unsigned long long* vcount;   // digest mode, optional: per-vertex triangle counts
+  int32_t head = 0;             // fixed orientation: b owns its out-edges only
 };
 
 // SplitMix64's output function (Steele, Lea and Flood, 2014) on state z.
@@ -805,7 +827,7 @@ __device__ void heavy_item(HeavyShared<kEmit>& sh, uint32_t* lds, const HeavyArg
   const int64_t ob = a.orow[b];
   const int32_t db = (int32_t)(a.orow[b + 1] - ob);
   const int64_t ib = a.irow[b];
-  const int32_t deg = db + (int32_t)(a.irow[b + 1] - ib);
+  const int32_t deg = db + (a.head ? 0 : (int32_t)(a.irow[b + 1] - ib));
   const int32_t j0 = item.y;
   // the whole row, or one window of the out-list or of the in-list
   const int32_t j1 = deg <= kSplitAbove ? min(deg, j0 + kItemSpan)
@@ -841,7 +863,7 @@ __device__ void heavy_item(HeavyShared<kEmit>& sh, uint32_t* lds, const HeavyArg
     if (near) {
       const int64_t oy = a.orow[y];
       const int32_t dy = (int32_t)(a.orow[y + 1] - oy);
-      const bool owned = dy < db || (dy == db && y < b);
+      const bool owned = a.head ? out_edge : dy < db || (dy == db && y < b);
       // an owned in-edge <y, b>: its id is b's place in N+(y), the list probed
       // next; the count pass finds it and keeps it for the write pass
       if (owned && !out_edge) {
@@ -995,7 +1017,26 @@ struct LightArgs {
   int32_t* out;
   unsigned long long* digest;   // write pass in digest mode
   unsigned long long* vcount;
+  int32_t head = 0;             // fixed orientation (edge_ends)
 };
+
+// One triangle of the write pass (t0, t1, t2: original ids) at global index at.
+template <bool kDigest>
+__device__ __forceinline__ void light_sink(const LightArgs& a, Digest& dg, int64_t at, int32_t t0,
+                                           int32_t t1, int32_t t2) {
+  sort3(t0, t1, t2);
+  if constexpr (kDigest) {
+    dg.add(t0, t1, t2);
+    if (a.vcount) {
+      atomicAdd(&a.vcount[t0], 1ull);
+      atomicAdd(&a.vcount[t1], 1ull);
+      atomicAdd(&a.vcount[t2], 1ull);
+    }
+  } else if (at >= a.first && at < a.first + a.count) {
+    int32_t* o = a.out + 3 * (at - a.first);
+    o[0] = t0; o[1] = t1; o[2] = t2;
+  }
+}
 
 // Binned light edges elist[t0 .. t1), G lanes per edge: each lane binary-
 // searches N+(b) for its share of N+(s).
@@ -1007,7 +1048,7 @@ __device__ __forceinline__ void light_range(const LightArgs& a, int64_t t0, int6
   for (int64_t t = t0 + gi; t < t1; t += kGroups) {
     const int32_t e = a.elist[t];
     const int32_t u = a.otail[e], v = a.ocol[e];
-    const EdgeEnds x = edge_ends(a.orow, u, v);
+    const EdgeEnds x = edge_ends(a.orow, u, v, a.head != 0);
     const int32_t* ps = a.ocol + a.orow[x.s];
     const int32_t* pb = a.ocol + a.orow[x.b];
     if constexpr (!kEmit) {
@@ -1027,22 +1068,58 @@ __device__ __forceinline__ void light_range(const LightArgs& a, int64_t t0, int6
         const bool hit = q < x.c && contains_sorted(pb, x.db, w);
         const uint64_t mask = ballot(hit);
         const int64_t at = pos + popc_below_in_group<G>(mask);
-        if (hit) {
-          int32_t t0_ = pu, t1_ = pv, t2_ = a.perm[w];
-          sort3(t0_, t1_, t2_);
-          if constexpr (kDigest) {
-            dg.add(t0_, t1_, t2_);
-            if (a.vcount) {
-              atomicAdd(&a.vcount[t0_], 1ull);
-              atomicAdd(&a.vcount[t1_], 1ull);
-              atomicAdd(&a.vcount[t2_], 1ull);
-            }
-          } else if (at >= a.first && at < a.first + a.count) {
-            int32_t* o = a.out + 3 * (at - a.first);
-            o[0] = t0_; o[1] = t1_; o[2] = t2_;
-          }
-        }
+        if (hit) light_sink<kDigest>(a, dg, at, pu, pv, a.perm[w]);
         pos += __popcll(group_bits<G>(mask));
+      }
+    }
+  }
+}
+
+// Algorithm 1's merge intersection of N+(u) and N+(v), G lanes per edge.
+// Lane li takes a contiguous run of N+(u) and merges it with N+(v) from the
+// first entry not below the run's first value, so the lanes together read
+// both lists about once (plus one binary search per lane).  Hits come out in
+// ascending order, lane after lane, as the other strategies emit them.
+template <int G, bool kEmit, bool kDigest>
+__device__ __forceinline__ void merge_range(const LightArgs& a, int64_t t0, int64_t t1,
+                                            int64_t& tri, Digest& dg) {
+  constexpr int kGroups = kBlock / G;
+  const int gi = threadIdx.x / G, li = threadIdx.x % G;
+  for (int64_t t = t0 + gi; t < t1; t += kGroups) {
+    const int32_t e = a.elist[t];
+    const int32_t u = a.otail[e], v = a.ocol[e];
+    const int64_t ou = a.orow[u], ov = a.orow[v];
+    const int32_t du = (int32_t)(a.orow[u + 1] - ou), dv = (int32_t)(a.orow[v + 1] - ov);
+    const int32_t* A = a.ocol + ou;
+    const int32_t* B = a.ocol + ov;
+    int64_t pos = 0;
+    if constexpr (kEmit) {
+      pos = a.tri_off[e];
+      const int64_t end = a.tri_off[e + 1];
+      if (pos == end || (!kDigest && (end <= a.first || pos >= a.first + a.count))) continue;
+    }
+    const int32_t per = (du + G - 1) / G;
+    const int32_t i0 = min(du, li * per), i1 = min(du, i0 + per);
+    const int32_t j0 = i0 < i1 ? (int32_t)lower_bound(B, dv, A[i0]) : dv;
+    int32_t hits = 0;
+    for (int32_t i = i0, j = j0; i < i1 && j < dv;) {
+      const int32_t x = A[i], y = B[j];
+      hits += x == y;
+      i += x <= y;
+      j += y <= x;
+    }
+    if constexpr (!kEmit) {
+      tri += hits;
+      hits = group_sum<G>(hits);
+      if (li == 0) a.cnt[e] = hits;
+    } else {
+      int64_t at = pos + group_exclusive_sum<G>(hits);
+      const int32_t pu = a.perm[u], pv = a.perm[v];
+      for (int32_t i = i0, j = j0; i < i1 && j < dv;) {
+        const int32_t x = A[i], y = B[j];
+        if (x == y) light_sink<kDigest>(a, dg, at++, pu, pv, a.perm[x]);
+        i += x <= y;
+        j += y <= x;
       }
     }
   }
@@ -1069,6 +1146,18 @@ __global__ __launch_bounds__(kBlock) void k_light(LightArgs a, int64_t base, int
   Digest dg;
   for (int64_t c = (int64_t)blockIdx.x * kGroups; c < total; c += (int64_t)gridDim.x * kGroups)
     light_range<G, kEmit, kDigest>(a, base + c, base + min(c + kGroups, total), tri, dg);
+  light_finish<kEmit, kDigest>(a, tri, dg, tri_stat);
+}
+
+// The merge strategy's launch over one bin.
+template <int G, bool kEmit, bool kDigest = false>
+__global__ __launch_bounds__(kBlock) void k_merge(LightArgs a, int64_t base, int64_t total,
+                                                  int64_t* tri_stat) {
+  constexpr int kGroups = kBlock / G;
+  int64_t tri = 0;
+  Digest dg;
+  for (int64_t c = (int64_t)blockIdx.x * kGroups; c < total; c += (int64_t)gridDim.x * kGroups)
+    merge_range<G, kEmit, kDigest>(a, base + c, base + min(c + kGroups, total), tri, dg);
   light_finish<kEmit, kDigest>(a, tri, dg, tri_stat);
 }
 
@@ -1332,8 +1421,10 @@ CountWs carve_count(Carve& c, int32_t n, int64_t m) {
 
 template <bool kEmit, bool kDigest = false>
 hipError_t launch_light(int tile, unsigned grid, const LightArgs& a, int64_t base, int64_t total,
-                        int64_t* tri_stat, hipStream_t s) {
-#define L(G) k_light<G, kEmit, kDigest><<<grid, kBlock, 0, s>>>(a, base, total, tri_stat)
+                        int64_t* tri_stat, bool merge, hipStream_t s) {
+#define L(G)                                                                     \
+  if (merge) k_merge<G, kEmit, kDigest><<<grid, kBlock, 0, s>>>(a, base, total, tri_stat); \
+  else k_light<G, kEmit, kDigest><<<grid, kBlock, 0, s>>>(a, base, total, tri_stat)
   switch (tile) {
     case 4: L(4); break;
     case 8: L(8); break;
@@ -1423,7 +1514,8 @@ int run_buckets(bool emit, const Plan& plan, const int64_t* hs, const CountWs& w
                 const int32_t* perm, const int64_t* irow, const int32_t* icol,
                 const int64_t* tri_off, int64_t first, int64_t count, int32_t* out,
                 unsigned long long* digest, unsigned long long* vcount, const int64_t* win,
-                hipStream_t s, const char** err) {
+                int strategy, hipStream_t s, const char** err) {
+  const bool merge = strategy == kStratMerge;
   int64_t lbase = 0;
   for (int k = 0; k < kLightBins; ++k) {
     const int64_t* st = hs + k * kStats;
@@ -1442,11 +1534,12 @@ int run_buckets(bool emit, const Plan& plan, const int64_t* hs, const CountWs& w
       la.cnt = emit ? nullptr : w.cnt;
       la.tri_off = tri_off; la.perm = perm; la.first = first; la.count = count; la.out = out;
       la.digest = digest; la.vcount = vcount;
+      la.head = strategy == kStratHead;
       const hipError_t e =
-          emit ? (digest ? launch_light<true, true>(tile, grid, la, b0, edges, nullptr, s)
-                         : launch_light<true>(tile, grid, la, b0, edges, nullptr, s))
+          emit ? (digest ? launch_light<true, true>(tile, grid, la, b0, edges, nullptr, merge, s)
+                         : launch_light<true>(tile, grid, la, b0, edges, nullptr, merge, s))
                : launch_light<false>(tile, grid, la, b0, edges,
-                                     w.stats + k * kStats + kSTriangles, s);
+                                     w.stats + k * kStats + kSTriangles, merge, s);
       AOT_TRY(e);
       timing_end(rec, s);
     }
@@ -1479,6 +1572,7 @@ int run_buckets(bool emit, const Plan& plan, const int64_t* hs, const CountWs& w
     a.out = out;
     a.digest = digest;
     a.vcount = vcount;
+    a.head = strategy == kStratHead;
     const int rec = timing_begin(emit ? 1 : 0, kHeavyBase + h, arm, kBlock, st[kSEdges],
                                  st[kSProbes], st[kSStaged], st[kSTriangles], s);
     const size_t dyn = sizeof(uint32_t) * (size_t)std::max(a.idx_words, 1);
@@ -1508,7 +1602,12 @@ int count_run(int32_t n, int64_t m, const int64_t* orow, const int32_t* ocol, co
     *err = "count workspace too small";
     return -4;
   }
-  const int32_t heavy_min = d.heavy_min > 0 ? d.heavy_min : kDefaultHeavyMin;
+  const int strategy = d.strategy;
+  // the merge and per-edge strategies keep no per-owner index: every edge is light
+  const int32_t heavy_min = strategy == kStratMerge || strategy == kStratPerEdge ? INT32_MAX
+                            : d.heavy_min > 0 ? d.heavy_min
+                                              : kDefaultHeavyMin;
+  const bool head = strategy == kStratHead;
   Plan plan;
   if (!plan_from(d, &plan)) {
     *err = "dispatch table holds an unknown arm or tile code";
@@ -1520,14 +1619,14 @@ int count_run(int32_t n, int64_t m, const int64_t* orow, const int32_t* ocol, co
   std::vector<int64_t> hs(kStatWords, 0);
   if (m > 0) {
     const unsigned ge = grid_cap(std::min<int64_t>(cdiv(m, kBlock), 2048));
-    k_bin_count<<<ge, kBlock, 0, s>>>(m, orow, ocol, otail, heavy_min, w.cnt, w.code, w.stats,
-                                      w.probes);
+    k_bin_count<<<ge, kBlock, 0, s>>>(m, orow, ocol, otail, heavy_min, strategy, w.cnt, w.code,
+                                      w.stats, w.probes);
     AOT_TRY(hipGetLastError());
     AOT_TRY(bin_scatter(m, w, s));
     const unsigned gv = grid_cap(std::min<int64_t>(cdiv(n, kBlock), 1024));
-    k_item_count<<<gv, kBlock, 0, s>>>(n, orow, ocol, irow, heavy_min, w.stats);
+    k_item_count<<<gv, kBlock, 0, s>>>(n, orow, ocol, irow, heavy_min, head, w.stats);
     AOT_TRY(hipGetLastError());
-    k_item_scatter<<<gv, kBlock, 0, s>>>(n, orow, irow, heavy_min, w.stats, w.items);
+    k_item_scatter<<<gv, kBlock, 0, s>>>(n, orow, irow, heavy_min, head, w.stats, w.items);
     AOT_TRY(hipGetLastError());
     AOT_TRY(hipMemcpyAsync(hs.data(), w.stats, sizeof(int64_t) * kStatWords,
                            hipMemcpyDeviceToHost, s));
@@ -1540,7 +1639,8 @@ int count_run(int32_t n, int64_t m, const int64_t* orow, const int32_t* ocol, co
       }
     }
     const int rc = run_buckets(false, plan, hs.data(), w, orow, ocol, otail, nullptr, irow, icol,
-                               nullptr, 0, 0, nullptr, nullptr, nullptr, nullptr, s, err);
+                               nullptr, 0, 0, nullptr, nullptr, nullptr, nullptr, strategy, s,
+                               err);
     if (rc) return rc;
   }
   {
@@ -1548,6 +1648,7 @@ int count_run(int32_t n, int64_t m, const int64_t* orow, const int32_t* ocol, co
     plan_to_table(plan, words);
     words[kNumBuckets] = learned;
     words[kNumBuckets + 1] = 1;      // plan valid
+    words[kNumBuckets + 2] = strategy;
     AOT_TRY(hipMemcpyAsync(w.plan, words, sizeof(words), hipMemcpyHostToDevice, s));
   }
   AOT_TRY(exclusive_scan(w.cnt, tri_off, m, w.scan_tmp, s));
@@ -1677,14 +1778,14 @@ int drain_run(int32_t n, int64_t m, const int64_t* orow, const int32_t* ocol,
   }
   if (m > 0) {
     const unsigned ge = grid_cap(std::min<int64_t>(cdiv(m, kBlock), 2048));
-    k_bin_count<<<ge, kBlock, 0, s>>>(m, orow, ocol, otail, heavy_min, w.cnt, w.code, w.stats,
-                                      w.probes);
+    k_bin_count<<<ge, kBlock, 0, s>>>(m, orow, ocol, otail, heavy_min, kStratAdaptive, w.cnt,
+                                      w.code, w.stats, w.probes);
     AOT_TRY(hipGetLastError());
     AOT_TRY(bin_scatter(m, w, s));
     const unsigned gv = grid_cap(std::min<int64_t>(cdiv(n, kBlock), 1024));
-    k_item_count<<<gv, kBlock, 0, s>>>(n, orow, ocol, irow, heavy_min, w.stats);
+    k_item_count<<<gv, kBlock, 0, s>>>(n, orow, ocol, irow, heavy_min, false, w.stats);
     AOT_TRY(hipGetLastError());
-    k_item_scatter<<<gv, kBlock, 0, s>>>(n, orow, irow, heavy_min, w.stats, w.items);
+    k_item_scatter<<<gv, kBlock, 0, s>>>(n, orow, irow, heavy_min, false, w.stats, w.items);
     AOT_TRY(hipGetLastError());
     k_heavy_drain<false><<<gh0, kBlock, dyn, s>>>(ha, w.stats, w.probes + 4);
     AOT_TRY(hipGetLastError());
@@ -1751,9 +1852,15 @@ int emit_run(int32_t n, int64_t m, const int64_t* orow, const int32_t* ocol, con
       t.table = words;
       if (!plan_from(t, &plan)) plan = plain_plan();
     }
+    // the bins and work items are the count's, so is the strategy
+    const int32_t strategy = words[kNumBuckets + 1] == 1 ? words[kNumBuckets + 2] : 0;
+    if (strategy < 0 || strategy >= kNumStrategies) {
+      *err = "the workspace holds no valid count";
+      return -4;
+    }
     const int rc = run_buckets(true, plan, hs.data(), w, orow, ocol, otail, perm, irow, icol,
                                tri_off, first, count, out, dg, vc, digest_mode ? nullptr : win,
-                               s, err);
+                               strategy, s, err);
     if (rc) return rc;
   }
   if (digest_mode) {

@@ -87,6 +87,7 @@ size_t count_workspace_bytes(int32_t n, int64_t m);
 struct DispatchView {
   bool given = false;              // a dispatch was passed (else: the stored plan / plain rule)
   int32_t heavy_min = 0;
+  int32_t strategy = 0;            // AOT_STRATEGY_*
   const int32_t* table = nullptr;  // host, kNumBuckets codes or nullptr
   const aot_mlp* model = nullptr;  // learned dispatch
 };

@@ -106,6 +106,13 @@ def test_count_and_list_argument_errors():
     assert lib.aot_count(ctypes.byref(o), ctypes.byref(no_table), FAKE, FAKE, ws, res, None) == -6
     neg = aot.DispatchC(0, -3, None)
     assert lib.aot_count(ctypes.byref(o), ctypes.byref(neg), FAKE, FAKE, ws, res, None) == -1
+    bad_strategy = aot.DispatchC(0, 0, None, None, 4)
+    assert lib.aot_count(ctypes.byref(o), ctypes.byref(bad_strategy), FAKE, FAKE, ws, res,
+                         None) == -1
+    learned_head = aot.DispatchC(aot.AOT_DISPATCH_LEARNED, 0, None, None, aot.AOT_STRATEGY_HEAD)
+    assert lib.aot_count(ctypes.byref(o), ctypes.byref(learned_head), FAKE, FAKE, ws, res,
+                         None) == -1
+    assert b"adaptive" in lib.aot_last_error()
     lst = lambda oo, dd, off, w, nb, first, cnt, out: lib.aot_list(oo, dd, off, w, nb, first, cnt,
                                                                   out, None, None)
     assert lst(ctypes.byref(o), ctypes.byref(d), None, FAKE, ws, 0, 1, FAKE) == -1
