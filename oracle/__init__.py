@@ -56,6 +56,10 @@ def _load():
     lib.orc_sum_min.restype = u64
     lib.orc_sum_head.argtypes = [i32, _i64p, _i32p]
     lib.orc_sum_head.restype = u64
+    lib.orc_core_rounds.argtypes = [i32, _i64p, _i32p, _i32p, ctypes.POINTER(i32)]
+    lib.orc_core_rounds.restype = i32
+    lib.orc_orient_core.argtypes = [i32, _i64p, _i32p, _i32p, _i32p, _i64p, _i32p]
+    lib.orc_orient_core.restype = i64
     lib.orc_sum_merge.argtypes = [i32, _i64p, _i32p]
     lib.orc_sum_merge.restype = u64
     lib.orc_aot_ref.argtypes = [i32, _i64p, _i32p, ctypes.c_int, _i32p, i64, ctypes.POINTER(u64)]
@@ -106,8 +110,9 @@ class Oriented:
         return np.repeat(np.arange(self.n, dtype=np.int32), self.dplus)
 
 
-def orient(rowptr, col) -> Oriented:
-    """Degree order with id tie-break; <u,v> iff eta(u) < eta(v) (Sec. 2.2)."""
+def orient(rowptr, col, order: str = "degree") -> Oriented:
+    """Degree order with id tie-break; <u,v> iff eta(u) < eta(v) (Sec. 2.2).
+    order="core": the core order of kClist (Sec. 2.3), see core_rounds."""
     lib = _load()
     rowptr, col = _arrays(rowptr, col)
     n = rowptr.size - 1
@@ -115,7 +120,10 @@ def orient(rowptr, col) -> Oriented:
     rank = np.empty(max(n, 1), np.int32)
     orow = np.empty(n + 1, np.int64)
     ocol = np.empty(max(col.size // 2, 1), np.int32)
-    m = lib.orc_orient(n, rowptr, col, perm, rank, orow, ocol)
+    if order not in ("degree", "core"):
+        raise ValueError(order)
+    fn = lib.orc_orient if order == "degree" else lib.orc_orient_core
+    m = fn(n, rowptr, col, perm, rank, orow, ocol)
     if m < 0:
         raise MemoryError("oracle orientation failed")
     return Oriented(n, perm[:n], rank[:n], orow, ocol[:m].copy())
@@ -200,6 +208,19 @@ def vertex_triangles(rowptr, col, vs) -> np.ndarray:
     if vs.size:
         lib.orc_vertex_triangles(rowptr, _nonempty(col), vs, vs.size, out)
     return out[: vs.size]
+
+
+def core_rounds(rowptr, col):
+    """Synchronous peeling (the core order, Sec. 2.3): (round[v], sub-rounds,
+    degeneracy); the order is (round, id) ascending."""
+    rowptr, col = _arrays(rowptr, col)
+    n = rowptr.size - 1
+    rnd = np.empty(max(n, 1), np.int32)
+    deg = ctypes.c_int32(0)
+    k = _load().orc_core_rounds(n, rowptr, col, rnd, ctypes.byref(deg))
+    if k < 0:
+        raise MemoryError("oracle peeling failed")
+    return rnd[:n], int(k), int(deg.value)
 
 
 def in_lists(o: Oriented):

@@ -124,6 +124,82 @@ int64_t orc_orient(int32_t n, const int64_t* rowptr, const int32_t* col,
   return orow[n];
 }
 
+/* The core (degeneracy) order that kClist orients by (Section 2.3), taken as
+ * synchronous peeling.  Sub-round r first raises the level to the smallest
+ * current degree among the remaining vertices if that is larger, then
+ * removes, all at once, every remaining vertex whose current degree is at
+ * most the level, and lowers its remaining neighbours' current degrees by
+ * one per removed neighbour.  round[v] = the sub-round that removes v.  A
+ * vertex has at most `level` neighbours left when it goes, so ordering by
+ * (round, id) gives every vertex at most that many out-neighbours, and the
+ * largest level reached is the degeneracy.  Returns the number of
+ * sub-rounds (*degeneracy = the largest level), or -1 if out of memory. */
+int32_t orc_core_rounds(int32_t n, const int64_t* rowptr, const int32_t* col, int32_t* round,
+                        int32_t* degeneracy) {
+  int64_t* cur = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+  int32_t* gone = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+  if (!cur || !gone) { free(cur); free(gone); return -1; }
+  int32_t left = n, r = 0;
+  int64_t level = 0;
+  for (int32_t v = 0; v < n; ++v) { cur[v] = rowptr[v + 1] - rowptr[v]; round[v] = -1; }
+  while (left > 0) {
+    int64_t low = -1;
+    for (int32_t v = 0; v < n; ++v)
+      if (round[v] < 0 && (low < 0 || cur[v] < low)) low = cur[v];
+    if (low > level) level = low;
+    int32_t k = 0;
+    for (int32_t v = 0; v < n; ++v)
+      if (round[v] < 0 && cur[v] <= level) gone[k++] = v;
+    for (int32_t i = 0; i < k; ++i) round[gone[i]] = r;
+    for (int32_t i = 0; i < k; ++i) {
+      int32_t v = gone[i];
+      for (int64_t e = rowptr[v]; e < rowptr[v + 1]; ++e)
+        if (round[col[e]] < 0) --cur[col[e]];
+    }
+    left -= k;
+    ++r;
+  }
+  *degeneracy = (int32_t)level;
+  free(cur);
+  free(gone);
+  return r;
+}
+
+typedef struct { int32_t key; int32_t id; } key_id;
+
+static int cmp_key_id(const void* a, const void* b) {
+  const key_id* x = (const key_id*)a;
+  const key_id* y = (const key_id*)b;
+  if (x->key != y->key) return x->key < y->key ? -1 : 1;
+  return (x->id > y->id) - (x->id < y->id);
+}
+
+/* The orientation by the core order: rank = position in (round, id)
+ * ascending, then as orc_orient.  Returns m, or -1. */
+int64_t orc_orient_core(int32_t n, const int64_t* rowptr, const int32_t* col, int32_t* perm,
+                        int32_t* rank, int64_t* orow, int32_t* ocol) {
+  int32_t* round = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+  key_id* order = (key_id*)malloc(sizeof(key_id) * (size_t)(n > 0 ? n : 1));
+  int64_t* dplus = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+  int32_t degeneracy;
+  if (!round || !order || !dplus || orc_core_rounds(n, rowptr, col, round, &degeneracy) < 0) {
+    free(round); free(order); free(dplus);
+    return -1;
+  }
+  for (int32_t v = 0; v < n; ++v) { order[v].key = round[v]; order[v].id = v; }
+  qsort(order, (size_t)n, sizeof(key_id), cmp_key_id);
+  for (int32_t r = 0; r < n; ++r) {
+    perm[r] = order[r].id;
+    rank[order[r].id] = r;
+  }
+  orc_orient_count(rowptr, col, perm, rank, 0, n, dplus);
+  orow[0] = 0;
+  for (int32_t r = 0; r < n; ++r) orow[r + 1] = orow[r] + dplus[r];
+  orc_orient_write(rowptr, col, perm, rank, orow, 0, n, ocol);
+  free(round); free(order); free(dplus);
+  return orow[n];
+}
+
 /* In-lists of the oriented graph (Algorithm 3's second loop walks them): for
  * rank r, every x with r in N+(x), in ascending rank x; ieid[j] is the index
  * in ocol of the edge <icol[j], r>.  Built as the transpose of the out-lists,

@@ -409,3 +409,71 @@ def test_threaded_orientation_and_sum_min(g, threads):
     assert np.array_equal(a.perm, b.perm) and np.array_equal(a.rank, b.rank)
     assert np.array_equal(a.orow, b.orow) and np.array_equal(a.ocol, b.ocol)
     assert oracle.sum_min_threaded(b, threads=threads) == oracle.sum_min(a)
+
+
+# ---------------------------------------------------------------- core order
+
+def brute_degeneracy(n, edges):
+    """max over vertex subsets S of the least degree inside S."""
+    adj = [0] * n
+    for a, b in edges:
+        adj[a] |= 1 << b
+        adj[b] |= 1 << a
+    best = 0
+    for s in range(1, 1 << n):
+        low = min(bin(adj[v] & s).count("1") for v in range(n) if s >> v & 1)
+        best = max(best, low)
+    return best
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_core_order_reaches_the_degeneracy(seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(4, 11))
+    p = float(rng.choice([0.2, 0.4, 0.6]))
+    edges = [(i, j) for i in range(n) for j in range(i + 1, n) if rng.random() < p]
+    rp, col = graph(n, edges).numpy()
+    rnd, k, d = oracle.core_rounds(rp, col)
+    assert d == brute_degeneracy(n, edges)
+    o = oracle.orient(rp, col, "core")
+    # the first vertex of the densest core has all its core neighbours after it,
+    # so no order does better than the degeneracy; the core order reaches it
+    assert (o.dplus.max() if n else 0) == d
+    assert sorted(set(rnd.tolist())) == list(range(k))      # every sub-round removes some
+    # the order is (round, id)
+    assert np.array_equal(o.perm, np.lexsort((np.arange(n), rnd)))
+
+
+def test_core_order_hand_examples():
+    # path 0-1-2-3-4: the ends go first, then their neighbours, then the middle
+    rp, col = graph(5, [(0, 1), (1, 2), (2, 3), (3, 4)]).numpy()
+    rnd, k, d = oracle.core_rounds(rp, col)
+    assert rnd.tolist() == [0, 1, 2, 1, 0] and (k, d) == (3, 1)
+    assert oracle.orient(rp, col, "core").perm.tolist() == [0, 4, 1, 3, 2]
+    # star: leaves at level 1, then the hub (degree 0 by then)
+    rp, col = graph(6, [(0, i) for i in range(1, 6)]).numpy()
+    rnd, k, d = oracle.core_rounds(rp, col)
+    assert rnd.tolist() == [1, 0, 0, 0, 0, 0] and (k, d) == (2, 1)
+    # K_n: one sub-round at level n - 1, so the order is the id order
+    rp, col = graph(7, itertools.combinations(range(7), 2)).numpy()
+    rnd, k, d = oracle.core_rounds(rp, col)
+    assert rnd.tolist() == [0] * 7 and (k, d) == (1, 6)
+    # empty graph
+    rnd, k, d = oracle.core_rounds(np.zeros(1, np.int64), np.zeros(0, np.int32))
+    assert (len(rnd), k, d) == (0, 0, 0)
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_core_order_lists_the_same_set(seed):
+    """Any total order lists every triangle exactly once (Section 3.2)."""
+    csr = inputs.rmat(11, 16, seed)
+    rp, col = csr.numpy()
+    a = oracle.orient(rp, col)
+    b = oracle.orient(rp, col, "core")
+    ta, tb = oracle.list_triangles(a), oracle.list_triangles(b)
+    tb = tb[np.lexsort((tb[:, 2], tb[:, 1], tb[:, 0]))]
+    ta = ta[np.lexsort((ta[:, 2], ta[:, 1], ta[:, 0]))]
+    assert np.array_equal(ta, tb)
+    assert int(oracle.edge_counts(b).sum()) == len(ta)
+    _, _, d = oracle.core_rounds(rp, col)
+    assert b.dplus.max() == d <= a.dplus.max()
