@@ -48,6 +48,8 @@ def parse():
     p.add_argument("--heavy-min", type=int, default=0)
     p.add_argument("--no-learned", action="store_true",
                    help="skip the learned-dispatch leg (training the cost model takes ~20 s)")
+    p.add_argument("--no-ablation", action="store_true",
+                   help="skip the probe-strategy ablation (fixed orientation, CF merge, per edge)")
     p.add_argument("--no-batch", action="store_true",
                    help="skip the batched leg (512 uneven graphs, one captured pass)")
     p.add_argument("--batch-count", type=int, default=512)
@@ -240,6 +242,75 @@ def learned_leg(aot, o, csr, cws, tri_off, list_all, T, probes, args):
     log(f"[bench] learned dispatch: step {ms:.3f} ms (model used: {used})")
     return {"accepted": True, "value": T / (ms / 1000.0), "unit": "triangles/s",
             "ms_per_step": ms, "model_used": used, "plan": table, "train_s": train_s, **report}
+
+
+ABLATION_NOTE = ("count + list of the whole graph per (order, probe strategy): aot = adaptive "
+                 "orientation (Algorithm 3); head = fixed orientation, kClist's cost; "
+                 "merge = CF's merge intersections (Algorithm 1); per_edge = min side into "
+                 "the larger list edge by edge, no per-owner index (CF-Hash); core_* = the "
+                 "same on the core order (core_head: kClist's order and cost), whose "
+                 "ms_orient includes the peeling")
+ABLATION_CASES = (("aot", "degree", "aot"), ("head", "degree", "head"),
+                  ("merge", "degree", "merge"), ("per_edge", "degree", "per_edge"),
+                  ("core_aot", "core", "aot"), ("core_head", "core", "head"))
+
+
+def ablation_leg(aot, csr, o, ows, cws, tri_off, out, T, args):
+    """Section 4's comparisons on this graph: the same count + list with each
+    probe strategy, on the degree order and on the core order.  All give the
+    same triangles; probes are each strategy's cost on that order."""
+    import torch
+
+    def med(xs):
+        return float(np.median(xs))
+
+    reps = max(args.steps, 3)
+    res = {}
+    oriented = {"degree": o}
+    orient_ms = {"degree": None}
+    for name, order, strategy in ABLATION_CASES:
+        if order not in oriented:
+            oo = aot.alloc_oriented(csr.n, csr.m, csr.rowptr.device)
+            ts = []
+            for r in range(reps + 1):
+                ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+                ev[0].record()
+                aot.orient(csr.rowptr, csr.col, out=oo, ws=ows, order=order)
+                ev[1].record()
+                ev[1].synchronize()
+                if r:
+                    ts.append(ev[0].elapsed_time(ev[1]))
+            oriented[order], orient_ms[order] = oo, med(ts)
+        oo = oriented[order]
+        d = aot.Dispatch(strategy=aot.STRATEGIES[strategy])
+        cc = aot.count(oo, d, ws=cws, tri_off=tri_off)
+        aot.list_triangles(oo, cc, out=out)
+        assert cc.T == T
+        tc, tl = [], []
+        for _ in range(reps):
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            ev[0].record()
+            cc = aot.count(oo, d, ws=cws, tri_off=tri_off)
+            ev[1].record()
+            aot.list_triangles(oo, cc, out=out)
+            ev[2].record()
+            ev[2].synchronize()
+            tc.append(ev[0].elapsed_time(ev[1]))
+            tl.append(ev[1].elapsed_time(ev[2]))
+        ms_c, ms_l = med(tc), med(tl)
+        dmax = int((oo.rowptr[1:] - oo.rowptr[:-1]).max()) if csr.n else 0
+        res[name] = {"order": order, "strategy": strategy, "probes": cc.probes,
+                     "max_out_degree": dmax, "ms_orient": orient_ms[order],
+                     "ms_count": ms_c, "ms_list": ms_l,
+                     "triangles_per_s": T / ((ms_c + ms_l) / 1000.0)}
+        log(f"[bench] {name}: probes {cc.probes} count {ms_c:.3f} ms list {ms_l:.3f} ms"
+            + (f" (orient {orient_ms[order]:.3f} ms)" if orient_ms[order] else ""))
+    base = res["aot"]["ms_count"] + res["aot"]["ms_list"]
+    for r in res.values():
+        r["aot_speedup"] = (r["ms_count"] + r["ms_list"]) / base
+    del oriented
+    res["note"] = ABLATION_NOTE
+    return res
 
 
 def _time_ms(fn, reps):
@@ -448,6 +519,9 @@ def main():
             f"({streamed['host_GB_per_s']:.1f} GB/s)")
 
     torch.cuda.empty_cache()        # return cached window buffers before the next legs
+    ablation = None
+    if not args.no_ablation and not windowed:
+        ablation = ablation_leg(aot, csr, o, ows, cws, tri_off, out, T, args)
     learned = None
     if not args.no_learned and not args.heavy_arm:
         learned = learned_leg(aot, o, csr, cws, tri_off, list_all, T, probes, args)
@@ -491,6 +565,7 @@ def main():
                                                  "bytes_per_launch", "per_unit")},
         "cpu_baseline": base,
         "learned": learned,
+        "ablation": ablation,
         "batched": batched,
         "streamed": streamed,
     }

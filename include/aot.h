@@ -61,6 +61,7 @@ extern "C" {
                                     costs a segmented sort of m entries, and
                                     makes windows of a very large triangle
                                     list cost about their own triangles     */
+#define AOT_ORDER_CORE 4u     /* rank by the core order instead of degree   */
 
 /* Text for a status code; never NULL. */
 const char* aot_status_str(int status);
@@ -78,7 +79,7 @@ typedef struct aot_graph {
 } aot_graph;
 
 /* Oriented graph in rank space: vertex r is the r-th vertex of the order eta
- * (degree ascending, ties by smaller original id).  All arrays are device
+ * (degree ascending, ties by smaller original id; or the core order).  All arrays are device
  * memory owned by the caller; aot_orient fills them.  m = nnz / 2. */
 typedef struct aot_oriented {
   int32_t n;
@@ -101,7 +102,15 @@ typedef struct aot_oriented {
  * taken ascending in rank space).  Also builds the in-lists that Algorithm 3's
  * second loop walks.
  *   g       input graph (device arrays).
- *   flags   0 or AOT_VALIDATE | AOT_IN_LISTS_BY_RANK.
+ *   flags   0 or AOT_VALIDATE | AOT_IN_LISTS_BY_RANK | AOT_ORDER_CORE.
+ *           AOT_ORDER_CORE: rank by the core (degeneracy) order that kClist
+ *           orients by (Section 2.3) instead of degree; AOT works on any
+ *           total order (Section 3.2).  The order is synchronous peeling:
+ *           sub-round r raises the level to the least current degree left
+ *           if that is larger and removes at once every remaining vertex of
+ *           current degree <= level; ranks follow (sub-round, id).  Then
+ *           deg+(r) <= the degeneracy.  Costs a few launches and one host
+ *           read per 16 sub-rounds.
  *   out     caller-allocated arrays of the sizes listed in aot_oriented;
  *           out->n and out->m are written.
  *   ws      device workspace of at least aot_orient_workspace() bytes.

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libaot.so")
 AOT_OK = 0
 AOT_VALIDATE = 1
 AOT_IN_LISTS_BY_RANK = 2
+AOT_ORDER_CORE = 4
 AOT_DISPATCH_PLAIN = 0
 AOT_DISPATCH_TABLE = 1
 AOT_DISPATCH_LEARNED = 2
@@ -311,8 +312,11 @@ def alloc_oriented(n: int, m: int, device) -> Oriented:
 
 def orient(rowptr: torch.Tensor, col: torch.Tensor, validate: bool = False, stream=None,
            ws: torch.Tensor | None = None, out: Oriented | None = None,
-           in_by_rank: bool = False) -> Oriented:
-    """aot_orient on a symmetric device CSR (rowptr int64[n+1], col int32[nnz])."""
+           in_by_rank: bool = False, order: str = "degree") -> Oriented:
+    """aot_orient on a symmetric device CSR (rowptr int64[n+1], col int32[nnz]);
+    order "degree" (Algorithm 3) or "core" (kClist's, AOT_ORDER_CORE)."""
+    if order not in ("degree", "core"):
+        raise ValueError(f"unknown order {order!r}")
     assert rowptr.dtype == torch.int64 and col.dtype == torch.int32
     assert rowptr.is_contiguous() and col.is_contiguous()
     dev = rowptr.device
@@ -326,7 +330,8 @@ def orient(rowptr: torch.Tensor, col: torch.Tensor, validate: bool = False, stre
         ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
     g = Graph(n, nnz, _ptr(rowptr) or ctypes.c_void_p(rowptr.data_ptr()), _ptr(col))
     oc = o.cstruct()
-    flags = (AOT_VALIDATE if validate else 0) | (AOT_IN_LISTS_BY_RANK if in_by_rank else 0)
+    flags = (AOT_VALIDATE if validate else 0) | (AOT_IN_LISTS_BY_RANK if in_by_rank else 0) | (
+        AOT_ORDER_CORE if order == "core" else 0)
     _check(load().aot_orient(ctypes.byref(g), flags, ctypes.byref(oc),
                              _ptr(ws), ws.numel(), _stream(stream)), "aot_orient")
     return o

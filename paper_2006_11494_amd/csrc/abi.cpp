@@ -185,7 +185,8 @@ int aot_orient_workspace(int32_t n, int64_t nnz, size_t* bytes) {
 int aot_orient(const aot_graph* g, uint32_t flags, aot_oriented* out, void* ws, size_t ws_bytes,
                void* stream) {
   if (!g || !out) return fail(AOT_E_ARG, "graph or output is NULL");
-  if (flags & ~(AOT_VALIDATE | AOT_IN_LISTS_BY_RANK)) return fail(AOT_E_ARG, "unknown flag");
+  if (flags & ~(AOT_VALIDATE | AOT_IN_LISTS_BY_RANK | AOT_ORDER_CORE))
+    return fail(AOT_E_ARG, "unknown flag");
   int rc = check_graph_sizes(g->n, g->nnz);
   if (rc) return rc;
   if (!g->rowptr) return fail(AOT_E_ARG, "rowptr is NULL");
@@ -202,7 +203,8 @@ int aot_orient(const aot_graph* g, uint32_t flags, aot_oriented* out, void* ws, 
   out->m = m;
   const char* err = nullptr;
   rc = aot::orient_run(g->n, g->nnz, g->rowptr, g->col, (flags & AOT_VALIDATE) != 0,
-                       (flags & AOT_IN_LISTS_BY_RANK) != 0, out->rowptr,
+                       (flags & AOT_IN_LISTS_BY_RANK) != 0, (flags & AOT_ORDER_CORE) != 0,
+                       out->rowptr,
                        out->col, out->tail, out->perm, out->rank, out->in_rowptr, out->in_col,
                        ws, ws_bytes, static_cast<hipStream_t>(stream), &err);
   return hip_status(rc, err);

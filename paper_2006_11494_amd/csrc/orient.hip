@@ -33,7 +33,12 @@ enum : int {
   kCRowCursor = 23,   // [23..27]
   kCInCount = 28,     // [28..32] in-lists per sort class
   kCInCursor = 33,    // [33..37]
-  kCounters = 38,
+  kCCoreLevel = 38,   // core order: the peeling level,
+  kCCoreMin = 39,     // the least current degree left (INT32_MAX: none),
+  kCCoreFront = 40,   // the vertices the sub-round removes,
+  kCCoreLeft = 41,    // the vertices not yet removed,
+  kCCoreRound = 42,   // and the sub-round's index
+  kCounters = 43,
 };
 
 constexpr int kSortClasses = 5;     // len <= 16, <= 64, <= 256, <= 4096, longer
@@ -121,6 +126,100 @@ __global__ __launch_bounds__(kBlock) void k_degree(int32_t n, const int64_t* __r
     atomicAdd(&counters[kCDeg16], c16);
     atomicAdd(&counters[kCDeg512], c512);
   }
+}
+
+// ---------------------------------------------------------------- core order
+// kClist orients by the core (degeneracy) order (Section 2.3); here it is
+// taken as synchronous peeling.  Sub-round r raises the level to the least
+// current degree left if that is larger, removes every remaining vertex whose
+// current degree is at most the level (round[v] = r) and takes one off the
+// current degree of each remaining neighbour per removed neighbour.  Sorting
+// by (round, id) then gives every vertex at most `level` out-neighbours.
+// Each sub-round is four launches that do nothing once every vertex is gone,
+// so the host checks progress only every few sub-rounds.
+
+__global__ __launch_bounds__(kBlock) void k_core_init(int32_t n, const int64_t* __restrict__ rowptr,
+                                                      int32_t* __restrict__ cur,
+                                                      int32_t* __restrict__ round,
+                                                      int32_t* __restrict__ vals,
+                                                      int32_t* __restrict__ counters) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    counters[kCCoreLevel] = 0;
+    counters[kCCoreMin] = INT32_MAX;
+    counters[kCCoreFront] = 0;
+    counters[kCCoreLeft] = n;
+    counters[kCCoreRound] = 0;
+  }
+  for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < n;
+       v += (int64_t)gridDim.x * kBlock) {
+    cur[v] = (int32_t)(rowptr[v + 1] - rowptr[v]);
+    round[v] = -1;
+    vals[v] = (int32_t)v;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_core_min(int32_t n, const int32_t* __restrict__ cur,
+                                                     const int32_t* __restrict__ round,
+                                                     int32_t* __restrict__ counters) {
+  int32_t lo = INT32_MAX;
+  for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < n;
+       v += (int64_t)gridDim.x * kBlock)
+    if (round[v] < 0) lo = min(lo, cur[v]);
+  for (int o = kWave / 2; o > 0; o >>= 1) lo = min(lo, __shfl_xor(lo, o, kWave));
+  if (lane_id() == 0 && lo != INT32_MAX) atomicMin(&counters[kCCoreMin], lo);
+}
+
+__global__ __launch_bounds__(kBlock) void k_core_mark(int32_t n, const int32_t* __restrict__ cur,
+                                                      int32_t* __restrict__ round,
+                                                      int32_t* __restrict__ front,
+                                                      int32_t* __restrict__ counters) {
+  const int32_t lo = counters[kCCoreMin];
+  if (lo == INT32_MAX) return;                      // nothing left
+  const int32_t level = max(counters[kCCoreLevel], lo);
+  const int32_t r = counters[kCCoreRound];
+  for (int64_t b0 = (int64_t)blockIdx.x * kBlock; b0 < n; b0 += (int64_t)gridDim.x * kBlock) {
+    const int64_t v = b0 + threadIdx.x;
+    const bool take = v < n && round[v] < 0 && cur[v] <= level;
+    const uint64_t mask = ballot(take);
+    if (!mask) continue;
+    const int leader = __ffsll((long long)mask) - 1;
+    int32_t at = 0;
+    if (lane_id() == leader) at = atomicAdd(&counters[kCCoreFront], (int32_t)__popcll(mask));
+    at = __shfl(at, leader, kWave);
+    if (take) {
+      round[v] = r;
+      front[at + popc_below(mask)] = (int32_t)v;
+    }
+  }
+}
+
+// One wave per removed vertex.
+__global__ __launch_bounds__(kBlock) void k_core_update(const int64_t* __restrict__ rowptr,
+                                                        const int32_t* __restrict__ col,
+                                                        const int32_t* __restrict__ front,
+                                                        const int32_t* __restrict__ round,
+                                                        int32_t* __restrict__ cur,
+                                                        const int32_t* __restrict__ counters) {
+  const int32_t k = counters[kCCoreFront];
+  const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
+  for (int64_t i = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kWave; i < k; i += nwaves) {
+    const int32_t v = front[i];
+    for (int64_t e = rowptr[v] + lane_id(); e < rowptr[v + 1]; e += kWave) {
+      const int32_t x = col[e];
+      if (round[x] < 0) atomicSub(&cur[x], 1);
+    }
+  }
+}
+
+__global__ void k_core_step(int32_t* __restrict__ counters) {
+  if (threadIdx.x != 0) return;
+  const int32_t lo = counters[kCCoreMin];
+  const int32_t k = counters[kCCoreFront];
+  if (lo != INT32_MAX && lo > counters[kCCoreLevel]) counters[kCCoreLevel] = lo;
+  counters[kCCoreLeft] -= k;
+  if (k > 0) counters[kCCoreRound] += 1;
+  counters[kCCoreFront] = 0;
+  counters[kCCoreMin] = INT32_MAX;
 }
 
 __global__ __launch_bounds__(kBlock) void k_perm_rank(int32_t n, const int32_t* __restrict__ sorted_ids,
@@ -637,8 +736,42 @@ struct BatchKeys {
   int dbits, bits;
 };
 
+constexpr int kCoreBatch = 16;      // sub-rounds launched between progress checks
+
+// round[v] of the core order into keys, ids into vals; *rounds = sub-rounds.
+// cur and front are n-entry scratch arrays.
+int core_order(int32_t n, const int64_t* rowptr, const int32_t* col, int32_t* keys, int32_t* vals,
+               int32_t* cur, int32_t* front, int32_t* counters, int32_t* rounds, hipStream_t s,
+               const char** err) {
+  const unsigned gv = std::min(grid_for(n, kBlock), 2048u);
+  k_core_init<<<gv, kBlock, 0, s>>>(n, rowptr, cur, keys, vals, counters);
+  AOT_TRY(hipGetLastError());
+  int32_t left = n;
+  while (left > 0) {
+    for (int b = 0; b < kCoreBatch; ++b) {
+      k_core_min<<<gv, kBlock, 0, s>>>(n, cur, keys, counters);
+      k_core_mark<<<gv, kBlock, 0, s>>>(n, cur, keys, front, counters);
+      k_core_update<<<2048, kBlock, 0, s>>>(rowptr, col, front, keys, cur, counters);
+      k_core_step<<<1, 64, 0, s>>>(counters);
+      AOT_TRY(hipGetLastError());
+    }
+    int32_t hc[2];
+    AOT_TRY(hipMemcpyAsync(hc, counters + kCCoreLeft, sizeof(hc), hipMemcpyDeviceToHost, s));
+    AOT_TRY(hipStreamSynchronize(s));
+    // every sub-round with vertices left removes at least the one of least degree
+    if (hc[0] >= left) {
+      *err = "core peeling made no progress";
+      return -5;
+    }
+    left = hc[0];
+    *rounds = hc[1];
+  }
+  return 0;
+}
+
 int orient_impl(int32_t n, int64_t nnz, const int64_t* rowptr, const int32_t* col, bool validate,
-                bool in_by_rank, const BatchKeys* bk, int64_t* orow, int32_t* ocol, int32_t* otail,
+                bool in_by_rank, bool core, const BatchKeys* bk, int64_t* orow, int32_t* ocol,
+                int32_t* otail,
                 int32_t* perm, int32_t* rank, int64_t* irow, int32_t* icol, void* ws,
                 size_t ws_bytes, hipStream_t s, const char** err) {
   const int64_t m = nnz / 2;
@@ -689,7 +822,16 @@ int orient_impl(int32_t n, int64_t nnz, const int64_t* rowptr, const int32_t* co
   }
   int bits;
   int32_t c0 = 0, c4 = 0, c16 = 0, c512 = 0;
-  if (!bk) {
+  // rank order is degree order only for the plain single-graph case; the
+  // others process rows from lists built on the device
+  const bool lists = bk || core;
+  if (core) {
+    int32_t rounds = 0;
+    const int rc = core_order(n, rowptr, col, key_a, val_a, dplus, dminus, counters, &rounds, s,
+                              err);
+    if (rc) return rc;
+    bits = ceil_log2((int64_t)rounds + 1);
+  } else if (!bk) {
     k_degree<<<std::min(grid_for(n, kBlock), 1024u), kBlock, 0, s>>>(n, rowptr, key_a, val_a,
                                                                      counters);
     AOT_TRY(hipGetLastError());
@@ -718,12 +860,12 @@ int orient_impl(int32_t n, int64_t nnz, const int64_t* rowptr, const int32_t* co
   for (int q = 0; q < 4; ++q) {
     sets[q].r0 = cuts[q];
     sets[q].r1 = cuts[q + 1];
-    sets[q].rows = bk ? rows : nullptr;
+    sets[q].rows = lists ? rows : nullptr;
     sets[q].counters = counters;
     sets[q].cls = q;
-    bound[q] = bk ? (int64_t)n : (int64_t)cuts[q + 1] - cuts[q];
+    bound[q] = lists ? (int64_t)n : (int64_t)cuts[q + 1] - cuts[q];
   }
-  if (bk) {
+  if (lists) {
     AOT_TRY(fill_i32(dplus, n, 0, s));
     AOT_TRY(fill_i32(dminus, n, 0, s));
     k_count_classes<kRowsByDegree><<<std::min(grid_for(n, kBlock), 1024u), kBlock, 0, s>>>(
@@ -782,11 +924,11 @@ int orient_impl(int32_t n, int64_t nnz, const int64_t* rowptr, const int32_t* co
 }  // namespace
 
 int orient_run(int32_t n, int64_t nnz, const int64_t* rowptr, const int32_t* col, bool validate,
-               bool in_by_rank, int64_t* orow, int32_t* ocol, int32_t* otail, int32_t* perm,
-               int32_t* rank, int64_t* irow, int32_t* icol, void* ws, size_t ws_bytes,
-               hipStream_t s, const char** err) {
-  return orient_impl(n, nnz, rowptr, col, validate, in_by_rank, nullptr, orow, ocol, otail, perm, rank, irow,
-                     icol, ws, ws_bytes, s, err);
+               bool in_by_rank, bool core, int64_t* orow, int32_t* ocol, int32_t* otail,
+               int32_t* perm, int32_t* rank, int64_t* irow, int32_t* icol, void* ws,
+               size_t ws_bytes, hipStream_t s, const char** err) {
+  return orient_impl(n, nnz, rowptr, col, validate, in_by_rank, core, nullptr, orow, ocol, otail,
+                     perm, rank, irow, icol, ws, ws_bytes, s, err);
 }
 
 int orient_batch_run(int32_t n, int64_t nnz, const int64_t* rowptr, const int32_t* col,
@@ -794,7 +936,8 @@ int orient_batch_run(int32_t n, int64_t nnz, const int64_t* rowptr, const int32_
                      int32_t* ocol, int32_t* otail, int32_t* perm, int32_t* rank, int64_t* irow,
                      int32_t* icol, void* ws, size_t ws_bytes, hipStream_t s, const char** err) {
   BatchKeys bk{voff, count, dbits, dbits + gbits};
-  return orient_impl(n, nnz, rowptr, col, false, false, &bk, orow, ocol, otail, perm, rank, irow,
+  return orient_impl(n, nnz, rowptr, col, false, false, false, &bk, orow, ocol, otail, perm, rank,
+                     irow,
                      icol,
                      ws, ws_bytes, s, err);
 }

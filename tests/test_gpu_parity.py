@@ -48,9 +48,9 @@ DISPATCHES = {
 }
 
 
-def reference(csr):
+def reference(csr, order="degree"):
     rp, col = csr.numpy()
-    o = oracle.orient(rp, col)
+    o = oracle.orient(rp, col, order)
     irow, icol, ieid = oracle.in_lists(o)
     return o, irow, icol, ieid
 
@@ -79,20 +79,20 @@ def check_orientation(o_gpu, ref, in_by_rank=False):
     assert np.all(ids[1:][same_row] > ids[:-1][same_row])
 
 
-def check_all(csr, name, dispatches=DISPATCHES, windows=True):
+def check_all(csr, name, dispatches=DISPATCHES, windows=True, order="degree"):
     need_gpu()
-    ref = reference(csr)
+    ref = reference(csr, order)
     o_ref = ref[0]
     cnt_ref = oracle.edge_counts(o_ref)
     T = int(cnt_ref.sum())
     probes = oracle.sum_min(o_ref)
     tri_ref = oracle.list_triangles(o_ref)
     g = csr.to(DEV)
-    say(f"[gpu] orient {name} n={csr.n} m={csr.m}")
-    o = aot.orient(g.rowptr, g.col, validate=True)
+    say(f"[gpu] orient {name} n={csr.n} m={csr.m} order={order}")
+    o = aot.orient(g.rowptr, g.col, validate=True, order=order)
     torch.cuda.synchronize()
     check_orientation(o, ref)
-    ob = aot.orient(g.rowptr, g.col, in_by_rank=True)
+    ob = aot.orient(g.rowptr, g.col, in_by_rank=True, order=order)
     torch.cuda.synchronize()
     check_orientation(ob, ref, in_by_rank=True)
     for dname, d in dispatches.items():
