@@ -56,6 +56,8 @@ def _load():
     lib.orc_sum_min.restype = u64
     lib.orc_sum_head.argtypes = [i32, _i64p, _i32p]
     lib.orc_sum_head.restype = u64
+    lib.orc_edge_support.argtypes = [i32, _i64p, _i32p, _i64p, _i32p, _i32p, _i32p]
+    lib.orc_edge_support.restype = None
     lib.orc_core_rounds.argtypes = [i32, _i64p, _i32p, _i32p, ctypes.POINTER(i32)]
     lib.orc_core_rounds.restype = i32
     lib.orc_orient_core.argtypes = [i32, _i64p, _i32p, _i32p, _i32p, _i64p, _i32p]
@@ -208,6 +210,15 @@ def vertex_triangles(rowptr, col, vs) -> np.ndarray:
     if vs.size:
         lib.orc_vertex_triangles(rowptr, _nonempty(col), vs, vs.size, out)
     return out[: vs.size]
+
+
+def edge_support(rowptr, col, o: Oriented) -> np.ndarray:
+    """Triangles through each oriented edge of o (in o's edge order): the
+    A^2 entry of its endpoints, from the input's full rows."""
+    rowptr, col = _arrays(rowptr, col)
+    sup = np.empty(max(o.m, 1), np.int32)
+    _load().orc_edge_support(o.n, rowptr, col, o.orow, _nonempty(o.ocol), _nonempty(o.perm), sup)
+    return sup[:o.m]
 
 
 def core_rounds(rowptr, col):

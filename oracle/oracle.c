@@ -235,6 +235,20 @@ static int64_t merge_count(const int32_t* a, int64_t na, const int32_t* b, int64
   return c;
 }
 
+/* Support of every oriented edge e = <r, x> (rank space): the number of
+ * triangles through it, |N(u) n N(v)| over the full neighbourhoods of its
+ * original endpoints u = perm[r], v = perm[x] (an entry of A^2), by merging
+ * the two sorted rows of the input. */
+void orc_edge_support(int32_t n, const int64_t* rowptr, const int32_t* col, const int64_t* orow,
+                      const int32_t* ocol, const int32_t* perm, int32_t* sup) {
+  for (int32_t r = 0; r < n; ++r)
+    for (int64_t e = orow[r]; e < orow[r + 1]; ++e) {
+      int32_t u = perm[r], v = perm[ocol[e]];
+      sup[e] = (int32_t)merge_count(col + rowptr[u], rowptr[u + 1] - rowptr[u],
+                                    col + rowptr[v], rowptr[v + 1] - rowptr[v]);
+    }
+}
+
 /* Source (rank) of directed edge e: the row r with orow[r] <= e < orow[r+1]. */
 static int32_t edge_tail(int32_t n, const int64_t* orow, int64_t e) {
   int32_t lo = 0, hi = n - 1;

@@ -477,3 +477,45 @@ def test_core_order_lists_the_same_set(seed):
     assert int(oracle.edge_counts(b).sum()) == len(ta)
     _, _, d = oracle.core_rounds(rp, col)
     assert b.dplus.max() == d <= a.dplus.max()
+
+
+# ---------------------------------------------------------------- edge support
+
+@pytest.mark.parametrize("seed", range(6))
+def test_edge_support_is_a_squared(seed):
+    """Triangles through edge {u,v} = (A^2)_uv; they sum to 3T."""
+    rng = np.random.default_rng(100 + seed)
+    n = int(rng.integers(5, 60))
+    p = float(rng.choice([0.1, 0.3, 0.6]))
+    A = np.triu(rng.random((n, n)) < p, 1)
+    A = (A | A.T).astype(np.int64)
+    iu, ju = np.nonzero(np.triu(A, 1))
+    rp, col = graph(n, zip(iu.tolist(), ju.tolist())).numpy()
+    o = oracle.orient(rp, col)
+    sup = oracle.edge_support(rp, col, o)
+    A2 = A @ A
+    u = o.perm[o.tail()]
+    v = o.perm[o.ocol]
+    assert np.array_equal(sup, A2[u, v])
+    assert int(sup.sum()) == 3 * len(oracle.list_triangles(o)) == int(np.trace(A2 @ A)) // 2
+
+
+def test_edge_support_closed_forms():
+    # K_n: every edge lies in n - 2 triangles
+    rp, col = graph(9, itertools.combinations(range(9), 2)).numpy()
+    o = oracle.orient(rp, col)
+    assert set(oracle.edge_support(rp, col, o).tolist()) == {7}
+    # wheel with hub 0 and rim 1..8: spokes lie in 2 triangles, rim edges in 1
+    n = 9
+    e = [(0, i) for i in range(1, n)] + [(i, i % (n - 1) + 1) for i in range(1, n)]
+    rp, col = graph(n, e).numpy()
+    o = oracle.orient(rp, col)
+    sup = oracle.edge_support(rp, col, o)
+    spoke = (o.perm[o.tail()] == 0) | (o.perm[o.ocol] == 0)
+    assert set(sup[spoke].tolist()) == {2} and set(sup[~spoke].tolist()) == {1}
+    # the core order relabels, the support of each undirected edge stays
+    oc = oracle.orient(rp, col, "core")
+    key = lambda oo: {tuple(sorted(t)): s for t, s in zip(
+        zip(oo.perm[oo.tail()].tolist(), oo.perm[oo.ocol].tolist()),
+        oracle.edge_support(rp, col, oo).tolist())}
+    assert key(o) == key(oc)
