@@ -256,6 +256,24 @@ int aot_digest(const aot_oriented* g, const aot_dispatch* d, const int64_t* tri_
                void* stream);
 
 /* ------------------------------------------------------------------------
+ * aot_support -- the triangle counts that analyses built on triangle listing
+ * consume (Section 1: clustering, truss-like cohesion), from the same write
+ * pass in digest mode: every triangle found adds one to each of its three
+ * oriented edges and, optionally, to each of its three vertices.
+ *   tri_off, ws    from a prior aot_count on the same graph (any strategy).
+ *   edge_support   device uint32[m], overwritten: for oriented edge e (index
+ *                  into g->col), the number of triangles through it, i.e.
+ *                  |N(u) n N(v)| of its endpoints.  They sum to 3T.
+ *   vertex_counts  device uint64[n] or NULL: triangles through each ORIGINAL
+ *                  vertex id (as aot_digest); local clustering coefficient of
+ *                  v = 2 t(v) / (deg(v) (deg(v) - 1)).
+ *   digest         host uint64[3] or NULL: as aot_digest.
+ * Synchronises `stream`. */
+int aot_support(const aot_oriented* g, const aot_dispatch* d, const int64_t* tri_off, void* ws,
+                size_t ws_bytes, uint32_t* edge_support, uint64_t* vertex_counts,
+                uint64_t* digest, void* stream);
+
+/* ------------------------------------------------------------------------
  * Batches of graphs.  Many (small, uneven) graphs are listed as one: their
  * CSRs sit in one arena, the block-diagonal union, and one pass of
  * orientation, binning, count, scan and write covers all of them.  Graph g

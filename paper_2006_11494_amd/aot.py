@@ -38,7 +38,7 @@ EXPORTS = (
     "aot_status_str", "aot_last_error", "aot_version",
     "aot_orient_workspace", "aot_orient",
     "aot_count_workspace", "aot_count",
-    "aot_list", "aot_digest", "aot_count_plan", "aot_bucket_features",
+    "aot_list", "aot_digest", "aot_support", "aot_count_plan", "aot_bucket_features",
     "aot_mlp_param_count", "aot_mlp_workspace", "aot_mlp_init", "aot_mlp_forward",
     "aot_mlp_loss_grad", "aot_mlp_train",
     "aot_timing_start", "aot_timing_stop",
@@ -123,6 +123,8 @@ def load(path: str = LIB_PATH):
                              ctypes.c_size_t, i64, i64, vp, ctypes.POINTER(ctypes.c_int64), vp]
     lib.aot_digest.argtypes = [ctypes.POINTER(OrientedC), ctypes.POINTER(DispatchC), vp, vp,
                                ctypes.c_size_t, vp, ctypes.POINTER(ctypes.c_uint64), vp]
+    lib.aot_support.argtypes = [ctypes.POINTER(OrientedC), ctypes.POINTER(DispatchC), vp, vp,
+                                ctypes.c_size_t, vp, vp, ctypes.POINTER(ctypes.c_uint64), vp]
     lib.aot_count_plan.argtypes = [vp, ctypes.c_size_t, i32, i64, ctypes.POINTER(i32),
                                    ctypes.POINTER(i32)]
     lib.aot_bucket_features.argtypes = [vp, ctypes.c_size_t, i32, i64,
@@ -381,6 +383,21 @@ def digest(o: Oriented, c: Counted, vertex_counts: bool = True,
     _check(load().aot_digest(ctypes.byref(oc), ctypes.byref(dc), _ptr(c.tri_off), _ptr(c.ws),
                              c.ws.numel(), _ptr(vc), res, _stream(stream)), "aot_digest")
     return (int(res[0]), int(res[1]), int(res[2])), (vc[:o.n] if vc is not None else None)
+
+
+def support(o: Oriented, c: Counted, vertex_counts: bool = True, stream=None):
+    """aot_support: triangles through each oriented edge (int32 device
+    tensor [m], in the edge order of o.col), through each original vertex
+    (int64 device tensor [n] or None) and the digest (T, hash sum, hash xor)."""
+    dev = o.rowptr.device
+    es = torch.empty(max(o.m, 1), dtype=torch.int32, device=dev)
+    vc = torch.empty(max(o.n, 1), dtype=torch.int64, device=dev) if vertex_counts else None
+    res = (ctypes.c_uint64 * 3)()
+    oc = o.cstruct()
+    _check(load().aot_support(ctypes.byref(oc), None, _ptr(c.tri_off), _ptr(c.ws), c.ws.numel(),
+                              _ptr(es), _ptr(vc), res, _stream(stream)), "aot_support")
+    return es[:o.m], (vc[:o.n] if vc is not None else None), (int(res[0]), int(res[1]),
+                                                               int(res[2]))
 
 
 def count_plan(o: Oriented, c: Counted):

@@ -281,6 +281,25 @@ int aot_digest(const aot_oriented* g, const aot_dispatch* d, const int64_t* tri_
   return hip_status(rc, err);
 }
 
+int aot_support(const aot_oriented* g, const aot_dispatch* d, const int64_t* tri_off, void* ws,
+                size_t ws_bytes, uint32_t* edge_support, uint64_t* vertex_counts,
+                uint64_t* digest, void* stream) {
+  int rc = check_oriented(g);
+  if (rc) return rc;
+  if (!tri_off) return fail(AOT_E_ARG, "tri_off is NULL");
+  if (g->m > 0 && !edge_support) return fail(AOT_E_ARG, "edge_support is NULL");
+  aot::DispatchView dv;
+  rc = check_dispatch(d, &dv);
+  if (rc) return rc;
+  const size_t need = aot::count_workspace_bytes(g->n, g->m);
+  if (ws_bytes < need || !ws) return fail(AOT_E_WORKSPACE, "count workspace smaller than aot_count_workspace()");
+  const char* err = nullptr;
+  rc = aot::support_run(g->n, g->m, g->rowptr, g->col, g->tail, g->perm, g->in_rowptr, g->in_col,
+                        dv, tri_off, ws, ws_bytes, edge_support, vertex_counts, digest,
+                        static_cast<hipStream_t>(stream), &err);
+  return hip_status(rc, err);
+}
+
 int aot_count_plan(const void* ws, size_t ws_bytes, int32_t n, int64_t m, int32_t* table,
                    int32_t* learned) {
   if (!ws || !table || !learned || n < 0 || m < 0) return fail(AOT_E_ARG, "bad argument");

@@ -488,9 +488,17 @@ struct HeavyArgs {
   int32_t y_lo, y_hi;           // the rows of its first and last edge
   int32_t* out;
   unsigned long long* digest;   // write pass in digest mode: {triangles, hash sum, hash xor}
-  unsigned long long* vcount;   // digest mode, optional: per-vertex triangle counts
+  uint32_t* esup = nullptr;     // digest mode, optional: per-edge support
   int32_t head = 0;             // fixed orientation: b owns its out-edges only
 };
+
+// Digest mode with per-edge support: a triangle adds one to each of its three
+// oriented edges (ids = indices into the out-lists).
+__device__ __forceinline__ void add_support(uint32_t* esup, int64_t e0, int64_t e1, int64_t e2) {
+  atomicAdd(&esup[e0], 1u);
+  atomicAdd(&esup[e1], 1u);
+  atomicAdd(&esup[e2], 1u);
+}
 
 // SplitMix64's output function (Steele, Lea and Flood, 2014) on state z.
 __device__ __forceinline__ uint64_t splitmix64(uint64_t z) {
@@ -537,18 +545,10 @@ __device__ void flush_digest(const Digest& d, unsigned long long* out) {
   }
 }
 
-// Where an emitted triangle goes: the output window, or the digest.
-template <bool kDigest>
-__device__ __forceinline__ void sink(const HeavyArgs& a, Digest& dg, int64_t pos, int32_t t0,
-                                     int32_t t1, int32_t t2) {
-  if constexpr (kDigest) {
-    dg.add(t0, t1, t2);
-    if (a.vcount) {
-      atomicAdd(&a.vcount[t0], 1ull);
-      atomicAdd(&a.vcount[t1], 1ull);
-      atomicAdd(&a.vcount[t2], 1ull);
-    }
-  } else if (pos >= a.first && pos < a.first + a.count) {
+// Write pass: a triangle at global index pos is stored if the window holds it.
+__device__ __forceinline__ void store(const HeavyArgs& a, int64_t pos, int32_t t0, int32_t t1,
+                                      int32_t t2) {
+  if (pos >= a.first && pos < a.first + a.count) {
     int32_t* o = a.out + 3 * (pos - a.first);
     o[0] = t0; o[1] = t1; o[2] = t2;
   }
@@ -750,11 +750,24 @@ __device__ void probe_emit(HeavyShared<true>& sh, const uint32_t* lds, const Hea
         const uint64_t hm = ballot(hit[u]);
         if (hit[u]) {
           const int32_t t = third[u];
-          sink<kDigest>(a, dg, base + before + popc_below(hm), min(lo, t), max(lo, min(hi, t)),
+          if constexpr (kDigest) {
+            // the edge {b, y} is the same for the whole run: its count is
+            // added once below; here <y, w> (the probed entry) and <b, w>
+            dg.add(min(lo, t), max(lo, min(hi, t)), max(hi, t));
+            if (a.esup) {
+              atomicAdd(&a.esup[sh.nb_src[ka] + w0 + u * kWave + lane_id()], 1u);
+              atomicAdd(&a.esup[(ix.list - a.ocol) + lower_bound(ix.list, ix.len, cur.wv[u])],
+                        1u);
+            }
+          } else {
+            store(a, base + before + popc_below(hm), min(lo, t), max(lo, min(hi, t)),
                         max(hi, t));
+          }
         }
         before += (int)__popcll(hm);
       }
+      if constexpr (kDigest)
+        if (a.esup && lane_id() == 0 && before) atomicAdd(&a.esup[sh.nb_e[ka]], (uint32_t)before);
       run += before;
       continue;
     }
@@ -784,9 +797,17 @@ __device__ void probe_emit(HeavyShared<true>& sh, const uint32_t* lds, const Hea
         run_k = k1;
       }
       if (hit[u]) {
-        int32_t t0 = pb, t1 = sh.nb_py[k], t2 = third[u];
+        const int32_t py = sh.nb_py[k];
+        int32_t t0 = pb, t1 = py, t2 = third[u];
         sort3(t0, t1, t2);
-        sink<kDigest>(a, dg, pos, t0, t1, t2);
+        if constexpr (kDigest) {
+          dg.add(t0, t1, t2);
+          if (a.esup)
+            add_support(a.esup, sh.nb_e[k], sh.nb_src[k] + w0 + u * kWave + lane_id(),
+                        (ix.list - a.ocol) + lower_bound(ix.list, ix.len, cur.wv[u]));
+        } else {
+          store(a, pos, t0, t1, t2);
+        }
       }
     }
   }
@@ -1016,22 +1037,19 @@ struct LightArgs {
   int64_t first, count;
   int32_t* out;
   unsigned long long* digest;   // write pass in digest mode
-  unsigned long long* vcount;
+  uint32_t* esup = nullptr;     // digest mode, optional: per-edge support
   int32_t head = 0;             // fixed orientation (edge_ends)
 };
 
-// One triangle of the write pass (t0, t1, t2: original ids) at global index at.
+// One triangle of edge {pu, pv} with third vertex pw (original ids) at global
+// index at: stored, or digested.
 template <bool kDigest>
-__device__ __forceinline__ void light_sink(const LightArgs& a, Digest& dg, int64_t at, int32_t t0,
-                                           int32_t t1, int32_t t2) {
+__device__ __forceinline__ void light_sink(const LightArgs& a, Digest& dg, int64_t at, int32_t pu,
+                                           int32_t pv, int32_t pw) {
+  int32_t t0 = pu, t1 = pv, t2 = pw;
   sort3(t0, t1, t2);
   if constexpr (kDigest) {
     dg.add(t0, t1, t2);
-    if (a.vcount) {
-      atomicAdd(&a.vcount[t0], 1ull);
-      atomicAdd(&a.vcount[t1], 1ull);
-      atomicAdd(&a.vcount[t2], 1ull);
-    }
   } else if (at >= a.first && at < a.first + a.count) {
     int32_t* o = a.out + 3 * (at - a.first);
     o[0] = t0; o[1] = t1; o[2] = t2;
@@ -1049,8 +1067,9 @@ __device__ __forceinline__ void light_range(const LightArgs& a, int64_t t0, int6
     const int32_t e = a.elist[t];
     const int32_t u = a.otail[e], v = a.ocol[e];
     const EdgeEnds x = edge_ends(a.orow, u, v, a.head != 0);
-    const int32_t* ps = a.ocol + a.orow[x.s];
-    const int32_t* pb = a.ocol + a.orow[x.b];
+    const int64_t os = a.orow[x.s], ob = a.orow[x.b];
+    const int32_t* ps = a.ocol + os;
+    const int32_t* pb = a.ocol + ob;
     if constexpr (!kEmit) {
       int32_t hits = 0;
       for (int32_t q = li; q < x.c; q += G) hits += contains_sorted(pb, x.db, ps[q]);
@@ -1062,13 +1081,24 @@ __device__ __forceinline__ void light_range(const LightArgs& a, int64_t t0, int6
       const int64_t end = a.tri_off[e + 1];
       if (pos == end || (!kDigest && (end <= a.first || pos >= a.first + a.count))) continue;
       const int32_t pu = a.perm[u], pv = a.perm[v];
+      // digest mode: the edge's own triangles (other triangles add to it too)
+      if constexpr (kDigest)
+        if (a.esup && li == 0) atomicAdd(&a.esup[e], (uint32_t)(end - pos));
       for (int32_t q0 = 0; q0 < x.c; q0 += G) {
         const int32_t q = q0 + li;
         const int32_t w = q < x.c ? ps[q] : 0;
-        const bool hit = q < x.c && contains_sorted(pb, x.db, w);
+        const int64_t j = q < x.c ? lower_bound(pb, x.db, w) : x.db;
+        const bool hit = j < x.db && pb[j] == w;
         const uint64_t mask = ballot(hit);
         const int64_t at = pos + popc_below_in_group<G>(mask);
-        if (hit) light_sink<kDigest>(a, dg, at, pu, pv, a.perm[w]);
+        if (hit) {
+          light_sink<kDigest>(a, dg, at, pu, pv, a.perm[w]);
+          if constexpr (kDigest)
+            if (a.esup) {
+              atomicAdd(&a.esup[os + q], 1u);
+              atomicAdd(&a.esup[ob + j], 1u);
+            }
+        }
         pos += __popcll(group_bits<G>(mask));
       }
     }
@@ -1092,10 +1122,10 @@ __device__ __forceinline__ void merge_range(const LightArgs& a, int64_t t0, int6
     const int32_t du = (int32_t)(a.orow[u + 1] - ou), dv = (int32_t)(a.orow[v + 1] - ov);
     const int32_t* A = a.ocol + ou;
     const int32_t* B = a.ocol + ov;
-    int64_t pos = 0;
+    int64_t pos = 0, end = 0;
     if constexpr (kEmit) {
       pos = a.tri_off[e];
-      const int64_t end = a.tri_off[e + 1];
+      end = a.tri_off[e + 1];
       if (pos == end || (!kDigest && (end <= a.first || pos >= a.first + a.count))) continue;
     }
     const int32_t per = (du + G - 1) / G;
@@ -1115,9 +1145,18 @@ __device__ __forceinline__ void merge_range(const LightArgs& a, int64_t t0, int6
     } else {
       int64_t at = pos + group_exclusive_sum<G>(hits);
       const int32_t pu = a.perm[u], pv = a.perm[v];
+      if constexpr (kDigest)
+        if (a.esup && li == 0) atomicAdd(&a.esup[e], (uint32_t)(end - pos));
       for (int32_t i = i0, j = j0; i < i1 && j < dv;) {
         const int32_t x = A[i], y = B[j];
-        if (x == y) light_sink<kDigest>(a, dg, at++, pu, pv, a.perm[x]);
+        if (x == y) {
+          light_sink<kDigest>(a, dg, at++, pu, pv, a.perm[x]);
+          if constexpr (kDigest)
+            if (a.esup) {
+              atomicAdd(&a.esup[ou + i], 1u);
+              atomicAdd(&a.esup[ov + j], 1u);
+            }
+        }
         i += x <= y;
         j += y <= x;
       }
@@ -1513,8 +1552,8 @@ int run_buckets(bool emit, const Plan& plan, const int64_t* hs, const CountWs& w
                 const int64_t* orow, const int32_t* ocol, const int32_t* otail,
                 const int32_t* perm, const int64_t* irow, const int32_t* icol,
                 const int64_t* tri_off, int64_t first, int64_t count, int32_t* out,
-                unsigned long long* digest, unsigned long long* vcount, const int64_t* win,
-                int strategy, hipStream_t s, const char** err) {
+                unsigned long long* digest, uint32_t* esup,
+                const int64_t* win, int strategy, hipStream_t s, const char** err) {
   const bool merge = strategy == kStratMerge;
   int64_t lbase = 0;
   for (int k = 0; k < kLightBins; ++k) {
@@ -1533,7 +1572,7 @@ int run_buckets(bool emit, const Plan& plan, const int64_t* hs, const CountWs& w
       la.elist = w.elist; la.orow = orow; la.ocol = ocol; la.otail = otail;
       la.cnt = emit ? nullptr : w.cnt;
       la.tri_off = tri_off; la.perm = perm; la.first = first; la.count = count; la.out = out;
-      la.digest = digest; la.vcount = vcount;
+      la.digest = digest; la.esup = esup;
       la.head = strategy == kStratHead;
       const hipError_t e =
           emit ? (digest ? launch_light<true, true>(tile, grid, la, b0, edges, nullptr, merge, s)
@@ -1571,7 +1610,7 @@ int run_buckets(bool emit, const Plan& plan, const int64_t* hs, const CountWs& w
     a.y_hi = win ? (int32_t)win[kWinWords - 1] : INT32_MAX;
     a.out = out;
     a.digest = digest;
-    a.vcount = vcount;
+    a.esup = esup;
     a.head = strategy == kStratHead;
     const int rec = timing_begin(emit ? 1 : 0, kHeavyBase + h, arm, kBlock, st[kSEdges],
                                  st[kSProbes], st[kSStaged], st[kSTriangles], s);
@@ -1764,12 +1803,11 @@ int drain_run(int32_t n, int64_t m, const int64_t* orow, const int32_t* ocol,
   ha.y_hi = INT32_MAX;
   ha.out = out;
   ha.digest = nullptr;
-  ha.vcount = nullptr;
   LightArgs la;
   la.elist = w.elist; la.orow = orow; la.ocol = ocol; la.otail = otail;
   la.cnt = w.cnt;
   la.tri_off = tri_off; la.perm = perm; la.first = first; la.count = count; la.out = out;
-  la.digest = nullptr; la.vcount = nullptr;
+  la.digest = nullptr;
   unsigned gh0, gh1, gl0, gl1;
   if (resident_grid(k_heavy_drain<false>, dyn, &gh0) || resident_grid(k_heavy_drain<true>, dyn, &gh1) ||
       resident_grid(k_light_drain<false>, 0, &gl0) || resident_grid(k_light_drain<true>, 0, &gl1)) {
@@ -1811,11 +1849,45 @@ int batch_totals(int32_t count, const int64_t* voff, const int64_t* orow, const 
 
 namespace {
 
+// Per-vertex counts from per-edge support: each triangle through v has two
+// of its edges at v, so t(v) is half the support summed over v's edges.
+// Tail side: one wave per out-list, stored; head side: one atomic per edge.
+__global__ __launch_bounds__(kBlock) void k_vertex_tail(int32_t n, const int64_t* __restrict__ orow,
+                                                        const uint32_t* __restrict__ sup,
+                                                        const int32_t* __restrict__ perm,
+                                                        unsigned long long* __restrict__ vcount) {
+  const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
+  for (int64_t r = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kWave; r < n; r += nwaves) {
+    uint64_t acc = 0;
+    for (int64_t e = orow[r] + lane_id(); e < orow[r + 1]; e += kWave) acc += sup[e];
+    acc = wave_sum(acc);
+    if (lane_id() == 0) vcount[perm[r]] = acc;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_vertex_head(int64_t m, const int32_t* __restrict__ ocol,
+                                                        const uint32_t* __restrict__ sup,
+                                                        const int32_t* __restrict__ perm,
+                                                        unsigned long long* __restrict__ vcount) {
+  for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < m;
+       e += (int64_t)gridDim.x * kBlock) {
+    const uint32_t c = sup[e];
+    if (c) atomicAdd(&vcount[perm[ocol[e]]], (unsigned long long)c);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_vertex_halve(int32_t n,
+                                                         unsigned long long* __restrict__ vcount) {
+  for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < n;
+       v += (int64_t)gridDim.x * kBlock)
+    vcount[v] >>= 1;
+}
+
 int emit_run(int32_t n, int64_t m, const int64_t* orow, const int32_t* ocol, const int32_t* otail,
              const int32_t* perm, const int64_t* irow, const int32_t* icol, const DispatchView& d,
              const int64_t* tri_off, void* ws, size_t ws_bytes, int64_t first, int64_t count,
-             int32_t* out, bool digest_mode, uint64_t* vcount, uint64_t* digest_host, hipStream_t s,
-             const char** err) {
+             int32_t* out, bool digest_mode, uint64_t* vcount, uint32_t* esup,
+             uint64_t* digest_host, hipStream_t s, const char** err) {
   Carve c(ws, ws_bytes);
   CountWs w = carve_count(c, n, m);
   if (!c.ok()) {
@@ -1830,9 +1902,12 @@ int emit_run(int32_t n, int64_t m, const int64_t* orow, const int32_t* ocol, con
   const bool stored = !d.given || d.model;     // use the plan the count resolved
   unsigned long long* dg = digest_mode ? w.digest : nullptr;
   unsigned long long* vc = reinterpret_cast<unsigned long long*>(vcount);
+  // vertex counts come from edge support: the caller's array, or the count
+  // pass's per-edge counts (no longer needed once tri_off is scanned)
+  uint32_t* sup = esup ? esup : vc ? reinterpret_cast<uint32_t*>(w.cnt) : nullptr;
   if (digest_mode) {
     AOT_TRY(fill_i64(reinterpret_cast<int64_t*>(w.digest), 4, 0, s));
-    if (vc) AOT_TRY(fill_i64(reinterpret_cast<int64_t*>(vc), n, 0, s));
+    if (sup) AOT_TRY(fill_i32(reinterpret_cast<int32_t*>(sup), m, 0, s));
   }
   if (m > 0 && (digest_mode || count > 0)) {
     std::vector<int64_t> hs(kStatWords, 0);
@@ -1859,17 +1934,29 @@ int emit_run(int32_t n, int64_t m, const int64_t* orow, const int32_t* ocol, con
       return -4;
     }
     const int rc = run_buckets(true, plan, hs.data(), w, orow, ocol, otail, perm, irow, icol,
-                               tri_off, first, count, out, dg, vc, digest_mode ? nullptr : win,
-                               strategy, s, err);
+                               tri_off, first, count, out, dg, sup,
+                               digest_mode ? nullptr : win, strategy, s, err);
     if (rc) return rc;
+  }
+  if (digest_mode && vc && n > 0) {
+    k_vertex_tail<<<grid_cap(cdiv(n, kWavesPerBlock)), kBlock, 0, s>>>(n, orow, sup, perm, vc);
+    AOT_TRY(hipGetLastError());
+    if (m > 0) {
+      k_vertex_head<<<grid_cap(cdiv(m, kBlock)), kBlock, 0, s>>>(m, ocol, sup, perm, vc);
+      AOT_TRY(hipGetLastError());
+    }
+    k_vertex_halve<<<grid_cap(cdiv(n, kBlock)), kBlock, 0, s>>>(n, vc);
+    AOT_TRY(hipGetLastError());
   }
   if (digest_mode) {
     unsigned long long h[4];
     AOT_TRY(hipMemcpyAsync(h, w.digest, sizeof(h), hipMemcpyDeviceToHost, s));
     AOT_TRY(hipStreamSynchronize(s));
-    digest_host[0] = h[0];
-    digest_host[1] = h[1];
-    digest_host[2] = h[2];
+    if (digest_host) {
+      digest_host[0] = h[0];
+      digest_host[1] = h[1];
+      digest_host[2] = h[2];
+    }
   }
   return 0;
 }
@@ -1881,7 +1968,7 @@ int list_run(int32_t n, int64_t m, const int64_t* orow, const int32_t* ocol, con
              const int64_t* tri_off, void* ws, size_t ws_bytes, int64_t first, int64_t count,
              int32_t* out, hipStream_t s, const char** err) {
   return emit_run(n, m, orow, ocol, otail, perm, irow, icol, d, tri_off, ws, ws_bytes, first,
-                  count, out, false, nullptr, nullptr, s, err);
+                  count, out, false, nullptr, nullptr, nullptr, s, err);
 }
 
 int digest_run(int32_t n, int64_t m, const int64_t* orow, const int32_t* ocol,
@@ -1890,7 +1977,16 @@ int digest_run(int32_t n, int64_t m, const int64_t* orow, const int32_t* ocol,
                size_t ws_bytes, uint64_t* vcount, uint64_t* digest, hipStream_t s,
                const char** err) {
   return emit_run(n, m, orow, ocol, otail, perm, irow, icol, d, tri_off, ws, ws_bytes, 0, 0,
-                  nullptr, true, vcount, digest, s, err);
+                  nullptr, true, vcount, nullptr, digest, s, err);
+}
+
+int support_run(int32_t n, int64_t m, const int64_t* orow, const int32_t* ocol,
+                const int32_t* otail, const int32_t* perm, const int64_t* irow,
+                const int32_t* icol, const DispatchView& d, const int64_t* tri_off, void* ws,
+                size_t ws_bytes, uint32_t* esup, uint64_t* vcount, uint64_t* digest,
+                hipStream_t s, const char** err) {
+  return emit_run(n, m, orow, ocol, otail, perm, irow, icol, d, tri_off, ws, ws_bytes, 0, 0,
+                  nullptr, true, vcount, esup, digest, s, err);
 }
 
 int count_plan(const void* ws, size_t ws_bytes, int32_t n, int64_t m, int32_t* table,

@@ -128,5 +128,11 @@ int digest_run(int32_t n, int64_t m, const int64_t* orow, const int32_t* ocol,
                const int32_t* icol, const DispatchView& d, const int64_t* tri_off, void* ws,
                size_t ws_bytes, uint64_t* vcount, uint64_t* digest, hipStream_t s,
                const char** err);
+// The digest pass with per-edge support (and optional vertex counts / digest).
+int support_run(int32_t n, int64_t m, const int64_t* orow, const int32_t* ocol,
+                const int32_t* otail, const int32_t* perm, const int64_t* irow,
+                const int32_t* icol, const DispatchView& d, const int64_t* tri_off, void* ws,
+                size_t ws_bytes, uint32_t* esup, uint64_t* vcount, uint64_t* digest,
+                hipStream_t s, const char** err);
 
 }  // namespace aot

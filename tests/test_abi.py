@@ -113,6 +113,10 @@ def test_count_and_list_argument_errors():
     assert lib.aot_count(ctypes.byref(o), ctypes.byref(learned_head), FAKE, FAKE, ws, res,
                          None) == -1
     assert b"adaptive" in lib.aot_last_error()
+    sup = lambda es, off: lib.aot_support(ctypes.byref(o), None, off, FAKE, ws, es, None, None,
+                                          None)
+    assert sup(None, FAKE) == -1                    # m > 0 needs the edge array
+    assert sup(FAKE, None) == -1
     lst = lambda oo, dd, off, w, nb, first, cnt, out: lib.aot_list(oo, dd, off, w, nb, first, cnt,
                                                                   out, None, None)
     assert lst(ctypes.byref(o), ctypes.byref(d), None, FAKE, ws, 0, 1, FAKE) == -1
