@@ -33,12 +33,15 @@ enum : int {
   kCRowCursor = 23,   // [23..27]
   kCInCount = 28,     // [28..32] in-lists per sort class
   kCInCursor = 33,    // [33..37]
-  kCCoreLevel = 38,   // core order: the peeling level,
-  kCCoreMin = 39,     // the least current degree left (INT32_MAX: none),
-  kCCoreFront = 40,   // the vertices the sub-round removes,
-  kCCoreLeft = 41,    // the vertices not yet removed,
-  kCCoreRound = 42,   // and the sub-round's index
-  kCounters = 43,
+  // core order, two slots each (sub-round parity): the least current degree
+  // left before the sub-round (INT32_MAX: none), its level, the vertices it
+  // removes; then the vertices not yet removed and the sub-rounds so far
+  kCCoreMin = 38,     // [38..39]
+  kCCoreLevel = 40,   // [40..41]
+  kCCoreFront = 42,   // [42..43]
+  kCCoreLeft = 44,
+  kCCoreRound = 45,
+  kCounters = 46,
 };
 
 constexpr int kSortClasses = 5;     // len <= 16, <= 64, <= 256, <= 4096, longer
@@ -135,62 +138,75 @@ __global__ __launch_bounds__(kBlock) void k_degree(int32_t n, const int64_t* __r
 // current degree is at most the level (round[v] = r) and takes one off the
 // current degree of each remaining neighbour per removed neighbour.  Sorting
 // by (round, id) then gives every vertex at most `level` out-neighbours.
-// Each sub-round is four launches that do nothing once every vertex is gone,
-// so the host checks progress only every few sub-rounds.
+//
+// A sub-round is two launches.  The least degree the next sub-round starts
+// from is gathered on the way: k_core_mark takes the minimum over the vertices
+// it leaves, k_core_update over the decremented degrees atomicSub returns.
+// Counters alternate between two slots by sub-round parity, so no launch
+// resets a slot another launch of the same sub-round uses.  Sub-rounds after
+// the last vertex do nothing, so the host checks progress every few.
+
+// Lowers *slot to the least x over the workgroup: one atomic per workgroup,
+// and none when the slot already holds no more (most workgroups see the same
+// least degree, and same-address atomics serialise).
+__device__ __forceinline__ void block_min_into(int32_t x, int32_t* slot) {
+  __shared__ int32_t red[kWavesPerBlock];
+  for (int o = kWave / 2; o > 0; o >>= 1) x = min(x, __shfl_xor(x, o, kWave));
+  if (lane_id() == 0) red[threadIdx.x / kWave] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int q = 1; q < kWavesPerBlock; ++q) x = min(x, red[q]);
+    if (x != INT32_MAX && x < __atomic_load_n(slot, __ATOMIC_RELAXED)) atomicMin(slot, x);
+  }
+}
 
 __global__ __launch_bounds__(kBlock) void k_core_init(int32_t n, const int64_t* __restrict__ rowptr,
                                                       int32_t* __restrict__ cur,
                                                       int32_t* __restrict__ round,
                                                       int32_t* __restrict__ vals,
                                                       int32_t* __restrict__ counters) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    counters[kCCoreLevel] = 0;
-    counters[kCCoreMin] = INT32_MAX;
-    counters[kCCoreFront] = 0;
-    counters[kCCoreLeft] = n;
-    counters[kCCoreRound] = 0;
-  }
-  for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < n;
-       v += (int64_t)gridDim.x * kBlock) {
-    cur[v] = (int32_t)(rowptr[v + 1] - rowptr[v]);
-    round[v] = -1;
-    vals[v] = (int32_t)v;
-  }
-}
-
-__global__ __launch_bounds__(kBlock) void k_core_min(int32_t n, const int32_t* __restrict__ cur,
-                                                     const int32_t* __restrict__ round,
-                                                     int32_t* __restrict__ counters) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) counters[kCCoreLeft] = n;
   int32_t lo = INT32_MAX;
   for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < n;
-       v += (int64_t)gridDim.x * kBlock)
-    if (round[v] < 0) lo = min(lo, cur[v]);
-  for (int o = kWave / 2; o > 0; o >>= 1) lo = min(lo, __shfl_xor(lo, o, kWave));
-  if (lane_id() == 0 && lo != INT32_MAX) atomicMin(&counters[kCCoreMin], lo);
+       v += (int64_t)gridDim.x * kBlock) {
+    const int32_t d = (int32_t)(rowptr[v + 1] - rowptr[v]);
+    cur[v] = d;
+    round[v] = -1;
+    vals[v] = (int32_t)v;
+    lo = min(lo, d);
+  }
+  block_min_into(lo, &counters[kCCoreMin]);
 }
 
 __global__ __launch_bounds__(kBlock) void k_core_mark(int32_t n, const int32_t* __restrict__ cur,
                                                       int32_t* __restrict__ round,
                                                       int32_t* __restrict__ front,
-                                                      int32_t* __restrict__ counters) {
-  const int32_t lo = counters[kCCoreMin];
+                                                      int32_t* __restrict__ counters, int32_t r) {
+  const int p = r & 1;
+  const int32_t lo = counters[kCCoreMin + p];
+  const int32_t prev = counters[kCCoreLevel + (p ^ 1)];
+  const int32_t level = lo == INT32_MAX ? prev : max(prev, lo);
+  if (blockIdx.x == 0 && threadIdx.x == 0) counters[kCCoreLevel + p] = level;
   if (lo == INT32_MAX) return;                      // nothing left
-  const int32_t level = max(counters[kCCoreLevel], lo);
-  const int32_t r = counters[kCCoreRound];
+  int32_t next = INT32_MAX;                         // least degree among those left
   for (int64_t b0 = (int64_t)blockIdx.x * kBlock; b0 < n; b0 += (int64_t)gridDim.x * kBlock) {
     const int64_t v = b0 + threadIdx.x;
-    const bool take = v < n && round[v] < 0 && cur[v] <= level;
+    const bool alive = v < n && round[v] < 0;
+    const int32_t d = alive ? cur[v] : 0;
+    const bool take = alive && d <= level;
+    if (alive && !take) next = min(next, d);
     const uint64_t mask = ballot(take);
     if (!mask) continue;
     const int leader = __ffsll((long long)mask) - 1;
     int32_t at = 0;
-    if (lane_id() == leader) at = atomicAdd(&counters[kCCoreFront], (int32_t)__popcll(mask));
+    if (lane_id() == leader) at = atomicAdd(&counters[kCCoreFront + p], (int32_t)__popcll(mask));
     at = __shfl(at, leader, kWave);
     if (take) {
       round[v] = r;
       front[at + popc_below(mask)] = (int32_t)v;
     }
   }
+  block_min_into(next, &counters[kCCoreMin + (p ^ 1)]);
 }
 
 // One wave per removed vertex.
@@ -199,27 +215,26 @@ __global__ __launch_bounds__(kBlock) void k_core_update(const int64_t* __restric
                                                         const int32_t* __restrict__ front,
                                                         const int32_t* __restrict__ round,
                                                         int32_t* __restrict__ cur,
-                                                        const int32_t* __restrict__ counters) {
-  const int32_t k = counters[kCCoreFront];
+                                                        int32_t* __restrict__ counters,
+                                                        int32_t r) {
+  const int p = r & 1;
+  const int32_t k = counters[kCCoreFront + p];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    counters[kCCoreMin + p] = INT32_MAX;      // read by this sub-round's mark only
+    counters[kCCoreFront + (p ^ 1)] = 0;      // the next sub-round's frontier
+    counters[kCCoreLeft] -= k;
+    if (k > 0) counters[kCCoreRound] = r + 1;
+  }
+  int32_t next = INT32_MAX;
   const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
   for (int64_t i = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kWave; i < k; i += nwaves) {
     const int32_t v = front[i];
     for (int64_t e = rowptr[v] + lane_id(); e < rowptr[v + 1]; e += kWave) {
       const int32_t x = col[e];
-      if (round[x] < 0) atomicSub(&cur[x], 1);
+      if (round[x] < 0) next = min(next, atomicSub(&cur[x], 1) - 1);
     }
   }
-}
-
-__global__ void k_core_step(int32_t* __restrict__ counters) {
-  if (threadIdx.x != 0) return;
-  const int32_t lo = counters[kCCoreMin];
-  const int32_t k = counters[kCCoreFront];
-  if (lo != INT32_MAX && lo > counters[kCCoreLevel]) counters[kCCoreLevel] = lo;
-  counters[kCCoreLeft] -= k;
-  if (k > 0) counters[kCCoreRound] += 1;
-  counters[kCCoreFront] = 0;
-  counters[kCCoreMin] = INT32_MAX;
+  block_min_into(next, &counters[kCCoreMin + (p ^ 1)]);
 }
 
 __global__ __launch_bounds__(kBlock) void k_perm_rank(int32_t n, const int32_t* __restrict__ sorted_ids,
@@ -743,16 +758,17 @@ constexpr int kCoreBatch = 16;      // sub-rounds launched between progress chec
 int core_order(int32_t n, const int64_t* rowptr, const int32_t* col, int32_t* keys, int32_t* vals,
                int32_t* cur, int32_t* front, int32_t* counters, int32_t* rounds, hipStream_t s,
                const char** err) {
-  const unsigned gv = std::min(grid_for(n, kBlock), 2048u);
+  const unsigned gv = std::min(grid_for(n, kBlock), 1024u);
+  AOT_TRY(fill_i32(counters + kCCoreMin, 2, INT32_MAX, s));
+  AOT_TRY(fill_i32(counters + kCCoreLevel, 6, 0, s));
   k_core_init<<<gv, kBlock, 0, s>>>(n, rowptr, cur, keys, vals, counters);
   AOT_TRY(hipGetLastError());
   int32_t left = n;
+  int32_t r = 0;
   while (left > 0) {
-    for (int b = 0; b < kCoreBatch; ++b) {
-      k_core_min<<<gv, kBlock, 0, s>>>(n, cur, keys, counters);
-      k_core_mark<<<gv, kBlock, 0, s>>>(n, cur, keys, front, counters);
-      k_core_update<<<2048, kBlock, 0, s>>>(rowptr, col, front, keys, cur, counters);
-      k_core_step<<<1, 64, 0, s>>>(counters);
+    for (int b = 0; b < kCoreBatch; ++b, ++r) {
+      k_core_mark<<<gv, kBlock, 0, s>>>(n, cur, keys, front, counters, r);
+      k_core_update<<<1024, kBlock, 0, s>>>(rowptr, col, front, keys, cur, counters, r);
       AOT_TRY(hipGetLastError());
     }
     int32_t hc[2];
