@@ -67,7 +67,7 @@ extern "C" {
 const char* aot_status_str(int status);
 /* Detail of the last failing call on this thread ("" if none). */
 const char* aot_last_error(void);
-/* ABI version, currently 1. */
+/* ABI version, currently 2 (aot_dispatch.strategy, AOT_ORDER_CORE, aot_support). */
 int aot_version(void);
 
 /* Input graph (device pointers). */

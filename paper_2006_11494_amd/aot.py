@@ -16,6 +16,7 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libaot.so")
 
+ABI_VERSION = 2          # the aot_version() this binding's structs match
 AOT_OK = 0
 AOT_VALIDATE = 1
 AOT_IN_LISTS_BY_RANK = 2
@@ -151,6 +152,9 @@ def load(path: str = LIB_PATH):
         if f in ("aot_status_str", "aot_last_error", "aot_version"):
             continue
         getattr(lib, f).restype = ctypes.c_int
+    if lib.aot_version() != ABI_VERSION:
+        raise RuntimeError(f"{path}: ABI version {lib.aot_version()}, this binding needs "
+                           f"{ABI_VERSION}; rebuild with python -m paper_2006_11494_amd.build")
     _lib = lib
     return lib
 

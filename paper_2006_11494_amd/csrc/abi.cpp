@@ -172,7 +172,7 @@ const char* aot_status_str(int status) {
 
 const char* aot_last_error(void) { return g_err.c_str(); }
 
-int aot_version(void) { return 1; }
+int aot_version(void) { return 2; }
 
 int aot_orient_workspace(int32_t n, int64_t nnz, size_t* bytes) {
   if (!bytes) return fail(AOT_E_ARG, "bytes is NULL");

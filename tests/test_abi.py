@@ -31,7 +31,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_version_and_status_strings():
     lib = aot.load()
-    assert lib.aot_version() == 1
+    assert lib.aot_version() == aot.ABI_VERSION == 2
     for code in (0, -1, -2, -3, -4, -5, -6, -7):
         assert lib.aot_status_str(code)
     assert lib.aot_status_str(12345) == b"unknown status"
