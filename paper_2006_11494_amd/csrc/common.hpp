@@ -12,7 +12,9 @@ constexpr int kWavesPerBlock = kBlock / kWave;
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
-__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+// The wave's lanes where p holds (the builtin takes the predicate as is,
+// without turning it into an int and back).
+__device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 
 // Number of set lanes strictly below this lane in `mask`.
 __device__ __forceinline__ int popc_below(uint64_t mask) {

@@ -605,12 +605,12 @@ struct Windows {
 
 template <int U>
 __device__ __forceinline__ void load_windows(Windows<U>& W, const int32_t* pre, const int32_t* src,
-                                             const int32_t* __restrict__ ocol, int& kc, int kend,
-                                             int32_t w0, int32_t end) {
+                                             const int32_t* __restrict__ ocol, int& kc, int32_t& nxt,
+                                             int kend, int32_t w0, int32_t end) {
   const int lane = lane_id();
-  // where the neighbour after kc starts: one LDS read serves every window
-  // until a probe crosses it (kc < kend while probes remain)
-  int32_t nxt = pre[kc + 1];
+  // nxt = pre[kc + 1], where the neighbour after kc starts, carried across
+  // calls: it changes only when a probe crosses it (kc < kend while probes
+  // remain)
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     const int32_t p = w0 + u * kWave + lane;
@@ -626,9 +626,13 @@ __device__ __forceinline__ void load_windows(Windows<U>& W, const int32_t* pre, 
   }
 #pragma unroll
   for (int u = 0; u < U; ++u) {
-    // every lane loads; a lane past the end reads ocol[0] and is ignored
+    // every lane loads; a lane past the end reads ocol[0] and is ignored.  The
+    // LDS read takes a valid slot on every lane, so the windows' reads issue
+    // together instead of behind a branch each
     const int32_t p = w0 + u * kWave + lane;
-    const int32_t at = W.kk[u] >= 0 ? src[W.kk[u]] + p : 0;
+    const int k = W.kk[u];
+    const int32_t s0 = src[k < 0 ? 0 : k];
+    const int32_t at = k >= 0 ? s0 + p : 0;
     W.wv[u] = ocol[at];
   }
 }
@@ -645,12 +649,13 @@ __device__ int64_t probe_count(HeavyShared<false>& sh, const uint32_t* lds, cons
   const int lane = lane_id();
   constexpr int32_t kStride = kBlock * kUnroll;
   int kc = 0;
+  int32_t nxt = sh.nb_pre[1];
   int64_t hits_wave = 0;
   int acc_k = -1;     // wave-uniform: neighbour being accumulated
   int acc = 0;        // and its hits so far
   for (int32_t w0 = wave * kWave * kUnroll; w0 < P; w0 += kStride) {
     Windows<kUnroll> cur;
-    load_windows(cur, sh.nb_pre, sh.nb_src, a.ocol, kc, K, w0, P);
+    load_windows(cur, sh.nb_pre, sh.nb_src, a.ocol, kc, nxt, K, w0, P);
     uint64_t hms[kUnroll];
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u)
@@ -724,11 +729,12 @@ __device__ void probe_emit(HeavyShared<true>& sh, const uint32_t* lds, const Hea
   const int32_t* __restrict__ perm = a.perm;
   constexpr int32_t kStride = kWave * kEmitUnroll;
   int kc = k_lo;
+  int32_t nxt = sh.nb_pre[k_lo + 1];
   int run_k = -1;     // wave-uniform: edge whose hits are being ranked
   int run = 0;        // hits of run_k emitted so far
   for (int32_t w0 = p_lo; w0 < p_hi; w0 += kStride) {
     Windows<kEmitUnroll> cur;
-    load_windows(cur, sh.nb_pre, sh.nb_src, a.ocol, kc, k_hi, w0, p_hi);
+    load_windows(cur, sh.nb_pre, sh.nb_src, a.ocol, kc, nxt, k_hi, w0, p_hi);
     bool hit[kEmitUnroll];
     int32_t third[kEmitUnroll];
 #pragma unroll
