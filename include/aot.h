@@ -304,6 +304,8 @@ int aot_support(const aot_oriented* g, const aot_dispatch* d, const int64_t* tri
  *                aot_dispatch's table; 0 = the plain rule), light_rounds
  *                (group-rounds of G lanes per light task, 0 = 4).  NULL =
  *                all defaults.  Every schedule gives the same bytes.
+ * A batch always ranks by degree (no AOT_ORDER_CORE) and probes with the
+ * adaptive strategy.
  */
 typedef struct aot_batch {
   int32_t count;
