@@ -555,7 +555,7 @@ def main():
                    "triangles": T, "probes": probes,
                    "listing": f"windows of {args.chunk} triangles in device memory"
                               if windowed else "one device buffer",
-                   "dispatch": args.heavy_arm or "plain", "heavy_min": args.heavy_min or 32},
+                   "dispatch": args.heavy_arm or "plain", "heavy_min": args.heavy_min or 64},
         "probes_per_s": probes / (ms_count / 1000.0),
         "ms_orient": ms_orient,
         "ms_count": ms_count,

@@ -128,7 +128,7 @@ int aot_orient(const aot_graph* g, uint32_t flags, aot_oriented* out,
  * AOT_DISPATCH_TABLE) gives one code per bucket, e.g. chosen by the cost
  * model.  Every choice gives identical results.
  *   heavy_min   owners with deg+ >= heavy_min are processed owner-grouped with
- *               an LDS index (0 = library default, 32).
+ *               an LDS index (0 = library default, 64).
  *   table       host array of AOT_NUM_BUCKETS codes, or NULL: entry k in 0..7
  *               (light bin k, see the timing recorder) = tile << 8 with tile in
  *               {4, 8, 16, 32, 64} lanes per edge; entry 16 + h (heavy class h)
@@ -300,7 +300,7 @@ int aot_support(const aot_oriented* g, const aot_dispatch* d, const int64_t* tri
  *                (graph, degree) sort key needs more than 31 bits, i.e.
  *                ceil(log2 count) + ceil(log2 max vertices of a graph) > 31.
  * aot_schedule   the choices an autotuner makes: heavy_min (light/heavy bin
- *                boundary, 0 = 32), use_table = 1 to use table (codes as in
+ *                boundary, 0 = 64), use_table = 1 to use table (codes as in
  *                aot_dispatch's table; 0 = the plain rule), light_rounds
  *                (group-rounds of G lanes per light task, 0 = 4).  NULL =
  *                all defaults.  Every schedule gives the same bytes.

@@ -57,7 +57,7 @@ constexpr int kMaxIndexWords = AOT_MAX_INDEX_WORDS;  // LDS index cap (12288: 48
 constexpr int kUnroll = AOT_PROBE_UNROLL;       // 64-probe windows in flight per wave: count pass
 constexpr int kEmitUnroll = AOT_EMIT_UNROLL;    // and write pass
 constexpr int kGrid = 4096;
-constexpr int kDefaultHeavyMin = 32;
+constexpr int kDefaultHeavyMin = 64;
 #ifndef AOT_SPLIT_ITEMS
 #define AOT_SPLIT_ITEMS 1
 #endif

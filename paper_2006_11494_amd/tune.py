@@ -93,7 +93,7 @@ def tune(b: aot.Batch, cap: int | None = None, repeats: int = 3, margin: float =
         return False
 
     for h in HEAVY_MINS:
-        if h != (best.heavy_min or 32):
+        if h != (best.heavy_min or 64):
             attempt(aot.Schedule(h, _table(best), best.light_rounds))
     for r in ROUNDS:
         if r != (best.light_rounds or 4):
