@@ -47,6 +47,7 @@ enum : int {
 constexpr int kSortClasses = 5;     // len <= 16, <= 64, <= 256, <= 4096, longer
 constexpr int kBitmapWords = 16384; // 64 KiB window for the long-list sort
 constexpr int kGrid = 4096;         // grid of the grid-stride kernels
+constexpr int kRowUnroll = 4;       // chunks of kBlock entries per step on a workgroup's row
 
 enum : int {
   kErrRowptr = 1, kErrRange = 2, kErrLoop = 4, kErrOrder = 8, kErrAsym = 16,
@@ -317,7 +318,25 @@ __global__ __launch_bounds__(kBlock) void k_orient_count(RowSet rs,
       const int32_t u = perm[r];
       const int64_t beg = rowptr[u];
       deg = rowptr[u + 1] - beg;
-      for (int64_t j = li; j < deg; j += G) cnt += rank[col[beg + j]] > r;
+      if constexpr (G == kBlock) {
+        // a workgroup per (long) row: kRowUnroll chunks per step, so their
+        // loads and rank gathers are in flight together (a hub row of tens
+        // of thousands of entries otherwise waits out one gather per chunk)
+        for (int64_t j0 = li; j0 < deg; j0 += (int64_t)G * kRowUnroll) {
+          bool ok[kRowUnroll];
+          int32_t c[kRowUnroll];
+#pragma unroll
+          for (int q = 0; q < kRowUnroll; ++q) {
+            const int64_t j = j0 + q * G;
+            ok[q] = j < deg;
+            c[q] = col[beg + (ok[q] ? j : 0)];
+          }
+#pragma unroll
+          for (int q = 0; q < kRowUnroll; ++q) cnt += ok[q] & (rank[c[q]] > r);
+        }
+      } else {
+        for (int64_t j = li; j < deg; j += G) cnt += rank[col[beg + j]] > r;
+      }
     }
     if constexpr (G <= kWave) {
       cnt = group_sum<G>(cnt);
@@ -337,6 +356,64 @@ __global__ __launch_bounds__(kBlock) void k_orient_count(RowSet rs,
 
 // Splits every row into its out-part (unsorted, original order) and in-part
 // (original order), and records each out-edge's tail.
+// Rows of one workgroup (G == kBlock): kRowUnroll chunks of kBlock entries
+// per step, ranked with one pair of barriers per step.
+template <int G>
+__device__ __forceinline__ void orient_write_long(int64_t r, int64_t beg, int64_t deg, int64_t op,
+                                                  int64_t ip, const int32_t* __restrict__ col,
+                                                  const int32_t* __restrict__ rank,
+                                                  int32_t* __restrict__ unsorted,
+                                                  int32_t* __restrict__ otail,
+                                                  int32_t* __restrict__ icol) {
+  __shared__ int32_t so[kRowUnroll][kWavesPerBlock], si[kRowUnroll][kWavesPerBlock];
+  const int w = threadIdx.x / kWave;
+  for (int64_t j0 = 0; j0 < deg; j0 += (int64_t)kBlock * kRowUnroll) {
+    int32_t rv[kRowUnroll];
+    bool out[kRowUnroll], in[kRowUnroll];
+    uint64_t bo[kRowUnroll], bi[kRowUnroll];
+#pragma unroll
+    for (int q = 0; q < kRowUnroll; ++q) {
+      const int64_t j = j0 + q * kBlock + threadIdx.x;
+      out[q] = j < deg;                   // valid, for now
+      rv[q] = col[beg + (out[q] ? j : 0)];
+    }
+#pragma unroll
+    for (int q = 0; q < kRowUnroll; ++q) {
+      const bool valid = out[q];
+      const int32_t x = rank[rv[q]];
+      rv[q] = x;
+      out[q] = valid && x > r;
+      in[q] = valid && x < r;
+      bo[q] = ballot(out[q]);
+      bi[q] = ballot(in[q]);
+      if (lane_id() == 0) { so[q][w] = (int32_t)__popcll(bo[q]); si[q][w] = (int32_t)__popcll(bi[q]); }
+    }
+    __syncthreads();
+    // chunk q of this step starts after chunks 0..q-1; inside a chunk, wave
+    // w after waves 0..w-1
+    int32_t ao = 0, ai = 0;
+#pragma unroll
+    for (int q = 0; q < kRowUnroll; ++q) {
+      int32_t wo = 0, wi = 0, to = 0, ti = 0;
+      for (int x = 0; x < kWavesPerBlock; ++x) {
+        if (x < w) { wo += so[q][x]; wi += si[q][x]; }
+        to += so[q][x]; ti += si[q][x];
+      }
+      if (out[q]) {
+        const int64_t at = op + ao + wo + popc_below(bo[q]);
+        unsorted[at] = rv[q];
+        otail[at] = (int32_t)r;
+      }
+      if (in[q]) icol[ip + ai + wi + popc_below(bi[q])] = rv[q];
+      ao += to;
+      ai += ti;
+    }
+    op += ao;
+    ip += ai;
+    __syncthreads();
+  }
+}
+
 template <int G>
 __global__ __launch_bounds__(kBlock) void k_orient_write(
     RowSet rs, const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
@@ -360,6 +437,10 @@ __global__ __launch_bounds__(kBlock) void k_orient_write(
       deg = rowptr[u + 1] - beg;
       op = orow[r];
       ip = irow[r];
+    }
+    if constexpr (G == kBlock) {
+      orient_write_long<G>(r, beg, deg, op, ip, col, rank, unsorted, otail, icol);
+      continue;
     }
     for (int64_t j0 = 0; j0 < deg; j0 += G) {
       const int64_t j = j0 + li;
