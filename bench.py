@@ -221,7 +221,7 @@ def learned_leg(aot, o, csr, cws, tri_off, list_all, T, probes, args):
     train_s = time.time() - t0
     if net is None:
         return {"accepted": False, "train_s": train_s, **report}
-    d = aot.Dispatch(aot.AOT_DISPATCH_LEARNED, 0, None, net)
+    d = aot.Dispatch(aot.AOT_DISPATCH_LEARNED, report["heavy_min"], None, net)
 
     def step():
         aot.orient(csr.rowptr, csr.col, out=o, in_by_rank=args.in_by_rank)

@@ -13,6 +13,10 @@ The plain rule stays both the fallback (a model that is missing, malformed or
 not finite is ignored by the library) and the judge: a trained model is kept
 only if, on calibration graphs it was not trained on, its plans run faster
 than the plain rule's.
+
+The heavy/light boundary decides which buckets exist at all, so the model is
+not asked to choose it: exploration covers every BOUNDARIES value, and the
+judge times the model's plans at each and keeps the faster.
 """
 
 from __future__ import annotations
@@ -26,6 +30,7 @@ import torch
 from . import aot, inputs
 
 TILES = (4, 8, 16, 32, 64)          # options 0..4 (light bins)
+BOUNDARIES = (0, 32)                # heavy_min: the library default (64), and 32
 ARMS = (0, 1, 2, 3)                 # options 5..8 (heavy classes): bitmap, hash, global, sorted
 N_EXPLORE = 5
 
@@ -89,21 +94,25 @@ def _timed(o, d, repeats: int, out):
     return ms, probes
 
 
-def record(csr, repeats: int = 3):
-    """Exploration on one graph: rows (features[8], option, log ns per probe)."""
+def record(csr, repeats: int = 3, boundaries=BOUNDARIES):
+    """Exploration on one graph, binned at each heavy/light boundary in turn:
+    rows (features[8], option, log ns per probe)."""
     o = aot.orient(csr.rowptr, csr.col)
-    c = aot.count(o)
-    feats, present = aot.bucket_features(o, c)
-    out = out_buffer(c, csr.rowptr.device)
     rows = []
-    for i in range(N_EXPLORE):
-        d = aot.Dispatch(aot.AOT_DISPATCH_TABLE, 0, exploration_table(i))
-        ms, probes = _timed(o, d, repeats, out)
-        for b, t in ms.items():
-            if not present[b]:
-                continue
-            y = math.log(max(t, 1e-6) * 1e6 / max(probes.get(b, 1), 1))
-            rows.append((feats[b].copy(), option_of(b, i), y))
+    out = None
+    for hm in boundaries:
+        c = aot.count(o, aot.Dispatch(aot.AOT_DISPATCH_PLAIN, hm))
+        feats, present = aot.bucket_features(o, c)
+        if out is None:
+            out = out_buffer(c, csr.rowptr.device)
+        for i in range(N_EXPLORE):
+            d = aot.Dispatch(aot.AOT_DISPATCH_TABLE, hm, exploration_table(i))
+            ms, probes = _timed(o, d, repeats, out)
+            for b, t in ms.items():
+                if not present[b]:
+                    continue
+                y = math.log(max(t, 1e-6) * 1e6 / max(probes.get(b, 1), 1))
+                rows.append((feats[b].copy(), option_of(b, i), y))
     return rows
 
 
@@ -151,18 +160,24 @@ def step_ms(o, d, repeats: int, out) -> float:
     return float(np.median(ts))
 
 
-def judge(net: aot.Mlp, graphs, repeats: int = 5, margin: float = 0.02):
-    """Plain vs learned time (ms) summed over calibration graphs; the model is
-    accepted only if it is faster by more than `margin` (timing noise)."""
-    plain = learned = 0.0
-    d_learned = aot.Dispatch(aot.AOT_DISPATCH_LEARNED, 0, None, net)
+def judge(net: aot.Mlp, graphs, repeats: int = 5, margin: float = 0.02,
+          boundaries=BOUNDARIES):
+    """Plain vs learned time (ms) summed over calibration graphs, the learned
+    plans timed at every boundary.  Returns (plain ms, learned ms at the best
+    boundary, accepted, that boundary); the model is accepted only if it is
+    faster than the plain rule by more than `margin` (timing noise)."""
+    plain = 0.0
+    learned = {hm: 0.0 for hm in boundaries}
     for csr in graphs:
         o = aot.orient(csr.rowptr, csr.col)
         c = aot.count(o)
         out = out_buffer(c, csr.rowptr.device)
         plain += step_ms(o, None, repeats, out)
-        learned += step_ms(o, d_learned, repeats, out)
-    return plain, learned, learned < plain * (1.0 - margin)
+        for hm in boundaries:
+            d = aot.Dispatch(aot.AOT_DISPATCH_LEARNED, hm, None, net)
+            learned[hm] += step_ms(o, d, repeats, out)
+    best = min(boundaries, key=lambda hm: learned[hm])
+    return plain, learned[best], learned[best] < plain * (1.0 - margin), best
 
 
 def training_graphs(device="cuda", scale: int = 1):
@@ -193,7 +208,7 @@ def learn(training=None, calibration=None, device="cuda", scale: int = 1, epochs
           repeats: int = 3, log=None):
     """Exploration on the training graphs, training, and the judge on the
     calibration graphs.  Returns (model or None if the judge rejects it,
-    report)."""
+    report); report["heavy_min"] is the boundary to use the model at."""
     training = training if training is not None else training_graphs(device, scale)
     calibration = calibration if calibration is not None else calibration_graphs(device, scale)
     rows = []
@@ -203,12 +218,13 @@ def learn(training=None, calibration=None, device="cuda", scale: int = 1, epochs
             log(f"[learn] explored {csr.name}: {len(rows)} rows")
     data = dataset(rows, device)
     net, losses = train(data, epochs=epochs)
-    plain, learned, ok = judge(net, calibration)
+    plain, learned, ok, heavy_min = judge(net, calibration)
     report = {"rows": len(rows), "loss_first": losses[0] if losses else None,
               "loss_last": losses[-1] if losses else None, "judge_plain_ms": plain,
-              "judge_learned_ms": learned, "accepted": ok,
+              "judge_learned_ms": learned, "accepted": ok, "heavy_min": heavy_min,
               "training": [g.name for g in training], "calibration": [g.name for g in calibration]}
     if log:
         log(f"[learn] loss {report['loss_first']:.3f} -> {report['loss_last']:.3f}; judge: "
-            f"plain {plain:.3f} ms, learned {learned:.3f} ms -> {'accept' if ok else 'reject'}")
+            f"plain {plain:.3f} ms, learned {learned:.3f} ms (heavy_min {heavy_min or 'default'})"
+            f" -> {'accept' if ok else 'reject'}")
     return (net if ok else None), report

@@ -124,7 +124,7 @@ def test_learned_dispatch_gain():
         o = aot.orient(csr.rowptr, csr.col)
         c = aot.count(o)
         out = torch.empty((max(c.T, 1), 3), dtype=torch.int32, device="cuda")
-        d = aot.Dispatch(aot.AOT_DISPATCH_LEARNED, 0, None, net)
+        d = aot.Dispatch(aot.AOT_DISPATCH_LEARNED, report["heavy_min"], None, net)
         plain = learn.step_ms(o, None, 5, out)
         learned = learn.step_ms(o, d, 5, out)
         say(f"[learn] {csr.name}: plain {plain:.3f} ms, learned {learned:.3f} ms, "
