@@ -25,6 +25,11 @@
 // The count pass writes cnt[e]; an exclusive scan gives each edge its slot in
 // the global triangle list; the write pass repeats the probes and stores the
 // hits of an edge in ascending w at those slots.
+//
+// The same passes take the comparison costs of Section 2 as strategies (the
+// fixed orientation of kClist, CF's merge, CF-Hash's per-edge probing) with
+// the same output, and, in digest mode, count each triangle once for its
+// three edges (the per-edge support) instead of storing it.
 #include <algorithm>
 #include <climits>
 #include <cmath>
@@ -50,9 +55,6 @@ constexpr int kMaxIndexWords = AOT_MAX_INDEX_WORDS;  // LDS index cap (12288: 48
 #endif
 #ifndef AOT_EMIT_UNROLL
 #define AOT_EMIT_UNROLL 8
-#endif
-#ifndef AOT_CHAINED_CURSOR
-#define AOT_CHAINED_CURSOR 1
 #endif
 constexpr int kUnroll = AOT_PROBE_UNROLL;       // 64-probe windows in flight per wave: count pass
 constexpr int kEmitUnroll = AOT_EMIT_UNROLL;    // and write pass
