@@ -41,7 +41,8 @@ enum : int {
   kCCoreFront = 42,   // [42..43]
   kCCoreLeft = 44,
   kCCoreRound = 45,
-  kCounters = 46,
+  kCCoreList = 46,    // entries appended by the compaction
+  kCounters = 47,
 };
 
 constexpr int kSortClasses = 5;     // len <= 16, <= 64, <= 256, <= 4096, longer
@@ -179,7 +180,10 @@ __global__ __launch_bounds__(kBlock) void k_core_init(int32_t n, const int64_t* 
   block_min_into(lo, &counters[kCCoreMin]);
 }
 
-__global__ __launch_bounds__(kBlock) void k_core_mark(int32_t n, const int32_t* __restrict__ cur,
+// Scans the remaining vertices: list[0 .. len), or every vertex 0 .. len
+// when list is null.
+__global__ __launch_bounds__(kBlock) void k_core_mark(int32_t len, const int32_t* __restrict__ list,
+                                                      const int32_t* __restrict__ cur,
                                                       int32_t* __restrict__ round,
                                                       int32_t* __restrict__ front,
                                                       int32_t* __restrict__ counters, int32_t r) {
@@ -190,9 +194,10 @@ __global__ __launch_bounds__(kBlock) void k_core_mark(int32_t n, const int32_t* 
   if (blockIdx.x == 0 && threadIdx.x == 0) counters[kCCoreLevel + p] = level;
   if (lo == INT32_MAX) return;                      // nothing left
   int32_t next = INT32_MAX;                         // least degree among those left
-  for (int64_t b0 = (int64_t)blockIdx.x * kBlock; b0 < n; b0 += (int64_t)gridDim.x * kBlock) {
-    const int64_t v = b0 + threadIdx.x;
-    const bool alive = v < n && round[v] < 0;
+  for (int64_t b0 = (int64_t)blockIdx.x * kBlock; b0 < len; b0 += (int64_t)gridDim.x * kBlock) {
+    const int64_t i = b0 + threadIdx.x;
+    const int64_t v = i < len ? (list ? list[i] : i) : 0;
+    const bool alive = i < len && round[v] < 0;
     const int32_t d = alive ? cur[v] : 0;
     const bool take = alive && d <= level;
     if (alive && !take) next = min(next, d);
@@ -208,6 +213,27 @@ __global__ __launch_bounds__(kBlock) void k_core_mark(int32_t n, const int32_t* 
     }
   }
   block_min_into(next, &counters[kCCoreMin + (p ^ 1)]);
+}
+
+// The remaining vertices of list[0 .. len) (every vertex when list is null)
+// appended to out, in no particular order (the peel does not depend on it).
+__global__ __launch_bounds__(kBlock) void k_core_compact(int32_t len,
+                                                         const int32_t* __restrict__ list,
+                                                         const int32_t* __restrict__ round,
+                                                         int32_t* __restrict__ out,
+                                                         int32_t* __restrict__ counters) {
+  for (int64_t b0 = (int64_t)blockIdx.x * kBlock; b0 < len; b0 += (int64_t)gridDim.x * kBlock) {
+    const int64_t i = b0 + threadIdx.x;
+    const int32_t v = i < len ? (list ? list[i] : (int32_t)i) : 0;
+    const bool keep = i < len && round[v] < 0;
+    const uint64_t mask = ballot(keep);
+    if (!mask) continue;
+    const int leader = __ffsll((long long)mask) - 1;
+    int32_t at = 0;
+    if (lane_id() == leader) at = atomicAdd(&counters[kCCoreList], (int32_t)__popcll(mask));
+    at = __shfl(at, leader, kWave);
+    if (keep) out[at + popc_below(mask)] = v;
+  }
 }
 
 // One wave per removed vertex.
@@ -833,12 +859,14 @@ struct BatchKeys {
 };
 
 constexpr int kCoreBatch = 16;      // sub-rounds launched between progress checks
+constexpr unsigned kCoreGrid = 256;  // workgroups of the per-sub-round launches
 
 // round[v] of the core order into keys, ids into vals; *rounds = sub-rounds.
-// cur and front are n-entry scratch arrays.
+// cur, front, la and lb are n-entry scratch arrays (la, lb: lists of the
+// remaining vertices, compacted whenever fewer than half of a list remain).
 int core_order(int32_t n, const int64_t* rowptr, const int32_t* col, int32_t* keys, int32_t* vals,
-               int32_t* cur, int32_t* front, int32_t* counters, int32_t* rounds, hipStream_t s,
-               const char** err) {
+               int32_t* cur, int32_t* front, int32_t* la, int32_t* lb, int32_t* counters,
+               int32_t* rounds, hipStream_t s, const char** err) {
   const unsigned gv = std::min(grid_for(n, kBlock), 1024u);
   AOT_TRY(fill_i32(counters + kCCoreMin, 2, INT32_MAX, s));
   AOT_TRY(fill_i32(counters + kCCoreLevel, 6, 0, s));
@@ -846,10 +874,13 @@ int core_order(int32_t n, const int64_t* rowptr, const int32_t* col, int32_t* ke
   AOT_TRY(hipGetLastError());
   int32_t left = n;
   int32_t r = 0;
+  const int32_t* list = nullptr;      // null: every vertex
+  int32_t len = n;
   while (left > 0) {
+    const unsigned gm = std::min(grid_for(len, kBlock), kCoreGrid);
     for (int b = 0; b < kCoreBatch; ++b, ++r) {
-      k_core_mark<<<gv, kBlock, 0, s>>>(n, cur, keys, front, counters, r);
-      k_core_update<<<1024, kBlock, 0, s>>>(rowptr, col, front, keys, cur, counters, r);
+      k_core_mark<<<gm, kBlock, 0, s>>>(len, list, cur, keys, front, counters, r);
+      k_core_update<<<kCoreGrid, kBlock, 0, s>>>(rowptr, col, front, keys, cur, counters, r);
       AOT_TRY(hipGetLastError());
     }
     int32_t hc[2];
@@ -862,6 +893,15 @@ int core_order(int32_t n, const int64_t* rowptr, const int32_t* col, int32_t* ke
     }
     left = hc[0];
     *rounds = hc[1];
+    if (left > 0 && left < len / 2) {
+      int32_t* out = list == la ? lb : la;
+      AOT_TRY(fill_i32(counters + kCCoreList, 1, 0, s));
+      k_core_compact<<<std::min(grid_for(len, kBlock), 1024u), kBlock, 0, s>>>(len, list, keys,
+                                                                             out, counters);
+      AOT_TRY(hipGetLastError());
+      list = out;
+      len = left;                    // exactly the vertices not yet removed
+    }
   }
   return 0;
 }
@@ -924,8 +964,8 @@ int orient_impl(int32_t n, int64_t nnz, const int64_t* rowptr, const int32_t* co
   const bool lists = bk || core;
   if (core) {
     int32_t rounds = 0;
-    const int rc = core_order(n, rowptr, col, key_a, val_a, dplus, dminus, counters, &rounds, s,
-                              err);
+    const int rc = core_order(n, rowptr, col, key_a, val_a, dplus, dminus, key_b, val_b, counters,
+                              &rounds, s, err);
     if (rc) return rc;
     bits = ceil_log2((int64_t)rounds + 1);
   } else if (!bk) {
