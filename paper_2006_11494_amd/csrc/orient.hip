@@ -42,13 +42,16 @@ enum : int {
   kCCoreLeft = 44,
   kCCoreRound = 45,
   kCCoreList = 46,    // entries appended by the compaction
-  kCounters = 47,
+  kCCoreBig = 47,     // [47..48] removed vertices with rows longer than kBigRow
+  kCounters = 49,
 };
 
 constexpr int kSortClasses = 5;     // len <= 16, <= 64, <= 256, <= 4096, longer
 constexpr int kBitmapWords = 16384; // 64 KiB window for the long-list sort
 constexpr int kGrid = 4096;         // grid of the grid-stride kernels
 constexpr int kRowUnroll = 4;       // chunks of kBlock entries per step on a workgroup's row
+constexpr int64_t kBigRow = 1024;   // core peel: rows updated by more than one wave,
+constexpr int32_t kBigShared = 8;   // by the whole grid when a sub-round has this few
 
 enum : int {
   kErrRowptr = 1, kErrRange = 2, kErrLoop = 4, kErrOrder = 8, kErrAsym = 16,
@@ -182,7 +185,12 @@ __global__ __launch_bounds__(kBlock) void k_core_init(int32_t n, const int64_t* 
 
 // Scans the remaining vertices: list[0 .. len), or every vertex 0 .. len
 // when list is null.
-__global__ __launch_bounds__(kBlock) void k_core_mark(int32_t len, const int32_t* __restrict__ list,
+// Removed vertices go to front[0 ..) when their rows are short, and to
+// front[n - 1], front[n - 2], ... when longer than kBigRow (the two never
+// meet: together they hold at most the n vertices).
+__global__ __launch_bounds__(kBlock) void k_core_mark(int32_t n, int32_t len,
+                                                      const int32_t* __restrict__ list,
+                                                      const int64_t* __restrict__ rowptr,
                                                       const int32_t* __restrict__ cur,
                                                       int32_t* __restrict__ round,
                                                       int32_t* __restrict__ front,
@@ -201,15 +209,20 @@ __global__ __launch_bounds__(kBlock) void k_core_mark(int32_t len, const int32_t
     const int32_t d = alive ? cur[v] : 0;
     const bool take = alive && d <= level;
     if (alive && !take) next = min(next, d);
-    const uint64_t mask = ballot(take);
-    if (!mask) continue;
-    const int leader = __ffsll((long long)mask) - 1;
-    int32_t at = 0;
-    if (lane_id() == leader) at = atomicAdd(&counters[kCCoreFront + p], (int32_t)__popcll(mask));
-    at = __shfl(at, leader, kWave);
+    if (!ballot(take)) continue;
+    const bool big = take && rowptr[v + 1] - rowptr[v] > kBigRow;
+    const uint64_t ms = ballot(take && !big), mb = ballot(big);
+    int32_t as = 0, ab = 0;
+    if (lane_id() == 0) {
+      if (ms) as = atomicAdd(&counters[kCCoreFront + p], (int32_t)__popcll(ms));
+      if (mb) ab = atomicAdd(&counters[kCCoreBig + p], (int32_t)__popcll(mb));
+    }
+    as = __shfl(as, 0, kWave);
+    ab = __shfl(ab, 0, kWave);
     if (take) {
       round[v] = r;
-      front[at + popc_below(mask)] = (int32_t)v;
+      if (big) front[n - 1 - (ab + popc_below(mb))] = (int32_t)v;
+      else front[as + popc_below(ms)] = (int32_t)v;
     }
   }
   block_min_into(next, &counters[kCCoreMin + (p ^ 1)]);
@@ -237,7 +250,11 @@ __global__ __launch_bounds__(kBlock) void k_core_compact(int32_t len,
 }
 
 // One wave per removed vertex.
-__global__ __launch_bounds__(kBlock) void k_core_update(const int64_t* __restrict__ rowptr,
+// One wave per removed vertex with a short row; long rows get a workgroup
+// each, or the whole grid each when there are only a few (a hub removed late
+// would otherwise hold one wave for its whole row).
+__global__ __launch_bounds__(kBlock) void k_core_update(int32_t n,
+                                                        const int64_t* __restrict__ rowptr,
                                                         const int32_t* __restrict__ col,
                                                         const int32_t* __restrict__ front,
                                                         const int32_t* __restrict__ round,
@@ -246,11 +263,13 @@ __global__ __launch_bounds__(kBlock) void k_core_update(const int64_t* __restric
                                                         int32_t r) {
   const int p = r & 1;
   const int32_t k = counters[kCCoreFront + p];
+  const int32_t kb = counters[kCCoreBig + p];
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     counters[kCCoreMin + p] = INT32_MAX;      // read by this sub-round's mark only
-    counters[kCCoreFront + (p ^ 1)] = 0;      // the next sub-round's frontier
-    counters[kCCoreLeft] -= k;
-    if (k > 0) counters[kCCoreRound] = r + 1;
+    counters[kCCoreFront + (p ^ 1)] = 0;      // the next sub-round's frontiers
+    counters[kCCoreBig + (p ^ 1)] = 0;
+    counters[kCCoreLeft] -= k + kb;
+    if (k + kb > 0) counters[kCCoreRound] = r + 1;
   }
   int32_t next = INT32_MAX;
   const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
@@ -259,6 +278,27 @@ __global__ __launch_bounds__(kBlock) void k_core_update(const int64_t* __restric
     for (int64_t e = rowptr[v] + lane_id(); e < rowptr[v + 1]; e += kWave) {
       const int32_t x = col[e];
       if (round[x] < 0) next = min(next, atomicSub(&cur[x], 1) - 1);
+    }
+  }
+  if (kb <= kBigShared) {
+    // a few long rows (hubs, late in the peel): the whole grid on each
+    const int64_t nthreads = (int64_t)gridDim.x * kBlock;
+    for (int32_t j = 0; j < kb; ++j) {
+      const int32_t v = front[n - 1 - j];
+      for (int64_t e = rowptr[v] + (int64_t)blockIdx.x * kBlock + threadIdx.x; e < rowptr[v + 1];
+           e += nthreads) {
+        const int32_t x = col[e];
+        if (round[x] < 0) next = min(next, atomicSub(&cur[x], 1) - 1);
+      }
+    }
+  } else {
+    // many: one workgroup per row
+    for (int32_t j = blockIdx.x; j < kb; j += gridDim.x) {
+      const int32_t v = front[n - 1 - j];
+      for (int64_t e = rowptr[v] + threadIdx.x; e < rowptr[v + 1]; e += kBlock) {
+        const int32_t x = col[e];
+        if (round[x] < 0) next = min(next, atomicSub(&cur[x], 1) - 1);
+      }
     }
   }
   block_min_into(next, &counters[kCCoreMin + (p ^ 1)]);
@@ -869,7 +909,7 @@ int core_order(int32_t n, const int64_t* rowptr, const int32_t* col, int32_t* ke
                int32_t* rounds, hipStream_t s, const char** err) {
   const unsigned gv = std::min(grid_for(n, kBlock), 1024u);
   AOT_TRY(fill_i32(counters + kCCoreMin, 2, INT32_MAX, s));
-  AOT_TRY(fill_i32(counters + kCCoreLevel, 6, 0, s));
+  AOT_TRY(fill_i32(counters + kCCoreLevel, kCounters - kCCoreLevel, 0, s));
   k_core_init<<<gv, kBlock, 0, s>>>(n, rowptr, cur, keys, vals, counters);
   AOT_TRY(hipGetLastError());
   int32_t left = n;
@@ -879,8 +919,8 @@ int core_order(int32_t n, const int64_t* rowptr, const int32_t* col, int32_t* ke
   while (left > 0) {
     const unsigned gm = std::min(grid_for(len, kBlock), kCoreGrid);
     for (int b = 0; b < kCoreBatch; ++b, ++r) {
-      k_core_mark<<<gm, kBlock, 0, s>>>(len, list, cur, keys, front, counters, r);
-      k_core_update<<<kCoreGrid, kBlock, 0, s>>>(rowptr, col, front, keys, cur, counters, r);
+      k_core_mark<<<gm, kBlock, 0, s>>>(n, len, list, rowptr, cur, keys, front, counters, r);
+      k_core_update<<<kCoreGrid, kBlock, 0, s>>>(n, rowptr, col, front, keys, cur, counters, r);
       AOT_TRY(hipGetLastError());
     }
     int32_t hc[2];
