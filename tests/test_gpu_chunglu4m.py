@@ -1,0 +1,92 @@
+"""The learned-dispatch configuration at full size: Chung-Lu, n = 4,000,000,
+mean degree 40, exponent 2.1, degree cap 100,000 (about 7.5e7 edges and 2e9
+triangles).  The whole list is beyond the CPU oracle, so parity rests on what
+it computes at this size:
+  * the whole orientation and the probe count, exactly;
+  * per-edge counts at 200,000 random edges and at edges of the heaviest
+    owners, exactly;
+  * complete, ordered triangle lists of rank ranges at several depths;
+  * triangles through sampled vertices (the hubs among them), exactly;
+and on invariants: every dispatch table and probe strategy gives the same
+digest of the whole list."""
+
+import sys
+import time
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2006_11494_amd import aot, inputs
+
+pytestmark = [pytest.mark.gpu, pytest.mark.timeout(900)]
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def test_chunglu4m_sampled_parity():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    t0 = time.time()
+    csr = inputs.workload("chunglu4m", device="cuda")
+    torch.cuda.synchronize()
+    n, m = csr.n, csr.m
+    say(f"[gpu] chunglu4m: n={n} m={m} in {time.time() - t0:.1f}s")
+    o = aot.orient(csr.rowptr, csr.col)
+    c = aot.count(o)
+    torch.cuda.synchronize()
+    say(f"[gpu] chunglu4m: T={c.T} probes={c.probes}")
+    rp, col = csr.numpy()
+    ref = oracle.orient_threaded(rp, col, threads=16)
+    assert np.array_equal(o.perm.cpu().numpy(), ref.perm)
+    assert np.array_equal(o.rowptr.cpu().numpy(), ref.orow)
+    assert np.array_equal(o.col.cpu().numpy(), ref.ocol)
+    assert oracle.sum_min_threaded(ref, threads=16) == c.probes
+    say(f"[gpu] chunglu4m: orientation and probe count equal at {time.time() - t0:.1f}s")
+
+    rng = np.random.default_rng(40)
+    dplus = np.diff(ref.orow)
+    top = np.argpartition(dplus, -200)[-200:]
+    heavy = np.concatenate([ref.orow[r] + rng.integers(0, dplus[r], 20) for r in top])
+    eids = np.unique(np.concatenate([rng.integers(0, m, 200_000), heavy]))
+    got = (c.tri_off[torch.from_numpy(eids + 1).cuda()] -
+           c.tri_off[torch.from_numpy(eids).cuda()]).cpu().numpy()
+    assert np.array_equal(got, oracle.edge_counts_at(ref, eids))
+    say(f"[gpu] chunglu4m: {eids.size} sampled edge counts equal")
+
+    for q in (0.5, 0.9, 0.99, 0.999, 0.99995):
+        r_lo = int(q * n)
+        r_hi = int(np.searchsorted(ref.orow, ref.orow[r_lo] + 20_000, side="right")) - 1
+        r_hi = min(max(r_hi, r_lo + 1), n)
+        want = oracle.list_triangles(ref, r_lo, r_hi)
+        first = int(c.tri_off[int(ref.orow[r_lo])])
+        last = int(c.tri_off[int(ref.orow[r_hi])])
+        got = aot.list_triangles(o, c, first=first, count=last - first).cpu().numpy()
+        assert np.array_equal(got, want), f"ranks [{r_lo}, {r_hi})"
+        say(f"[gpu] chunglu4m: ranks [{r_lo}, {r_hi}): {len(want)} triangles equal")
+
+    (t, s, x), vc = aot.digest(o, c)
+    assert t == c.T and int(vc.sum()) == 3 * t
+    # the oracle merges each neighbour's row with v's (about deg(v)^2 steps):
+    # the three largest hubs, 20 of the top 1000 and 2000 random vertices
+    deg = np.diff(rp)
+    top = np.argpartition(deg, -1000)[-1000:]
+    vs = np.unique(np.concatenate([rng.integers(0, n, 2000), top[np.argsort(deg[top])[-3:]],
+                                   rng.choice(top, 20, replace=False)])).astype(np.int32)
+    want = oracle.vertex_triangles(rp, col, vs)
+    assert np.array_equal(vc.cpu().numpy()[vs], want)
+    say(f"[gpu] chunglu4m: triangles through {vs.size} sampled vertices equal")
+
+    tiles = [tile << 8 for tile in (4, 4, 4, 8, 16, 32, 64, 64)]
+    others = {"all_hash": aot.Dispatch(aot.AOT_DISPATCH_TABLE, 0, tiles + [0] * 8 + [1] * 16),
+              "sorted_4lane": aot.Dispatch(aot.AOT_DISPATCH_TABLE, 32,
+                                           [4 << 8] * 8 + [0] * 8 + [3] * 16)}
+    others.update({k: aot.Dispatch(strategy=v) for k, v in aot.STRATEGIES.items() if k != "aot"})
+    for name, d in others.items():
+        cd = aot.count(o, d)
+        assert cd.T == c.T and torch.equal(cd.tri_off, c.tri_off), name
+        assert aot.digest(o, cd, vertex_counts=False)[0] == (t, s, x), name
+        say(f"[gpu] chunglu4m: {name}: same digest at {time.time() - t0:.1f}s")
