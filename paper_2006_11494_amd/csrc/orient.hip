@@ -607,7 +607,13 @@ __global__ __launch_bounds__(kBlock) void k_count_classes(int32_t n,
   }
 }
 
-// Rows into their classes; one global atomic per wave and class.
+// Rows into their classes.  A workgroup takes kClassChunk rows at a time:
+// it counts them per class, reserves their slots with one global atomic per
+// class, then places them through LDS cursors (the order inside a class is
+// free: each row is then processed on its own).  One atomic per wave and
+// class, on five addresses, serialised badly on millions of rows.
+constexpr int kClassChunk = 16 * kBlock;
+
 template <int kMode>
 __global__ __launch_bounds__(kBlock) void k_scatter_classes(int32_t n,
                                                             const int32_t* __restrict__ len,
@@ -617,24 +623,43 @@ __global__ __launch_bounds__(kBlock) void k_scatter_classes(int32_t n,
                                                             int32_t* __restrict__ rows) {
   constexpr int kOff = ClassSlots<kMode>::count;
   constexpr int kCur = ClassSlots<kMode>::cursor;
-  __shared__ int32_t base[kSortClasses];
+  __shared__ int32_t base[kSortClasses], cnt[kSortClasses], at[kSortClasses];
   if (threadIdx.x == 0) {
     int32_t run = 0;
     for (int q = 0; q < kSortClasses; ++q) { base[q] = run; run += counters[kOff + q]; }
   }
-  __syncthreads();
-  for (int64_t r0 = (int64_t)blockIdx.x * kBlock; r0 < n; r0 += (int64_t)gridDim.x * kBlock) {
-    const int64_t r = r0 + threadIdx.x;
-    const int c = r < n ? row_class<kMode>(r, len, perm, rowptr) : -1;
-    for (int q = 0; q < kSortClasses; ++q) {
-      const uint64_t mask = ballot(c == q);
-      if (!mask) continue;
-      const int leader = __ffsll((long long)mask) - 1;
-      int32_t at = 0;
-      if (lane_id() == leader) at = atomicAdd(&counters[kCur + q], (int32_t)__popcll(mask));
-      at = __shfl(at, leader, kWave);
-      if (c == q) rows[base[q] + at + popc_below(mask)] = (int32_t)r;
+  for (int64_t c0 = (int64_t)blockIdx.x * kClassChunk; c0 < n;
+       c0 += (int64_t)gridDim.x * kClassChunk) {
+    const int64_t c1 = min((int64_t)n, c0 + kClassChunk);
+    if (threadIdx.x < kSortClasses) cnt[threadIdx.x] = 0;
+    __syncthreads();
+    for (int64_t r0 = c0; r0 < c1; r0 += kBlock) {
+      const int64_t r = r0 + threadIdx.x;
+      const int c = r < c1 ? row_class<kMode>(r, len, perm, rowptr) : -1;
+      for (int q = 0; q < kSortClasses; ++q) {
+        const uint64_t mask = ballot(c == q);
+        if (mask && lane_id() == 0) atomicAdd(&cnt[q], (int32_t)__popcll(mask));
+      }
     }
+    __syncthreads();
+    if (threadIdx.x < kSortClasses) {
+      const int q = threadIdx.x;
+      at[q] = base[q] + (cnt[q] ? atomicAdd(&counters[kCur + q], cnt[q]) : 0);
+    }
+    __syncthreads();
+    for (int64_t r0 = c0; r0 < c1; r0 += kBlock) {
+      const int64_t r = r0 + threadIdx.x;
+      const int c = r < c1 ? row_class<kMode>(r, len, perm, rowptr) : -1;
+      for (int q = 0; q < kSortClasses; ++q) {
+        const uint64_t mask = ballot(c == q);
+        if (!mask) continue;
+        int32_t slot = 0;
+        if (lane_id() == 0) slot = atomicAdd(&at[q], (int32_t)__popcll(mask));
+        slot = __shfl(slot, 0, kWave);
+        if (c == q) rows[slot + popc_below(mask)] = (int32_t)r;
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -1048,7 +1073,7 @@ int orient_impl(int32_t n, int64_t nnz, const int64_t* rowptr, const int32_t* co
     k_count_classes<kRowsByDegree><<<std::min(grid_for(n, kBlock), 1024u), kBlock, 0, s>>>(
         n, dplus, perm, rowptr, counters);
     AOT_TRY(hipGetLastError());
-    k_scatter_classes<kRowsByDegree><<<grid_for(n, kBlock), kBlock, 0, s>>>(n, dplus, perm, rowptr,
+    k_scatter_classes<kRowsByDegree><<<grid_for(n, kClassChunk), kBlock, 0, s>>>(n, dplus, perm, rowptr,
                                                                    counters, rows);
     AOT_TRY(hipGetLastError());
   } else {
@@ -1076,7 +1101,7 @@ int orient_impl(int32_t n, int64_t nnz, const int64_t* rowptr, const int32_t* co
   k_count_classes<kOutLists><<<std::min(grid_for(n, kBlock), 1024u), kBlock, 0, s>>>(
       n, dplus, perm, rowptr, counters);
   AOT_TRY(hipGetLastError());
-  k_scatter_classes<kOutLists><<<grid_for(n, kBlock), kBlock, 0, s>>>(n, dplus, perm, rowptr,
+  k_scatter_classes<kOutLists><<<grid_for(n, kClassChunk), kBlock, 0, s>>>(n, dplus, perm, rowptr,
                                                                   counters, rows);
   AOT_TRY(hipGetLastError());
   const unsigned g_small = (unsigned)std::min<int64_t>(kGrid, cdiv(n, kBlock / 16) + 1);
@@ -1091,7 +1116,7 @@ int orient_impl(int32_t n, int64_t nnz, const int64_t* rowptr, const int32_t* co
   k_count_classes<kInLists><<<std::min(grid_for(n, kBlock), 1024u), kBlock, 0, s>>>(
       n, dminus, perm, rowptr, counters);
   AOT_TRY(hipGetLastError());
-  k_scatter_classes<kInLists><<<grid_for(n, kBlock), kBlock, 0, s>>>(n, dminus, perm, rowptr,
+  k_scatter_classes<kInLists><<<grid_for(n, kClassChunk), kBlock, 0, s>>>(n, dminus, perm, rowptr,
                                                                      counters, rows);
   AOT_TRY(hipGetLastError());
   AOT_TRY(sort_lists(kCInCount, g_small, counters, rows, irow, unsorted, icol, s));
