@@ -62,6 +62,8 @@ def _load():
     lib.orc_core_rounds.restype = i32
     lib.orc_orient_core.argtypes = [i32, _i64p, _i32p, _i32p, _i32p, _i64p, _i32p]
     lib.orc_orient_core.restype = i64
+    lib.orc_orient_by_id.argtypes = [i32, _i64p, _i32p, _i32p, _i64p, _i32p]
+    lib.orc_orient_by_id.restype = i64
     lib.orc_sum_merge.argtypes = [i32, _i64p, _i32p]
     lib.orc_sum_merge.restype = u64
     lib.orc_aot_ref.argtypes = [i32, _i64p, _i32p, ctypes.c_int, _i32p, i64, ctypes.POINTER(u64)]
@@ -95,7 +97,8 @@ def _arrays(rowptr, col):
 
 
 class Oriented:
-    """Oriented graph in rank space (rank = position in the degree order)."""
+    """Oriented graph in label space: labels are ranks (position in the order)
+    by default, original ids with local="id" (perm and rank the identity)."""
 
     def __init__(self, n, perm, rank, orow, ocol):
         self.n, self.perm, self.rank, self.orow, self.ocol = n, perm, rank, orow, ocol
@@ -112,11 +115,23 @@ class Oriented:
         return np.repeat(np.arange(self.n, dtype=np.int32), self.dplus)
 
 
-def orient(rowptr, col, order: str = "degree") -> Oriented:
+def orient(rowptr, col, order: str = "degree", local: str = "rank") -> Oriented:
     """Degree order with id tie-break; <u,v> iff eta(u) < eta(v) (Sec. 2.2).
-    order="core": the core order of kClist (Sec. 2.3), see core_rounds."""
+    order="core": the core order of kClist (Sec. 2.3), see core_rounds.
+    local="id": the same edges with original ids as labels, so each out-list
+    is in id order (AOT-randomOrder, Sec. 4.3, for inputs with permuted ids)."""
     lib = _load()
     rowptr, col = _arrays(rowptr, col)
+    if local not in ("rank", "id"):
+        raise ValueError(local)
+    if local == "id":
+        eta = orient(rowptr, col, order)
+        n = eta.n
+        orow = np.empty(n + 1, np.int64)
+        ocol = np.empty(max(col.size // 2, 1), np.int32)
+        m = lib.orc_orient_by_id(n, rowptr, _nonempty(col), _nonempty(eta.rank), orow, ocol)
+        ident = np.arange(n, dtype=np.int32)
+        return Oriented(n, ident, ident.copy(), orow, ocol[:m].copy())
     n = rowptr.size - 1
     perm = np.empty(max(n, 1), np.int32)
     rank = np.empty(max(n, 1), np.int32)

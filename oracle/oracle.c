@@ -200,6 +200,26 @@ int64_t orc_orient_core(int32_t n, const int64_t* rowptr, const int32_t* col, in
   return orow[n];
 }
 
+/* Orientation that keeps the original ids as labels: the order eta (given as
+ * rank[v]) still directs every edge, but the out-list of vertex u holds the
+ * original ids of its neighbours v with eta(v) > eta(u), sorted ascending, and
+ * rows are indexed by original id.  Inside each list, vertices then follow id
+ * order instead of the degree local order of Section 3.2; for inputs with
+ * randomly permuted ids this is the random local order of AOT-randomOrder
+ * (Section 4.3).  Returns m. */
+int64_t orc_orient_by_id(int32_t n, const int64_t* rowptr, const int32_t* col,
+                         const int32_t* rank, int64_t* orow, int32_t* ocol) {
+  orow[0] = 0;
+  for (int32_t u = 0; u < n; ++u) {
+    int64_t at = orow[u];
+    for (int64_t k = rowptr[u]; k < rowptr[u + 1]; ++k)
+      if (rank[col[k]] > rank[u]) ocol[at++] = col[k];
+    qsort(ocol + orow[u], (size_t)(at - orow[u]), sizeof(int32_t), cmp_i32);
+    orow[u + 1] = at;
+  }
+  return orow[n];
+}
+
 /* In-lists of the oriented graph (Algorithm 3's second loop walks them): for
  * rank r, every x with r in N+(x), in ascending rank x; ieid[j] is the index
  * in ocol of the edge <icol[j], r>.  Built as the transpose of the out-lists,

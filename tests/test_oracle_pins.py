@@ -479,6 +479,69 @@ def test_core_order_lists_the_same_set(seed):
     assert b.dplus.max() == d <= a.dplus.max()
 
 
+# ---------------------------------------------------------------- labels by id
+
+@pytest.mark.parametrize("n,p,seed", SMALL + [(300, 0.05, 99)])
+def test_orientation_by_id_keeps_the_edges_in_id_order(n, p, seed):
+    """Labels by id (AOT-randomOrder's local order, Section 4.3): the degree
+    order, computed here from scratch, still directs every edge; rows are
+    indexed by id and ascending in id."""
+    g = random_graph(n, p, seed)
+    rp, col = g.numpy()
+    o = oracle.orient(rp, col, local="id")
+    assert np.array_equal(o.perm, np.arange(n)) and np.array_equal(o.rank, np.arange(n))
+    deg = np.diff(rp)
+    key = deg.astype(np.int64) * (n + 1) + np.arange(n)        # (degree, id)
+    rows = np.repeat(np.arange(n), deg)
+    up = key[rows] < key[col]
+    want = sorted(zip(rows[up].tolist(), col[up].tolist()))
+    assert list(zip(o.tail().tolist(), o.ocol.tolist())) == want
+    assert o.m == g.m
+
+
+@pytest.mark.parametrize("n,p,seed", SMALL + [(60, 0.3, 61)])
+def test_list_by_id_is_the_brute_force_set_in_edge_order(n, p, seed):
+    g = random_graph(n, p, seed)
+    rp, col = g.numpy()
+    o = oracle.orient(rp, col, local="id")
+    tri = oracle.list_triangles(o)
+    assert as_set(tri) == brute_force(g)
+    # Sigma min does not depend on the labels
+    deg = np.diff(rp)
+    key = deg.astype(np.int64) * (n + 1) + np.arange(n)
+    rows = np.repeat(np.arange(n), deg)
+    up = key[rows] < key[col]
+    dplus = np.bincount(rows[up], minlength=n)
+    assert oracle.sum_min(o) == int(np.minimum(dplus[rows[up]], dplus[col[up]]).sum())
+    # per-edge counts from the oriented adjacency matrix
+    D = np.zeros((n, n), np.int64)
+    t = o.tail()
+    D[t, o.ocol] = 1
+    cnt = oracle.edge_counts(o)
+    assert np.array_equal(cnt, (D[t] * D[o.ocol]).sum(1) if o.m else cnt)
+    # order: edge by edge, each triangle holds both ends, third vertex ascending
+    off = np.concatenate([[0], np.cumsum(cnt)])
+    for e in range(o.m):
+        seg = tri[off[e]:off[e + 1]].tolist()
+        third = []
+        for row in seg:
+            assert t[e] in row and o.ocol[e] in row
+            third.append([x for x in row if x not in (t[e], o.ocol[e])][0])
+        assert third == sorted(set(third))
+
+
+def test_orientation_by_id_with_the_core_order():
+    csr = inputs.rmat(10, 16, 5)
+    rp, col = csr.numpy()
+    b = oracle.orient(rp, col, "core", local="id")
+    a = oracle.orient(rp, col, "core")
+    # the same directed edges, named by original id
+    ea = sorted(zip(a.perm[a.tail()].tolist(), a.perm[a.ocol].tolist()))
+    eb = list(zip(b.tail().tolist(), b.ocol.tolist()))
+    assert eb == ea
+    assert oracle.sum_min(a) == oracle.sum_min(b)
+
+
 # ---------------------------------------------------------------- edge support
 
 @pytest.mark.parametrize("seed", range(6))
