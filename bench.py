@@ -249,16 +249,22 @@ ABLATION_NOTE = ("count + list of the whole graph per (order, probe strategy): a
                  "merge = CF's merge intersections (Algorithm 1); per_edge = min side into "
                  "the larger list edge by edge, no per-owner index (CF-Hash); core_* = the "
                  "same on the core order (core_head: kClist's order and cost), whose "
-                 "ms_orient includes the peeling")
-ABLATION_CASES = (("aot", "degree", "aot"), ("head", "degree", "head"),
-                  ("merge", "degree", "merge"), ("per_edge", "degree", "per_edge"),
-                  ("core_aot", "core", "aot"), ("core_head", "core", "head"))
+                 "ms_orient includes the peeling; random_order = aot with original ids as "
+                 "labels, i.e. a random local order on these permuted-id inputs "
+                 "(AOT-randomOrder)")
+# (name, order, labels, probe strategy)
+ABLATION_CASES = (("aot", "degree", "rank", "aot"), ("head", "degree", "rank", "head"),
+                  ("merge", "degree", "rank", "merge"),
+                  ("per_edge", "degree", "rank", "per_edge"),
+                  ("random_order", "degree", "id", "aot"),
+                  ("core_aot", "core", "rank", "aot"), ("core_head", "core", "rank", "head"))
 
 
 def ablation_leg(aot, csr, o, ows, cws, tri_off, out, T, args):
     """Section 4's comparisons on this graph: the same count + list with each
-    probe strategy, on the degree order and on the core order.  All give the
-    same triangles; probes are each strategy's cost on that order."""
+    probe strategy, on the degree order and on the core order, and with the
+    local order of Section 3.2 replaced by id order.  All give the same
+    triangles; probes are each strategy's cost on that order."""
     import torch
 
     def med(xs):
@@ -266,22 +272,23 @@ def ablation_leg(aot, csr, o, ows, cws, tri_off, out, T, args):
 
     reps = max(args.steps, 3)
     res = {}
-    oriented = {"degree": o}
-    orient_ms = {"degree": None}
-    for name, order, strategy in ABLATION_CASES:
-        if order not in oriented:
+    oriented = {("degree", "rank"): o}
+    orient_ms = {("degree", "rank"): None}
+    for name, order, labels, strategy in ABLATION_CASES:
+        key = (order, labels)
+        if key not in oriented:
             oo = aot.alloc_oriented(csr.n, csr.m, csr.rowptr.device)
             ts = []
             for r in range(reps + 1):
                 ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
                 ev[0].record()
-                aot.orient(csr.rowptr, csr.col, out=oo, ws=ows, order=order)
+                aot.orient(csr.rowptr, csr.col, out=oo, ws=ows, order=order, local=labels)
                 ev[1].record()
                 ev[1].synchronize()
                 if r:
                     ts.append(ev[0].elapsed_time(ev[1]))
-            oriented[order], orient_ms[order] = oo, med(ts)
-        oo = oriented[order]
+            oriented[key], orient_ms[key] = oo, med(ts)
+        oo = oriented[key]
         d = aot.Dispatch(strategy=aot.STRATEGIES[strategy])
         cc = aot.count(oo, d, ws=cws, tri_off=tri_off)
         aot.list_triangles(oo, cc, out=out)
@@ -299,12 +306,13 @@ def ablation_leg(aot, csr, o, ows, cws, tri_off, out, T, args):
             tl.append(ev[1].elapsed_time(ev[2]))
         ms_c, ms_l = med(tc), med(tl)
         dmax = int((oo.rowptr[1:] - oo.rowptr[:-1]).max()) if csr.n else 0
-        res[name] = {"order": order, "strategy": strategy, "probes": cc.probes,
-                     "max_out_degree": dmax, "ms_orient": orient_ms[order],
+        res[name] = {"order": order, "labels": labels, "strategy": strategy,
+                     "probes": cc.probes,
+                     "max_out_degree": dmax, "ms_orient": orient_ms[key],
                      "ms_count": ms_c, "ms_list": ms_l,
                      "triangles_per_s": T / ((ms_c + ms_l) / 1000.0)}
         log(f"[bench] {name}: probes {cc.probes} count {ms_c:.3f} ms list {ms_l:.3f} ms"
-            + (f" (orient {orient_ms[order]:.3f} ms)" if orient_ms[order] else ""))
+            + (f" (orient {orient_ms[key]:.3f} ms)" if orient_ms[key] else ""))
     base = res["aot"]["ms_count"] + res["aot"]["ms_list"]
     for r in res.values():
         r["aot_speedup"] = (r["ms_count"] + r["ms_list"]) / base

@@ -62,12 +62,15 @@ extern "C" {
                                     makes windows of a very large triangle
                                     list cost about their own triangles     */
 #define AOT_ORDER_CORE 4u     /* rank by the core order instead of degree   */
+#define AOT_LOCAL_BY_ID 8u    /* keep original ids as labels (random local
+                                 order for inputs with permuted ids)        */
 
 /* Text for a status code; never NULL. */
 const char* aot_status_str(int status);
 /* Detail of the last failing call on this thread ("" if none). */
 const char* aot_last_error(void);
-/* ABI version, currently 2 (aot_dispatch.strategy, AOT_ORDER_CORE, aot_support). */
+/* ABI version, currently 3 (aot_dispatch.strategy, AOT_ORDER_CORE, aot_support,
+ * AOT_LOCAL_BY_ID). */
 int aot_version(void);
 
 /* Input graph (device pointers). */
@@ -78,9 +81,12 @@ typedef struct aot_graph {
   const int32_t* col;     /* device, [nnz] */
 } aot_graph;
 
-/* Oriented graph in rank space: vertex r is the r-th vertex of the order eta
- * (degree ascending, ties by smaller original id; or the core order).  All arrays are device
- * memory owned by the caller; aot_orient fills them.  m = nnz / 2. */
+/* Oriented graph in label space.  By default the label of a vertex is its rank:
+ * vertex r is the r-th vertex of the order eta (degree ascending, ties by
+ * smaller original id; or the core order).  With AOT_LOCAL_BY_ID the label is
+ * the original id (perm and rank are then the identity); eta still directs the
+ * edges.  Below, "rank" means the label.  All arrays are device memory owned
+ * by the caller; aot_orient fills them.  m = nnz / 2. */
 typedef struct aot_oriented {
   int32_t n;
   int64_t m;
@@ -102,7 +108,8 @@ typedef struct aot_oriented {
  * taken ascending in rank space).  Also builds the in-lists that Algorithm 3's
  * second loop walks.
  *   g       input graph (device arrays).
- *   flags   0 or AOT_VALIDATE | AOT_IN_LISTS_BY_RANK | AOT_ORDER_CORE.
+ *   flags   0 or AOT_VALIDATE | AOT_IN_LISTS_BY_RANK | AOT_ORDER_CORE |
+ *           AOT_LOCAL_BY_ID.
  *           AOT_ORDER_CORE: rank by the core (degeneracy) order that kClist
  *           orients by (Section 2.3) instead of degree; AOT works on any
  *           total order (Section 3.2).  The order is synchronous peeling:
@@ -111,6 +118,14 @@ typedef struct aot_oriented {
  *           current degree <= level; ranks follow (sub-round, id).  Then
  *           deg+(r) <= the degeneracy.  Costs a few launches and one host
  *           read per 16 sub-rounds.
+ *           AOT_LOCAL_BY_ID: the order still directs every edge, but
+ *           vertices keep their original ids as labels, so each out-list is
+ *           in ascending id instead of the degree local order (Section 3.2).
+ *           On inputs whose ids are randomly permuted this is the random
+ *           local order of AOT-randomOrder (Section 4.3).  Rows are indexed
+ *           by id, perm and rank are the identity, and both in-list orders
+ *           coincide (ascending id).  Counts, the probe count and the
+ *           triangle set do not change; the list order follows the labels.
  *   out     caller-allocated arrays of the sizes listed in aot_oriented;
  *           out->n and out->m are written.
  *   ws      device workspace of at least aot_orient_workspace() bytes.

@@ -16,11 +16,12 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libaot.so")
 
-ABI_VERSION = 2          # the aot_version() this binding's structs match
+ABI_VERSION = 3          # the aot_version() this binding's structs match
 AOT_OK = 0
 AOT_VALIDATE = 1
 AOT_IN_LISTS_BY_RANK = 2
 AOT_ORDER_CORE = 4
+AOT_LOCAL_BY_ID = 8
 AOT_DISPATCH_PLAIN = 0
 AOT_DISPATCH_TABLE = 1
 AOT_DISPATCH_LEARNED = 2
@@ -318,11 +319,16 @@ def alloc_oriented(n: int, m: int, device) -> Oriented:
 
 def orient(rowptr: torch.Tensor, col: torch.Tensor, validate: bool = False, stream=None,
            ws: torch.Tensor | None = None, out: Oriented | None = None,
-           in_by_rank: bool = False, order: str = "degree") -> Oriented:
+           in_by_rank: bool = False, order: str = "degree", local: str = "rank") -> Oriented:
     """aot_orient on a symmetric device CSR (rowptr int64[n+1], col int32[nnz]);
-    order "degree" (Algorithm 3) or "core" (kClist's, AOT_ORDER_CORE)."""
+    order "degree" (Algorithm 3) or "core" (kClist's, AOT_ORDER_CORE); local
+    "rank" (labels are ranks: the degree local order of Section 3.2) or "id"
+    (labels are original ids, AOT_LOCAL_BY_ID: AOT-randomOrder of Section 4.3
+    on inputs with permuted ids)."""
     if order not in ("degree", "core"):
         raise ValueError(f"unknown order {order!r}")
+    if local not in ("rank", "id"):
+        raise ValueError(f"unknown local order {local!r}")
     assert rowptr.dtype == torch.int64 and col.dtype == torch.int32
     assert rowptr.is_contiguous() and col.is_contiguous()
     dev = rowptr.device
@@ -337,7 +343,7 @@ def orient(rowptr: torch.Tensor, col: torch.Tensor, validate: bool = False, stre
     g = Graph(n, nnz, _ptr(rowptr) or ctypes.c_void_p(rowptr.data_ptr()), _ptr(col))
     oc = o.cstruct()
     flags = (AOT_VALIDATE if validate else 0) | (AOT_IN_LISTS_BY_RANK if in_by_rank else 0) | (
-        AOT_ORDER_CORE if order == "core" else 0)
+        AOT_ORDER_CORE if order == "core" else 0) | (AOT_LOCAL_BY_ID if local == "id" else 0)
     _check(load().aot_orient(ctypes.byref(g), flags, ctypes.byref(oc),
                              _ptr(ws), ws.numel(), _stream(stream)), "aot_orient")
     return o

@@ -172,7 +172,7 @@ const char* aot_status_str(int status) {
 
 const char* aot_last_error(void) { return g_err.c_str(); }
 
-int aot_version(void) { return 2; }
+int aot_version(void) { return 3; }
 
 int aot_orient_workspace(int32_t n, int64_t nnz, size_t* bytes) {
   if (!bytes) return fail(AOT_E_ARG, "bytes is NULL");
@@ -185,7 +185,7 @@ int aot_orient_workspace(int32_t n, int64_t nnz, size_t* bytes) {
 int aot_orient(const aot_graph* g, uint32_t flags, aot_oriented* out, void* ws, size_t ws_bytes,
                void* stream) {
   if (!g || !out) return fail(AOT_E_ARG, "graph or output is NULL");
-  if (flags & ~(AOT_VALIDATE | AOT_IN_LISTS_BY_RANK | AOT_ORDER_CORE))
+  if (flags & ~(AOT_VALIDATE | AOT_IN_LISTS_BY_RANK | AOT_ORDER_CORE | AOT_LOCAL_BY_ID))
     return fail(AOT_E_ARG, "unknown flag");
   int rc = check_graph_sizes(g->n, g->nnz);
   if (rc) return rc;
@@ -204,7 +204,7 @@ int aot_orient(const aot_graph* g, uint32_t flags, aot_oriented* out, void* ws, 
   const char* err = nullptr;
   rc = aot::orient_run(g->n, g->nnz, g->rowptr, g->col, (flags & AOT_VALIDATE) != 0,
                        (flags & AOT_IN_LISTS_BY_RANK) != 0, (flags & AOT_ORDER_CORE) != 0,
-                       out->rowptr,
+                       (flags & AOT_LOCAL_BY_ID) != 0, out->rowptr,
                        out->col, out->tail, out->perm, out->rank, out->in_rowptr, out->in_col,
                        ws, ws_bytes, static_cast<hipStream_t>(stream), &err);
   return hip_status(rc, err);

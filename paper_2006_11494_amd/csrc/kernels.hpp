@@ -60,7 +60,8 @@ struct OrientScratch {
 };
 size_t orient_workspace_bytes(int32_t n, int64_t nnz);
 int orient_run(int32_t n, int64_t nnz, const int64_t* rowptr, const int32_t* col, bool validate,
-               bool in_by_rank, bool core, int64_t* orow, int32_t* ocol, int32_t* otail, int32_t* perm,
+               bool in_by_rank, bool core, bool by_id, int64_t* orow, int32_t* ocol, int32_t* otail,
+               int32_t* perm,
                int32_t* rank, int64_t* irow, int32_t* icol, void* ws, size_t ws_bytes,
                hipStream_t s, const char** err);
 // Orientation of a batch held as one block-diagonal CSR (graph g owns

@@ -10,6 +10,12 @@
 // rank, so the sort step first bins rows by length.  On request, in-lists are
 // sorted the same way into ascending rank, which is the order of their edges'
 // ids (this makes windows of a huge triangle list cheap; see aot_list).
+//
+// Labels by id (AOT-randomOrder of Section 4.3): the order still directs every
+// edge, but vertices keep their original ids as labels, so an out-list is in
+// ascending id instead of the degree local order of Section 3.2; with
+// randomly permuted ids that is a random local order.  Rows are then written
+// at their id, and perm/rank are the identity.
 #include <algorithm>
 #include <climits>
 
@@ -315,6 +321,16 @@ __global__ __launch_bounds__(kBlock) void k_perm_rank(int32_t n, const int32_t* 
   }
 }
 
+// perm and rank when labels stay original ids: both the identity.
+__global__ __launch_bounds__(kBlock) void k_identity(int32_t n, int32_t* __restrict__ perm,
+                                                     int32_t* __restrict__ rank) {
+  for (int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x; r < n;
+       r += (int64_t)gridDim.x * kBlock) {
+    perm[r] = (int32_t)r;
+    rank[r] = (int32_t)r;
+  }
+}
+
 // Sort keys of a batch of graphs held as one block-diagonal CSR: vertex v of
 // graph g (voff[g] <= v < voff[g+1]) gets key (g << dbits) | deg(v), so the
 // stable sort ranks graph by graph and, inside a graph, by (degree, id).
@@ -367,6 +383,7 @@ __global__ __launch_bounds__(kBlock) void k_orient_count(RowSet rs,
                                                          const int32_t* __restrict__ col,
                                                          const int32_t* __restrict__ perm,
                                                          const int32_t* __restrict__ rank,
+                                                         bool by_id,
                                                          int32_t* __restrict__ dplus,
                                                          int32_t* __restrict__ dminus) {
   constexpr int kGroups = kBlock / G;
@@ -379,9 +396,10 @@ __global__ __launch_bounds__(kBlock) void k_orient_count(RowSet rs,
     const bool live = tb + gi < total;
     const int64_t r = live ? rs.at(base, tb + gi) : 0;
     int32_t cnt = 0;
-    int64_t deg = 0;
+    int64_t deg = 0, o = 0;
     if (live) {
       const int32_t u = perm[r];
+      o = by_id ? (int64_t)u : r;        // the row's label
       const int64_t beg = rowptr[u];
       deg = rowptr[u + 1] - beg;
       if constexpr (G == kBlock) {
@@ -407,26 +425,29 @@ __global__ __launch_bounds__(kBlock) void k_orient_count(RowSet rs,
     if constexpr (G <= kWave) {
       cnt = group_sum<G>(cnt);
       if (li == 0 && live) {
-        dplus[r] = cnt;
-        dminus[r] = (int32_t)(deg - cnt);
+        dplus[o] = cnt;
+        dminus[o] = (int32_t)(deg - cnt);
       }
     } else {
       cnt = block_sum(cnt, red);
       if (threadIdx.x == 0) {
-        dplus[r] = cnt;
-        dminus[r] = (int32_t)(deg - cnt);
+        dplus[o] = cnt;
+        dminus[o] = (int32_t)(deg - cnt);
       }
     }
   }
 }
 
 // Splits every row into its out-part (unsorted, original order) and in-part
-// (original order), and records each out-edge's tail.
+// (original order), and records each out-edge's tail.  r is the row's rank,
+// o its label: the rank itself, or with labels by id the original id, in
+// which case entries are written as original ids too.
 // Rows of one workgroup (G == kBlock): kRowUnroll chunks of kBlock entries
 // per step, ranked with one pair of barriers per step.
 template <int G>
-__device__ __forceinline__ void orient_write_long(int64_t r, int64_t beg, int64_t deg, int64_t op,
-                                                  int64_t ip, const int32_t* __restrict__ col,
+__device__ __forceinline__ void orient_write_long(int64_t r, int64_t o, bool by_id, int64_t beg,
+                                                  int64_t deg, int64_t op, int64_t ip,
+                                                  const int32_t* __restrict__ col,
                                                   const int32_t* __restrict__ rank,
                                                   int32_t* __restrict__ unsorted,
                                                   int32_t* __restrict__ otail,
@@ -447,7 +468,7 @@ __device__ __forceinline__ void orient_write_long(int64_t r, int64_t beg, int64_
     for (int q = 0; q < kRowUnroll; ++q) {
       const bool valid = out[q];
       const int32_t x = rank[rv[q]];
-      rv[q] = x;
+      if (!by_id) rv[q] = x;
       out[q] = valid && x > r;
       in[q] = valid && x < r;
       bo[q] = ballot(out[q]);
@@ -468,7 +489,7 @@ __device__ __forceinline__ void orient_write_long(int64_t r, int64_t beg, int64_
       if (out[q]) {
         const int64_t at = op + ao + wo + popc_below(bo[q]);
         unsorted[at] = rv[q];
-        otail[at] = (int32_t)r;
+        otail[at] = (int32_t)o;
       }
       if (in[q]) icol[ip + ai + wi + popc_below(bi[q])] = rv[q];
       ao += to;
@@ -483,7 +504,7 @@ __device__ __forceinline__ void orient_write_long(int64_t r, int64_t beg, int64_
 template <int G>
 __global__ __launch_bounds__(kBlock) void k_orient_write(
     RowSet rs, const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
-    const int32_t* __restrict__ perm, const int32_t* __restrict__ rank,
+    const int32_t* __restrict__ perm, const int32_t* __restrict__ rank, bool by_id,
     const int64_t* __restrict__ orow, const int64_t* __restrict__ irow,
     int32_t* __restrict__ unsorted, int32_t* __restrict__ otail, int32_t* __restrict__ icol) {
   constexpr int kGroups = kBlock / G;
@@ -496,24 +517,27 @@ __global__ __launch_bounds__(kBlock) void k_orient_write(
        tb += (int64_t)gridDim.x * kGroups) {
     const bool live = tb + gi < total;
     const int64_t r = live ? rs.at(base, tb + gi) : 0;
-    int64_t beg = 0, deg = 0, op = 0, ip = 0;
+    int64_t beg = 0, deg = 0, op = 0, ip = 0, o = 0;
     if (live) {
       const int32_t u = perm[r];
+      o = by_id ? (int64_t)u : r;
       beg = rowptr[u];
       deg = rowptr[u + 1] - beg;
-      op = orow[r];
-      ip = irow[r];
+      op = orow[o];
+      ip = irow[o];
     }
     if constexpr (G == kBlock) {
-      orient_write_long<G>(r, beg, deg, op, ip, col, rank, unsorted, otail, icol);
+      orient_write_long<G>(r, o, by_id, beg, deg, op, ip, col, rank, unsorted, otail, icol);
       continue;
     }
     for (int64_t j0 = 0; j0 < deg; j0 += G) {
       const int64_t j = j0 + li;
       const bool valid = j < deg;
-      const int32_t rv = valid ? rank[col[beg + j]] : 0;
-      const bool out = valid && rv > r;
-      const bool in = valid && rv < r;
+      const int32_t cv = valid ? col[beg + j] : 0;
+      const int32_t x = valid ? rank[cv] : 0;
+      const int32_t rv = by_id ? cv : x;
+      const bool out = valid && x > r;
+      const bool in = valid && x < r;
       const uint64_t bo = ballot(out), bi = ballot(in);
       int32_t po, pi, to, ti;
       if constexpr (G <= kWave) {
@@ -536,7 +560,7 @@ __global__ __launch_bounds__(kBlock) void k_orient_write(
       }
       if (out) {
         unsorted[op + po] = rv;
-        otail[op + po] = (int32_t)r;
+        otail[op + po] = (int32_t)o;
       }
       if (in) icol[ip + pi] = rv;
       op += to;
@@ -972,7 +996,8 @@ int core_order(int32_t n, const int64_t* rowptr, const int32_t* col, int32_t* ke
 }
 
 int orient_impl(int32_t n, int64_t nnz, const int64_t* rowptr, const int32_t* col, bool validate,
-                bool in_by_rank, bool core, const BatchKeys* bk, int64_t* orow, int32_t* ocol,
+                bool in_by_rank, bool core, bool by_id, const BatchKeys* bk, int64_t* orow,
+                int32_t* ocol,
                 int32_t* otail,
                 int32_t* perm, int32_t* rank, int64_t* irow, int32_t* icol, void* ws,
                 size_t ws_bytes, hipStream_t s, const char** err) {
@@ -1050,8 +1075,17 @@ int orient_impl(int32_t n, int64_t nnz, const int64_t* rowptr, const int32_t* co
   }
   int32_t *sk, *sv;
   AOT_TRY(radix_sort_pairs(key_a, val_a, key_b, val_b, n, bits, radix_tmp, s, &sk, &sv));
-  k_perm_rank<<<grid_for(n, kBlock), kBlock, 0, s>>>(n, sv, perm, rank);
+  // With labels by id, the order eta (rank -> id, id -> rank) only directs
+  // the edges: it goes to the two key buffers, free once the sorted ids sv
+  // (a value buffer) are read, and perm/rank become the identity.
+  int32_t* eperm = by_id ? key_a : perm;
+  int32_t* erank = by_id ? key_b : rank;
+  k_perm_rank<<<grid_for(n, kBlock), kBlock, 0, s>>>(n, sv, eperm, erank);
   AOT_TRY(hipGetLastError());
+  if (by_id) {
+    k_identity<<<grid_for(n, kBlock), kBlock, 0, s>>>(n, perm, rank);
+    AOT_TRY(hipGetLastError());
+  }
 
   // Row sets of the four row-group widths.  Single graph: rank order is
   // degree order, so each is a rank range.  Batch: ranks go graph by graph,
@@ -1071,33 +1105,37 @@ int orient_impl(int32_t n, int64_t nnz, const int64_t* rowptr, const int32_t* co
     AOT_TRY(fill_i32(dplus, n, 0, s));
     AOT_TRY(fill_i32(dminus, n, 0, s));
     k_count_classes<kRowsByDegree><<<std::min(grid_for(n, kBlock), 1024u), kBlock, 0, s>>>(
-        n, dplus, perm, rowptr, counters);
+        n, dplus, eperm, rowptr, counters);
     AOT_TRY(hipGetLastError());
-    k_scatter_classes<kRowsByDegree><<<grid_for(n, kClassChunk), kBlock, 0, s>>>(n, dplus, perm, rowptr,
+    k_scatter_classes<kRowsByDegree><<<grid_for(n, kClassChunk), kBlock, 0, s>>>(n, dplus, eperm, rowptr,
                                                                    counters, rows);
     AOT_TRY(hipGetLastError());
   } else {
-    AOT_TRY(fill_i32(dplus, c0, 0, s));
-    AOT_TRY(fill_i32(dminus, c0, 0, s));
+    // rows of degree 0 are not visited: the first c0 ranks, or with labels
+    // by id anywhere
+    AOT_TRY(fill_i32(dplus, by_id ? n : c0, 0, s));
+    AOT_TRY(fill_i32(dminus, by_id ? n : c0, 0, s));
   }
 #define ROWS(q, G, KERNEL, ...)                                                          \
   AOT_TRY(launch_rows<G>(sets[q], bound[q], s,                                          \
                          [&](const RowSet& rs, unsigned grid, hipStream_t st) {          \
                            KERNEL<G><<<grid, kBlock, 0, st>>>(rs, __VA_ARGS__);          \
                          }))
-  ROWS(0, 4, k_orient_count, rowptr, col, perm, rank, dplus, dminus);
-  ROWS(1, 16, k_orient_count, rowptr, col, perm, rank, dplus, dminus);
-  ROWS(2, 64, k_orient_count, rowptr, col, perm, rank, dplus, dminus);
-  ROWS(3, 256, k_orient_count, rowptr, col, perm, rank, dplus, dminus);
+  ROWS(0, 4, k_orient_count, rowptr, col, eperm, erank, by_id, dplus, dminus);
+  ROWS(1, 16, k_orient_count, rowptr, col, eperm, erank, by_id, dplus, dminus);
+  ROWS(2, 64, k_orient_count, rowptr, col, eperm, erank, by_id, dplus, dminus);
+  ROWS(3, 256, k_orient_count, rowptr, col, eperm, erank, by_id, dplus, dminus);
   AOT_TRY(exclusive_scan(dplus, orow, n, scan_tmp, s));
   AOT_TRY(exclusive_scan(dminus, irow, n, scan_tmp, s));
-  ROWS(0, 4, k_orient_write, rowptr, col, perm, rank, orow, irow, unsorted, otail, icol);
-  ROWS(1, 16, k_orient_write, rowptr, col, perm, rank, orow, irow, unsorted, otail, icol);
-  ROWS(2, 64, k_orient_write, rowptr, col, perm, rank, orow, irow, unsorted, otail, icol);
-  ROWS(3, 256, k_orient_write, rowptr, col, perm, rank, orow, irow, unsorted, otail, icol);
+  ROWS(0, 4, k_orient_write, rowptr, col, eperm, erank, by_id, orow, irow, unsorted, otail, icol);
+  ROWS(1, 16, k_orient_write, rowptr, col, eperm, erank, by_id, orow, irow, unsorted, otail, icol);
+  ROWS(2, 64, k_orient_write, rowptr, col, eperm, erank, by_id, orow, irow, unsorted, otail, icol);
+  ROWS(3, 256, k_orient_write, rowptr, col, eperm, erank, by_id, orow, irow, unsorted, otail, icol);
 #undef ROWS
 
-  // sort each out-list into ocol
+  // sort each out-list into ocol (with labels by id, rows of a valid CSR
+  // are already ascending; the sort still guarantees it for the probe
+  // kernels' windows and searches)
   k_count_classes<kOutLists><<<std::min(grid_for(n, kBlock), 1024u), kBlock, 0, s>>>(
       n, dplus, perm, rowptr, counters);
   AOT_TRY(hipGetLastError());
@@ -1126,11 +1164,11 @@ int orient_impl(int32_t n, int64_t nnz, const int64_t* rowptr, const int32_t* co
 }  // namespace
 
 int orient_run(int32_t n, int64_t nnz, const int64_t* rowptr, const int32_t* col, bool validate,
-               bool in_by_rank, bool core, int64_t* orow, int32_t* ocol, int32_t* otail,
+               bool in_by_rank, bool core, bool by_id, int64_t* orow, int32_t* ocol, int32_t* otail,
                int32_t* perm, int32_t* rank, int64_t* irow, int32_t* icol, void* ws,
                size_t ws_bytes, hipStream_t s, const char** err) {
-  return orient_impl(n, nnz, rowptr, col, validate, in_by_rank, core, nullptr, orow, ocol, otail,
-                     perm, rank, irow, icol, ws, ws_bytes, s, err);
+  return orient_impl(n, nnz, rowptr, col, validate, in_by_rank, core, by_id, nullptr, orow, ocol,
+                     otail, perm, rank, irow, icol, ws, ws_bytes, s, err);
 }
 
 int orient_batch_run(int32_t n, int64_t nnz, const int64_t* rowptr, const int32_t* col,
@@ -1138,7 +1176,7 @@ int orient_batch_run(int32_t n, int64_t nnz, const int64_t* rowptr, const int32_
                      int32_t* ocol, int32_t* otail, int32_t* perm, int32_t* rank, int64_t* irow,
                      int32_t* icol, void* ws, size_t ws_bytes, hipStream_t s, const char** err) {
   BatchKeys bk{voff, count, dbits, dbits + gbits};
-  return orient_impl(n, nnz, rowptr, col, false, false, false, &bk, orow, ocol, otail, perm, rank,
+  return orient_impl(n, nnz, rowptr, col, false, false, false, false, &bk, orow, ocol, otail, perm, rank,
                      irow,
                      icol,
                      ws, ws_bytes, s, err);

@@ -31,7 +31,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_version_and_status_strings():
     lib = aot.load()
-    assert lib.aot_version() == aot.ABI_VERSION == 2
+    assert lib.aot_version() == aot.ABI_VERSION == 3
     for code in (0, -1, -2, -3, -4, -5, -6, -7):
         assert lib.aot_status_str(code)
     assert lib.aot_status_str(12345) == b"unknown status"
@@ -76,7 +76,7 @@ def test_orient_argument_errors():
     call = lambda gg, flags, oo, ws, nb: lib.aot_orient(gg, flags, oo, ws, nb, None)
     assert call(None, 0, ctypes.byref(o), FAKE, ok_ws) == -1
     assert call(ctypes.byref(g), 0, None, FAKE, ok_ws) == -1
-    assert call(ctypes.byref(g), 8, ctypes.byref(o), FAKE, ok_ws) == -1           # unknown flag
+    assert call(ctypes.byref(g), 16, ctypes.byref(o), FAKE, ok_ws) == -1          # unknown flag
     assert call(ctypes.byref(aot.Graph(-1, 6, FAKE, FAKE)), 0, ctypes.byref(o), FAKE, ok_ws) == -1
     assert call(ctypes.byref(aot.Graph(4, 5, FAKE, FAKE)), 0, ctypes.byref(o), FAKE, ok_ws) == -2
     assert call(ctypes.byref(aot.Graph(4, 6, None, FAKE)), 0, ctypes.byref(o), FAKE, ok_ws) == -1

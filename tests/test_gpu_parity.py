@@ -48,9 +48,9 @@ DISPATCHES = {
 }
 
 
-def reference(csr, order="degree"):
+def reference(csr, order="degree", local="rank"):
     rp, col = csr.numpy()
-    o = oracle.orient(rp, col, order)
+    o = oracle.orient(rp, col, order, local)
     irow, icol, ieid = oracle.in_lists(o)
     return o, irow, icol, ieid
 
@@ -79,20 +79,20 @@ def check_orientation(o_gpu, ref, in_by_rank=False):
     assert np.all(ids[1:][same_row] > ids[:-1][same_row])
 
 
-def check_all(csr, name, dispatches=DISPATCHES, windows=True, order="degree"):
+def check_all(csr, name, dispatches=DISPATCHES, windows=True, order="degree", local="rank"):
     need_gpu()
-    ref = reference(csr, order)
+    ref = reference(csr, order, local)
     o_ref = ref[0]
     cnt_ref = oracle.edge_counts(o_ref)
     T = int(cnt_ref.sum())
     probes = oracle.sum_min(o_ref)
     tri_ref = oracle.list_triangles(o_ref)
     g = csr.to(DEV)
-    say(f"[gpu] orient {name} n={csr.n} m={csr.m} order={order}")
-    o = aot.orient(g.rowptr, g.col, validate=True, order=order)
+    say(f"[gpu] orient {name} n={csr.n} m={csr.m} order={order} local={local}")
+    o = aot.orient(g.rowptr, g.col, validate=True, order=order, local=local)
     torch.cuda.synchronize()
     check_orientation(o, ref)
-    ob = aot.orient(g.rowptr, g.col, in_by_rank=True, order=order)
+    ob = aot.orient(g.rowptr, g.col, in_by_rank=True, order=order, local=local)
     torch.cuda.synchronize()
     check_orientation(ob, ref, in_by_rank=True)
     for dname, d in dispatches.items():
@@ -164,7 +164,7 @@ def test_small_graphs(name):
     check_all(SMALL[name], name)
 
 
-def test_example1():
+def example1_edges():
     import os
     edges = []
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "example1.txt")
@@ -172,8 +172,12 @@ def test_example1():
         p = line.split()
         if p and p[0] == "edge":
             edges.append((int(p[1]) - 1, int(p[2]) - 1))
+    return edges
+
+
+def test_example1():
     need_gpu()
-    g = graph(14, edges)
+    g = graph(14, example1_edges())
     o = check_all(g, "example1")
     c = aot.count(o)
     assert (c.T, c.probes) == (6, 12)      # probes: Example 1's sum of minima
@@ -202,6 +206,35 @@ def test_long_out_lists():
     u = torch.arange(a, dtype=torch.int64).repeat_interleave(b)
     v = a + torch.arange(b, dtype=torch.int64).repeat(a)
     check_all(inputs.csr_from_pairs(a + b, u, v), "k_4100_4200",
+              dispatches={"plain": None}, windows=False)
+
+
+@pytest.mark.parametrize("name", ["empty", "isolated", "tiebreak", "k40", "wheel50", "star300",
+                                  "rand_a", "rand_b", "rand_c", "dense_c", "er2000", "rmat14",
+                                  "chunglu60k", "example1"])
+def test_labels_by_id(name):
+    """AOT_LOCAL_BY_ID (AOT-randomOrder's local order): orientation, counts,
+    the probe count and the list in id-labelled order, every dispatch."""
+    if name in SMALL:
+        g = SMALL[name]
+    elif name == "er2000":
+        g = inputs.workload("er2000")
+    elif name == "rmat14":
+        g = inputs.rmat(14, 16, 21)
+    elif name == "chunglu60k":
+        g = inputs.chung_lu(60000, 20.0, 2.1, 3000.0, 22)
+    else:
+        g = graph(14, example1_edges())
+    check_all(g, name, local="id")
+
+
+def test_labels_by_id_core_order_and_long_lists():
+    check_all(inputs.rmat(13, 16, 24), "rmat13_core", order="core", local="id",
+              dispatches={"plain": None, "all_heavy_hash": DISPATCHES["all_heavy_hash"]})
+    a, b = 1100, 1200
+    u = torch.arange(a, dtype=torch.int64).repeat_interleave(b)
+    v = a + torch.arange(b, dtype=torch.int64).repeat(a)
+    check_all(inputs.csr_from_pairs(a + b, u, v), "k_1100_1200", local="id",
               dispatches={"plain": None}, windows=False)
 
 

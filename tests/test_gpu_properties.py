@@ -1,5 +1,5 @@
-"""GPU parity on random simple graphs drawn by hypothesis: for both orders
-and every probe strategy, the orientation, per-edge counts, probe count,
+"""GPU parity on random simple graphs drawn by hypothesis: for both orders,
+both labellings (ranks, or original ids) and every probe strategy, the orientation, per-edge counts, probe count,
 ordered list and per-edge support equal the oracle's."""
 
 import itertools
@@ -30,19 +30,19 @@ def graphs(draw, max_n=48):
 
 
 @settings(max_examples=40, deadline=None, suppress_health_check=[HealthCheck.too_slow])
-@given(graphs(), st.sampled_from(["degree", "core"]))
-def test_gpu_equals_oracle(g, order):
+@given(graphs(), st.sampled_from(["degree", "core"]), st.sampled_from(["rank", "id"]))
+def test_gpu_equals_oracle(g, order, local):
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     n, edges = g
     c = inputs.csr_from_edges_np(n, edges)
     rp, col = c.numpy()
-    ref = oracle.orient(rp, col, order)
+    ref = oracle.orient(rp, col, order, local)
     cnt = oracle.edge_counts(ref)
     tri = oracle.list_triangles(ref)
     sup = oracle.edge_support(rp, col, ref)
     d = c.to("cuda")
-    o = aot.orient(d.rowptr, d.col, validate=True, order=order)
+    o = aot.orient(d.rowptr, d.col, validate=True, order=order, local=local)
     assert np.array_equal(o.perm.cpu().numpy(), ref.perm)
     assert np.array_equal(o.rowptr.cpu().numpy(), ref.orow)
     assert np.array_equal(o.col.cpu().numpy(), ref.ocol)

@@ -54,15 +54,15 @@ def cost(o_ref, strategy):
             "merge": oracle.sum_merge}[strategy](o_ref)
 
 
-def check_strategies(csr, name, cases=CASES, windows=True):
+def check_strategies(csr, name, cases=CASES, windows=True, local="rank"):
     need_gpu()
     rp, col = csr.numpy()
-    o_ref = oracle.orient(rp, col)
+    o_ref = oracle.orient(rp, col, local=local)
     cnt_ref = oracle.edge_counts(o_ref)
     T = int(cnt_ref.sum())
     tri_ref = oracle.list_triangles(o_ref)
     g = csr.to(DEV)
-    o = aot.orient(g.rowptr, g.col)
+    o = aot.orient(g.rowptr, g.col, local=local)
     for cname, (strategy, d) in cases.items():
         say(f"[gpu] strategy {name} {cname}")
         c = aot.count(o, d)
@@ -114,6 +114,14 @@ def test_rmat14():
 def test_chung_lu_small():
     check_strategies(inputs.chung_lu(60000, 20.0, 2.1, 3000.0, 22), "chunglu60k",
                      windows=False)
+
+
+@pytest.mark.parametrize("name", ["rand_b", "dense_c", "wheel50", "rmat14"])
+def test_labels_by_id(name):
+    """Every strategy on the id-labelled orientation (AOT-randomOrder's local
+    order): same counts, costs and list as the oracle's id-labelled graph."""
+    csr = SMALL[name] if name in SMALL else inputs.rmat(14, 16, 21)
+    check_strategies(csr, name + "_by_id", local="id", windows=name != "rmat14")
 
 
 def test_long_lists_merge():
