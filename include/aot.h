@@ -149,8 +149,9 @@ int aot_orient(const aot_graph* g, uint32_t flags, aot_oriented* out,
  *               {4, 8, 16, 32, 64} lanes per edge; entry 16 + h (heavy class h)
  *               = index arm 0 bitmap, 1 hash, 2 global binary search, 3 LDS
  *               sorted copy (an owner whose list does not fit the arm's LDS
- *               budget uses the next of bitmap, hash, sorted, global that
- *               does).  Other entries are ignored.  AOT_E_MODEL on a bad code.
+ *               budget uses the next that does: bitmap or hash -> sorted
+ *               -> global).  Other entries are ignored.  AOT_E_MODEL on a
+ *               bad code.
  *   model       AOT_DISPATCH_LEARNED: after binning, aot_count computes every
  *               bucket's features, runs the cost model (aot_mlp_* below) and
  *               gives each bucket the option with the lowest predicted

@@ -373,10 +373,12 @@ __host__ __device__ __forceinline__ int64_t floor_pow2(int64_t x) {
 }
 
 // The arm an owner actually uses: the requested one if its list fits that
-// arm in `words` LDS words, else the next that fits (bitmap -> hash ->
-// sorted -> global).
+// arm in `words` LDS words, else the next that fits (bitmap or hash ->
+// sorted -> global).  A bitmap too wide for its window goes to the sorted
+// copy, which needs the fewest words and probes faster than the hash on
+// every workload measured.
 __host__ __device__ __forceinline__ int resolve_arm(int arm, int64_t db, int64_t span, int words) {
-  if (arm == kArmBitmap && span > (int64_t)words * 32) arm = kArmHash;
+  if (arm == kArmBitmap && span > (int64_t)words * 32) arm = kArmSorted;
   if (arm == kArmHash && 2 * db > floor_pow2(words)) arm = kArmSorted;
   if (arm == kArmSorted && db > words) arm = kArmGlobal;
   return arm;
@@ -1486,16 +1488,20 @@ hipError_t launch_light(int tile, unsigned grid, const LightArgs& a, int64_t bas
 // LDS words a heavy class's launch reserves for its index: enough for the
 // requested arm on every owner of the class (bitmap: the class's widest
 // span; hash: a power-of-two table of twice deg+; sorted: deg+), capped at
-// kMaxIndexWords, beyond which owners fall back to the next arm.
+// kMaxIndexWords, beyond which owners fall back to the next arm.  A class
+// whose widest bitmap exceeds the cap reserves only the sorted copy's
+// deg+ words: its narrow owners keep the bitmap within them, the others
+// take the sorted copy, and the launch keeps its occupancy instead of
+// holding the cap for owners that could not use it.
 int index_words(int arm, int h, int64_t max_span) {
   const int64_t dmax = int64_t(1) << h;       // class h holds deg+ in (2^(h-1), 2^h]
   int64_t need = 0;
   if (arm == kArmBitmap) {
     need = (max_span + 31) / 32;
-    if (need > kMaxIndexWords) need = kMaxIndexWords;
-    else return (int)std::max<int64_t>(need, 1);
+    if (need <= kMaxIndexWords) return (int)std::max<int64_t>(need, 1);
+    return (int)std::min<int64_t>(dmax, kMaxIndexWords);
   }
-  if (arm == kArmBitmap || arm == kArmHash) {
+  if (arm == kArmHash) {
     int64_t t = 2;
     while (t < 2 * dmax) t <<= 1;
     need = std::max(need, t);
