@@ -325,3 +325,27 @@ def test_digest_matches_oracle(name):
         if csr.n:
             assert np.array_equal(vc.cpu().numpy().astype(np.uint64), tv), dname
             assert int(vc.sum()) == 3 * t
+
+
+def wide_and_narrow_windows():
+    """A 600 k-vertex Chung-Lu graph plus a dense block on 300 further ids."""
+    base = inputs.chung_lu(600000, 12.0, 2.1, 5000.0, 25)
+    rp, col = base.numpy()
+    rows = np.repeat(np.arange(base.n), np.diff(rp))
+    keep = rows < col
+    rng = np.random.default_rng(26)
+    iu, ju = np.nonzero(np.triu(rng.random((300, 300)) < 0.6, 1))
+    u = torch.from_numpy(np.concatenate([rows[keep], base.n + iu]).astype(np.int64))
+    v = torch.from_numpy(np.concatenate([col[keep], base.n + ju]).astype(np.int64))
+    return inputs.csr_from_pairs(base.n + 300, u, v)
+
+
+def test_bitmap_wider_than_its_lds_takes_the_sorted_copy():
+    """With id labels the Chung-Lu owners' windows span most of the 600 k ids,
+    beyond what any LDS bitmap holds: their classes reserve only the sorted
+    copy's words and those owners take it.  The block's owners, in the same
+    classes, have windows of at most 300 ids and keep the bitmap inside
+    those words."""
+    check_all(wide_and_narrow_windows(), "chunglu600k_block_id", local="id", windows=False,
+              dispatches={k: DISPATCHES[k] for k in ("plain", "all_heavy_bitmap",
+                                                     "all_heavy_hash", "mixed")})
