@@ -196,6 +196,23 @@ def cpu_baseline(csr, frac: float, threads: int = 1):
                       f"host: {os.cpu_count()} cores visible, oracle on {threads} thread(s)"}
 
 
+def host_info():
+    """CPU model and memory of the host the oracle ran on."""
+    model, ram = None, None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+        for line in open("/proc/meminfo"):
+            if line.startswith("MemTotal"):
+                ram = round(int(line.split()[1]) / 2**20, 1)
+                break
+    except OSError:
+        pass
+    return {"cpu_model": model, "ram_gib": ram, "cores_visible": os.cpu_count()}
+
+
 # Graphs the cost model trains and is judged on when the workload itself is
 # too large to hold twice: same recipe, smaller scale, other seeds.
 PROXY = {"rmat26": ("rmat23x32", "rmat24x32")}
@@ -542,8 +559,18 @@ def main():
     roof = roofline(recs, args.workload, windowed)
     log(f"[bench] dominant kernel {roof['kernel']}: {roof['achieved']:.1f} GB/s "
         f"({roof['frac'] * 100:.1f}% of peak) over {roof['launches']} launches")
-    base = None if args.no_cpu_baseline else cpu_baseline(
-        csr, args.cpu_sample if not windowed else args.cpu_sample / 20, 16 if windowed else 1)
+    base = None
+    if not args.no_cpu_baseline:
+        # one thread, and all of the host's share of cores (16 per GPU); the
+        # large list is sampled on all cores only
+        cores = min(16, os.cpu_count() or 1)
+        if windowed:
+            base = cpu_baseline(csr, args.cpu_sample / 20, cores)
+        else:
+            base = cpu_baseline(csr, args.cpu_sample, 1)
+            wide = cpu_baseline(csr, args.cpu_sample, cores)
+            base["all_cores"] = {k: wide[k] for k in ("value", "cores", "sample")}
+        base["host"] = host_info()
 
     result = {
         "metric": "triangles/s (whole orient+count+list step); probes/s = sum of min(deg+) "
