@@ -81,6 +81,28 @@ def copy_calibration():
                                            "launches": 3}}), flush=True)
 
 
+def copy_bandwidth(reps: int = 5) -> float:
+    """Achievable HBM bandwidth on this device: a 1 GiB device-to-device copy
+    (1 GiB read + 1 GiB written), median of `reps` timed with events."""
+    import torch
+
+    n = (1 << 30) // 4
+    src = torch.ones(n, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        dst.copy_(src)
+    ts = []
+    for _ in range(reps):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record()
+        dst.copy_(src)
+        ev[1].record()
+        ev[1].synchronize()
+        ts.append(ev[0].elapsed_time(ev[1]))
+    del src, dst
+    return 2 * 4 * n / (sorted(ts)[reps // 2] / 1000.0) / 1e9
+
+
 # Algorithmic bytes of one bucket launch (what the method must move):
 #  count pass: 4 B per probe (the probed out-list id), 4 B per staged owner
 #    list entry, 8 B per edge (its id and its count);
@@ -559,6 +581,9 @@ def main():
     roof = roofline(recs, args.workload, windowed)
     log(f"[bench] dominant kernel {roof['kernel']}: {roof['achieved']:.1f} GB/s "
         f"({roof['frac'] * 100:.1f}% of peak) over {roof['launches']} launches")
+    copy_gbs = copy_bandwidth()
+    log(f"[bench] device copy: {copy_gbs:.1f} GB/s ({copy_gbs / HBM_PEAK_GBS * 100:.1f}% of peak); "
+        f"dominant kernel at {roof['achieved'] / copy_gbs * 100:.1f}% of it")
     base = None
     if not args.no_cpu_baseline:
         # one thread, and all of the host's share of cores (16 per GPU); the
@@ -596,8 +621,9 @@ def main():
         "ms_count": ms_count,
         "ms_list": ms_list,
         "roofline": {k: roof[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic")},
-        "roofline_kernel": {k: roof[k] for k in ("kernel", "launches", "avg_launch_ms",
-                                                 "bytes_per_launch", "per_unit")},
+        "roofline_kernel": dict({k: roof[k] for k in ("kernel", "launches", "avg_launch_ms",
+                                                      "bytes_per_launch", "per_unit")},
+                                copy_GBs=copy_gbs, frac_of_copy=roof["achieved"] / copy_gbs),
         "cpu_baseline": base,
         "learned": learned,
         "ablation": ablation,
