@@ -66,6 +66,23 @@ def test_list_is_the_brute_force_set_and_counts_add_up(g):
 
 
 @SETTINGS
+@given(graphs())
+def test_id_labels_list_the_same_set_with_the_same_edges(g):
+    """Original ids as labels (AOT-randomOrder's local order): the same
+    directed edges, named by id, the brute-force set, and the same costs."""
+    n, edges = g
+    rp, col = csr(n, edges)
+    a = oracle.orient(rp, col)
+    b = oracle.orient(rp, col, local="id")
+    ea = sorted(zip(a.perm[a.tail()].tolist(), a.perm[a.ocol].tolist())) if a.m else []
+    assert list(zip(b.tail().tolist(), b.ocol.tolist())) == ea
+    assert sorted_list(oracle.list_triangles(b)) == brute(n, edges)
+    assert oracle.sum_min(a) == oracle.sum_min(b)
+    assert oracle.sum_head(a) == oracle.sum_head(b)
+    assert oracle.sum_merge(a) == oracle.sum_merge(b)
+
+
+@SETTINGS
 @given(graphs(max_n=9), graphs(max_n=9))
 def test_disjoint_union_adds(g1, g2):
     (n1, e1), (n2, e2) = g1, g2
