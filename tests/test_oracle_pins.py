@@ -312,6 +312,79 @@ def test_tie_break_is_needed():
     assert len(lost) == 1
 
 
+def cf_on(n, mod):
+    """The plain oriented lister on arbitrary out-lists: common out-neighbours
+    of the two ends of every arc.  A triangle is found iff it is not cyclic."""
+    return {tuple(sorted((u, v, w))) for u in range(n) for v in mod[u] for w in mod[u] & mod[v]}
+
+
+def naive_reversal(n, edges):
+    """The idea Section 1 (Challenges) and Section 3.1 reject: orient by
+    (degree, id), reverse every edge whose head has the larger out-degree, and
+    run the plain oriented lister (common out-neighbours of each edge's ends)
+    on the result.  Returns its triangle set and the modified out-lists."""
+    adj = [set() for _ in range(n)]
+    for a, b in edges:
+        adj[a].add(b)
+        adj[b].add(a)
+    key = [(len(adj[v]), v) for v in range(n)]
+    out = [{v for v in adj[u] if key[v] > key[u]} for u in range(n)]
+    dplus = [len(o) for o in out]
+    mod = [set() for _ in range(n)]
+    for u in range(n):
+        for v in out[u]:
+            (mod[v] if dplus[v] > dplus[u] else mod[u]).add(v if dplus[v] <= dplus[u] else u)
+    return cf_on(n, mod), mod
+
+
+def sequential_reversal(n, edges):
+    """The same idea with edges flipped one at a time, in row order, each
+    judged by the out-degrees as they stand after the earlier flips."""
+    adj = [set() for _ in range(n)]
+    for a, b in edges:
+        adj[a].add(b)
+        adj[b].add(a)
+    key = [(len(adj[v]), v) for v in range(n)]
+    mod = [{v for v in adj[u] if key[v] > key[u]} for u in range(n)]
+    for u in range(n):
+        for v in sorted(mod[u]):
+            if v in mod[u] and len(mod[v]) > len(mod[u]):
+                mod[u].discard(v)
+                mod[v].add(u)
+    return cf_on(n, mod)
+
+
+def test_reversal_by_out_degree_is_another_total_order():
+    """Section 1 (Challenges) and Section 3.1 reject reversing the edges
+    whose head has the larger out-degree, since cyclic triangles would be
+    missed.  Reversing every such edge at once by the orientation's deg+
+    points every edge from larger to smaller deg+ (ties: up the order), which
+    is itself a total order: acyclic, and no triangle is lost.  A cycle needs
+    a reversal that follows no single order, like one flipped edge of the
+    paper's figure; that triangle is then lost.  AOT reverses nothing: it
+    keeps the orientation and only chooses which side to probe."""
+    for seed in range(40):
+        g = random_graph(14 + seed % 10, 0.35, 700 + seed)
+        rp, col = g.numpy()
+        rows = np.repeat(np.arange(g.n), np.diff(rp))
+        edges = [(int(a), int(b)) for a, b in zip(rows, col) if a < b]
+        got, mod = naive_reversal(g.n, edges)
+        o = oracle.orient(rp, col)
+        dplus = np.zeros(g.n, np.int64)
+        dplus[o.perm] = o.dplus
+        # every arc goes down the order (deg+ descending, then rank ascending)
+        for u in range(g.n):
+            for v in mod[u]:
+                assert (-dplus[u], o.rank[u]) < (-dplus[v], o.rank[v])
+        assert sorted(got) == brute_force(g)
+        assert sorted(sequential_reversal(g.n, edges)) == brute_force(g)
+    # one flipped edge of a transitive triangle: the cycle u -> x -> v -> u
+    u, x, v = 0, 1, 2
+    mod = [{x}, {v}, {u}]
+    assert cf_on(3, mod) == set()
+    assert cf_on(3, [{x, v}, {v}, set()]) == {(0, 1, 2)}
+
+
 # ---------------------------------------------------------------- digests
 
 def test_fingerprint_and_digest_agree():
