@@ -2,9 +2,10 @@
 // "The main idea"; Section 3.2, Correctness and Time Complexity).
 //
 // Every directed edge e = <u,v> of the oriented graph is charged to its owner
-// b, the endpoint with the larger (deg+, rank) (ties by id, the footnote of
-// Section 3.2); the other endpoint s is probed: each w in N+(s) is looked up
-// in an index of N+(b), so edge e costs min(deg+(u), deg+(v)) look-ups.
+// b, the endpoint with the larger (deg+, label) (equal out-degrees go by the
+// label, the footnote of Section 3.2; labels are ranks, or original ids); the
+// other endpoint s is probed: each w in N+(s) is looked up in an index of
+// N+(b), so edge e costs min(deg+(u), deg+(v)) look-ups.
 //
 // Edges fall into buckets:
 //  * heavy owner classes (deg+(b) >= heavy_min), one per ceil(log2 deg+(b)):
@@ -12,11 +13,13 @@
 //    (Section 3.2, the remark on the bitmap).  A workgroup takes a work item
 //    = an owner and its whole row if that holds at most kItemSpan
 //    neighbours, else a window of up to kItemSpan of its out-neighbours or of
-//    its in-neighbours (in-lists are in rank order, so the in-items of a long
+//    its in-neighbours (with in-lists sorted by label, the in-items of a long
 //    in-list each hold a narrow run of the edge order), compacts the
 //    neighbours it owns into LDS with a prefix sum
 //    of their out-degrees, stages N+(b) in LDS (bitmap over [min, max] of the
-//    list, open-addressing hash, or a sorted copy), and then spreads the
+//    list, open-addressing hash, or a sorted copy; a list too long or too
+//    wide for its launch's LDS takes the sorted copy, then a global binary
+//    search), and then spreads the
 //    flattened probes over all its lanes: each lane takes consecutive probes,
 //    so reads of the probed out-lists are coalesced and no lane idles on
 //    short lists.
@@ -1333,7 +1336,8 @@ struct Plan {
 };
 
 // The plain rule: lanes per edge about the bin's c; heavy owners use the
-// bitmap (falling back to hash / sorted / global when it does not fit).
+// bitmap (falling back to the sorted copy, then the global search, when it
+// does not fit).
 Plan plain_plan() {
   Plan p;
   for (int k = 0; k < kLightBins; ++k)

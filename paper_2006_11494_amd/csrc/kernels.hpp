@@ -47,18 +47,10 @@ hipError_t radix_sort_pairs(int32_t* keys, int32_t* vals, int32_t* keys_alt, int
                             int32_t** keys_out, int32_t** vals_out);
 
 // ---- orient.hip
-struct OrientScratch {
-  int32_t* key_a; int32_t* val_a; int32_t* key_b; int32_t* val_b;  // [n] each
-  int32_t* dplus;        // [n] by rank
-  int32_t* dminus;       // [n] by rank
-  int32_t* unsorted;     // [m] out-lists before sorting
-  int32_t* rows_by_len;  // [n] rank ids grouped by out-list length class
-  int32_t* counters;     // small device counters
-  int64_t* host_info;    // device copy of the scalars read back by the host
-  void* scan_tmp;
-  void* radix_tmp;
-};
 size_t orient_workspace_bytes(int32_t n, int64_t nnz);
+// One graph.  in_by_rank: sort each in-list by label; core: rank by the core
+// order instead of degree; by_id: keep original ids as labels (the order
+// still directs the edges; perm and rank come out as the identity).
 int orient_run(int32_t n, int64_t nnz, const int64_t* rowptr, const int32_t* col, bool validate,
                bool in_by_rank, bool core, bool by_id, int64_t* orow, int32_t* ocol, int32_t* otail,
                int32_t* perm,
