@@ -582,6 +582,8 @@ def main():
     log(f"[bench] dominant kernel {roof['kernel']}: {roof['achieved']:.1f} GB/s "
         f"({roof['frac'] * 100:.1f}% of peak) over {roof['launches']} launches")
     copy_gbs = copy_bandwidth()
+    hbm_gbs = (roof["traffic"] / (roof["avg_launch_ms"] / 1000.0) / 1e9
+               if roof["traffic"] else None)
     log(f"[bench] device copy: {copy_gbs:.1f} GB/s ({copy_gbs / HBM_PEAK_GBS * 100:.1f}% of peak); "
         f"dominant kernel at {roof['achieved'] / copy_gbs * 100:.1f}% of it")
     base = None
@@ -623,7 +625,11 @@ def main():
         "roofline": {k: roof[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic")},
         "roofline_kernel": dict({k: roof[k] for k in ("kernel", "launches", "avg_launch_ms",
                                                       "bytes_per_launch", "per_unit")},
-                                copy_GBs=copy_gbs, frac_of_copy=roof["achieved"] / copy_gbs),
+                                copy_GBs=copy_gbs, frac_of_copy=roof["achieved"] / copy_gbs,
+                                # rocprofv3's FETCH_SIZE + WRITE_SIZE bytes of one launch over
+                                # this run's average launch time (null without a profile)
+                                hbm_measured_GBs=hbm_gbs,
+                                hbm_measured_frac=hbm_gbs / HBM_PEAK_GBS if hbm_gbs else None),
         "cpu_baseline": base,
         "learned": learned,
         "ablation": ablation,
