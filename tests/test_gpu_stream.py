@@ -48,3 +48,22 @@ def test_streamed_windows_equal_the_oracle(chunk):
     aot.stream_list(o, c, chunk, lambda f, v: got.append(v.cpu().numpy()), first=first,
                     last=last, to_host=False)
     assert np.array_equal(np.concatenate(got), ref[first:last])
+
+
+@pytest.mark.parametrize("in_by_rank", [False, True])
+def test_streamed_windows_with_id_labels(in_by_rank):
+    """AOT-randomOrder's id labels: windows of the list in id-labelled edge
+    order, with in-lists in either order."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    csr = inputs.rmat(14, 16, 35)
+    rp, col = csr.numpy()
+    ref = oracle.list_triangles(oracle.orient(rp, col, local="id"))
+    g = csr.to("cuda")
+    o = aot.orient(g.rowptr, g.col, local="id", in_by_rank=in_by_rank)
+    c = aot.count(o)
+    assert c.T == len(ref)
+    got = []
+    say(f"[gpu] stream id labels T={c.T} in_by_rank={in_by_rank}")
+    aot.stream_list(o, c, 100003, lambda f, v: got.append(v.numpy().copy()))
+    assert np.array_equal(np.concatenate(got), ref)

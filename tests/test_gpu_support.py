@@ -27,18 +27,18 @@ def say(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def check_support(csr, name, cases=CASES, order="degree"):
+def check_support(csr, name, cases=CASES, order="degree", local="rank"):
     need_gpu()
     rp, col = csr.numpy()
-    o_ref = oracle.orient(rp, col, order)
+    o_ref = oracle.orient(rp, col, order, local)
     sup_ref = oracle.edge_support(rp, col, o_ref)
     tri = oracle.list_triangles(o_ref)
     (f1, f2), tv = oracle.fingerprint(tri, csr.n)
     assert int(sup_ref.sum()) == 3 * len(tri)
     g = csr.to("cuda")
-    o = aot.orient(g.rowptr, g.col, order=order)
+    o = aot.orient(g.rowptr, g.col, order=order, local=local)
     for cname, d in cases.items():
-        say(f"[gpu] support {name} {order} {cname}")
+        say(f"[gpu] support {name} {order} {local} {cname}")
         c = aot.count(o, d)
         es, vc, dig = aot.support(o, c)
         assert np.array_equal(es.cpu().numpy(), sup_ref), cname
@@ -58,6 +58,14 @@ def test_small_graphs(name):
 
 def test_er2000():
     check_support(inputs.workload("er2000"), "er2000")
+
+
+@pytest.mark.parametrize("name", ["tiebreak", "wheel50", "rand_b", "dense_c", "rmat13"])
+def test_id_labels(name):
+    """Support, vertex counts and digest on the id-labelled orientation
+    (AOT-randomOrder's local order), every arm, tile and strategy."""
+    csr = SMALL[name] if name in SMALL else inputs.rmat(13, 16, 34)
+    check_support(csr, name, local="id")
 
 
 def test_rmat14():
