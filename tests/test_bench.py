@@ -58,14 +58,18 @@ def test_windowed_write_bytes_come_from_the_whole_buckets():
     assert r["achieved"] == pytest.approx(whole / 4.0e-3 / 1e9)
 
 
-def test_traffic_only_for_the_profiled_sources(tmp_path, monkeypatch):
-    prof = os.path.join(ROOT, "profiles", "k_heavy_write_rmat20_traffic.json")
+@pytest.mark.parametrize("workload", ["rmat20", "chunglu4m"])
+def test_traffic_only_for_the_profiled_sources(workload, monkeypatch):
+    prof = os.path.join(ROOT, "profiles", f"k_heavy_write_{workload}_traffic.json")
     with open(prof) as f:
         stored = json.load(f)
+    assert stored["workload"] == workload
     if stored["source_hash"] == bench.kernel_source_hash():
-        assert bench.profiled_traffic("k_heavy<write>", "rmat20") == \
+        assert bench.profiled_traffic("k_heavy<write>", workload) == \
             stored["traffic_bytes_per_launch"]
+    # no profile for another workload
+    assert bench.profiled_traffic("k_heavy<write>", "rmat18") is None
     # a different kernel source: no traffic
     monkeypatch.setattr(bench, "kernel_source_hash", lambda: "0" * 16)
-    assert bench.profiled_traffic("k_heavy<write>", "rmat20") is None
-    assert bench.profiled_traffic("k_light<64><write>", "rmat20") is None
+    assert bench.profiled_traffic("k_heavy<write>", workload) is None
+    assert bench.profiled_traffic("k_light<64><write>", workload) is None
