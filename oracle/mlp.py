@@ -7,7 +7,8 @@ with x' = (x - mean) * inv_std, h1 = relu(W1 x' + b1), h2 = relu(W2 h1 + b2),
 y = W3 h2 + b3, and the masked mean squared error
     L = (1/N) sum_i sum_k mask[i][k] (y[i][k] - t[i][k])^2   (N = set mask entries).
 The gradient is derived by hand (chain rule); the tests pin it with central
-finite differences.  Parity unpinned: nothing (see tests/test_oracle_mlp.py).
+finite differences (tests/test_oracle_mlp.py), and every function here has
+such a pin.
 """
 
 import numpy as np
