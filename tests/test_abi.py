@@ -104,6 +104,16 @@ def test_count_and_list_argument_errors():
     assert lib.aot_count(ctypes.byref(o), ctypes.byref(bad_mode), FAKE, FAKE, ws, res, None) == -1
     no_table = aot.DispatchC(1, 0, None)
     assert lib.aot_count(ctypes.byref(o), ctypes.byref(no_table), FAKE, FAKE, ws, res, None) == -6
+    # table codes are checked before anything runs: a tile outside {4..64},
+    # a light code with an arm byte, a heavy arm outside 0..3
+    plain = [t << 8 for t in (4, 4, 4, 8, 16, 32, 64, 64)] + [0] * 24
+    for k, code in ((2, 5 << 8), (0, (4 << 8) | 1), (16, 4), (31, -1)):
+        codes = list(plain)
+        codes[k] = code
+        table = (ctypes.c_int32 * aot.AOT_NUM_BUCKETS)(*codes)
+        bad = aot.DispatchC(aot.AOT_DISPATCH_TABLE, 0, ctypes.cast(table, ctypes.c_void_p).value)
+        assert lib.aot_count(ctypes.byref(o), ctypes.byref(bad), FAKE, FAKE, ws, res, None) == -6
+        assert b"unknown arm or tile" in lib.aot_last_error()
     neg = aot.DispatchC(0, -3, None)
     assert lib.aot_count(ctypes.byref(o), ctypes.byref(neg), FAKE, FAKE, ws, res, None) == -1
     bad_strategy = aot.DispatchC(0, 0, None, None, 4)
