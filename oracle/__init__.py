@@ -66,7 +66,8 @@ def _load():
     lib.orc_orient_by_id.restype = i64
     lib.orc_sum_merge.argtypes = [i32, _i64p, _i32p]
     lib.orc_sum_merge.restype = u64
-    lib.orc_aot_ref.argtypes = [i32, _i64p, _i32p, ctypes.c_int, _i32p, i64, ctypes.POINTER(u64)]
+    lib.orc_aot_ref.argtypes = [i32, _i64p, _i32p, ctypes.c_int, ctypes.c_void_p, i64,
+                                ctypes.c_void_p, ctypes.POINTER(u64)]
     lib.orc_aot_ref.restype = i64
     lib.orc_fingerprint.argtypes = [_i32p, i64, _u64p, ctypes.c_void_p]
     lib.orc_fingerprint.restype = None
@@ -326,16 +327,26 @@ def sum_merge(o: Oriented) -> int:
     return int(_load().orc_sum_merge(o.n, o.orow, _nonempty(o.ocol)))
 
 
-def aot_ref(rowptr, col, tie_break: bool = True, cap: int | None = None):
-    """Algorithm 3 as written, on original ids.  Returns (triangles (T,3), probes)."""
+def aot_ref(rowptr, col, tie_break: bool = True, cap: int | None = None, digest: bool = False):
+    """AOT (Algorithm 3) on original ids, the cross-check of CF.  Returns
+    (triangles (T,3), probes), or with digest=True (T, (F1, F2), probes)
+    without storing the list."""
     lib = _load()
     rowptr, col = _arrays(rowptr, col)
     n = rowptr.size - 1
+    probes = ctypes.c_uint64(0)
+    if digest:
+        fp = np.zeros(2, np.uint64)
+        t = lib.orc_aot_ref(n, rowptr, _nonempty(col), int(tie_break), None, 0, fp.ctypes.data,
+                            ctypes.byref(probes))
+        if t == np.iinfo(np.int64).min:
+            raise MemoryError("oracle AOT reference failed")
+        return int(t), (int(fp[0]), int(fp[1])), int(probes.value)
     if cap is None:
         cap = max(16, col.size * 4)
     out = np.empty(3 * cap, np.int32)
-    probes = ctypes.c_uint64(0)
-    t = lib.orc_aot_ref(n, rowptr, _nonempty(col), int(tie_break), out, cap, ctypes.byref(probes))
+    t = lib.orc_aot_ref(n, rowptr, _nonempty(col), int(tie_break), out.ctypes.data, cap, None,
+                        ctypes.byref(probes))
     if t == np.iinfo(np.int64).min:
         raise MemoryError("oracle AOT reference failed")
     if t < 0:

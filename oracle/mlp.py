@@ -6,9 +6,18 @@ inputs, h hidden units and k outputs, a flat buffer
 with x' = (x - mean) * inv_std, h1 = relu(W1 x' + b1), h2 = relu(W2 h1 + b2),
 y = W3 h2 + b3, and the masked mean squared error
     L = (1/N) sum_i sum_k mask[i][k] (y[i][k] - t[i][k])^2   (N = set mask entries).
-The gradient is derived by hand (chain rule); the tests pin it with central
-finite differences (tests/test_oracle_mlp.py), and every function here has
-such a pin.
+The gradient is derived by hand (chain rule).  Training sets the input
+normalisation from the data (mean and population standard deviation of each
+input, a standard deviation of zero read as one) and then takes full-batch
+Adam steps (Kingma and Ba 2015, Algorithm 1: exponential moment estimates with
+bias correction).
+
+Pins (tests/test_oracle_mlp.py): the forward pass and the loss against a tiny
+network evaluated by hand; the gradient against central finite differences
+and a hand-computed bias gradient; the normalisation against hand-computed
+moments; Adam against its constant-gradient property and a two-step example
+worked out by hand; training against Adam's first-step property and a network
+in which only the output bias can move.
 """
 
 import numpy as np
@@ -72,3 +81,48 @@ def loss_grad(p, x, t, mask, n_in, h, k):
     gb1 = dh1.sum(0)
     g = np.concatenate([gw1.ravel(), gb1, gw2.ravel(), gb2, gw3.ravel(), gb3])
     return L, g
+
+
+def normalisation(x):
+    """(mean, inv_std) of every input column of x (population moments); a
+    column whose variance is zero (below 1e-12) gets inv_std = 1."""
+    x = np.asarray(x, np.float64)
+    mean = x.mean(0)
+    var = ((x - mean) ** 2).mean(0)
+    sd = np.where(var > 1e-12, np.sqrt(np.maximum(var, 0.0)), 1.0)
+    return mean, 1.0 / sd
+
+
+def adam_step(w, g, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam update at step t >= 1 (Kingma and Ba 2015, Algorithm 1):
+    first and second moment estimates, their bias-corrected values, then
+    w - lr * m_hat / (sqrt(v_hat) + eps).  Returns (w, m, v)."""
+    g = np.asarray(g, np.float64)
+    m = beta1 * np.asarray(m, np.float64) + (1.0 - beta1) * g
+    v = beta2 * np.asarray(v, np.float64) + (1.0 - beta2) * g * g
+    m_hat = m / (1.0 - beta1 ** t)
+    v_hat = v / (1.0 - beta2 ** t)
+    return np.asarray(w, np.float64) - lr * m_hat / (np.sqrt(v_hat) + eps), m, v
+
+
+def train(p, x, t, mask, n_in, h, k, epochs, lr, grads=None):
+    """Sets the normalisation of p from x, then `epochs` full-batch Adam steps
+    on the masked mean squared error (moments start at zero).  Returns the new
+    parameter buffer and the loss before each step; each step's gradient is
+    appended to `grads` when a list is given."""
+    p = np.array(p, dtype=np.float64)
+    mean, istd = normalisation(x)
+    p[:n_in] = mean
+    p[n_in:2 * n_in] = istd
+    w = p[2 * n_in:].copy()
+    m = np.zeros_like(w)
+    v = np.zeros_like(w)
+    losses = []
+    for step in range(1, epochs + 1):
+        L, g = loss_grad(np.concatenate([p[:2 * n_in], w]), x, t, mask, n_in, h, k)
+        losses.append(L)
+        if grads is not None:
+            grads.append(g)
+        w, m, v = adam_step(w, g, m, v, step, lr)
+    p[2 * n_in:] = w
+    return p, losses

@@ -397,90 +397,88 @@ uint64_t orc_sum_merge(int32_t n, const int64_t* orow, const int32_t* ocol) {
   return s;
 }
 
-/* Algorithm 3 (AOT), literally, on the original ids.
- *  tie_break = 1: a vertex x is "smaller" than the pivot u when
- *                 (deg+(x), x) < (deg+(u), u) lexicographically;
- *  tie_break = 0: strict deg+(x) < deg+(u) only (drops tied edges; kept to
- *                 show that the footnote's tie rule is needed).
- * Output: triangles (ascending ids) into out up to cap, *probes = number of
- * hash look-ups.  Returns the triangle count (or -count if cap was short),
- * or INT64_MIN on allocation failure. */
+static uint64_t triple_hash(uint32_t a, uint32_t b, uint32_t c);
+
+/* AOT (Algorithm 3, Section 3.2) on the original ids: the cross-check of the
+ * CF procedure above, written from the algorithm's idea.
+ *
+ * Orientation: the degree order with the smaller id first on ties; each
+ * out-list N+(x) is kept in decreasing degree order (the local order of
+ * Section 3.2).  Then every vertex u takes one turn as the indexed vertex:
+ * N+(u) is marked in a table H of |V| flags, and every neighbour x of u in
+ * the undirected graph -- the edge may point out of u or into u -- whose key
+ * (deg+(x), x) is below u's has each w in N+(x) looked up in H.  A hit closes
+ * the triangle {u, x, w}.  So each edge is worked on from the endpoint with
+ * the larger key only, and only the smaller out-list is read (Section 3.1;
+ * the id tie-break of Section 3.2's footnote).  H is cleared after the turn.
+ *   tie_break = 0 compares deg+ alone, strictly, so edges whose endpoints
+ *               have equal deg+ are never worked on; kept to show that the
+ *               tie rule is needed.
+ * Output: with out != NULL, triangles (ascending ids) up to cap; with
+ * fp != NULL, fp[0] = sum and fp[1] = xor of the triple hashes (as
+ * orc_fingerprint).  *probes = number of look-ups in H.  Returns the triangle
+ * count (-count if out was too short), or INT64_MIN on allocation failure. */
 int64_t orc_aot_ref(int32_t n, const int64_t* rowptr, const int32_t* col, int tie_break,
-                    int32_t* out, int64_t cap, uint64_t* probes) {
-  int64_t* eta = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
-  deg_id* order = (deg_id*)malloc(sizeof(deg_id) * (size_t)(n > 0 ? n : 1));
-  int64_t* dplus = (int64_t*)calloc((size_t)(n > 0 ? n : 1), sizeof(int64_t));
-  int64_t* dminus = (int64_t*)calloc((size_t)(n > 0 ? n : 1), sizeof(int64_t));
-  unsigned char* H = (unsigned char*)calloc((size_t)(n > 0 ? n : 1), 1);
-  int64_t nnz = rowptr[n];
-  int32_t* outl = (int32_t*)malloc(sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1));
-  int32_t* inl = (int32_t*)malloc(sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1));
-  int64_t* orow = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n + 1));
-  int64_t* irow = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n + 1));
-  if (!eta || !order || !dplus || !dminus || !H || !outl || !inl || !orow || !irow) {
-    free(eta); free(order); free(dplus); free(dminus); free(H); free(outl); free(inl);
-    free(orow); free(irow);
+                    int32_t* out, int64_t cap, uint64_t* fp, uint64_t* probes) {
+  const size_t nn = (size_t)(n > 0 ? n : 1);
+  int64_t m2 = rowptr[n];
+  int32_t* eta = (int32_t*)malloc(sizeof(int32_t) * nn);
+  deg_id* order = (deg_id*)malloc(sizeof(deg_id) * nn);
+  int64_t* dplus = (int64_t*)calloc(nn, sizeof(int64_t));
+  int64_t* orow = (int64_t*)malloc(sizeof(int64_t) * (nn + 1));
+  int64_t* fill = (int64_t*)malloc(sizeof(int64_t) * nn);
+  int32_t* nplus = (int32_t*)malloc(sizeof(int32_t) * (size_t)(m2 / 2 > 0 ? m2 / 2 : 1));
+  unsigned char* H = (unsigned char*)calloc(nn, 1);
+  if (!eta || !order || !dplus || !orow || !fill || !nplus || !H) {
+    free(eta); free(order); free(dplus); free(orow); free(fill); free(nplus); free(H);
     return INT64_MIN;
   }
-  /* line 1: orientation by degree order, ties by id */
   for (int32_t v = 0; v < n; ++v) { order[v].deg = rowptr[v + 1] - rowptr[v]; order[v].id = v; }
   qsort(order, (size_t)n, sizeof(deg_id), cmp_deg_id);
   for (int32_t r = 0; r < n; ++r) eta[order[r].id] = r;
-  for (int32_t u = 0; u < n; ++u)
-    for (int64_t k = rowptr[u]; k < rowptr[u + 1]; ++k) {
-      if (eta[col[k]] > eta[u]) dplus[u]++; else dminus[u]++;
+  for (int32_t x = 0; x < n; ++x)
+    for (int64_t k = rowptr[x]; k < rowptr[x + 1]; ++k) dplus[x] += eta[col[k]] > eta[x];
+  orow[0] = 0;
+  for (int32_t x = 0; x < n; ++x) { orow[x + 1] = orow[x] + dplus[x]; fill[x] = orow[x]; }
+  /* visiting the vertices from the top of the order down and appending each
+   * to the out-list of every lower neighbour leaves every out-list in
+   * decreasing degree order */
+  for (int32_t r = n - 1; r >= 0; --r) {
+    int32_t w = order[r].id;
+    for (int64_t k = rowptr[w]; k < rowptr[w + 1]; ++k) {
+      int32_t x = col[k];
+      if (eta[x] < eta[w]) nplus[fill[x]++] = w;
     }
-  orow[0] = irow[0] = 0;
-  for (int32_t u = 0; u < n; ++u) { orow[u + 1] = orow[u] + dplus[u]; irow[u + 1] = irow[u] + dminus[u]; }
-  /* neighbour lists in decreasing degree order (local order): walk the
-   * vertices from the top of eta down and append each to its neighbours' lists */
-  {
-    int64_t* fo = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
-    int64_t* fi = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
-    if (!fo || !fi) { free(fo); free(fi); return INT64_MIN; }
-    for (int32_t u = 0; u < n; ++u) { fo[u] = orow[u]; fi[u] = irow[u]; }
-    for (int32_t r = n - 1; r >= 0; --r) {
-      int32_t x = order[r].id;                  /* x, in decreasing eta */
-      for (int64_t k = rowptr[x]; k < rowptr[x + 1]; ++k) {
-        int32_t u = col[k];
-        if (eta[x] > eta[u]) outl[fo[u]++] = x;  /* x in N+(u) */
-        else inl[fi[u]++] = x;                   /* x in N-(u) */
-      }
-    }
-    free(fo); free(fi);
   }
   int64_t t = 0;
-  uint64_t pr = 0;
-#define SMALLER(x, u) (dplus[x] < dplus[u] || (tie_break && dplus[x] == dplus[u] && (x) < (u)))
-#define EMIT(a, b, c) do { if (t < cap) { int32_t* o = out + 3 * t; o[0] = (a); o[1] = (b); o[2] = (c); sort3(o); } ++t; } while (0)
+  uint64_t looked = 0, hsum = 0, hxor = 0;
   for (int32_t u = 0; u < n; ++u) {
-    for (int64_t k = orow[u]; k < orow[u + 1]; ++k) H[outl[k]] = 1;          /* line 3 */
-    for (int64_t k = orow[u]; k < orow[u + 1]; ++k) {                         /* lines 4-8 */
-      int32_t v = outl[k];
-      if (SMALLER(v, u))
-        for (int64_t j = orow[v]; j < orow[v + 1]; ++j) {
-          int32_t w = outl[j];
-          ++pr;
-          if (H[w]) EMIT(u, v, w);
+    for (int64_t k = orow[u]; k < orow[u + 1]; ++k) H[nplus[k]] = 1;
+    for (int64_t k = rowptr[u]; k < rowptr[u + 1]; ++k) {
+      int32_t x = col[k];
+      int below = dplus[x] < dplus[u] || (tie_break && dplus[x] == dplus[u] && x < u);
+      if (!below) continue;
+      for (int64_t j = orow[x]; j < orow[x + 1]; ++j) {
+        int32_t w = nplus[j];
+        ++looked;
+        if (!H[w]) continue;
+        int32_t tri[3] = {u, x, w};
+        sort3(tri);
+        if (out && t < cap) memcpy(out + 3 * t, tri, sizeof tri);
+        if (fp) {
+          uint64_t h = triple_hash((uint32_t)tri[0], (uint32_t)tri[1], (uint32_t)tri[2]);
+          hsum += h;
+          hxor ^= h;
         }
+        ++t;
+      }
     }
-    for (int64_t k = irow[u]; k < irow[u + 1]; ++k) {                         /* lines 9-13 */
-      int32_t x = inl[k];
-      if (SMALLER(x, u))
-        for (int64_t j = orow[x]; j < orow[x + 1]; ++j) {
-          int32_t y = outl[j];
-          ++pr;
-          if (H[y]) EMIT(u, x, y);
-        }
-    }
-    for (int64_t k = orow[u]; k < orow[u + 1]; ++k) H[outl[k]] = 0;          /* clean H */
+    for (int64_t k = orow[u]; k < orow[u + 1]; ++k) H[nplus[k]] = 0;
   }
-#undef SMALLER
-#undef EMIT
-  *probes = pr;
-  free(eta); free(order); free(dplus); free(dminus); free(H); free(outl); free(inl);
-  free(orow); free(irow);
-  return t <= cap ? t : -t;
+  *probes = looked;
+  if (fp) { fp[0] = hsum; fp[1] = hxor; }
+  free(eta); free(order); free(dplus); free(orow); free(fill); free(nplus); free(H);
+  return (!out || t <= cap) ? t : -t;
 }
 
 /* SplitMix64's output function (Steele, Lea, Flood 2014) on z + golden gamma. */

@@ -73,6 +73,39 @@ def test_training_decreases_the_loss():
     assert torch.equal(net.params, net2.params)
 
 
+@pytest.mark.parametrize("hidden,b,steps,lr,seed", [(16, 64, 10, 1e-2, 21), (32, 200, 25, 1e-3, 22)])
+def test_mlp_training_matches_cpu_reference(hidden, b, steps, lr, seed):
+    """aot_mlp_train (normalisation from the data, then full-batch Adam) against
+    the float64 reference from the same fp32 starting parameters.  Adam's step
+    is lr * m_hat / (sqrt(v_hat) + eps): where a parameter's gradient stays well
+    above the fp32 gradient error, the step agrees to that relative error;
+    where it nears zero the step direction is noise, bounded by 2 lr a step."""
+    need_gpu()
+    n_in, k = 8, 9
+    x, t, mask = toy(b, n_in, k, seed)
+    net = aot.Mlp(n_in, hidden, k).init(seed)
+    p0 = net.params.cpu().numpy().astype(np.float64)
+    dev = lambda a: torch.from_numpy(a).cuda()
+    losses = net.train(dev(x), dev(t), dev(mask), steps, lr)
+    q = net.params.cpu().numpy().astype(np.float64)
+    grads = []
+    ref, ref_losses = ref_mlp.train(p0, x.astype(np.float64), t, mask.astype(bool), n_in, hidden,
+                                    k, steps, lr, grads=grads)
+    mean, istd = ref_mlp.normalisation(x.astype(np.float64))
+    assert np.allclose(q[:n_in], mean, rtol=1e-5, atol=1e-5)
+    assert np.allclose(q[n_in:2 * n_in], istd, rtol=1e-5)
+    assert np.allclose(losses, ref_losses, rtol=1e-4, atol=1e-6)
+    g = np.abs(np.array(grads))                      # steps x trainable
+    steady = g.min(0) >= 1e-3 * max(g.max(), 1e-30)
+    d = np.abs(q[2 * n_in:] - ref[2 * n_in:])
+    say(f"[mlp] {steps} Adam steps: {steady.sum()} of {d.size} parameters with a steady "
+        f"gradient, max diff {d[steady].max() if steady.any() else 0:.2e} (others "
+        f"{d[~steady].max() if (~steady).any() else 0:.2e}, bound {2 * steps * lr:.1e})")
+    assert steady.sum() > d.size // 2
+    assert np.all(d[steady] <= steps * lr * 1e-2 + 1e-6)
+    assert np.all(d <= 2 * steps * lr + 1e-6)
+
+
 def test_learned_dispatch_is_bit_exact_and_falls_back():
     need_gpu()
     csr = inputs.rmat(14, 16, 77).to("cuda")
