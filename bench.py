@@ -36,25 +36,35 @@ def log(*a):
     print(f"[{time.time() - _T0:7.1f}s]", *a, file=sys.stderr, flush=True)
 
 
+HEADLINE = "rmat26"
+# the other configurations, measured as extra keys of the headline run
+EXTRAS = ("rmat20", "chunglu4m")
+
+
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=2)
-    p.add_argument("--workload", default="rmat20")
+    p.add_argument("--workload", default=HEADLINE)
     p.add_argument("--seed", type=int, default=None)
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--cpu-sample", type=float, default=0.5,
-                   help="fraction of the oriented edges the CPU oracle lists")
+    p.add_argument("--cpu-sample", type=float, default=None,
+                   help="fraction of the oriented edges the CPU oracle lists (default 0.5, "
+                        "or 0.01 for a list listed in windows)")
     p.add_argument("--heavy-arm", default=None, choices=["bitmap", "hash", "global", "sorted"],
                    help="force one index arm for every heavy owner class")
     p.add_argument("--heavy-min", type=int, default=0)
     p.add_argument("--no-learned", action="store_true",
-                   help="skip the learned-dispatch leg (training the cost model takes ~20 s)")
+                   help="skip the learned-dispatch legs (training the cost model)")
+    p.add_argument("--learned-steps", type=int, default=3,
+                   help="timed steps of each of plain and learned in the learned leg")
     p.add_argument("--no-ablation", action="store_true",
                    help="skip the probe-strategy ablation (fixed orientation, CF merge, per edge)")
     p.add_argument("--no-batch", action="store_true",
                    help="skip the batched leg (512 uneven graphs, one captured pass)")
+    p.add_argument("--no-extras", action="store_true",
+                   help="headline workload only: skip the other configurations' legs")
     p.add_argument("--batch-count", type=int, default=512)
     p.add_argument("--resident-gb", type=float, default=48.0,
                    help="list into one device buffer up to this size, else in windows")
@@ -63,8 +73,9 @@ def parse():
                         "(capped at 60%% of the free device memory)")
     p.add_argument("--stream-chunk", type=int, default=1 << 29,
                    help="triangles per window streamed to pinned host memory")
-    p.add_argument("--no-stream", action="store_true",
-                   help="skip the pass that streams every window to pinned host memory")
+    p.add_argument("--stream", action="store_true",
+                   help="also stream every window of a list too large to hold to pinned host "
+                        "memory (the PCIe-inclusive rate; about a minute at R-MAT scale 26)")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a plain 1 GiB read + 1 GiB write elementwise kernel, the "
                         "reference that scales rocprofv3's FETCH_SIZE / WRITE_SIZE counters")
@@ -240,50 +251,67 @@ def host_info():
 
 # Graphs the cost model trains and is judged on when the workload itself is
 # too large to hold twice: same recipe, smaller scale, other seeds.
-PROXY = {"rmat26": ("rmat23x32", "rmat24x32")}
-JUDGE_PROXY = {"rmat26": "rmat25x32"}
+PROXY = {"rmat26": ("rmat22x32", "rmat23x32")}
+JUDGE_PROXY = {"rmat26": "rmat24x32"}
 
 
-def learned_leg(aot, o, csr, cws, tri_off, list_all, T, probes, args):
-    """Train the cost model on other graphs (seeds >= 1000), judge it on
-    calibration graphs, then time the same step with the learned dispatch."""
+def alternate_ms(fns, reps):
+    """Wall time per call of each fn (ms), the fns run in turn `reps` times
+    after one untimed round, so that drift hits every fn alike; each call is
+    bracketed by device synchronisation.  Returns the mean of each."""
     import torch
 
+    tot = [0.0] * len(fns)
+    for r in range(reps + 1):
+        for i, fn in enumerate(fns):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            if r:
+                tot[i] += (time.perf_counter() - t) * 1000.0
+    return [x / max(reps, 1) for x in tot]
+
+
+def learned_leg(aot, name, o, step, T, probes, reps, log, scale=2, repeats=2):
+    """Train the cost model on other graphs (seeds >= 1000), judge it on a
+    calibration graph, then time the whole step with the plain rule and with
+    the learned dispatch in turn (same timing, recorder off) on this graph."""
     from paper_2006_11494_amd import learn
 
     t0 = time.time()
     # training: the standard family mix plus two graphs of this workload's own
     # recipe; judge: a third graph of the recipe (all seeds >= 1000)
-    names = PROXY.get(args.workload, (args.workload, args.workload))
-    training = learn.training_graphs(scale=2) + [
-        learn.workload_graphs(name, (seed,))[0] for name, seed in zip(names, (1021, 1022))]
-    calibration = learn.workload_graphs(JUDGE_PROXY.get(args.workload, args.workload), (1020,))
-    net, report = learn.learn(training, calibration, epochs=1000, repeats=2, log=log)
+    names = PROXY.get(name, (name, name))
+    training = learn.training_graphs(scale=scale) + [
+        learn.workload_graphs(nm, (seed,))[0] for nm, seed in zip(names, (1021, 1022))]
+    calibration = learn.workload_graphs(JUDGE_PROXY.get(name, name), (1020,))
+    net, report = learn.learn(training, calibration, epochs=1000, repeats=repeats, log=log)
     del training, calibration
     train_s = time.time() - t0
+    res = {"train_s": train_s, **report}
     if net is None:
-        return {"accepted": False, "train_s": train_s, **report}
+        log(f"[bench] {name}: the judge kept the plain rule; the learned step is the plain step")
+        return res
     d = aot.Dispatch(aot.AOT_DISPATCH_LEARNED, report["heavy_min"], None, net)
+    got = {}
 
-    def step():
-        aot.orient(csr.rowptr, csr.col, out=o, in_by_rank=args.in_by_rank)
-        cc = aot.count(o, d, ws=cws, tri_off=tri_off)
-        list_all(cc, d)
-        return cc
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    for _ in range(args.steps):
-        cc = step()
+    def run(disp, key):
+        cc = step(disp)
         assert (cc.T, cc.probes) == (T, probes)
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t) * 1000.0 / args.steps
-    table, used = aot.count_plan(o, cc)
-    log(f"[bench] learned dispatch: step {ms:.3f} ms (model used: {used})")
-    return {"accepted": True, "value": T / (ms / 1000.0), "unit": "triangles/s",
-            "ms_per_step": ms, "model_used": used, "plan": table, "train_s": train_s, **report}
+        got[key] = cc
+
+    plain_ms, learned_ms = alternate_ms([lambda: run(None, "plain"), lambda: run(d, "learned")],
+                                        reps)
+    table, used = aot.count_plan(o, got["learned"])
+    log(f"[bench] {name}: plain {plain_ms:.3f} ms, learned {learned_ms:.3f} ms per step "
+        f"({plain_ms / learned_ms:.3f}x, model used: {used})")
+    res.update({"plain_ms_per_step": plain_ms, "ms_per_step": learned_ms,
+                "value": T / (learned_ms / 1000.0), "unit": "triangles/s",
+                "gain_vs_plain": plain_ms / learned_ms, "model_used": used, "plan": table,
+                "timed_steps_each": reps,
+                "timing": "plain and learned steps alternated, wall clock, recorder off"})
+    return res
 
 
 ABLATION_NOTE = ("count + list of the whole graph per (order, probe strategy): aot = adaptive "
@@ -407,17 +435,23 @@ def batched_leg(aot, args, dev):
     out = torch.empty((max(T, 1), 3), dtype=torch.int32, device=dev)
     max_n = max(c.n for c in csrs)
     max_nnz = max(c.nnz for c in csrs)
+    # every buffer of the per-graph baseline is allocated once, outside the
+    # timed loop: each graph's oriented arrays and offsets are views of them
     ows = torch.empty(aot.orient_workspace(max_n, max_nnz), dtype=torch.uint8, device=dev)
     cws = torch.empty(aot.count_workspace(max_n, max_nnz // 2), dtype=torch.uint8, device=dev)
+    big = aot.alloc_oriented(max_n, max_nnz // 2, dev)
+    toff = torch.empty(max_nnz // 2 + 1, dtype=torch.int64, device=dev)
+    views = [aot.Oriented(c.n, c.m, big.rowptr[:c.n + 1], big.col[:c.m], big.tail[:c.m],
+                          big.perm[:c.n], big.rank[:c.n], big.in_rowptr[:c.n + 1],
+                          big.in_col[:c.m]) for c in csrs]
     per_T = []
 
     def per_graph():
         per_T.clear()
         pos = 0
-        for c in csrs:
-            o = aot.alloc_oriented(c.n, c.m, dev)
+        for c, o in zip(csrs, views):
             aot.orient(c.rowptr, c.col, out=o, ws=ows)
-            cc = aot.count(o, ws=cws)
+            cc = aot.count(o, ws=cws, tri_off=toff[:c.m + 1])
             aot.list_triangles(o, cc, out=out[pos:pos + cc.T])
             pos += cc.T
             per_T.append(cc.T)
@@ -456,6 +490,137 @@ def batched_leg(aot, args, dev):
             "tuning_batch": "128 graphs of the same recipe, seeds mix(1004, j)"}
 
 
+class Workload:
+    """One graph resident in HBM with every buffer the step needs."""
+
+    def __init__(self, aot, name, seed, dev, args, dispatch=None):
+        import torch
+
+        t0 = time.time()
+        self.aot, self.name, self.args, self.dispatch = aot, name, args, dispatch
+        self.csr = csr = inputs_mod().workload(name, seed, device=dev)
+        torch.cuda.synchronize()
+        log(f"[bench] generated {csr.name}: n={csr.n} m={csr.m} in {time.time() - t0:.1f}s")
+        self.o = aot.alloc_oriented(csr.n, csr.m, dev)
+        self.ows = torch.empty(aot.orient_workspace(csr.n, csr.nnz), dtype=torch.uint8,
+                               device=dev)
+        self.cws = torch.empty(aot.count_workspace(csr.n, csr.m), dtype=torch.uint8, device=dev)
+        self.tri_off = torch.empty(csr.m + 1, dtype=torch.int64, device=dev)
+        aot.orient(csr.rowptr, csr.col, out=self.o, ws=self.ows)
+        c = aot.count(self.o, dispatch, ws=self.cws, tri_off=self.tri_off)
+        self.T, self.probes = c.T, c.probes
+        self.windowed = self.T * 12 > args.resident_gb * 1e9
+        self.chunk = args.chunk
+        if self.windowed:
+            free, _ = torch.cuda.mem_get_info(dev)
+            self.chunk = int(min(args.chunk, self.T, 0.6 * free // 12))
+        self.out = None if self.windowed else torch.empty((max(self.T, 1), 3), dtype=torch.int32,
+                                                          device=dev)
+        # a list too large to hold is listed in windows: in-lists in rank
+        # order make each window cost about its own triangles
+        self.in_by_rank = self.windowed
+        log(f"[bench] {name}: T={self.T} probes={self.probes}; output {self.T * 12 / 1e9:.2f} GB"
+            + (f", listed in windows of {self.chunk} triangles" if self.windowed else ""))
+
+    def list_all(self, cc, d):
+        if self.windowed:
+            self.aot.stream_list(self.o, cc, self.chunk, None, dispatch=d, to_host=False)
+        else:
+            self.aot.list_triangles(self.o, cc, out=self.out, dispatch=d)
+
+    def step(self, d=None, ev=None):
+        """orient + count + list of the whole graph (optional events between
+        the passes)."""
+        aot, csr = self.aot, self.csr
+        d = self.dispatch if d is None else d
+        if ev:
+            ev[0].record()
+        aot.orient(csr.rowptr, csr.col, out=self.o, ws=self.ows, in_by_rank=self.in_by_rank)
+        if ev:
+            ev[1].record()
+        cc = aot.count(self.o, d, ws=self.cws, tri_off=self.tri_off)
+        if ev:
+            ev[2].record()
+        self.list_all(cc, d)
+        if ev:
+            ev[3].record()
+        return cc
+
+    def timed(self, steps, warmup):
+        """`steps` whole steps after `warmup` untimed ones, wall clock between
+        device synchronisations, with per-pass event times; the timing
+        recorder is off."""
+        import torch
+
+        for _ in range(warmup):
+            self.step()
+        torch.cuda.synchronize()
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(steps):
+            cc = self.step(ev=evs[k])
+            assert (cc.T, cc.probes) == (self.T, self.probes)
+        torch.cuda.synchronize()
+        ms_step = (time.perf_counter() - t0) * 1000.0 / steps
+        per = [sum(e[i].elapsed_time(e[i + 1]) for e in evs) / steps for i in range(3)]
+        log(f"[bench] {self.name}: step {ms_step:.3f} ms: orient {per[0]:.3f} count {per[1]:.3f} "
+            f"list {per[2]:.3f}")
+        return {"ms_per_step": ms_step, "value": self.T / (ms_step / 1000.0),
+                "ms_orient": per[0], "ms_count": per[1], "ms_list": per[2],
+                "probes_per_s": self.probes / (per[1] / 1000.0)}
+
+    def records(self):
+        """One more step with the per-launch recorder on: the per-bucket launch
+        times the roofline is computed from."""
+        self.aot.timing_start()
+        cc = self.step()
+        assert (cc.T, cc.probes) == (self.T, self.probes)
+        return self.aot.timing_stop(cap=1 << 16)
+
+    def config(self):
+        csr = self.csr
+        return {"workload": self.name, "graph": csr.name, "n": csr.n, "m": csr.m,
+                "triangles": self.T, "probes": self.probes,
+                "listing": f"windows of {self.chunk} triangles in device memory"
+                           if self.windowed else "one device buffer"}
+
+
+def inputs_mod():
+    from paper_2006_11494_amd import inputs
+    return inputs
+
+
+def bucket_summary(recs):
+    """Per-bucket totals of the recorded launches (both passes)."""
+    out = {}
+    for r in recs:
+        k = f"{'write' if r['pass'] else 'count'}:{r['bucket']}"
+        d = out.setdefault(k, {"launches": 0, "ms": 0.0, "edges": r["edges"],
+                               "probes": r["probes"], "staged": r["staged"],
+                               "triangles": r["triangles"]})
+        d["launches"] += 1
+        d["ms"] += r["ms"]
+    return out
+
+
+def extra_leg(aot, name, dev, args):
+    """Another configuration: plain steps, and plain against learned."""
+    import torch
+
+    w = Workload(aot, name, None, dev, args)
+    res = {"config": w.config(), **w.timed(max(3, args.steps // 2), 1)}
+    if not args.no_learned:
+        res["learned"] = learned_leg(aot, name, w.o, w.step, w.T, w.probes,
+                                     max(3, args.learned_steps), log, scale=1, repeats=1)
+    if name == "rmat20" and not args.no_ablation:
+        res["ablation"] = ablation_leg(aot, w.csr, w.o, w.ows, w.cws, w.tri_off, w.out, w.T,
+                                       args)
+    del w
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -467,15 +632,10 @@ def main():
         return
     import torch
 
-    from paper_2006_11494_amd import aot, inputs
+    from paper_2006_11494_amd import aot
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    t0 = time.time()
-    csr = inputs.workload(args.workload, args.seed, device=dev)
-    torch.cuda.synchronize()
-    log(f"[bench] generated {csr.name}: n={csr.n} m={csr.m} in {time.time() - t0:.1f}s")
-
     dispatch = None
     if args.heavy_arm or args.heavy_min:
         table = None
@@ -484,67 +644,14 @@ def main():
             table = [t << 8 for t in (4, 4, 4, 8, 16, 32, 64, 64)] + [0] * 8 + [arm] * 16
         dispatch = aot.Dispatch(aot.AOT_DISPATCH_TABLE if table else aot.AOT_DISPATCH_PLAIN,
                                 args.heavy_min, table)
-    o = aot.alloc_oriented(csr.n, csr.m, dev)
-    ows = torch.empty(aot.orient_workspace(csr.n, csr.nnz), dtype=torch.uint8, device=dev)
-    cws = torch.empty(aot.count_workspace(csr.n, csr.m), dtype=torch.uint8, device=dev)
-    tri_off = torch.empty(csr.m + 1, dtype=torch.int64, device=dev)
-    aot.orient(csr.rowptr, csr.col, out=o, ws=ows)
-    c = aot.count(o, dispatch, ws=cws, tri_off=tri_off)
-    T, probes = c.T, c.probes
-    windowed = T * 12 > args.resident_gb * 1e9
-    if windowed:
-        free, _ = torch.cuda.mem_get_info(dev)
-        args.chunk = int(min(args.chunk, T, 0.6 * free // 12))
-    out = None if windowed else torch.empty((max(T, 1), 3), dtype=torch.int32, device=dev)
-    log(f"[bench] T={T} probes={probes}; output {T * 12 / 1e9:.2f} GB"
-        + (f", listed in windows of {args.chunk} triangles" if windowed else ""))
-
-    # a list too large to hold is listed in windows: orient with in-lists in
-    # rank order so that each window costs about its own triangles
-    args.in_by_rank = windowed
-
-    def list_all(cc, d):
-        if windowed:
-            aot.stream_list(o, cc, args.chunk, None, dispatch=d, to_host=False)
-        else:
-            aot.list_triangles(o, cc, out=out, dispatch=d)
-
-    def step(ev=None):
-        if ev:
-            ev[0].record()
-        aot.orient(csr.rowptr, csr.col, out=o, ws=ows, in_by_rank=args.in_by_rank)
-        if ev:
-            ev[1].record()
-        cc = aot.count(o, dispatch, ws=cws, tri_off=tri_off)
-        if ev:
-            ev[2].record()
-        list_all(cc, dispatch)
-        if ev:
-            ev[3].record()
-        return cc
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    aot.timing_start()          # per-launch HIP events on the launch stream
-    t_start = time.perf_counter()
-    for k in range(args.steps):
-        cc = step(evs[k])
-        assert (cc.T, cc.probes) == (T, probes)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t_start
-    recs = aot.timing_stop(cap=1 << 16)
-    ms_orient = sum(e[0].elapsed_time(e[1]) for e in evs) / args.steps
-    ms_count = sum(e[1].elapsed_time(e[2]) for e in evs) / args.steps
-    ms_list = sum(e[2].elapsed_time(e[3]) for e in evs) / args.steps
-    ms_step = wall * 1000.0 / args.steps
-    log(f"[bench] step {ms_step:.3f} ms: orient {ms_orient:.3f} count {ms_count:.3f} "
-        f"list {ms_list:.3f}")
+    w = Workload(aot, args.workload, args.seed, dev, args, dispatch)
+    T, probes = w.T, w.probes
+    timed = w.timed(args.steps, args.warmup)
+    recs = w.records()
+    ms_step = timed["ms_per_step"]
 
     streamed = None
-    if windowed and not args.no_stream:
+    if w.windowed and args.stream:
         state = {"windows": 0, "last": time.time()}
 
         def consume(first, view):
@@ -553,11 +660,11 @@ def main():
                 log(f"[bench] streamed {first + len(view)} of {T} triangles to the host")
                 state["last"] = time.time()
 
-        aot.orient(csr.rowptr, csr.col, out=o, ws=ows, in_by_rank=True)
+        aot.orient(w.csr.rowptr, w.csr.col, out=w.o, ws=w.ows, in_by_rank=True)
         torch.cuda.synchronize()
         t = time.perf_counter()
-        cc = aot.count(o, dispatch, ws=cws, tri_off=tri_off)
-        aot.stream_list(o, cc, args.stream_chunk, consume, dispatch=dispatch, to_host=True)
+        cc = aot.count(w.o, dispatch, ws=w.cws, tri_off=w.tri_off)
+        aot.stream_list(w.o, cc, args.stream_chunk, consume, dispatch=dispatch, to_host=True)
         torch.cuda.synchronize()
         s_ms = (time.perf_counter() - t) * 1000.0
         streamed = {"ms_count_and_list": s_ms, "windows": state["windows"],
@@ -570,18 +677,13 @@ def main():
 
     torch.cuda.empty_cache()        # return cached window buffers before the next legs
     ablation = None
-    if not args.no_ablation and not windowed:
-        ablation = ablation_leg(aot, csr, o, ows, cws, tri_off, out, T, args)
+    if not args.no_ablation and not w.windowed:
+        ablation = ablation_leg(aot, w.csr, w.o, w.ows, w.cws, w.tri_off, w.out, T, args)
     learned = None
     if not args.no_learned and not args.heavy_arm:
-        learned = learned_leg(aot, o, csr, cws, tri_off, list_all, T, probes, args)
+        learned = learned_leg(aot, args.workload, w.o, w.step, T, probes, args.learned_steps, log)
 
-    del out
-    batched = None
-    if not args.no_batch and not windowed:
-        batched = batched_leg(aot, args, dev)
-
-    roof = roofline(recs, args.workload, windowed)
+    roof = roofline(recs, args.workload, w.windowed)
     log(f"[bench] dominant kernel {roof['kernel']}: {roof['achieved']:.1f} GB/s "
         f"({roof['frac'] * 100:.1f}% of peak) over {roof['launches']} launches")
     copy_gbs = copy_bandwidth()
@@ -591,16 +693,28 @@ def main():
         f"dominant kernel at {roof['achieved'] / copy_gbs * 100:.1f}% of it")
     base = None
     if not args.no_cpu_baseline:
-        # one thread, and all of the host's share of cores (16 per GPU); the
-        # large list is sampled on all cores only
+        # the large list is sampled on the host's share of cores (16 per GPU)
+        # only; smaller ones on one thread and on all of them
         cores = min(16, os.cpu_count() or 1)
-        if windowed:
-            base = cpu_baseline(csr, args.cpu_sample / 20, cores)
+        if w.windowed:
+            base = cpu_baseline(w.csr, args.cpu_sample or 0.01, cores)
         else:
-            base = cpu_baseline(csr, args.cpu_sample, 1)
-            wide = cpu_baseline(csr, args.cpu_sample, cores)
+            base = cpu_baseline(w.csr, args.cpu_sample or 0.5, 1)
+            wide = cpu_baseline(w.csr, args.cpu_sample or 0.5, cores)
             base["all_cores"] = {k: wide[k] for k in ("value", "cores", "sample")}
         base["host"] = host_info()
+    config = dict(w.config(), dispatch=args.heavy_arm or "plain",
+                  heavy_min=args.heavy_min or 64)
+    del w
+    torch.cuda.empty_cache()
+
+    extras = {}
+    if args.workload == HEADLINE and not args.no_extras:
+        for name in EXTRAS:
+            extras[name] = extra_leg(aot, name, dev, args)
+    batched = None
+    if not args.no_batch and (args.workload != HEADLINE or not args.no_extras):
+        batched = batched_leg(aot, args, dev)
 
     result = {
         "metric": "triangles/s (whole orient+count+list step); probes/s = sum of min(deg+) "
@@ -616,15 +730,11 @@ def main():
         "vs_baseline": None,
         "dtype": "int32",
         "data": "synthetic",
-        "config": {"workload": args.workload, "graph": csr.name, "n": csr.n, "m": csr.m,
-                   "triangles": T, "probes": probes,
-                   "listing": f"windows of {args.chunk} triangles in device memory"
-                              if windowed else "one device buffer",
-                   "dispatch": args.heavy_arm or "plain", "heavy_min": args.heavy_min or 64},
-        "probes_per_s": probes / (ms_count / 1000.0),
-        "ms_orient": ms_orient,
-        "ms_count": ms_count,
-        "ms_list": ms_list,
+        "config": config,
+        "probes_per_s": timed["probes_per_s"],
+        "ms_orient": timed["ms_orient"],
+        "ms_count": timed["ms_count"],
+        "ms_list": timed["ms_list"],
         "roofline": {k: roof[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic")},
         "roofline_kernel": dict({k: roof[k] for k in ("kernel", "launches", "avg_launch_ms",
                                                       "bytes_per_launch", "per_unit")},
@@ -632,12 +742,16 @@ def main():
                                 # rocprofv3's FETCH_SIZE + WRITE_SIZE bytes of one launch over
                                 # this run's average launch time (null without a profile)
                                 hbm_measured_GBs=hbm_gbs,
-                                hbm_measured_frac=hbm_gbs / HBM_PEAK_GBS if hbm_gbs else None),
+                                hbm_measured_frac=hbm_gbs / HBM_PEAK_GBS if hbm_gbs else None,
+                                records="one extra step with the per-launch recorder on, "
+                                        "outside the timed steps"),
+        "buckets": bucket_summary(recs),
         "cpu_baseline": base,
         "learned": learned,
         "ablation": ablation,
         "batched": batched,
         "streamed": streamed,
+        "extras": extras,
     }
     print(json.dumps(result), flush=True)
 

@@ -117,11 +117,14 @@ def csr_from_pairs(n: int, u: torch.Tensor, v: torch.Tensor, name: str = "") -> 
     return Csr(n, rowptr, cols.to(torch.int32), name)
 
 
-def csr_from_pairs_partitioned(n: int, u, v, name: str = "", parts: int = 32) -> Csr:
+def csr_from_pairs_partitioned(n: int, u, v, name: str = "", parts: int = 32,
+                               consume: bool = False) -> Csr:
     """The same CSR as csr_from_pairs, built one range of rows at a time so
     that no sort ever holds more than about 2 * pairs / parts keys (graphs
     with billions of entries).  u, v: tensors (int32 or int64), or equally
-    chunked lists of them, so that no single operation sees all pairs."""
+    chunked lists of them, so that no single operation sees all pairs.  With
+    consume=True and lists, the lists are emptied once every range is built,
+    so the pairs are freed before the rows are joined."""
     us = list(u) if isinstance(u, (list, tuple)) else [u]
     vs = list(v) if isinstance(v, (list, tuple)) else [v]
     dev = us[0].device if us else torch.device("cpu")
@@ -145,6 +148,12 @@ def csr_from_pairs_partitioned(n: int, u, v, name: str = "", parts: int = 32) ->
         counts[lo:hi] = torch.bincount(rows, minlength=hi - lo)
         cols.append((key - rows * n).to(torch.int32))
         del key, rows
+    if consume:
+        for lst in (u, v):
+            if isinstance(lst, list):
+                lst.clear()
+        us.clear()
+        vs.clear()
     rowptr = torch.zeros(n + 1, dtype=torch.int64, device=dev)
     rowptr[1:] = torch.cumsum(counts, 0)
     col = torch.cat(cols) if cols else torch.zeros(0, dtype=torch.int32, device=dev)
@@ -226,7 +235,8 @@ def rmat(scale: int, edge_factor: int, seed: int, a=0.57, b=0.19, c=0.19,
     name = f"rmat(scale={scale},ef={edge_factor},seed={seed})"
     if parts is None and ntup < (1 << 27):
         return csr_from_pairs(n, torch.cat(us), torch.cat(vs), name)
-    return csr_from_pairs_partitioned(n, us, vs, name, parts or max(8, ntup >> 26))
+    return csr_from_pairs_partitioned(n, us, vs, name, parts or max(8, ntup >> 26),
+                                      consume=True)
 
 
 def chung_lu(n: int, mean_degree: float, gamma: float, max_degree: float, seed: int,

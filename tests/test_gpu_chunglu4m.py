@@ -1,14 +1,17 @@
 """The learned-dispatch configuration at full size: Chung-Lu, n = 4,000,000,
 mean degree 40, exponent 2.1, degree cap 100,000 (about 7.5e7 edges and 2e9
-triangles).  The whole list is beyond the CPU oracle, so parity rests on what
-it computes at this size:
+triangles).  The whole list is not stored on the host, so parity rests on
+what the oracle computes at this size:
   * the whole orientation and the probe count, exactly;
   * per-edge counts at 200,000 random edges and at edges of the heaviest
     owners, exactly;
   * complete, ordered triangle lists of rank ranges at several depths;
   * triangles through sampled vertices (the hubs among them), exactly;
-and on invariants: every dispatch table and probe strategy gives the same
-digest of the whole list."""
+  * the digest of the whole list -- T, the sum and xor of the triple hashes
+    and the triangles through every vertex -- against the oracle's CF run
+    over rank ranges on 16 host threads, exactly;
+and every dispatch table, probe strategy and a learned dispatch gives that
+same digest."""
 
 import sys
 import time
@@ -18,7 +21,7 @@ import pytest
 import torch
 
 import oracle
-from paper_2006_11494_amd import aot, inputs
+from paper_2006_11494_amd import aot, inputs, learn
 
 pytestmark = [pytest.mark.gpu, pytest.mark.timeout(900)]
 
@@ -69,7 +72,11 @@ def test_chunglu4m_sampled_parity():
         say(f"[gpu] chunglu4m: ranks [{r_lo}, {r_hi}): {len(want)} triangles equal")
 
     (t, s, x), vc = aot.digest(o, c)
-    assert t == c.T and int(vc.sum()) == 3 * t
+    rt, (rf1, rf2), rtv = oracle.list_digest_threaded(ref, threads=16)
+    assert (t, s, x) == (rt, rf1, rf2) and t == c.T
+    assert np.array_equal(vc.cpu().numpy().astype(np.uint64), rtv)
+    say(f"[gpu] chunglu4m: whole-list digest and all {n} vertex counts equal the oracle's "
+        f"at {time.time() - t0:.1f}s")
     # the oracle merges each neighbour's row with v's (about deg(v)^2 steps):
     # the three largest hubs, 20 of the top 1000 and 2000 random vertices
     deg = np.diff(rp)
@@ -85,8 +92,15 @@ def test_chunglu4m_sampled_parity():
               "sorted_4lane": aot.Dispatch(aot.AOT_DISPATCH_TABLE, 32,
                                            [4 << 8] * 8 + [0] * 8 + [3] * 16)}
     others.update({k: aot.Dispatch(strategy=v) for k, v in aot.STRATEGIES.items() if k != "aot"})
+    # a cost model trained on a small graph of another recipe; whatever plan
+    # it picks here, the list is the oracle's
+    net, _ = learn.train(learn.dataset(learn.record(inputs.rmat(15, 16, 1031).to("cuda"),
+                                                    repeats=1)), epochs=300)
+    others["learned"] = aot.Dispatch(aot.AOT_DISPATCH_LEARNED, 0, None, net)
     for name, d in others.items():
         cd = aot.count(o, d)
         assert cd.T == c.T and torch.equal(cd.tri_off, c.tri_off), name
-        assert aot.digest(o, cd, vertex_counts=False)[0] == (t, s, x), name
+        assert aot.digest(o, cd, vertex_counts=False)[0] == (rt, rf1, rf2), name
+        if name == "learned":
+            say(f"[gpu] chunglu4m: learned plan {aot.count_plan(o, cd)}")
         say(f"[gpu] chunglu4m: {name}: same digest at {time.time() - t0:.1f}s")

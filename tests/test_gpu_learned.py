@@ -121,6 +121,9 @@ def test_learned_dispatch_is_bit_exact_and_falls_back():
     assert learned
     assert (c1.T, c1.probes) == (c0.T, c0.probes) and torch.equal(c1.tri_off, c0.tri_off)
     t1 = aot.list_triangles(o, c1)           # the stored learned plan
+    ref = oracle.orient(*csr.numpy())
+    assert np.array_equal(t1.cpu().numpy(), oracle.list_triangles(ref))
+    assert c1.probes == oracle.sum_min(ref)
     assert torch.equal(t0, t1)
     (dg0, vc0), (dg1, vc1) = aot.digest(o, c0), aot.digest(o, c1)
     assert dg0 == dg1 and torch.equal(vc0, vc1)

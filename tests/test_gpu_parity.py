@@ -305,6 +305,54 @@ def test_timing_recorder():
     assert aot.timing_stop() == []          # stopped: nothing new recorded
 
 
+def oracle_buckets(ref, heavy_min=64):
+    """Per-bucket (edges, probes, triangles) from the oracle's orientation and
+    per-edge counts, binned by the recorder's documented rule: an edge whose
+    owner b (the endpoint with the larger (deg+, rank)) has deg+(b) >=
+    heavy_min is in heavy bucket 16 + min(ceil(log2 deg+(b)), 15); otherwise,
+    if c = min(deg+) > 0, in light bin min(ceil(log2 c), 7) ({1} is bin 0);
+    edges with c = 0 and a light owner are in no bucket."""
+    dplus = np.diff(ref.orow)
+    u = np.repeat(np.arange(ref.n), dplus)
+    v = ref.ocol
+    du, dv = dplus[u], dplus[v]
+    c = np.minimum(du, dv)
+    db = np.where(du <= dv, dv, du)               # on a tie the tail u is probed
+    clog = lambda x: np.ceil(np.log2(np.maximum(x, 1))).astype(np.int64)
+    bucket = np.where(db >= heavy_min, 16 + np.minimum(clog(db), 15),
+                      np.where(c > 0, np.minimum(clog(c), 7), -1))
+    tri = oracle.edge_counts(ref)
+    out = {}
+    for b in np.unique(bucket[bucket >= 0]):
+        sel = bucket == b
+        out[int(b)] = (int(sel.sum()), int(c[sel].sum()), int(tri[sel].sum()))
+    return out
+
+
+@pytest.mark.parametrize("name", ["rmat13", "chunglu"])
+def test_timing_recorder_statistics_match_oracle(name):
+    """The recorder's per-bucket edges, probes and triangles -- the cost
+    model's features and training targets -- against the oracle's per-edge
+    minima and counts binned by the same rule."""
+    need_gpu()
+    g = {"rmat13": lambda: inputs.rmat(13, 16, 7),
+         "chunglu": lambda: inputs.chung_lu(100_000, 30.0, 2.1, 10_000.0, 31)}[name]()
+    rp, col = g.numpy()
+    want = oracle_buckets(oracle.orient(rp, col))
+    gd = g.to(DEV)
+    o = aot.orient(gd.rowptr, gd.col)
+    aot.timing_start()
+    aot.count(o)
+    recs = aot.timing_stop()
+    got = {}
+    for r in recs:
+        assert r["pass"] == 0
+        e, p, t = got.get(r["bucket"], (0, 0, 0))
+        got[r["bucket"]] = (e + r["edges"], p + r["probes"], t + r["triangles"])
+    assert got == want
+    assert any(b >= 16 for b in got) and any(b < 8 for b in got)
+
+
 @pytest.mark.parametrize("name", ["er2000", "rmat14", "k40", "tiebreak", "empty", "star300"])
 def test_digest_matches_oracle(name):
     need_gpu()
