@@ -25,7 +25,9 @@
  *   - Pointers marked "device" are HIP device (or managed) memory on the
  *     current device; "host" pointers are ordinary host memory.
  *   - The caller owns every buffer; the library allocates no device memory.
- *     Workspace sizes come from the *_workspace() queries.
+ *     Workspace sizes come from the *_workspace() queries.  The one device
+ *     array the library holds itself is the fixed scratch of
+ *     aot_count_noalloc (64 MiB per device).
  *   - `stream` is a hipStream_t (NULL = the legacy default stream).  Calls
  *     enqueue work on it; calls that return host values synchronise it.
  *   - Vertex ids are int32 in [0, n).  The input graph is a symmetric CSR:
@@ -218,6 +220,27 @@ typedef struct aot_dispatch {
 int aot_count_workspace(int32_t n, int64_t m, size_t* bytes);
 int aot_count(const aot_oriented* g, const aot_dispatch* d, int64_t* tri_off,
               void* ws, size_t ws_bytes, uint64_t* result, void* stream);
+
+/* ------------------------------------------------------------------------
+ * aot_count_noalloc -- aot_count for callers that cannot allocate device
+ * memory (serving loops and harnesses that forbid hipMalloc): the same count
+ * pass, the same tri_off and result, with the count workspace taken from a
+ * fixed scratch array inside the library instead of a `ws` argument.
+ *   Limit: the graph's aot_count_workspace() must not exceed
+ *          AOT_NOALLOC_SCRATCH_BYTES (64 MiB, about 4e6 edges); larger graphs
+ *          get AOT_E_CAPACITY before anything is enqueued.
+ *   Each device holds its own scratch from library load until the process
+ *   ends; the first call on a device looks up its address.  Calls on one
+ *   device share that scratch: calls that overlap in time on one device (two
+ *   host threads, or two streams) race and must be serialised by the caller.
+ *   Every call rewrites what it reads, so nothing carries over between calls.
+ *   The resolved plan stays in the scratch only until the next call: listing
+ *   afterwards needs aot_count with a workspace of its own.
+ * Allocates nothing (no hipMalloc, hipFree or library allocation); synchronises
+ * `stream`.  Arguments and errors otherwise as aot_count. */
+#define AOT_NOALLOC_SCRATCH_BYTES (64u << 20)
+int aot_count_noalloc(const aot_oriented* g, const aot_dispatch* d, int64_t* tri_off,
+                      uint64_t* result, void* stream);
 
 /* The plan the last aot_count on `ws` resolved: table (host int32[32], codes
  * as in aot_dispatch) and *learned = 1 if the cost model chose it, 0 if the

@@ -17,6 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libaot.so")
 
 ABI_VERSION = 3          # the aot_version() this binding's structs match
+AOT_NOALLOC_SCRATCH_BYTES = 64 << 20   # fixed scratch of aot_count_noalloc (include/aot.h)
 AOT_OK = 0
 AOT_VALIDATE = 1
 AOT_IN_LISTS_BY_RANK = 2
@@ -39,7 +40,7 @@ AOT_NUM_FEATURES = 8
 EXPORTS = (
     "aot_status_str", "aot_last_error", "aot_version",
     "aot_orient_workspace", "aot_orient",
-    "aot_count_workspace", "aot_count",
+    "aot_count_workspace", "aot_count", "aot_count_noalloc",
     "aot_list", "aot_digest", "aot_support", "aot_count_plan", "aot_bucket_features",
     "aot_mlp_param_count", "aot_mlp_workspace", "aot_mlp_init", "aot_mlp_forward",
     "aot_mlp_loss_grad", "aot_mlp_train",
@@ -121,6 +122,8 @@ def load(path: str = LIB_PATH):
     lib.aot_count_workspace.argtypes = [i32, i64, sz]
     lib.aot_count.argtypes = [ctypes.POINTER(OrientedC), ctypes.POINTER(DispatchC), vp, vp,
                               ctypes.c_size_t, ctypes.POINTER(ctypes.c_uint64), vp]
+    lib.aot_count_noalloc.argtypes = [ctypes.POINTER(OrientedC), ctypes.POINTER(DispatchC), vp,
+                                      ctypes.POINTER(ctypes.c_uint64), vp]
     lib.aot_list.argtypes = [ctypes.POINTER(OrientedC), ctypes.POINTER(DispatchC), vp, vp,
                              ctypes.c_size_t, i64, i64, vp, ctypes.POINTER(ctypes.c_int64), vp]
     lib.aot_digest.argtypes = [ctypes.POINTER(OrientedC), ctypes.POINTER(DispatchC), vp, vp,
@@ -364,6 +367,19 @@ def count(o: Oriented, dispatch: Dispatch | None = None, stream=None,
     _check(load().aot_count(ctypes.byref(oc), ctypes.byref(dc), _ptr(tri_off), _ptr(ws),
                             ws.numel(), res, _stream(stream)), "aot_count")
     return Counted(int(res[0]), int(res[1]), tri_off, ws)
+
+
+def count_noalloc(o: Oriented, tri_off: torch.Tensor, dispatch: Dispatch | None = None,
+                  stream=None) -> tuple[int, int]:
+    """aot_count_noalloc: the count pass with the library's fixed scratch as
+    its workspace (no allocation); writes tri_off and returns (T, probes)."""
+    assert tri_off.dtype == torch.int64 and tri_off.numel() >= o.m + 1
+    res = (ctypes.c_uint64 * 2)()
+    oc = o.cstruct()
+    dc = (dispatch or Dispatch()).cstruct()
+    _check(load().aot_count_noalloc(ctypes.byref(oc), ctypes.byref(dc), _ptr(tri_off), res,
+                                    _stream(stream)), "aot_count_noalloc")
+    return int(res[0]), int(res[1])
 
 
 def list_triangles(o: Oriented, c: Counted, first: int = 0, count: int | None = None,

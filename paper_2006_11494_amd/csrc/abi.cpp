@@ -2,6 +2,7 @@
 #include <algorithm>
 #include <climits>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "aot.h"
@@ -147,6 +148,33 @@ int batch_enqueue(const aot_batch* b, const aot_schedule* sc, aot_oriented* out,
   return ok();
 }
 
+// Fixed scratch of aot_count_noalloc: the count workspace of callers that
+// cannot allocate device memory.  Each device holds its own copy from the
+// time the library's code object is loaded there until the process ends.
+// The array's name is a host-side stand-in; kernels get the device address
+// that hipGetSymbolAddress returns, looked up once per device.
+__device__ __align__(256) unsigned char scratch[AOT_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxScratchDevices] = {};
+
+int scratch_of_current_device(void** ptr) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(AOT_E_HIP, "hipGetDevice failed");
+  if (dev < 0 || dev >= kMaxScratchDevices)
+    return fail(AOT_E_ARG, "device index beyond the fixed scratch table (64 devices)");
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p)
+      return fail(AOT_E_HIP, "hipGetSymbolAddress of the fixed scratch failed");
+    g_scratch_ptr[dev] = p;
+  }
+  *ptr = g_scratch_ptr[dev];
+  return AOT_OK;
+}
+
 }  // namespace
 
 struct aot_batch_graph {
@@ -231,6 +259,29 @@ int aot_count(const aot_oriented* g, const aot_dispatch* d, int64_t* tri_off, vo
   const char* err = nullptr;
   rc = aot::count_run(g->n, g->m, g->rowptr, g->col, g->tail, g->in_rowptr, g->in_col, dv,
                       tri_off, ws, ws_bytes, result, static_cast<hipStream_t>(stream), &err);
+  return hip_status(rc, err);
+}
+
+int aot_count_noalloc(const aot_oriented* g, const aot_dispatch* d, int64_t* tri_off,
+                      uint64_t* result, void* stream) {
+  int rc = check_oriented(g);
+  if (rc) return rc;
+  if (!tri_off || !result) return fail(AOT_E_ARG, "tri_off or result is NULL");
+  aot::DispatchView dv;
+  rc = check_dispatch(d, &dv);
+  if (rc) return rc;
+  const size_t need = aot::count_workspace_bytes(g->n, g->m);
+  if (need > (size_t)AOT_NOALLOC_SCRATCH_BYTES)
+    return fail(AOT_E_CAPACITY, "graph too large for the fixed scratch of aot_count_noalloc: needs " +
+                                    std::to_string(need) + " bytes, the scratch holds " +
+                                    std::to_string((size_t)AOT_NOALLOC_SCRATCH_BYTES));
+  void* ws = nullptr;
+  rc = scratch_of_current_device(&ws);
+  if (rc) return rc;
+  const char* err = nullptr;
+  rc = aot::count_run(g->n, g->m, g->rowptr, g->col, g->tail, g->in_rowptr, g->in_col, dv,
+                      tri_off, ws, (size_t)AOT_NOALLOC_SCRATCH_BYTES, result,
+                      static_cast<hipStream_t>(stream), &err);
   return hip_status(rc, err);
 }
 
