@@ -818,19 +818,61 @@ __global__ __launch_bounds__(kBlock) void k_sort_block(int cbase, int cls, const
   }
 }
 
-// Long rows: values are distinct ranks, so a bitmap over [min, max] in LDS
-// (one 524288-id window at a time) sorts them; set bits are written out in
-// order after a block-wide prefix count.
+// Long rows: values are distinct labels, so a bitmap in LDS sorts them, one
+// window of kBits ids at a time.  A row whose [min, max] fits one window is
+// set into the bitmap straight from src.  A wider row is first partitioned by
+// window into its place in dst (a histogram of windows, its prefix sum, and
+// a scatter whose lanes with the same window take consecutive slots with one
+// LDS atomic per group); then each window's bucket is read back, set into the
+// bitmap and written over itself in ascending order.  Every entry is read
+// four times and written twice however wide the row's range is.
+constexpr int64_t kBits = (int64_t)kBitmapWords * 32;
+constexpr int kMaxWindows = 4096;   // (INT32_MAX + 1) / kBits: every id range
+
+// Lanes (among the active ones) whose window w equals this lane's; w < 2^nbits.
+__device__ __forceinline__ uint64_t match_window(int w, int nbits, bool active) {
+  uint64_t peers = ballot(active);
+  for (int b = 0; b < nbits; ++b) {
+    const bool bit = (w >> b) & 1;
+    const uint64_t m = ballot(bit);
+    peers &= bit ? m : ~m;
+  }
+  return peers;
+}
+
+// Writes the set bits of bm (ids w0 + bit index) to out[0..) in ascending
+// order; `tmp` holds kWavesPerBlock + 1 entries.  Ends with a barrier.
+__device__ __forceinline__ int64_t emit_bitmap(const uint32_t* bm, int64_t w0, int32_t* out,
+                                               int64_t* tmp) {
+  constexpr int kWordsPerThread = kBitmapWords / kBlock;
+  const int wbeg = threadIdx.x * kWordsPerThread;
+  int64_t c = 0;
+  for (int q = 0; q < kWordsPerThread; ++q) c += __popc(bm[wbeg + q]);
+  int64_t total;
+  int64_t pos = block_exclusive_scan(c, tmp, &total);
+  for (int q = 0; q < kWordsPerThread; ++q) {
+    uint32_t bits = bm[wbeg + q];
+    while (bits) {
+      const int b = __ffs(bits) - 1;
+      out[pos++] = (int32_t)(w0 + (int64_t)(wbeg + q) * 32 + b);
+      bits &= bits - 1;
+    }
+  }
+  __syncthreads();
+  return total;
+}
+
 __global__ __launch_bounds__(kBlock) void k_sort_bitmap(int cbase, int cls, const int32_t* __restrict__ counters,
                                                         const int32_t* __restrict__ rows,
                                                         const int64_t* __restrict__ orow,
                                                         const int32_t* __restrict__ src,
                                                         int32_t* __restrict__ dst) {
   __shared__ uint32_t bm[kBitmapWords];
+  __shared__ int32_t woff[kMaxWindows + 1];
   __shared__ int64_t tmp[kWavesPerBlock + 1];
   __shared__ int32_t red[2][kWavesPerBlock];
-  constexpr int64_t kBits = (int64_t)kBitmapWords * 32;
-  constexpr int kWordsPerThread = kBitmapWords / kBlock;
+  __shared__ int32_t stmp[kWavesPerBlock + 1];
+  int32_t* cursor = reinterpret_cast<int32_t*>(bm);   // during the scatter only
   int32_t base = 0;
   for (int q = 0; q < cls; ++q) base += counters[cbase + q];
   const int32_t count = counters[cbase + cls];
@@ -853,30 +895,77 @@ __global__ __launch_bounds__(kBlock) void k_sort_bitmap(int cbase, int cls, cons
     lo = red[0][0]; hi = red[1][0];
     for (int q = 1; q < kWavesPerBlock; ++q) { lo = min(lo, red[0][q]); hi = max(hi, red[1][q]); }
     __syncthreads();
-    int64_t out = beg;
-    for (int64_t w0 = lo; w0 <= hi; w0 += kBits) {
+    const int nwin = (int)(((int64_t)hi - lo) / kBits) + 1;   // <= kMaxWindows
+    if (nwin == 1) {
       for (int i = threadIdx.x; i < kBitmapWords; i += kBlock) bm[i] = 0u;
       __syncthreads();
       for (int64_t i = threadIdx.x; i < len; i += kBlock) {
-        const int64_t off = (int64_t)src[beg + i] - w0;
-        if (off >= 0 && off < kBits) atomicOr(&bm[off >> 5], 1u << (off & 31));
+        const int64_t off = (int64_t)src[beg + i] - lo;
+        atomicOr(&bm[off >> 5], 1u << (off & 31));
       }
       __syncthreads();
-      const int wbeg = threadIdx.x * kWordsPerThread;
-      int64_t c = 0;
-      for (int q = 0; q < kWordsPerThread; ++q) c += __popc(bm[wbeg + q]);
-      int64_t total;
-      int64_t pos = out + block_exclusive_scan(c, tmp, &total);
-      for (int q = 0; q < kWordsPerThread; ++q) {
-        uint32_t bits = bm[wbeg + q];
-        while (bits) {
-          const int b = __ffs(bits) - 1;
-          dst[pos++] = (int32_t)(w0 + (int64_t)(wbeg + q) * 32 + b);
-          bits &= bits - 1;
+      emit_bitmap(bm, lo, dst + beg, tmp);
+      continue;
+    }
+    // histogram of windows
+    const int nbits = ceil_log2(nwin);
+    for (int i = threadIdx.x; i < nwin; i += kBlock) woff[i] = 0;
+    __syncthreads();
+    for (int64_t i0 = 0; i0 < len; i0 += kBlock) {
+      const int64_t i = i0 + threadIdx.x;
+      const bool live = i < len;
+      const int w = live ? (int)(((int64_t)src[beg + i] - lo) / kBits) : 0;
+      const uint64_t peers = match_window(w, nbits, live);
+      if (live && popc_below(peers) == 0) atomicAdd(&woff[w], (int32_t)__popcll(peers));
+    }
+    __syncthreads();
+    // exclusive prefix over the windows: each thread a run of consecutive ones
+    {
+      constexpr int kPer = kMaxWindows / kBlock;
+      const int w0 = threadIdx.x * kPer;
+      int32_t run = 0;
+      for (int q = 0; q < kPer; ++q)
+        if (w0 + q < nwin) run += woff[w0 + q];
+      int32_t total;
+      int32_t at = block_exclusive_scan(run, stmp, &total);
+      for (int q = 0; q < kPer; ++q)
+        if (w0 + q < nwin) {
+          const int32_t c = woff[w0 + q];
+          woff[w0 + q] = at;
+          at += c;
         }
-      }
-      out += total;
+      if (threadIdx.x == 0) woff[nwin] = total;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nwin; i += kBlock) cursor[i] = woff[i];
+    __syncthreads();
+    // scatter into the row's place in dst, bucketed by window
+    for (int64_t i0 = 0; i0 < len; i0 += kBlock) {
+      const int64_t i = i0 + threadIdx.x;
+      const bool live = i < len;
+      const int32_t v = live ? src[beg + i] : 0;
+      const int w = live ? (int)(((int64_t)v - lo) / kBits) : 0;
+      const uint64_t peers = match_window(w, nbits, live);
+      const int leader = peers ? __ffsll((long long)peers) - 1 : 0;
+      int32_t at = 0;
+      if (live && lane_id() == leader) at = atomicAdd(&cursor[w], (int32_t)__popcll(peers));
+      at = __shfl(at, leader, kWave);
+      if (live) dst[beg + at + popc_below(peers)] = v;
+    }
+    __syncthreads();
+    // each window's bucket through the bitmap, written over itself in order
+    for (int w = 0; w < nwin; ++w) {
+      const int32_t b0 = woff[w], b1 = woff[w + 1];
+      if (b1 == b0) continue;
+      const int64_t w0 = (int64_t)lo + (int64_t)w * kBits;
+      for (int i = threadIdx.x; i < kBitmapWords; i += kBlock) bm[i] = 0u;
       __syncthreads();
+      for (int32_t i = b0 + threadIdx.x; i < b1; i += kBlock) {
+        const int64_t off = (int64_t)dst[beg + i] - w0;
+        atomicOr(&bm[off >> 5], 1u << (off & 31));
+      }
+      __syncthreads();
+      emit_bitmap(bm, w0, dst + beg + b0, tmp);
     }
   }
 }
