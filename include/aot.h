@@ -124,7 +124,7 @@ typedef struct aot_oriented {
  *           vertices keep their original ids as labels, so each out-list is
  *           in ascending id instead of the degree local order (Section 3.2).
  *           On inputs whose ids are randomly permuted this is the random
- *           local order of AOT-randomOrder (Section 4.3).  Rows are indexed
+ *           local order of AOT-randomOrder (Section 4.2).  Rows are indexed
  *           by id, perm and rank are the identity, and both in-list orders
  *           coincide (ascending id).  Counts, the probe count and the
  *           triangle set do not change; the list order follows the labels.

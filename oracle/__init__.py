@@ -120,7 +120,7 @@ def orient(rowptr, col, order: str = "degree", local: str = "rank") -> Oriented:
     """Degree order with id tie-break; <u,v> iff eta(u) < eta(v) (Sec. 2.2).
     order="core": the core order of kClist (Sec. 2.3), see core_rounds.
     local="id": the same edges with original ids as labels, so each out-list
-    is in id order (AOT-randomOrder, Sec. 4.3, for inputs with permuted ids)."""
+    is in id order (AOT-randomOrder, Sec. 4.2, for inputs with permuted ids)."""
     lib = _load()
     rowptr, col = _arrays(rowptr, col)
     if local not in ("rank", "id"):

@@ -206,7 +206,7 @@ int64_t orc_orient_core(int32_t n, const int64_t* rowptr, const int32_t* col, in
  * rows are indexed by original id.  Inside each list, vertices then follow id
  * order instead of the degree local order of Section 3.2; for inputs with
  * randomly permuted ids this is the random local order of AOT-randomOrder
- * (Section 4.3).  Returns m. */
+ * (Section 4.2).  Returns m. */
 int64_t orc_orient_by_id(int32_t n, const int64_t* rowptr, const int32_t* col,
                          const int32_t* rank, int64_t* orow, int32_t* ocol) {
   orow[0] = 0;

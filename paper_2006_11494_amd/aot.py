@@ -326,7 +326,7 @@ def orient(rowptr: torch.Tensor, col: torch.Tensor, validate: bool = False, stre
     """aot_orient on a symmetric device CSR (rowptr int64[n+1], col int32[nnz]);
     order "degree" (Algorithm 3) or "core" (kClist's, AOT_ORDER_CORE); local
     "rank" (labels are ranks: the degree local order of Section 3.2) or "id"
-    (labels are original ids, AOT_LOCAL_BY_ID: AOT-randomOrder of Section 4.3
+    (labels are original ids, AOT_LOCAL_BY_ID: AOT-randomOrder of Section 4.2
     on inputs with permuted ids)."""
     if order not in ("degree", "core"):
         raise ValueError(f"unknown order {order!r}")

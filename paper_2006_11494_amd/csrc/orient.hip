@@ -11,7 +11,7 @@
 // sorted the same way into ascending rank, which is the order of their edges'
 // ids (this makes windows of a huge triangle list cheap; see aot_list).
 //
-// Labels by id (AOT-randomOrder of Section 4.3): the order still directs every
+// Labels by id (AOT-randomOrder of Section 4.2): the order still directs every
 // edge, but vertices keep their original ids as labels, so an out-list is in
 // ascending id instead of the degree local order of Section 3.2; with
 // randomly permuted ids that is a random local order.  Rows are then written

@@ -556,7 +556,7 @@ def test_core_order_lists_the_same_set(seed):
 
 @pytest.mark.parametrize("n,p,seed", SMALL + [(300, 0.05, 99)])
 def test_orientation_by_id_keeps_the_edges_in_id_order(n, p, seed):
-    """Labels by id (AOT-randomOrder's local order, Section 4.3): the degree
+    """Labels by id (AOT-randomOrder's local order, Section 4.2): the degree
     order, computed here from scratch, still directs every edge; rows are
     indexed by id and ascending in id."""
     g = random_graph(n, p, seed)
