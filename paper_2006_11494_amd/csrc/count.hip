@@ -92,7 +92,7 @@ __host__ __device__ __forceinline__ int heavy_class(int32_t db) {
   return h < kHeavyClasses ? h : kHeavyClasses - 1;
 }
 
-// Probe strategies (the ablation of Section 4.3 and the costs of Section 2):
+// Probe strategies (the comparisons of Sections 4.1 and 4.2 and the costs of Section 2):
 // which list an edge probes and into what.  All list the same triangles in
 // the same order.
 constexpr int kStratAdaptive = 0;   // Algorithm 3: min side into the owner's index

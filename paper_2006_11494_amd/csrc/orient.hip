@@ -862,11 +862,16 @@ __device__ __forceinline__ int64_t emit_bitmap(const uint32_t* bm, int64_t w0, i
   return total;
 }
 
+// One workgroup per row and a 64 KiB bitmap leave room for one workgroup per
+// CU, so every pass over a row keeps kSortUnroll loads per thread in flight.
+constexpr int kSortUnroll = 8;
+
 __global__ __launch_bounds__(kBlock) void k_sort_bitmap(int cbase, int cls, const int32_t* __restrict__ counters,
                                                         const int32_t* __restrict__ rows,
                                                         const int64_t* __restrict__ orow,
                                                         const int32_t* __restrict__ src,
                                                         int32_t* __restrict__ dst) {
+  constexpr int U = kSortUnroll;
   __shared__ uint32_t bm[kBitmapWords];
   __shared__ int32_t woff[kMaxWindows + 1];
   __shared__ int64_t tmp[kWavesPerBlock + 1];
@@ -881,10 +886,16 @@ __global__ __launch_bounds__(kBlock) void k_sort_bitmap(int cbase, int cls, cons
     const int64_t beg = orow[r];
     const int64_t len = orow[r + 1] - beg;
     int32_t lo = INT_MAX, hi = INT_MIN;
-    for (int64_t i = threadIdx.x; i < len; i += kBlock) {
-      const int32_t v = src[beg + i];
-      lo = min(lo, v);
-      hi = max(hi, v);
+    for (int64_t i0 = threadIdx.x; i0 < len; i0 += (int64_t)kBlock * U) {
+      int32_t v[U];
+#pragma unroll
+      for (int q = 0; q < U; ++q) {
+        const int64_t i = i0 + q * kBlock;
+        v[q] = src[beg + (i < len ? i : 0)];
+      }
+#pragma unroll
+      for (int q = 0; q < U; ++q)
+        if (i0 + q * kBlock < len) { lo = min(lo, v[q]); hi = max(hi, v[q]); }
     }
     for (int o = kWave / 2; o > 0; o >>= 1) {
       lo = min(lo, __shfl_xor(lo, o, kWave));
@@ -899,9 +910,19 @@ __global__ __launch_bounds__(kBlock) void k_sort_bitmap(int cbase, int cls, cons
     if (nwin == 1) {
       for (int i = threadIdx.x; i < kBitmapWords; i += kBlock) bm[i] = 0u;
       __syncthreads();
-      for (int64_t i = threadIdx.x; i < len; i += kBlock) {
-        const int64_t off = (int64_t)src[beg + i] - lo;
-        atomicOr(&bm[off >> 5], 1u << (off & 31));
+      for (int64_t i0 = threadIdx.x; i0 < len; i0 += (int64_t)kBlock * U) {
+        int32_t v[U];
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+          const int64_t i = i0 + q * kBlock;
+          v[q] = src[beg + (i < len ? i : 0)];
+        }
+#pragma unroll
+        for (int q = 0; q < U; ++q)
+          if (i0 + q * kBlock < len) {
+            const int64_t off = (int64_t)v[q] - lo;
+            atomicOr(&bm[off >> 5], 1u << (off & 31));
+          }
       }
       __syncthreads();
       emit_bitmap(bm, lo, dst + beg, tmp);
@@ -911,12 +932,20 @@ __global__ __launch_bounds__(kBlock) void k_sort_bitmap(int cbase, int cls, cons
     const int nbits = ceil_log2(nwin);
     for (int i = threadIdx.x; i < nwin; i += kBlock) woff[i] = 0;
     __syncthreads();
-    for (int64_t i0 = 0; i0 < len; i0 += kBlock) {
-      const int64_t i = i0 + threadIdx.x;
-      const bool live = i < len;
-      const int w = live ? (int)(((int64_t)src[beg + i] - lo) / kBits) : 0;
-      const uint64_t peers = match_window(w, nbits, live);
-      if (live && popc_below(peers) == 0) atomicAdd(&woff[w], (int32_t)__popcll(peers));
+    for (int64_t i0 = 0; i0 < len; i0 += (int64_t)kBlock * U) {
+      int32_t v[U];
+#pragma unroll
+      for (int q = 0; q < U; ++q) {
+        const int64_t i = i0 + q * kBlock + threadIdx.x;
+        v[q] = src[beg + (i < len ? i : 0)];
+      }
+#pragma unroll
+      for (int q = 0; q < U; ++q) {
+        const bool live = i0 + q * kBlock + threadIdx.x < len;
+        const int w = live ? (int)(((int64_t)v[q] - lo) / kBits) : 0;
+        const uint64_t peers = match_window(w, nbits, live);
+        if (live && popc_below(peers) == 0) atomicAdd(&woff[w], (int32_t)__popcll(peers));
+      }
     }
     __syncthreads();
     // exclusive prefix over the windows: each thread a run of consecutive ones
@@ -940,17 +969,24 @@ __global__ __launch_bounds__(kBlock) void k_sort_bitmap(int cbase, int cls, cons
     for (int i = threadIdx.x; i < nwin; i += kBlock) cursor[i] = woff[i];
     __syncthreads();
     // scatter into the row's place in dst, bucketed by window
-    for (int64_t i0 = 0; i0 < len; i0 += kBlock) {
-      const int64_t i = i0 + threadIdx.x;
-      const bool live = i < len;
-      const int32_t v = live ? src[beg + i] : 0;
-      const int w = live ? (int)(((int64_t)v - lo) / kBits) : 0;
-      const uint64_t peers = match_window(w, nbits, live);
-      const int leader = peers ? __ffsll((long long)peers) - 1 : 0;
-      int32_t at = 0;
-      if (live && lane_id() == leader) at = atomicAdd(&cursor[w], (int32_t)__popcll(peers));
-      at = __shfl(at, leader, kWave);
-      if (live) dst[beg + at + popc_below(peers)] = v;
+    for (int64_t i0 = 0; i0 < len; i0 += (int64_t)kBlock * U) {
+      int32_t v[U];
+#pragma unroll
+      for (int q = 0; q < U; ++q) {
+        const int64_t i = i0 + q * kBlock + threadIdx.x;
+        v[q] = src[beg + (i < len ? i : 0)];
+      }
+#pragma unroll
+      for (int q = 0; q < U; ++q) {
+        const bool live = i0 + q * kBlock + threadIdx.x < len;
+        const int w = live ? (int)(((int64_t)v[q] - lo) / kBits) : 0;
+        const uint64_t peers = match_window(w, nbits, live);
+        const int leader = peers ? __ffsll((long long)peers) - 1 : 0;
+        int32_t at = 0;
+        if (live && lane_id() == leader) at = atomicAdd(&cursor[w], (int32_t)__popcll(peers));
+        at = __shfl(at, leader, kWave);
+        if (live) dst[beg + at + popc_below(peers)] = v[q];
+      }
     }
     __syncthreads();
     // each window's bucket through the bitmap, written over itself in order
@@ -960,9 +996,19 @@ __global__ __launch_bounds__(kBlock) void k_sort_bitmap(int cbase, int cls, cons
       const int64_t w0 = (int64_t)lo + (int64_t)w * kBits;
       for (int i = threadIdx.x; i < kBitmapWords; i += kBlock) bm[i] = 0u;
       __syncthreads();
-      for (int32_t i = b0 + threadIdx.x; i < b1; i += kBlock) {
-        const int64_t off = (int64_t)dst[beg + i] - w0;
-        atomicOr(&bm[off >> 5], 1u << (off & 31));
+      for (int32_t i0 = b0 + threadIdx.x; i0 < b1; i0 += kBlock * U) {
+        int32_t v[U];
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+          const int32_t i = i0 + q * kBlock;
+          v[q] = dst[beg + (i < b1 ? i : b0)];
+        }
+#pragma unroll
+        for (int q = 0; q < U; ++q)
+          if (i0 + q * kBlock < b1) {
+            const int64_t off = (int64_t)v[q] - w0;
+            atomicOr(&bm[off >> 5], 1u << (off & 31));
+          }
       }
       __syncthreads();
       emit_bitmap(bm, w0, dst + beg + b0, tmp);
