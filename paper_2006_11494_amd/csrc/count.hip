@@ -556,8 +556,12 @@ __device__ void flush_digest(const Digest& d, unsigned long long* out) {
 __device__ __forceinline__ void store(const HeavyArgs& a, int64_t pos, int32_t t0, int32_t t1,
                                       int32_t t2) {
   if (pos >= a.first && pos < a.first + a.count) {
+    // the list is written once and never read back here: streaming stores
+    // keep it from evicting the out-lists the probes re-read
     int32_t* o = a.out + 3 * (pos - a.first);
-    o[0] = t0; o[1] = t1; o[2] = t2;
+    __builtin_nontemporal_store(t0, o);
+    __builtin_nontemporal_store(t1, o + 1);
+    __builtin_nontemporal_store(t2, o + 2);
   }
 }
 
@@ -1064,8 +1068,10 @@ __device__ __forceinline__ void light_sink(const LightArgs& a, Digest& dg, int64
   if constexpr (kDigest) {
     dg.add(t0, t1, t2);
   } else if (at >= a.first && at < a.first + a.count) {
-    int32_t* o = a.out + 3 * (at - a.first);
-    o[0] = t0; o[1] = t1; o[2] = t2;
+    int32_t* o = a.out + 3 * (at - a.first);      // streaming stores, as in store()
+    __builtin_nontemporal_store(t0, o);
+    __builtin_nontemporal_store(t1, o + 1);
+    __builtin_nontemporal_store(t2, o + 2);
   }
 }
 
