@@ -76,6 +76,12 @@ def parse():
     p.add_argument("--stream", action="store_true",
                    help="also stream every window of a list too large to hold to pinned host "
                         "memory (the PCIe-inclusive rate; about a minute at R-MAT scale 26)")
+    p.add_argument("--save-csr", default=None, metavar="PREFIX",
+                   help="only generate the workload and save its CSR to PREFIX_rowptr.npy and "
+                        "PREFIX_col.npy (for a profiled run that should not run the generator)")
+    p.add_argument("--load-csr", default=None, metavar="PREFIX",
+                   help="read the workload's CSR from files written by --save-csr instead of "
+                        "generating it")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a plain 1 GiB read + 1 GiB write elementwise kernel, the "
                         "reference that scales rocprofv3's FETCH_SIZE / WRITE_SIZE counters")
@@ -143,10 +149,11 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def profiled_traffic(kernel: str, workload: str):
+def profiled_traffic(kernel: str, workload: str, launches: int):
     """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
-    summary, or None when there is none for this kernel and workload or the
-    kernel source changed since it was taken."""
+    summary (its bytes over one whole pass, spread over this run's `launches`
+    launches of that pass), or None when there is none for this kernel and
+    workload or the kernel source changed since it was taken."""
     name = {"k_heavy<write>": "k_heavy_write"}.get(kernel)
     if name is None:
         return None
@@ -157,16 +164,20 @@ def profiled_traffic(kernel: str, workload: str):
         prof = json.load(f)
     if prof.get("source_hash") != kernel_source_hash():
         return None
-    return prof["traffic_bytes_per_launch"]
+    return prof["traffic_bytes_per_pass"] / max(launches, 1)
 
 
 def roofline(recs, workload: str, windowed: bool = False):
     """HBM roofline of the kernel with the most recorded time.  Windowed
     listing splits a bucket's write work over many launches: then a write
     kernel's algorithmic bytes are those of its buckets' whole write pass
-    (from the count-pass records, which always cover whole buckets), over
-    the summed time of all its write launches."""
+    over the summed time of all its write launches.  A heavy write record
+    carries its whole bucket's figures (the write pass probes the hit spans
+    the count pass found); a light bin's write work is its count-pass
+    record's, plus the triangles."""
     per = {}
+    seen = set()
+    count_rec = {r["bucket"]: r for r in recs if r["pass"] == 0}
     for r in recs:
         k = kernel_of(r)
         d = per.setdefault(k, {"ms": 0.0, "bytes": 0, "launches": 0})
@@ -174,20 +185,22 @@ def roofline(recs, workload: str, windowed: bool = False):
         d["launches"] += 1
         if not windowed:
             d["bytes"] += launch_bytes(r)
-        elif r["pass"] == 0:
-            d["bytes"] += launch_bytes(r)
-            w = per.setdefault(kernel_of(dict(r, **{"pass": 1})),
-                               {"ms": 0.0, "bytes": 0, "launches": 0})
-            w["bytes"] += launch_bytes(dict(r, **{"pass": 1}))
+        elif (r["pass"], r["bucket"]) not in seen:
+            seen.add((r["pass"], r["bucket"]))
+            whole = r if r["pass"] == 0 or r["probes"] >= 0 else \
+                dict(count_rec[r["bucket"]], **{"pass": 1})
+            d["bytes"] += launch_bytes(whole)
     kern, d = max(((k, v) for k, v in per.items() if v["launches"]), key=lambda kv: kv[1]["ms"])
     achieved = d["bytes"] / (d["ms"] / 1000.0) / 1e9
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": profiled_traffic(kern, workload),
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": profiled_traffic(kern, workload, d["launches"]),
             "kernel": kern,
             "launches": d["launches"], "avg_launch_ms": d["ms"] / d["launches"],
             "bytes_per_launch": d["bytes"] / d["launches"],
-            "per_unit": "4 B/probe + 4 B/staged owner-list entry + 8 B/edge"
-                        " (+ 8 B/edge + 12 B/triangle in the write pass)"}
+            "per_unit": "4 B/probe made + 4 B/staged owner-list entry + 8 B/edge"
+                        " (+ 8 B/edge + 12 B/triangle in the write pass, whose heavy"
+                        " owners probe only the hit spans the count pass found)"}
 
 
 def cpu_baseline(csr, frac: float, threads: int = 1):
@@ -493,14 +506,19 @@ def batched_leg(aot, args, dev):
 class Workload:
     """One graph resident in HBM with every buffer the step needs."""
 
-    def __init__(self, aot, name, seed, dev, args, dispatch=None):
+    def __init__(self, aot, name, seed, dev, args, dispatch=None, load=None):
         import torch
 
         t0 = time.time()
         self.aot, self.name, self.args, self.dispatch = aot, name, args, dispatch
-        self.csr = csr = inputs_mod().workload(name, seed, device=dev)
-        torch.cuda.synchronize()
-        log(f"[bench] generated {csr.name}: n={csr.n} m={csr.m} in {time.time() - t0:.1f}s")
+        if load:
+            self.csr = csr = load_csr(load, dev)
+            log(f"[bench] loaded {csr.name} from {load}_*.npy: n={csr.n} m={csr.m} in "
+                f"{time.time() - t0:.1f}s")
+        else:
+            self.csr = csr = inputs_mod().workload(name, seed, device=dev)
+            torch.cuda.synchronize()
+            log(f"[bench] generated {csr.name}: n={csr.n} m={csr.m} in {time.time() - t0:.1f}s")
         self.o = aot.alloc_oriented(csr.n, csr.m, dev)
         self.ows = torch.empty(aot.orient_workspace(csr.n, csr.nnz), dtype=torch.uint8,
                                device=dev)
@@ -591,6 +609,31 @@ def inputs_mod():
     return inputs
 
 
+def save_csr(csr, prefix):
+    """The CSR as two .npy files (plain arrays, no pickled objects) and its
+    name in a text file."""
+    rp, col = csr.numpy()
+    np.save(prefix + "_rowptr.npy", rp)
+    np.save(prefix + "_col.npy", col)
+    with open(prefix + "_name.txt", "w") as f:
+        f.write(csr.name)
+
+
+def load_csr(prefix, dev):
+    import torch
+
+    rp = np.load(prefix + "_rowptr.npy", mmap_mode="r")
+    col = np.load(prefix + "_col.npy", mmap_mode="r")
+    with open(prefix + "_name.txt") as f:
+        name = f.read().strip()
+    rowptr = torch.from_numpy(np.array(rp)).to(dev)
+    c = torch.empty(col.shape[0], dtype=torch.int32, device=dev)
+    step = 1 << 28
+    for i in range(0, col.shape[0], step):          # bounded host copies
+        c[i:i + step].copy_(torch.from_numpy(np.array(col[i:i + step])))
+    return inputs_mod().Csr(rp.shape[0] - 1, rowptr, c, name)
+
+
 def bucket_summary(recs):
     """Per-bucket totals of the recorded launches (both passes)."""
     out = {}
@@ -644,7 +687,13 @@ def main():
             table = [t << 8 for t in (4, 4, 4, 8, 16, 32, 64, 64)] + [0] * 8 + [arm] * 16
         dispatch = aot.Dispatch(aot.AOT_DISPATCH_TABLE if table else aot.AOT_DISPATCH_PLAIN,
                                 args.heavy_min, table)
-    w = Workload(aot, args.workload, args.seed, dev, args, dispatch)
+    if args.save_csr:
+        csr = inputs_mod().workload(args.workload, args.seed, device=dev)
+        torch.cuda.synchronize()
+        save_csr(csr, args.save_csr)
+        log(f"[bench] saved {csr.name} to {args.save_csr}_*.npy")
+        return
+    w = Workload(aot, args.workload, args.seed, dev, args, dispatch, load=args.load_csr)
     T, probes = w.T, w.probes
     timed = w.timed(args.steps, args.warmup)
     recs = w.records()

@@ -76,7 +76,9 @@ static_assert(kNumBuckets == kHeavyBase + kHeavyClasses, "bucket layout");
 
 // per-bucket statistics (int64, device), bucket = light bin or kHeavyBase + class
 enum : int {
-  kSEdges = 0, kSProbes, kSTriangles, kSItems, kSStaged, kSCursor, kSItemBase, kSSpan, kSDb, kStats,
+  kSEdges = 0, kSProbes, kSTriangles, kSItems, kSStaged, kSCursor, kSItemBase, kSSpan, kSDb,
+  kSLookups,   // heavy: probes the write pass makes (the hit spans of the count pass)
+  kStats,
 };
 constexpr int kStatWords = kNumBuckets * kStats;
 
@@ -481,6 +483,10 @@ struct HeavyArgs {
                                 // probes (count pass writes, write pass reads)
   int32_t* ieid;                // per in-list entry: the id of an owned in-edge
                                 // (count pass writes, write pass reads)
+  int32_t* hfirst;              // per owned edge with triangles: offset of its first
+                                // hit in the probed list (count pass writes, write
+                                // pass reads)
+  int64_t* look_stat;           // count pass: the bucket's write-pass probes
   int64_t item_base, item_count;
   const int64_t* orow;
   const int32_t* ocol;
@@ -572,6 +578,8 @@ struct HeavyShared {
   int32_t nb_pre[kItemSpan + 1];
   int32_t nb_e[kItemSpan];
   int32_t nb_acc[kItemSpan];          // count: hits; write: running rank within the edge
+  int32_t nb_first[kEmit ? 1 : kItemSpan];   // count: first hit, as a probe index of the item
+  unsigned long long looks;                  // count: the block's write-pass probes
   int32_t nb_py[kEmit ? kItemSpan : 1];
   int32_t wave_k[kWavesPerBlock + 1];
   int64_t scan_tmp[kWavesPerBlock + 1];
@@ -656,14 +664,22 @@ __device__ __forceinline__ void load_windows(Windows<U>& W, const int32_t* pre, 
 template <int ARM>
 __device__ int64_t probe_count(HeavyShared<false>& sh, const uint32_t* lds, const HeavyArgs& a,
                                const Index& ix, int K, int32_t P) {
-  const int wave = threadIdx.x / kWave;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);   // same on every lane
   const int lane = lane_id();
   constexpr int32_t kStride = kBlock * kUnroll;
   int kc = 0;
   int32_t nxt = sh.nb_pre[1];
   int64_t hits_wave = 0;
   int acc_k = -1;     // wave-uniform: neighbour being accumulated
-  int acc = 0;        // and its hits so far
+  int acc = 0;        // and its hits so far,
+  int32_t acc_f = 0;  // and the first of them (a probe index)
+  // adds the accumulated hits and first hit to their neighbour's slot
+  auto flush = [&]() {
+    if (acc_k >= 0 && lane == 0 && acc) {
+      atomicAdd(&sh.nb_acc[acc_k], acc);
+      atomicMin(&sh.nb_first[acc_k], acc_f);
+    }
+  };
   for (int32_t w0 = wave * kWave * kUnroll; w0 < P; w0 += kStride) {
     Windows<kUnroll> cur;
     load_windows(cur, sh.nb_pre, sh.nb_src, a.ocol, kc, nxt, K, w0, P);
@@ -683,9 +699,15 @@ __device__ int64_t probe_count(HeavyShared<false>& sh, const uint32_t* lds, cons
         if (ka == acc_k) {
           acc += c;
         } else {
-          if (acc_k >= 0 && lane == 0) atomicAdd(&sh.nb_acc[acc_k], acc);
+          flush();
           acc_k = ka;
           acc = c;
+          // the run's first hit: this wave's first for the neighbour
+          int32_t f = w0 + kWave * kUnroll;
+#pragma unroll
+          for (int u = kUnroll - 1; u >= 0; --u)
+            if (hms[u]) f = w0 + u * kWave + (int32_t)__builtin_ctzll(hms[u]);
+          acc_f = f;
         }
       }
       continue;
@@ -704,22 +726,26 @@ __device__ int64_t probe_count(HeavyShared<false>& sh, const uint32_t* lds, cons
         if (k0 == acc_k) {
           acc += c;
         } else {
-          if (acc_k >= 0 && lane == 0) atomicAdd(&sh.nb_acc[acc_k], acc);
+          flush();
           acc_k = k0;
           acc = c;
+          acc_f = w0 + u * kWave + (int32_t)__builtin_ctzll(hm);
         }
       } else {
-        if (acc_k >= 0 && lane == 0 && acc) atomicAdd(&sh.nb_acc[acc_k], acc);
+        flush();
         acc_k = -1;
         acc = 0;
         int tot;
         bool first;
-        segment_rank(valid, cur.kk[u], hm, &tot, &first);
+        const int below = segment_rank(valid, cur.kk[u], hm, &tot, &first);
         if (first && tot) atomicAdd(&sh.nb_acc[cur.kk[u]], tot);
+        // a segment's first hit (none of its hits below it)
+        if (((hm >> lane) & 1ull) && below == 0)
+          atomicMin(&sh.nb_first[cur.kk[u]], w0 + u * kWave + lane);
       }
     }
   }
-  if (acc_k >= 0 && lane == 0 && acc) atomicAdd(&sh.nb_acc[acc_k], acc);
+  flush();
   return lane == 0 ? hits_wave : 0;
 }
 
@@ -733,10 +759,13 @@ __device__ int64_t probe_count(HeavyShared<false>& sh, const uint32_t* lds, cons
 template <int ARM, bool kDigest>
 __device__ void probe_emit(HeavyShared<true>& sh, const uint32_t* lds, const HeavyArgs& a,
                            const Index& ix, int K, int32_t P, int32_t pb, Digest& dg) {
-  const int wave = threadIdx.x / kWave;
-  const int k_lo = sh.wave_k[wave], k_hi = sh.wave_k[wave + 1];
+  // the wave's bounds are the same on every lane: kept in scalar registers
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int k_lo = __builtin_amdgcn_readfirstlane(sh.wave_k[wave]);
+  const int k_hi = __builtin_amdgcn_readfirstlane(sh.wave_k[wave + 1]);
   if (k_lo >= k_hi) return;
-  const int32_t p_lo = sh.nb_pre[k_lo], p_hi = sh.nb_pre[k_hi];
+  const int32_t p_lo = __builtin_amdgcn_readfirstlane(sh.nb_pre[k_lo]);
+  const int32_t p_hi = __builtin_amdgcn_readfirstlane(sh.nb_pre[k_hi]);
   const int32_t* __restrict__ perm = a.perm;
   constexpr int32_t kStride = kWave * kEmitUnroll;
   int kc = k_lo;
@@ -847,7 +876,7 @@ __device__ int64_t run_item(HeavyShared<kEmit>& sh, uint32_t* lds, const HeavyAr
 // (out-list, then in-list).  Ends with a barrier.
 template <bool kEmit, bool kDigest>
 __device__ void heavy_item(HeavyShared<kEmit>& sh, uint32_t* lds, const HeavyArgs& a, int64_t it,
-                           int64_t& tri_block, Digest& dg) {
+                           int64_t& tri_block, int64_t& look_block, Digest& dg) {
   const int tid = threadIdx.x;
   if constexpr (kEmit) {
     // an item whose owned edges hold no slot in the window is skipped whole
@@ -922,6 +951,13 @@ __device__ void heavy_item(HeavyShared<kEmit>& sh, uint32_t* lds, const HeavyArg
           const int64_t lo = a.tri_off[e], hi = a.tri_off[e + 1];
           nbase[i] = lo;
           keep[i] = hi > lo && (kDigest || (hi > a.first && lo < a.first + a.count));
+          if (keep[i]) {
+            // no hit lies before the first one the count pass found: the
+            // write pass probes N+(y) from there on
+            const int32_t f = a.hfirst[e];
+            noy[i] = oy + f;
+            nd[i] = dy - f;
+          }
         }
       }
     }
@@ -950,6 +986,7 @@ __device__ void heavy_item(HeavyShared<kEmit>& sh, uint32_t* lds, const HeavyArg
       sh.nb_pre[slot] = (int32_t)(at & 0xFFFFFFFF);
       sh.nb_e[slot] = ne[i];
       sh.nb_acc[slot] = 0;
+      if constexpr (!kEmit) sh.nb_first[slot] = INT_MAX;
       if constexpr (kEmit) {
         sh.nb_base[slot] = nbase[i];
         sh.nb_py[slot] = a.perm[ny[i]];
@@ -986,17 +1023,30 @@ __device__ void heavy_item(HeavyShared<kEmit>& sh, uint32_t* lds, const HeavyArg
   }
   if constexpr (!kEmit) tri_block += t;
   __syncthreads();
-  if constexpr (!kEmit)
-    for (int s = tid; s < K; s += kBlock) a.cnt[sh.nb_e[s]] = sh.nb_acc[s];
+  if constexpr (!kEmit) {
+    int32_t looks = 0;
+    for (int s = tid; s < K; s += kBlock) {
+      const int32_t hits = sh.nb_acc[s];
+      a.cnt[sh.nb_e[s]] = hits;
+      if (hits) {
+        a.hfirst[sh.nb_e[s]] = sh.nb_first[s] - sh.nb_pre[s];
+        looks += sh.nb_pre[s + 1] - sh.nb_first[s];
+      }
+    }
+    looks = wave_sum(looks);
+    if (lane_id() == 0 && looks) atomicAdd(&sh.looks, (unsigned long long)looks);
+  }
   __syncthreads();
 }
 
 template <bool kEmit, bool kDigest>
 __device__ void heavy_finish(HeavyShared<kEmit>& sh, const HeavyArgs& a, int64_t tri_block,
-                             const Digest& dg) {
+                             int64_t look_block, const Digest& dg) {
   if constexpr (!kEmit) {
     const int64_t t = block_sum(tri_block, sh.scan_tmp);
     if (a.tri_stat && threadIdx.x == 0 && t) atomicAdd(u64p(a.tri_stat), (unsigned long long)t);
+    (void)look_block;
+    if (a.look_stat && threadIdx.x == 0 && sh.looks) atomicAdd(u64p(a.look_stat), sh.looks);
   } else {
     if constexpr (kDigest) flush_digest(dg, a.digest);
   }
@@ -1008,11 +1058,14 @@ template <bool kEmit, bool kDigest = false>
 __global__ __launch_bounds__(kBlock) void k_heavy(HeavyArgs a) {
   __shared__ HeavyShared<kEmit> sh;
   extern __shared__ uint32_t lds[];
-  int64_t tri_block = 0;
+  int64_t tri_block = 0, look_block = 0;
   Digest dg;
+  if constexpr (!kEmit) {
+    if (threadIdx.x == 0) sh.looks = 0;      // read after the last item's barriers
+  }
   for (int64_t it = blockIdx.x; it < a.item_count; it += gridDim.x)
-    heavy_item<kEmit, kDigest>(sh, lds, a, a.item_base + it, tri_block, dg);
-  heavy_finish<kEmit, kDigest>(sh, a, tri_block, dg);
+    heavy_item<kEmit, kDigest>(sh, lds, a, a.item_base + it, tri_block, look_block, dg);
+  heavy_finish<kEmit, kDigest>(sh, a, tri_block, look_block, dg);
 }
 
 // Persistent form: one launch drains the work items of every heavy class
@@ -1028,17 +1081,20 @@ __global__ __launch_bounds__(kBlock) void k_heavy_drain(HeavyArgs a,
   extern __shared__ uint32_t lds[];
   int64_t total = 0;
   for (int q = 0; q < kHeavyClasses; ++q) total += stats[(kHeavyBase + q) * kStats + kSItems];
-  int64_t tri_block = 0;
+  int64_t tri_block = 0, look_block = 0;
   Digest dg;
+  if constexpr (!kEmit) {
+    if (threadIdx.x == 0) sh.looks = 0;
+  }
   while (true) {
     if (threadIdx.x == 0) next = (int64_t)atomicAdd(cursor, 1ull);
     __syncthreads();
     const int64_t t = next;
     __syncthreads();
     if (t >= total) break;
-    heavy_item<kEmit, false>(sh, lds, a, total - 1 - t, tri_block, dg);
+    heavy_item<kEmit, false>(sh, lds, a, total - 1 - t, tri_block, look_block, dg);
   }
-  heavy_finish<kEmit, false>(sh, a, tri_block, dg);
+  heavy_finish<kEmit, false>(sh, a, tri_block, look_block, dg);
 }
 
 // ---------------------------------------------------------------- light path
@@ -1439,6 +1495,7 @@ struct CountWs {
   int2* items;
   int2* item_e;                      // per item: owned edge-id bounds
   int32_t* ieid;                     // [m] per in-list entry: owned in-edge id
+  int32_t* hfirst;                   // [m] per heavy-owned edge: its first hit
   int32_t* hist;                     // [kLightBins][chunks] light edges per chunk
   int64_t* hoff;                     // its exclusive scan
   int64_t* win;                      // window: edge range, then each bin's elist run
@@ -1459,6 +1516,7 @@ CountWs carve_count(Carve& c, int32_t n, int64_t m) {
   w.items = c.take<int2>(max_items(n, m));
   w.item_e = c.take<int2>(max_items(n, m));
   w.ieid = c.take<int32_t>(m);
+  w.hfirst = c.take<int32_t>(m);
   const int64_t cells = kLightBins * cdiv(m, kScatterChunk);
   w.hist = c.take<int32_t>(cells);
   w.hoff = c.take<int64_t>(cells + 1);
@@ -1619,6 +1677,8 @@ int run_buckets(bool emit, const Plan& plan, const int64_t* hs, const CountWs& w
     a.items = w.items;
     a.item_e = w.item_e;
     a.ieid = w.ieid;
+    a.hfirst = w.hfirst;
+    a.look_stat = emit ? nullptr : w.stats + (kHeavyBase + h) * kStats + kSLookups;
     a.item_base = st[kSItemBase];
     a.item_count = items;
     a.orow = orow; a.ocol = ocol; a.irow = irow; a.icol = icol;
@@ -1636,8 +1696,10 @@ int run_buckets(bool emit, const Plan& plan, const int64_t* hs, const CountWs& w
     a.digest = digest;
     a.esup = esup;
     a.head = strategy == kStratHead;
+    // the write pass probes each owned list from its first hit on
     const int rec = timing_begin(emit ? 1 : 0, kHeavyBase + h, arm, kBlock, st[kSEdges],
-                                 st[kSProbes], st[kSStaged], st[kSTriangles], s);
+                                 emit ? st[kSLookups] : st[kSProbes], st[kSStaged],
+                                 st[kSTriangles], s);
     const size_t dyn = sizeof(uint32_t) * (size_t)std::max(a.idx_words, 1);
     if (emit && digest) k_heavy<true, true><<<grid_cap(items), kBlock, dyn, s>>>(a);
     else if (emit) k_heavy<true><<<grid_cap(items), kBlock, dyn, s>>>(a);
@@ -1812,6 +1874,8 @@ int drain_run(int32_t n, int64_t m, const int64_t* orow, const int32_t* ocol,
   ha.items = w.items;
   ha.item_e = w.item_e;
   ha.ieid = w.ieid;
+  ha.hfirst = w.hfirst;
+  ha.look_stat = nullptr;
   ha.item_base = 0;
   ha.item_count = 0;
   ha.orow = orow; ha.ocol = ocol; ha.irow = irow; ha.icol = icol;

@@ -47,29 +47,39 @@ def test_roofline_takes_the_kernel_with_the_most_time():
 
 
 def test_windowed_write_bytes_come_from_the_whole_buckets():
-    # a bucket's write split over two windows: its bytes are those of the
-    # whole bucket (from the count record), over both launches' time
+    # a heavy bucket's write split over two windows: each write record carries
+    # the whole bucket (its probes are the hit-span look-ups of the write
+    # pass), counted once, over both launches' time
     recs = [rec(0, 20, 2.0, probes=10**9, edges=10**6, triangles=10**8),
-            rec(1, 20, 2.0, probes=10**9, edges=10**6, triangles=-1),
-            rec(1, 20, 2.0, probes=10**9, edges=10**6, triangles=-1)]
+            rec(1, 20, 2.0, probes=6 * 10**8, edges=10**6, triangles=10**8),
+            rec(1, 20, 2.0, probes=6 * 10**8, edges=10**6, triangles=10**8)]
     r = bench.roofline(recs, "no-such-workload", windowed=True)
     assert r["kernel"] == "k_heavy<write>" and r["launches"] == 2
+    assert r["achieved"] == pytest.approx(bench.launch_bytes(recs[1]) / 4.0e-3 / 1e9)
+    # a light bin's partial write launches (probes -1) take the count record's
+    # figures as a write pass
+    recs = [rec(0, 5, 1.0, probes=10**9, edges=10**7, triangles=10**8, tile=32),
+            rec(1, 5, 3.0, probes=-1, edges=10**6, triangles=-1, tile=32),
+            rec(1, 5, 3.0, probes=-1, edges=10**6, triangles=-1, tile=32)]
+    r = bench.roofline(recs, "no-such-workload", windowed=True)
+    assert r["kernel"] == "k_light<32><write>" and r["launches"] == 2
     whole = bench.launch_bytes(dict(recs[0], **{"pass": 1}))
-    assert r["achieved"] == pytest.approx(whole / 4.0e-3 / 1e9)
+    assert r["achieved"] == pytest.approx(whole / 6.0e-3 / 1e9)
 
 
-@pytest.mark.parametrize("workload", ["rmat20", "chunglu4m"])
+@pytest.mark.parametrize("workload", ["rmat20", "chunglu4m", "rmat26"])
 def test_traffic_only_for_the_profiled_sources(workload, monkeypatch):
     prof = os.path.join(ROOT, "profiles", f"k_heavy_write_{workload}_traffic.json")
     with open(prof) as f:
         stored = json.load(f)
     assert stored["workload"] == workload
     if stored["source_hash"] == bench.kernel_source_hash():
-        assert bench.profiled_traffic("k_heavy<write>", workload) == \
-            stored["traffic_bytes_per_launch"]
+        # a pass's bytes spread over the launches of this run's pass
+        assert bench.profiled_traffic("k_heavy<write>", workload, 4) == \
+            pytest.approx(stored["traffic_bytes_per_pass"] / 4)
     # no profile for another workload
-    assert bench.profiled_traffic("k_heavy<write>", "rmat18") is None
+    assert bench.profiled_traffic("k_heavy<write>", "rmat18", 4) is None
     # a different kernel source: no traffic
     monkeypatch.setattr(bench, "kernel_source_hash", lambda: "0" * 16)
-    assert bench.profiled_traffic("k_heavy<write>", workload) is None
-    assert bench.profiled_traffic("k_light<64><write>", workload) is None
+    assert bench.profiled_traffic("k_heavy<write>", workload, 4) is None
+    assert bench.profiled_traffic("k_light<64><write>", workload, 4) is None

@@ -3,16 +3,24 @@
 and counted on the device, listed in windows streamed to pinned host memory.
 
 Its list (a few times 1e11 triangles) is far beyond what the CPU oracle can
-list, so parity rests on everything the oracle can compute at this size:
+store, so parity rests on everything the oracle computes at this size:
   * the whole orientation (ranks, out-list offsets, out-lists), exactly;
   * the probe count sum of min(deg+), exactly;
   * per-edge triangle counts at 200,000 random edges and at edges of the
     heaviest owners, exactly;
   * complete triangle lists of rank ranges at several depths of the order,
     exactly (the device windows that hold them, streamed to the host);
-and on invariants at full size: the digest of the whole list counts T
-triangles, and two dispatches give the same digest."""
+  * the digest of the whole list -- T, the sum and xor of the triple hashes
+    and the triangles through every vertex (SHA-256 of the array, its sum and
+    sampled entries) -- against the oracle's CF run stored in
+    tests/golden/rmat26_digest.json (written by tests/golden/rmat26_digest.py,
+    which calls only the oracle), after checking by SHA-256 that the stored
+    run saw the same input;
+and a second dispatch gives the same digest."""
 
+import hashlib
+import json
+import os
 import sys
 import time
 
@@ -28,6 +36,17 @@ pytestmark = [pytest.mark.gpu, pytest.mark.timeout(1100)]
 
 def say(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "rmat26_digest.json")
+
+
+def sha(a: np.ndarray) -> str:
+    h = hashlib.sha256()
+    flat = np.ascontiguousarray(a).view(np.uint8).reshape(-1)
+    for i in range(0, flat.size, 1 << 28):
+        h.update(flat[i:i + (1 << 28)])
+    return h.hexdigest()
 
 
 def test_rmat26_sampled_parity():
@@ -53,6 +72,13 @@ def test_rmat26_sampled_parity():
     say(f"[gpu] rmat26: T={c.T} probes={c.probes} at {time.time() - t0:.1f}s")
     rp, col = csr.numpy()
     del csr
+    with open(GOLDEN) as f:
+        gold = json.load(f)
+    assert (gold["n"], gold["nnz"]) == (n, nnz)
+    assert sha(rp.astype("<i8")) == gold["rowptr_sha256"]
+    assert sha(col.astype("<i4")) == gold["col_sha256"]
+    assert c.probes == gold["probes"] and c.T == gold["T"]
+    say(f"[gpu] rmat26: same input as the stored oracle run; T and probes equal")
     say(f"[gpu] rmat26: input on the host; oracle orientation")
     ref = oracle.orient_threaded(rp, col, threads=16, log=say)
     del col
@@ -88,8 +114,15 @@ def test_rmat26_sampled_parity():
         assert np.array_equal(got, want), f"ranks [{r_lo}, {r_hi})"
         say(f"[gpu] rmat26: ranks [{r_lo}, {r_hi}): {len(want)} triangles equal")
 
-    (t, s, x), _ = aot.digest(o, c, vertex_counts=False)
-    assert t == c.T
+    (t, s, x), vc = aot.digest(o, c)
+    assert (t, s, x) == (gold["T"], gold["F1"], gold["F2"])
+    vcn = vc.cpu().numpy().astype(np.uint64)
+    assert int(vcn.sum(dtype=np.uint64)) == gold["vertex_counts_sum"] == 3 * t
+    assert np.array_equal(vcn[np.array(gold["sample_vertices"])],
+                          np.array(gold["sample_counts"], dtype=np.uint64))
+    assert sha(vcn.astype("<u8")) == gold["vertex_counts_sha256"]
+    del vc, vcn
+    say(f"[gpu] rmat26: whole-list digest and every vertex count equal the oracle's")
     table = [tile << 8 for tile in (4, 4, 4, 8, 16, 32, 64, 64)] + [0] * 8 + [1] * 16
     d = aot.Dispatch(aot.AOT_DISPATCH_TABLE, 0, table)
     assert aot.digest(o, c, vertex_counts=False, dispatch=d)[0] == (t, s, x)

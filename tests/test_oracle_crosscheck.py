@@ -53,3 +53,13 @@ def test_rmat20_aot_equals_cf():
     assert (t, fp) == cf_digest(o)
     assert t == 424_180_754
     assert probes == oracle.sum_min(o) == 1_969_802_408
+
+
+@pytest.mark.slow
+def test_chunglu4m_aot_equals_cf():
+    csr = inputs.workload("chunglu4m")
+    rp, col = csr.numpy()
+    t, fp, probes = oracle.aot_ref(rp, col, digest=True)
+    o = oracle.orient(rp, col)
+    assert (t, fp) == cf_digest(o)
+    assert probes == oracle.sum_min(o)
