@@ -154,16 +154,17 @@ def profiled_traffic(kernel: str, workload: str, launches: int):
     summary (its bytes over one whole pass, spread over this run's `launches`
     launches of that pass), or None when there is none for this kernel and
     workload or the kernel source changed since it was taken."""
-    name = {"k_heavy<write>": "k_heavy_write"}.get(kernel)
-    if name is None:
+    if kernel not in ("k_heavy<write>", "k_heavy<count>"):
         return None
-    path = os.path.join(ROOT, "profiles", f"{name}_{workload}_traffic.json")
+    path = os.path.join(ROOT, "profiles", f"k_heavy_write_{workload}_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         prof = json.load(f)
     if prof.get("source_hash") != kernel_source_hash():
         return None
+    if kernel == "k_heavy<count>":        # the same runs' figures for the count pass
+        prof = prof["count_pass"]
     return prof["traffic_bytes_per_pass"] / max(launches, 1)
 
 
