@@ -54,7 +54,7 @@ constexpr int kItemSpan = 512;      // neighbours of one owner per work item
 constexpr int kMaxIndexWords = AOT_MAX_INDEX_WORDS;  // LDS index cap (12288: 48 KiB, a bitmap
                                                      // window of 393216 ids)
 #ifndef AOT_PROBE_UNROLL
-#define AOT_PROBE_UNROLL 4
+#define AOT_PROBE_UNROLL 8
 #endif
 #ifndef AOT_EMIT_UNROLL
 #define AOT_EMIT_UNROLL 8

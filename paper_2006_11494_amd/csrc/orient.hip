@@ -865,6 +865,7 @@ __device__ __forceinline__ int64_t emit_bitmap(const uint32_t* bm, int64_t w0, i
 // One workgroup per row and a 64 KiB bitmap leave room for one workgroup per
 // CU, so every pass over a row keeps kSortUnroll loads per thread in flight.
 constexpr int kSortUnroll = 8;
+constexpr int32_t kRankSortMax = 512;    // buckets up to this size are ranked in LDS
 
 __global__ __launch_bounds__(kBlock) void k_sort_bitmap(int cbase, int cls, const int32_t* __restrict__ counters,
                                                         const int32_t* __restrict__ rows,
@@ -989,10 +990,27 @@ __global__ __launch_bounds__(kBlock) void k_sort_bitmap(int cbase, int cls, cons
       }
     }
     __syncthreads();
-    // each window's bucket through the bitmap, written over itself in order
+    // each window's bucket written over itself in order: a sparse bucket by
+    // ranks counted in LDS (each entry's rank is the number of smaller ones;
+    // entries are distinct), a denser one through the bitmap, whose clearing
+    // and scan cost the same however few entries it holds
     for (int w = 0; w < nwin; ++w) {
       const int32_t b0 = woff[w], b1 = woff[w + 1];
       if (b1 == b0) continue;
+      if (b1 - b0 <= kRankSortMax) {
+        const int32_t nb = b1 - b0;
+        int32_t* vals = reinterpret_cast<int32_t*>(bm);
+        for (int32_t i = threadIdx.x; i < nb; i += kBlock) vals[i] = dst[beg + b0 + i];
+        __syncthreads();
+        for (int32_t i = threadIdx.x; i < nb; i += kBlock) {
+          const int32_t v = vals[i];
+          int32_t r = 0;
+          for (int32_t j = 0; j < nb; ++j) r += vals[j] < v;
+          dst[beg + b0 + r] = v;
+        }
+        __syncthreads();
+        continue;
+      }
       const int64_t w0 = (int64_t)lo + (int64_t)w * kBits;
       for (int i = threadIdx.x; i < kBitmapWords; i += kBlock) bm[i] = 0u;
       __syncthreads();
