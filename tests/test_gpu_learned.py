@@ -145,24 +145,30 @@ def test_learned_dispatch_is_bit_exact_and_falls_back():
 
 def test_learned_dispatch_gain():
     """Trains on the training graphs, judges on the calibration graphs, then
-    measures plain vs learned on held-out graphs; prints the gain.  The judge
-    only keeps a model that beats the plain rule on calibration graphs, so the
-    learned form may not be slower beyond timing noise anywhere."""
+    times plain and learned steps in turn on held-out graphs and prints the
+    gain.  A rejected model is reported as a skip (the plain rule is kept, so
+    there is nothing to time).  The judge only keeps a model that beats the
+    plain rule on its calibration graphs, so on held-out graphs of the same
+    families the learned form may not be slower beyond the timing noise of
+    these few-millisecond steps (10%)."""
     need_gpu()
     net, report = learn.learn(scale=1, epochs=1000, repeats=2, log=say)
     assert report["loss_last"] < report["loss_first"]
+    if net is None:
+        pytest.skip("judge rejected the model on the calibration graphs: "
+                    f"plain {report.get('judge_plain_ms', float('nan')):.3f} ms vs learned "
+                    f"{report.get('judge_learned_ms', float('nan')):.3f} ms; the plain rule is kept")
     held_out = [inputs.rmat(17, 16, 2001, device="cuda"),
                 inputs.chung_lu(300_000, 40.0, 2.1, 30_000.0, 2002, device="cuda")]
-    if net is None:
-        say("[learn] judge rejected the model: the plain rule is kept")
-        return
     for csr in held_out:
         o = aot.orient(csr.rowptr, csr.col)
         c = aot.count(o)
         out = torch.empty((max(c.T, 1), 3), dtype=torch.int32, device="cuda")
         d = aot.Dispatch(aot.AOT_DISPATCH_LEARNED, report["heavy_min"], None, net)
-        plain = learn.step_ms(o, None, 5, out)
-        learned = learn.step_ms(o, d, 5, out)
-        say(f"[learn] {csr.name}: plain {plain:.3f} ms, learned {learned:.3f} ms, "
+        plain = learned = 0.0
+        for _ in range(5):  # alternated, so that drift hits both forms alike
+            plain += learn.step_ms(o, None, 3, out)
+            learned += learn.step_ms(o, d, 3, out)
+        say(f"[learn] {csr.name}: plain {plain / 5:.3f} ms, learned {learned / 5:.3f} ms, "
             f"gain {plain / learned:.3f}x; plan {aot.count_plan(o, aot.count(o, d))[0]}")
-        assert learned <= 1.15 * plain
+        assert learned <= 1.10 * plain
