@@ -455,6 +455,39 @@ __device__ __forceinline__ bool index_has(const Index& ix, const uint32_t* lds, 
   }
 }
 
+// index_has for U probes at once.  The sorted copy takes a branchless search
+// whose trip count depends only on the owner's deg+ (the same on every lane):
+// each step narrows [b, b + n) to the half holding the last entry <= w with
+// one LDS read, a compare and a select, and the U searches advance together so
+// their reads issue back to back.
+template <int ARM, int U>
+__device__ __forceinline__ void index_has_all(const Index& ix, const uint32_t* lds,
+                                              const int32_t (&w)[U], bool (&has)[U]) {
+  if constexpr (ARM == kArmSorted) {
+    typedef const __attribute__((address_space(3))) int32_t* LdsPtr;   // 32-bit LDS address
+    const LdsPtr l = (LdsPtr)lds;
+    const int len = __builtin_amdgcn_readfirstlane(ix.len);   // >= 1: an owner has out-neighbours
+    constexpr int G = U < 4 ? U : 4;     // searches in step together (register budget)
+#pragma unroll
+    for (int g = 0; g < U; g += G) {
+      LdsPtr b[G];
+#pragma unroll
+      for (int u = 0; u < G; ++u) b[u] = l;
+      for (int n = len; n > 1;) {
+        const int half = n >> 1;
+#pragma unroll
+        for (int u = 0; u < G; ++u) b[u] = b[u][half] <= w[g + u] ? b[u] + half : b[u];
+        n -= half;
+      }
+#pragma unroll
+      for (int u = 0; u < G; ++u) has[g + u] = *b[u] == w[g + u];
+    }
+  } else {
+#pragma unroll
+    for (int u = 0; u < U; ++u) has[u] = index_has<ARM>(ix, lds, w[u]);
+  }
+}
+
 // ---------------------------------------------------------------- heavy path
 
 // Largest k in [kc, K) with pre[k] <= p, given pre[kc] <= p < pre[K].
@@ -683,10 +716,11 @@ __device__ int64_t probe_count(HeavyShared<false>& sh, const uint32_t* lds, cons
   for (int32_t w0 = wave * kWave * kUnroll; w0 < P; w0 += kStride) {
     Windows<kUnroll> cur;
     load_windows(cur, sh.nb_pre, sh.nb_src, a.ocol, kc, nxt, K, w0, P);
+    bool has[kUnroll];
+    index_has_all<ARM>(ix, lds, cur.wv, has);
     uint64_t hms[kUnroll];
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u)
-      hms[u] = ballot((cur.kk[u] >= 0) & index_has<ARM>(ix, lds, cur.wv[u]));
+    for (int u = 0; u < kUnroll; ++u) hms[u] = ballot((cur.kk[u] >= 0) & has[u]);
     // a full run inside one out-list: one accumulator update for all windows
     const int ka = __builtin_amdgcn_readfirstlane(cur.kk[0]);
     const int kb = __builtin_amdgcn_readlane(cur.kk[kUnroll - 1], kWave - 1);
@@ -777,9 +811,10 @@ __device__ void probe_emit(HeavyShared<true>& sh, const uint32_t* lds, const Hea
     load_windows(cur, sh.nb_pre, sh.nb_src, a.ocol, kc, nxt, k_hi, w0, p_hi);
     bool hit[kEmitUnroll];
     int32_t third[kEmitUnroll];
+    index_has_all<ARM>(ix, lds, cur.wv, hit);
 #pragma unroll
     for (int u = 0; u < kEmitUnroll; ++u) {
-      hit[u] = (cur.kk[u] >= 0) & index_has<ARM>(ix, lds, cur.wv[u]);
+      hit[u] = (cur.kk[u] >= 0) & hit[u];
       third[u] = perm[hit[u] ? cur.wv[u] : 0];      // gathers issued before any store
     }
     // a full run inside one out-list: one base and one neighbour for all windows
@@ -874,7 +909,11 @@ __device__ int64_t run_item(HeavyShared<kEmit>& sh, uint32_t* lds, const HeavyAr
 
 // One work item: owner b and a window of up to kItemSpan of its neighbours
 // (out-list, then in-list).  Ends with a barrier.
-template <bool kEmit, bool kDigest>
+// kArms: the index arms compiled in (bit per Arm).  A launch whose class can
+// resolve to fewer arms takes a kernel with only those, which is smaller.
+constexpr unsigned kAllArms = (1u << kNumArms) - 1u;
+
+template <bool kEmit, bool kDigest, unsigned kArms = kAllArms>
 __device__ void heavy_item(HeavyShared<kEmit>& sh, uint32_t* lds, const HeavyArgs& a, int64_t it,
                            int64_t& tri_block, int64_t& look_block, Digest& dg) {
   const int tid = threadIdx.x;
@@ -1015,11 +1054,21 @@ __device__ void heavy_item(HeavyShared<kEmit>& sh, uint32_t* lds, const HeavyArg
   const int arm = resolve_arm(a.arms[heavy_class(db)], db, span, a.idx_words);
   const int32_t pb = kEmit ? a.perm[b] : 0;
   int64_t t = 0;
-  switch (arm) {
-    case kArmBitmap: t = run_item<kArmBitmap, kEmit, kDigest>(sh, lds, a, list, db, K, P, pb, dg); break;
-    case kArmHash: t = run_item<kArmHash, kEmit, kDigest>(sh, lds, a, list, db, K, P, pb, dg); break;
-    case kArmSorted: t = run_item<kArmSorted, kEmit, kDigest>(sh, lds, a, list, db, K, P, pb, dg); break;
-    default: t = run_item<kArmGlobal, kEmit, kDigest>(sh, lds, a, list, db, K, P, pb, dg); break;
+  if constexpr (kArms == (1u << kArmBitmap)) {
+    t = run_item<kArmBitmap, kEmit, kDigest>(sh, lds, a, list, db, K, P, pb, dg);
+  } else if constexpr (kArms == (1u << kArmSorted)) {
+    t = run_item<kArmSorted, kEmit, kDigest>(sh, lds, a, list, db, K, P, pb, dg);
+  } else if constexpr (kArms == ((1u << kArmBitmap) | (1u << kArmSorted))) {
+    if (arm == kArmBitmap) t = run_item<kArmBitmap, kEmit, kDigest>(sh, lds, a, list, db, K, P, pb, dg);
+    else t = run_item<kArmSorted, kEmit, kDigest>(sh, lds, a, list, db, K, P, pb, dg);
+  } else {
+    static_assert(kArms == kAllArms, "arm subsets: bitmap, sorted, bitmap + sorted, all");
+    switch (arm) {
+      case kArmBitmap: t = run_item<kArmBitmap, kEmit, kDigest>(sh, lds, a, list, db, K, P, pb, dg); break;
+      case kArmHash: t = run_item<kArmHash, kEmit, kDigest>(sh, lds, a, list, db, K, P, pb, dg); break;
+      case kArmSorted: t = run_item<kArmSorted, kEmit, kDigest>(sh, lds, a, list, db, K, P, pb, dg); break;
+      default: t = run_item<kArmGlobal, kEmit, kDigest>(sh, lds, a, list, db, K, P, pb, dg); break;
+    }
   }
   if constexpr (!kEmit) tri_block += t;
   __syncthreads();
@@ -1054,7 +1103,7 @@ __device__ void heavy_finish(HeavyShared<kEmit>& sh, const HeavyArgs& a, int64_t
 
 // A launch covers the work items of one heavy class; the LDS index lives in
 // dynamic shared memory of a.idx_words words.
-template <bool kEmit, bool kDigest = false>
+template <bool kEmit, bool kDigest = false, unsigned kArms = kAllArms>
 __global__ __launch_bounds__(kBlock) void k_heavy(HeavyArgs a) {
   __shared__ HeavyShared<kEmit> sh;
   extern __shared__ uint32_t lds[];
@@ -1064,7 +1113,7 @@ __global__ __launch_bounds__(kBlock) void k_heavy(HeavyArgs a) {
     if (threadIdx.x == 0) sh.looks = 0;      // read after the last item's barriers
   }
   for (int64_t it = blockIdx.x; it < a.item_count; it += gridDim.x)
-    heavy_item<kEmit, kDigest>(sh, lds, a, a.item_base + it, tri_block, look_block, dg);
+    heavy_item<kEmit, kDigest, kArms>(sh, lds, a, a.item_base + it, tri_block, look_block, dg);
   heavy_finish<kEmit, kDigest>(sh, a, tri_block, look_block, dg);
 }
 
@@ -1579,6 +1628,40 @@ int index_words(int arm, int h, int64_t max_span) {
   return (int)std::min<int64_t>(std::max<int64_t>(need, 1), kMaxIndexWords);
 }
 
+// The arms the owners of heavy class h can resolve to (resolve_arm) when the
+// class requests `arm` with `words` LDS words and its widest list spans
+// max_span ids.  Bitmap and sorted fail on independent monotone conditions
+// (span, deg+), so the corners of the class's (deg+, span) box give every
+// outcome; the hash arm and the open-ended last class take every arm.
+unsigned class_arms(int arm, int h, int64_t max_span, int words) {
+  if (arm == kArmHash || h >= kHeavyClasses - 1) return kAllArms;
+  const int64_t dmin = (int64_t(1) << (h > 0 ? h - 1 : 0)) + (h > 0 ? 1 : 0);
+  const int64_t dmax = int64_t(1) << h;
+  unsigned m = 0;
+  for (const int64_t d : {dmin, dmax})
+    for (const int64_t sp : {int64_t(1), std::max<int64_t>(max_span, 1)})
+      m |= 1u << resolve_arm(arm, d, sp, words);
+  if (m == (1u << kArmBitmap) || m == (1u << kArmSorted) ||
+      m == ((1u << kArmBitmap) | (1u << kArmSorted)))
+    return m;
+  return kAllArms;
+}
+
+hipError_t launch_heavy(bool emit, bool digest, unsigned arms, const HeavyArgs& a, unsigned grid,
+                        size_t dyn, hipStream_t s) {
+  constexpr unsigned B = 1u << kArmBitmap, S = 1u << kArmSorted;
+  if (emit && digest) k_heavy<true, true><<<grid, kBlock, dyn, s>>>(a);
+  else if (emit && arms == B) k_heavy<true, false, B><<<grid, kBlock, dyn, s>>>(a);
+  else if (emit && arms == S) k_heavy<true, false, S><<<grid, kBlock, dyn, s>>>(a);
+  else if (emit && arms == (B | S)) k_heavy<true, false, B | S><<<grid, kBlock, dyn, s>>>(a);
+  else if (emit) k_heavy<true><<<grid, kBlock, dyn, s>>>(a);
+  else if (arms == B) k_heavy<false, false, B><<<grid, kBlock, dyn, s>>>(a);
+  else if (arms == S) k_heavy<false, false, S><<<grid, kBlock, dyn, s>>>(a);
+  else if (arms == (B | S)) k_heavy<false, false, B | S><<<grid, kBlock, dyn, s>>>(a);
+  else k_heavy<false><<<grid, kBlock, dyn, s>>>(a);
+  return hipGetLastError();
+}
+
 unsigned grid_cap(int64_t work_units) {
   return (unsigned)std::max<int64_t>(1, std::min<int64_t>(kGrid * 4, work_units));
 }
@@ -1701,10 +1784,8 @@ int run_buckets(bool emit, const Plan& plan, const int64_t* hs, const CountWs& w
                                  emit ? st[kSLookups] : st[kSProbes], st[kSStaged],
                                  st[kSTriangles], s);
     const size_t dyn = sizeof(uint32_t) * (size_t)std::max(a.idx_words, 1);
-    if (emit && digest) k_heavy<true, true><<<grid_cap(items), kBlock, dyn, s>>>(a);
-    else if (emit) k_heavy<true><<<grid_cap(items), kBlock, dyn, s>>>(a);
-    else k_heavy<false><<<grid_cap(items), kBlock, dyn, s>>>(a);
-    AOT_TRY(hipGetLastError());
+    AOT_TRY(launch_heavy(emit, digest, class_arms(arm, h, st[kSSpan], a.idx_words), a,
+                         grid_cap(items), dyn, s));
     timing_end(rec, s);
   }
   return 0;
