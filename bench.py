@@ -124,12 +124,14 @@ def copy_bandwidth(reps: int = 5) -> float:
 
 
 # Algorithmic bytes of one bucket launch (what the method must move):
-#  count pass: 4 B per probe (the probed out-list id), 4 B per staged owner
-#    list entry, 8 B per edge (its id and its count);
-#  write pass: the same plus 8 B per edge (its two triangle offsets) and
-#    12 B per triangle written.
+#  count pass: 4 B per look-up made (the probed out-list id; heavy owners skip
+#    each probed list's lines below their smallest out-neighbour), 4 B per
+#    staged owner list entry, 8 B per edge (its id and its count);
+#  write pass: the same (heavy owners probe from each edge's first hit) plus
+#    8 B per edge (its two triangle offsets) and 12 B per triangle written.
 def launch_bytes(r) -> int:
-    b = 4 * r["probes"] + 4 * r["staged"] + 8 * r["edges"]
+    looks = r.get("lookups", r["probes"])
+    b = 4 * looks + 4 * r["staged"] + 8 * r["edges"]
     if r["pass"] == 1:
         b += 8 * r["edges"] + 12 * r["triangles"]
     return b
@@ -199,9 +201,10 @@ def roofline(recs, workload: str, windowed: bool = False):
             "kernel": kern,
             "launches": d["launches"], "avg_launch_ms": d["ms"] / d["launches"],
             "bytes_per_launch": d["bytes"] / d["launches"],
-            "per_unit": "4 B/probe made + 4 B/staged owner-list entry + 8 B/edge"
-                        " (+ 8 B/edge + 12 B/triangle in the write pass, whose heavy"
-                        " owners probe only the hit spans the count pass found)"}
+            "per_unit": "4 B/look-up made + 4 B/staged owner-list entry + 8 B/edge"
+                        " (+ 8 B/edge + 12 B/triangle in the write pass); heavy owners"
+                        " probe each list from its line below their smallest"
+                        " out-neighbour (count) or from the edge's first hit (write)"}
 
 
 def cpu_baseline(csr, frac: float, threads: int = 1):
@@ -641,8 +644,8 @@ def bucket_summary(recs):
     for r in recs:
         k = f"{'write' if r['pass'] else 'count'}:{r['bucket']}"
         d = out.setdefault(k, {"launches": 0, "ms": 0.0, "edges": r["edges"],
-                               "probes": r["probes"], "staged": r["staged"],
-                               "triangles": r["triangles"]})
+                               "probes": r["probes"], "lookups": r.get("lookups", r["probes"]),
+                               "staged": r["staged"], "triangles": r["triangles"]})
         d["launches"] += 1
         d["ms"] += r["ms"]
     return out

@@ -445,11 +445,17 @@ typedef struct aot_timing {
                          2 global binary search, 3 LDS sorted copy); light: 0 */
   int32_t tile;       /* lanes per edge (light) or workgroup size (heavy)    */
   int64_t edges;      /* directed edges in the bucket                        */
-  int64_t probes;     /* their sum of min(deg+): look-ups made (-1 for a
-                         write-pass launch over part of a light bin)          */
+  int64_t probes;     /* count pass: their sum of min(deg+); write pass: the
+                         look-ups made (-1 for a launch over part of a light
+                         bin)                                                  */
   int64_t staged;     /* owner out-list entries staged into LDS (heavy)      */
   int64_t triangles;  /* triangles the bucket's edges hold (-1 as probes)    */
   double ms;          /* launch time from HIP events on the launch stream    */
+  int64_t lookups;    /* look-ups the launch made: heavy count launches start
+                         each probed list at its last 32-entry line below the
+                         owner's smallest out-neighbour, heavy write launches
+                         at the edge's first hit; light launches make all
+                         (-1 as probes)                                        */
 } aot_timing;
 int aot_timing_start(void);
 int aot_timing_stop(aot_timing* out, int32_t cap, int32_t* count);

@@ -73,7 +73,7 @@ class TimingC(ctypes.Structure):
     _fields_ = [("pass_", ctypes.c_int32), ("bucket", ctypes.c_int32), ("arm", ctypes.c_int32),
                 ("tile", ctypes.c_int32), ("edges", ctypes.c_int64), ("probes", ctypes.c_int64),
                 ("staged", ctypes.c_int64), ("triangles", ctypes.c_int64),
-                ("ms", ctypes.c_double)]
+                ("ms", ctypes.c_double), ("lookups", ctypes.c_int64)]
 
 
 class DispatchC(ctypes.Structure):
@@ -456,7 +456,7 @@ def timing_stop(cap: int = 4096) -> list[dict]:
     buf = (TimingC * cap)()
     n = ctypes.c_int32(0)
     _check(load().aot_timing_stop(buf, cap, ctypes.byref(n)), "aot_timing_stop")
-    keys = ("bucket", "arm", "tile", "edges", "probes", "staged", "triangles", "ms")
+    keys = ("bucket", "arm", "tile", "edges", "probes", "staged", "triangles", "ms", "lookups")
     return [dict({"pass": buf[i].pass_}, **{k: getattr(buf[i], k) for k in keys})
             for i in range(min(n.value, cap))]
 

@@ -48,6 +48,8 @@ constexpr int kLightBins = 8;       // c in {1}, {2}, (2,4], (4,8], ..., last bi
 constexpr int kHeavyClasses = 16;   // owner classes by ceil(log2 deg+(b))
 constexpr int kHeavyBase = 16;      // bucket id of heavy class 0
 constexpr int kItemSpan = 512;      // neighbours of one owner per work item
+constexpr int kLine = 32;           // int32 entries per 128-byte line (count-pass skip)
+constexpr int32_t kSkipMin = 2 * kLine;  // shorter probed lists are probed whole
 #ifndef AOT_MAX_INDEX_WORDS
 #define AOT_MAX_INDEX_WORDS 12288
 #endif
@@ -78,6 +80,7 @@ static_assert(kNumBuckets == kHeavyBase + kHeavyClasses, "bucket layout");
 enum : int {
   kSEdges = 0, kSProbes, kSTriangles, kSItems, kSStaged, kSCursor, kSItemBase, kSSpan, kSDb,
   kSLookups,   // heavy: probes the write pass makes (the hit spans of the count pass)
+  kSCountLooks,  // heavy: probes the count pass makes (each list from its line below min N+(b))
   kStats,
 };
 constexpr int kStatWords = kNumBuckets * kStats;
@@ -259,6 +262,16 @@ __global__ __launch_bounds__(kBlock) void k_bin_place(int64_t m, const uint8_t* 
       __syncthreads();
     }
   }
+}
+
+// lsamp[q] = ocol[kLine * q]: one entry per line of the oriented out-lists,
+// which the count pass searches for where to start probing a list.
+__global__ __launch_bounds__(kBlock) void k_line_samples(int64_t m, const int32_t* __restrict__ ocol,
+                                                         int32_t* __restrict__ lsamp) {
+  const int64_t lines = (m + kLine - 1) / kLine;
+  for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < lines;
+       q += (int64_t)gridDim.x * kBlock)
+    lsamp[q] = ocol[q * kLine];
 }
 
 // Work items per heavy class, the owner-list entries they stage, and the
@@ -516,10 +529,12 @@ struct HeavyArgs {
                                 // probes (count pass writes, write pass reads)
   int32_t* ieid;                // per in-list entry: the id of an owned in-edge
                                 // (count pass writes, write pass reads)
-  int32_t* hfirst;              // per owned edge with triangles: offset of its first
-                                // hit in the probed list (count pass writes, write
-                                // pass reads)
+  int32_t* hfirst;              // per owned edge with triangles: the ocol index of its
+                                // first hit (count pass writes, write pass reads)
   int64_t* look_stat;           // count pass: the bucket's write-pass probes
+  int64_t* made_stat = nullptr; // count pass: the bucket's own probes
+  const int32_t* lsamp = nullptr;  // count pass: lsamp[q] = ocol[kLine * q], the first
+                                   // entry of every kLine-entry line of the out-lists
   int64_t item_base, item_count;
   const int64_t* orow;
   const int32_t* ocol;
@@ -909,6 +924,28 @@ __device__ int64_t run_item(HeavyShared<kEmit>& sh, uint32_t* lds, const HeavyAr
 
 // One work item: owner b and a window of up to kItemSpan of its neighbours
 // (out-list, then in-list).  Ends with a barrier.
+// Entries of the out-list ocol[oy, oy + dy) that the count pass may skip: no
+// entry below lo, the smallest of the owner's out-neighbours, can be in its
+// index.  The line samples give the last kLine-aligned position q * kLine in
+// the list whose entry is still below lo; everything before it is below lo
+// too, so the probes start there (up to kLine - 1 known misses remain, the
+// price of reading one sample per line instead of searching the list).
+
+__device__ __forceinline__ int32_t skip_below(const int32_t* __restrict__ lsamp, int64_t oy,
+                                              int32_t dy, int32_t lo) {
+  // line indices fit in int32: m <= INT32_MAX
+  const int32_t y0 = (int32_t)oy;
+  int32_t q = (y0 + kLine - 1) / kLine;                 // samples inside the list
+  int32_t n = (y0 + dy - 1) / kLine - q + 1;
+  if (n <= 0 || lsamp[q] >= lo) return 0;
+  // last sample below lo: lsamp[q] < lo holds, narrow [q, q + n)
+  while (n > 1) {
+    const int32_t half = n >> 1;
+    if (lsamp[q + half] < lo) { q += half; n -= half; } else { n = half; }
+  }
+  return q * kLine - y0;
+}
+
 // kArms: the index arms compiled in (bit per Arm).  A launch whose class can
 // resolve to fewer arms takes a kernel with only those, which is smaller.
 constexpr unsigned kAllArms = (1u << kNumArms) - 1u;
@@ -935,6 +972,7 @@ __device__ void heavy_item(HeavyShared<kEmit>& sh, uint32_t* lds, const HeavyArg
   const int64_t ib = a.irow[b];
   const int32_t deg = db + (a.head ? 0 : (int32_t)(a.irow[b + 1] - ib));
   const int32_t j0 = item.y;
+  const int32_t lo_b = kEmit ? 0 : a.ocol[ob];   // smallest entry of the index
   // the whole row, or one window of the out-list or of the in-list
   const int32_t j1 = deg <= kSplitAbove ? min(deg, j0 + kItemSpan)
                                         : min(j0 < db ? db : deg, j0 + kItemSpan);
@@ -985,6 +1023,11 @@ __device__ void heavy_item(HeavyShared<kEmit>& sh, uint32_t* lds, const HeavyArg
       if constexpr (!kEmit) {
         if (owned && dy == 0) a.cnt[e] = 0;
         keep[i] = owned && dy > 0;
+        if (keep[i] && a.lsamp && dy >= kSkipMin) {
+          const int32_t f = skip_below(a.lsamp, oy, dy, lo_b);
+          noy[i] = oy + f;
+          nd[i] = dy - f;
+        }
       } else {
         if (owned) {
           const int64_t lo = a.tri_off[e], hi = a.tri_off[e + 1];
@@ -993,7 +1036,7 @@ __device__ void heavy_item(HeavyShared<kEmit>& sh, uint32_t* lds, const HeavyArg
           if (keep[i]) {
             // no hit lies before the first one the count pass found: the
             // write pass probes N+(y) from there on
-            const int32_t f = a.hfirst[e];
+            const int32_t f = (int32_t)(a.hfirst[e] - oy);
             noy[i] = oy + f;
             nd[i] = dy - f;
           }
@@ -1017,6 +1060,9 @@ __device__ void heavy_item(HeavyShared<kEmit>& sh, uint32_t* lds, const HeavyArg
   int64_t at = block_exclusive_scan(packed, sh.scan_tmp, &total);
   const int K = (int)(total >> 32);
   const int32_t P = (int32_t)(total & 0xFFFFFFFF);
+  if constexpr (!kEmit) {
+    if (tid == 0) look_block += P;          // the probes this item makes
+  }
 #pragma unroll
   for (int i = 0; i < kPer; ++i) {
     if (keep[i]) {
@@ -1078,7 +1124,7 @@ __device__ void heavy_item(HeavyShared<kEmit>& sh, uint32_t* lds, const HeavyArg
       const int32_t hits = sh.nb_acc[s];
       a.cnt[sh.nb_e[s]] = hits;
       if (hits) {
-        a.hfirst[sh.nb_e[s]] = sh.nb_first[s] - sh.nb_pre[s];
+        a.hfirst[sh.nb_e[s]] = sh.nb_src[s] + sh.nb_first[s];   // ocol index of the hit
         looks += sh.nb_pre[s + 1] - sh.nb_first[s];
       }
     }
@@ -1094,7 +1140,8 @@ __device__ void heavy_finish(HeavyShared<kEmit>& sh, const HeavyArgs& a, int64_t
   if constexpr (!kEmit) {
     const int64_t t = block_sum(tri_block, sh.scan_tmp);
     if (a.tri_stat && threadIdx.x == 0 && t) atomicAdd(u64p(a.tri_stat), (unsigned long long)t);
-    (void)look_block;
+    if (a.made_stat && threadIdx.x == 0 && look_block)
+      atomicAdd(u64p(a.made_stat), (unsigned long long)look_block);
     if (a.look_stat && threadIdx.x == 0 && sh.looks) atomicAdd(u64p(a.look_stat), sh.looks);
   } else {
     if constexpr (kDigest) flush_digest(dg, a.digest);
@@ -1104,7 +1151,8 @@ __device__ void heavy_finish(HeavyShared<kEmit>& sh, const HeavyArgs& a, int64_t
 // A launch covers the work items of one heavy class; the LDS index lives in
 // dynamic shared memory of a.idx_words words.
 template <bool kEmit, bool kDigest = false, unsigned kArms = kAllArms>
-__global__ __launch_bounds__(kBlock) void k_heavy(HeavyArgs a) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kEmit ? 1 : 6)))
+void k_heavy(HeavyArgs a) {
   __shared__ HeavyShared<kEmit> sh;
   extern __shared__ uint32_t lds[];
   int64_t tri_block = 0, look_block = 0;
@@ -1544,7 +1592,8 @@ struct CountWs {
   int2* items;
   int2* item_e;                      // per item: owned edge-id bounds
   int32_t* ieid;                     // [m] per in-list entry: owned in-edge id
-  int32_t* hfirst;                   // [m] per heavy-owned edge: its first hit
+  int32_t* hfirst;                   // [m] per heavy-owned edge: ocol index of its first hit
+  int32_t* lsamp;                    // [m / kLine + 1] first entry of each line of ocol
   int32_t* hist;                     // [kLightBins][chunks] light edges per chunk
   int64_t* hoff;                     // its exclusive scan
   int64_t* win;                      // window: edge range, then each bin's elist run
@@ -1566,6 +1615,7 @@ CountWs carve_count(Carve& c, int32_t n, int64_t m) {
   w.item_e = c.take<int2>(max_items(n, m));
   w.ieid = c.take<int32_t>(m);
   w.hfirst = c.take<int32_t>(m);
+  w.lsamp = c.take<int32_t>(cdiv(m, kLine) + 1);
   const int64_t cells = kLightBins * cdiv(m, kScatterChunk);
   w.hist = c.take<int32_t>(cells);
   w.hoff = c.take<int64_t>(cells + 1);
@@ -1762,6 +1812,8 @@ int run_buckets(bool emit, const Plan& plan, const int64_t* hs, const CountWs& w
     a.ieid = w.ieid;
     a.hfirst = w.hfirst;
     a.look_stat = emit ? nullptr : w.stats + (kHeavyBase + h) * kStats + kSLookups;
+    a.made_stat = emit ? nullptr : w.stats + (kHeavyBase + h) * kStats + kSCountLooks;
+    a.lsamp = emit ? nullptr : w.lsamp;
     a.item_base = st[kSItemBase];
     a.item_count = items;
     a.orow = orow; a.ocol = ocol; a.irow = irow; a.icol = icol;
@@ -1834,6 +1886,8 @@ int count_run(int32_t n, int64_t m, const int64_t* orow, const int32_t* ocol, co
     AOT_TRY(hipGetLastError());
     k_item_scatter<<<gv, kBlock, 0, s>>>(n, orow, irow, heavy_min, head, w.stats, w.items);
     AOT_TRY(hipGetLastError());
+    k_line_samples<<<grid_cap(cdiv(cdiv(m, kLine), kBlock)), kBlock, 0, s>>>(m, ocol, w.lsamp);
+    AOT_TRY(hipGetLastError());
     AOT_TRY(hipMemcpyAsync(hs.data(), w.stats, sizeof(int64_t) * kStatWords,
                            hipMemcpyDeviceToHost, s));
     AOT_TRY(hipStreamSynchronize(s));
@@ -1867,7 +1921,7 @@ int count_run(int32_t n, int64_t m, const int64_t* orow, const int32_t* ocol, co
   AOT_TRY(hipStreamSynchronize(s));
   result[0] = (uint64_t)t;
   result[1] = (uint64_t)pr;
-  timing_fill_triangles(hs.data(), kStats, kSTriangles);
+  timing_fill_count(hs.data(), kStats, kSTriangles, kSCountLooks, kHeavyBase);
   return 0;
 }
 
@@ -1957,6 +2011,7 @@ int drain_run(int32_t n, int64_t m, const int64_t* orow, const int32_t* ocol,
   ha.ieid = w.ieid;
   ha.hfirst = w.hfirst;
   ha.look_stat = nullptr;
+  ha.lsamp = w.lsamp;
   ha.item_base = 0;
   ha.item_count = 0;
   ha.orow = orow; ha.ocol = ocol; ha.irow = irow; ha.icol = icol;
@@ -1993,6 +2048,8 @@ int drain_run(int32_t n, int64_t m, const int64_t* orow, const int32_t* ocol,
     k_item_count<<<gv, kBlock, 0, s>>>(n, orow, ocol, irow, heavy_min, false, w.stats);
     AOT_TRY(hipGetLastError());
     k_item_scatter<<<gv, kBlock, 0, s>>>(n, orow, irow, heavy_min, false, w.stats, w.items);
+    AOT_TRY(hipGetLastError());
+    k_line_samples<<<grid_cap(cdiv(cdiv(m, kLine), kBlock)), kBlock, 0, s>>>(m, ocol, w.lsamp);
     AOT_TRY(hipGetLastError());
     k_heavy_drain<false><<<gh0, kBlock, dyn, s>>>(ha, w.stats, w.probes + 4);
     AOT_TRY(hipGetLastError());

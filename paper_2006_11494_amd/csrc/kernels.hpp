@@ -72,8 +72,10 @@ constexpr int kNumBuckets = 32;
 int timing_begin(int pass, int bucket, int arm, int tile, int64_t edges, int64_t probes,
                  int64_t staged, int64_t triangles, hipStream_t s);
 void timing_end(int rec, hipStream_t s);
-// Fills the triangle totals of the count-pass records still missing them.
-void timing_fill_triangles(const int64_t* stats, int stride, int offset);
+// Fills the triangle totals of the count-pass records still missing them,
+// and the look-ups the heavy ones made.
+void timing_fill_count(const int64_t* stats, int stride, int tri_offset, int look_offset,
+                       int heavy_base);
 
 // ---- count.hip
 size_t count_workspace_bytes(int32_t n, int64_t m);

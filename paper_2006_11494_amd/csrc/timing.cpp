@@ -45,6 +45,7 @@ int timing_begin(int pass, int bucket, int arm, int tile, int64_t edges, int64_t
   r.t.probes = probes;
   r.t.staged = staged;
   r.t.triangles = pass == 0 ? -1 : triangles;
+  r.t.lookups = probes;             // heavy count launches: filled in after the pass
   r.t.ms = 0.0;
   if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess ||
       hipEventRecord(r.a, s) != hipSuccess) {
@@ -61,9 +62,13 @@ void timing_end(int rec, hipStream_t s) {
   (void)hipEventRecord(g_rec.recs[rec].b, s);
 }
 
-void timing_fill_triangles(const int64_t* stats, int stride, int offset) {
-  for (Rec& r : g_rec.recs)
-    if (r.t.pass == 0 && r.t.triangles < 0) r.t.triangles = stats[r.t.bucket * stride + offset];
+void timing_fill_count(const int64_t* stats, int stride, int tri_offset, int look_offset,
+                       int heavy_base) {
+  for (Rec& r : g_rec.recs) {
+    if (r.t.pass != 0 || r.t.triangles >= 0) continue;
+    r.t.triangles = stats[r.t.bucket * stride + tri_offset];
+    if (r.t.bucket >= heavy_base) r.t.lookups = stats[r.t.bucket * stride + look_offset];
+  }
 }
 
 }  // namespace aot
