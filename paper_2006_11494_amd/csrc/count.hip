@@ -619,13 +619,15 @@ __device__ __forceinline__ void store(const HeavyArgs& a, int64_t pos, int32_t t
   }
 }
 
-template <bool kEmit>
+// Per-item shared state; arrays a pass does not use shrink to one entry, so
+// the write pass's static LDS leaves room for one more workgroup per CU.
+template <bool kEmit, bool kDigest = false>
 struct HeavyShared {
   int32_t nb_src[kItemSpan];          // start of N+(y) minus its probe prefix (int32: m <= INT32_MAX)
   int64_t nb_base[kEmit ? kItemSpan : 1];
   int32_t nb_pre[kItemSpan + 1];
-  int32_t nb_e[kItemSpan];
-  int32_t nb_acc[kItemSpan];          // count: hits; write: running rank within the edge
+  int32_t nb_e[kEmit && !kDigest ? 1 : kItemSpan];   // edge ids: count, and digest support
+  int32_t nb_acc[kEmit ? 1 : kItemSpan];             // count: hits
   int32_t nb_first[kEmit ? 1 : kItemSpan];   // count: first hit, as a probe index of the item
   unsigned long long looks;                  // count: the block's write-pass probes
   int32_t nb_py[kEmit ? kItemSpan : 1];
@@ -806,7 +808,7 @@ __device__ int64_t probe_count(HeavyShared<false>& sh, const uint32_t* lds, cons
 // a hit's rank is its count of hitting lanes below it; a window across a
 // boundary ranks hits per segment.
 template <int ARM, bool kDigest>
-__device__ void probe_emit(HeavyShared<true>& sh, const uint32_t* lds, const HeavyArgs& a,
+__device__ void probe_emit(HeavyShared<true, kDigest>& sh, const uint32_t* lds, const HeavyArgs& a,
                            const Index& ix, int K, int32_t P, int32_t pb, Digest& dg) {
   // the wave's bounds are the same on every lane: kept in scalar registers
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
@@ -910,7 +912,7 @@ __device__ void probe_emit(HeavyShared<true>& sh, const uint32_t* lds, const Hea
 }
 
 template <int ARM, bool kEmit, bool kDigest>
-__device__ int64_t run_item(HeavyShared<kEmit>& sh, uint32_t* lds, const HeavyArgs& a,
+__device__ int64_t run_item(HeavyShared<kEmit, kDigest>& sh, uint32_t* lds, const HeavyArgs& a,
                             const int32_t* list, int32_t db, int K, int32_t P, int32_t pb,
                             Digest& dg) {
   const Index ix = build_index<ARM>(list, db, lds);   // ends with a barrier
@@ -951,7 +953,7 @@ __device__ __forceinline__ int32_t skip_below(const int32_t* __restrict__ lsamp,
 constexpr unsigned kAllArms = (1u << kNumArms) - 1u;
 
 template <bool kEmit, bool kDigest, unsigned kArms = kAllArms>
-__device__ void heavy_item(HeavyShared<kEmit>& sh, uint32_t* lds, const HeavyArgs& a, int64_t it,
+__device__ void heavy_item(HeavyShared<kEmit, kDigest>& sh, uint32_t* lds, const HeavyArgs& a, int64_t it,
                            int64_t& tri_block, int64_t& look_block, Digest& dg) {
   const int tid = threadIdx.x;
   if constexpr (kEmit) {
@@ -1069,8 +1071,8 @@ __device__ void heavy_item(HeavyShared<kEmit>& sh, uint32_t* lds, const HeavyArg
       const int slot = (int)(at >> 32);
       sh.nb_src[slot] = (int32_t)(noy[i] - (at & 0xFFFFFFFF));
       sh.nb_pre[slot] = (int32_t)(at & 0xFFFFFFFF);
-      sh.nb_e[slot] = ne[i];
-      sh.nb_acc[slot] = 0;
+      if constexpr (!kEmit || kDigest) sh.nb_e[slot] = ne[i];
+      if constexpr (!kEmit) sh.nb_acc[slot] = 0;
       if constexpr (!kEmit) sh.nb_first[slot] = INT_MAX;
       if constexpr (kEmit) {
         sh.nb_base[slot] = nbase[i];
@@ -1135,7 +1137,7 @@ __device__ void heavy_item(HeavyShared<kEmit>& sh, uint32_t* lds, const HeavyArg
 }
 
 template <bool kEmit, bool kDigest>
-__device__ void heavy_finish(HeavyShared<kEmit>& sh, const HeavyArgs& a, int64_t tri_block,
+__device__ void heavy_finish(HeavyShared<kEmit, kDigest>& sh, const HeavyArgs& a, int64_t tri_block,
                              int64_t look_block, const Digest& dg) {
   if constexpr (!kEmit) {
     const int64_t t = block_sum(tri_block, sh.scan_tmp);
@@ -1153,7 +1155,7 @@ __device__ void heavy_finish(HeavyShared<kEmit>& sh, const HeavyArgs& a, int64_t
 template <bool kEmit, bool kDigest = false, unsigned kArms = kAllArms>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kEmit ? 1 : 6)))
 void k_heavy(HeavyArgs a) {
-  __shared__ HeavyShared<kEmit> sh;
+  __shared__ HeavyShared<kEmit, kDigest> sh;
   extern __shared__ uint32_t lds[];
   int64_t tri_block = 0, look_block = 0;
   Digest dg;
