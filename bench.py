@@ -127,13 +127,15 @@ def copy_bandwidth(reps: int = 5) -> float:
 #  count pass: 4 B per look-up made (the probed out-list id; heavy owners skip
 #    each probed list's lines below their smallest out-neighbour), 4 B per
 #    staged owner list entry, 8 B per edge (its id and its count);
-#  write pass: the same (heavy owners probe from each edge's first hit) plus
-#    8 B per edge (its two triangle offsets) and 12 B per triangle written.
+#  write pass: the same (heavy owners probe from each edge's first hit) plus,
+#    per edge, 8 B for its two triangle offsets and 4 B for the original id of
+#    its probed endpoint, and per triangle 4 B for the original id of its third
+#    vertex (the list is in original ids: perm of the hit) and 12 B written.
 def launch_bytes(r) -> int:
     looks = r.get("lookups", r["probes"])
     b = 4 * looks + 4 * r["staged"] + 8 * r["edges"]
     if r["pass"] == 1:
-        b += 8 * r["edges"] + 12 * r["triangles"]
+        b += 12 * r["edges"] + 16 * r["triangles"]
     return b
 
 
@@ -202,9 +204,10 @@ def roofline(recs, workload: str, windowed: bool = False):
             "launches": d["launches"], "avg_launch_ms": d["ms"] / d["launches"],
             "bytes_per_launch": d["bytes"] / d["launches"],
             "per_unit": "4 B/look-up made + 4 B/staged owner-list entry + 8 B/edge"
-                        " (+ 8 B/edge + 12 B/triangle in the write pass); heavy owners"
-                        " probe each list from its line below their smallest"
-                        " out-neighbour (count) or from the edge's first hit (write)"}
+                        " (+ 12 B/edge and 16 B/triangle in the write pass: offsets,"
+                        " original ids read, 12 B written); heavy owners probe each"
+                        " list from its line below their smallest out-neighbour (count)"
+                        " or from the edge's first hit (write)"}
 
 
 def cpu_baseline(csr, frac: float, threads: int = 1):

@@ -141,9 +141,12 @@ int aot_orient(const aot_graph* g, uint32_t flags, aot_oriented* out,
 /* ------------------------------------------------------------------------
  * Dispatch of the probe kernels.  Edges are grouped into buckets; a bucket's
  * arm picks the index the probes go into and its tile the lanes per edge.
- * The plain rule (mode AOT_DISPATCH_PLAIN) is fixed; a table (mode
- * AOT_DISPATCH_TABLE) gives one code per bucket, e.g. chosen by the cost
- * model.  Every choice gives identical results.
+ * The plain rule (mode AOT_DISPATCH_PLAIN) is fixed: light tiles by bin, and
+ * per heavy class the LDS bitmap when the class's widest out-list window fits
+ * 28 KiB (four workgroups per CU), else the LDS sorted copy; aot_count_plan
+ * reports the arms it chose.  A table (mode AOT_DISPATCH_TABLE) gives one
+ * code per bucket, e.g. chosen by the cost model.  Every choice gives
+ * identical results.
  *   heavy_min   owners with deg+ >= heavy_min are processed owner-grouped with
  *               an LDS index (0 = library default, 64).
  *   table       host array of AOT_NUM_BUCKETS codes, or NULL: entry k in 0..7

@@ -1507,6 +1507,21 @@ Plan plain_plan() {
   return p;
 }
 
+// The plain rule's heavy arms once the classes' widest windows are known: the
+// bitmap where the widest fits kPlainBitmapWords, so that every owner of the
+// class uses it and the launch keeps four workgroups per CU; otherwise the
+// sorted copy for every owner (one probe costs log2 deg+ LDS reads instead of
+// one, at up to twice the resident workgroups of a wide bitmap).
+constexpr int64_t kPlainBitmapWords = 7168;   // 28 KiB
+
+void plain_heavy_arms(const int64_t* hs, Plan* p) {
+  for (int h = 0; h < kHeavyClasses; ++h) {
+    const int64_t* st = hs + (kHeavyBase + h) * kStats;
+    if (p->heavy_arm[h] == kArmBitmap && st[kSItems] > 0 && cdiv(st[kSSpan], 32) > kPlainBitmapWords)
+      p->heavy_arm[h] = kArmSorted;
+  }
+}
+
 bool valid_tile(int t) { return t == 4 || t == 8 || t == 16 || t == 32 || t == 64; }
 
 // Table codes: entry k < kLightBins is tile << 8 (arm byte 0 = binary
@@ -1900,6 +1915,7 @@ int count_run(int32_t n, int64_t m, const int64_t* orow, const int32_t* ocol, co
         return rc;
       }
     }
+    if (!d.table && !learned) plain_heavy_arms(hs.data(), &plan);
     const int rc = run_buckets(false, plan, hs.data(), w, orow, ocol, otail, nullptr, irow, icol,
                                nullptr, 0, 0, nullptr, nullptr, nullptr, nullptr, strategy, s,
                                err);

@@ -30,7 +30,12 @@ def test_launch_bytes_follow_the_per_unit_figures():
     count = rec(0, 20, 1.0, probes=1000, staged=100, edges=10, triangles=7)
     write = rec(1, 20, 1.0, probes=1000, staged=100, edges=10, triangles=7)
     assert bench.launch_bytes(count) == 4 * 1000 + 4 * 100 + 8 * 10
-    assert bench.launch_bytes(write) == 4 * 1000 + 4 * 100 + 8 * 10 + 8 * 10 + 12 * 7
+    # write: + per edge its two offsets and one original id, + per triangle
+    # the third vertex's original id and the 12 bytes written
+    assert bench.launch_bytes(write) == 4 * 1000 + 4 * 100 + 8 * 10 + 12 * 10 + 16 * 7
+    # the look-ups a launch made, where the record has them, replace its probes
+    made = dict(count, lookups=700)
+    assert bench.launch_bytes(made) == 4 * 700 + 4 * 100 + 8 * 10
 
 
 def test_roofline_takes_the_kernel_with_the_most_time():

@@ -397,3 +397,28 @@ def test_bitmap_wider_than_its_lds_takes_the_sorted_copy():
     check_all(wide_and_narrow_windows(), "chunglu600k_block_id", local="id", windows=False,
               dispatches={k: DISPATCHES[k] for k in ("plain", "all_heavy_bitmap",
                                                      "all_heavy_hash", "mixed")})
+
+
+def test_plain_rule_takes_the_sorted_copy_for_classes_with_wide_windows():
+    """The plain rule keeps the LDS bitmap for a heavy class whose widest
+    out-list window fits 28 KiB (7168 words) and gives every owner of any
+    other class the sorted copy; expected arms from the oracle's oriented
+    graph (owners with deg+ >= 64, class ceil(log2 deg+))."""
+    need_gpu()
+    for csr, local in ((wide_and_narrow_windows(), "id"), (inputs.rmat(16, 16, 7), "rank")):
+        o_ref = reference(csr, "degree", local)[0]
+        d = np.diff(o_ref.orow)
+        expect = {}
+        for v in np.nonzero(d >= 64)[0]:
+            h = min(int(np.ceil(np.log2(d[v]))), 15)
+            span = int(o_ref.ocol[o_ref.orow[v + 1] - 1]) - int(o_ref.ocol[o_ref.orow[v]]) + 1
+            expect[h] = max(expect.get(h, 0), span)
+        g = csr.to(DEV)
+        o = aot.orient(g.rowptr, g.col, local=local)
+        table, learned = aot.count_plan(o, aot.count(o))
+        assert not learned
+        for h, span in expect.items():
+            want = 0 if (span + 31) // 32 <= 7168 else 3
+            assert table[16 + h] == want, (local, h, span, table[16 + h])
+        if local == "id":
+            assert 3 in [table[16 + h] for h in expect]     # the wide classes
