@@ -228,14 +228,20 @@ def cpu_baseline(csr, frac: float, threads: int = 1):
     t_orient = time.perf_counter() - t0
     m = o.m
     k = 64
-    per = max(1, int(frac * m / k))
     ranges = []
-    for st in np.linspace(0, m, k, endpoint=False).astype(np.int64):
-        r_lo = int(np.searchsorted(o.orow, st, side="right") - 1)
-        r_hi = int(np.searchsorted(o.orow, min(m, st + per), side="left"))
-        r_hi = max(r_hi, r_lo + 1)
-        if not ranges or r_lo >= ranges[-1][1]:
-            ranges.append((r_lo, min(r_hi, o.n)))
+    if frac >= 1.0:
+        # the whole graph: k consecutive rank ranges of about m / k edges each
+        cuts = np.searchsorted(o.orow, np.linspace(0, m, k + 1).astype(np.int64), side="left")
+        cuts[0], cuts[-1] = 0, o.n
+        ranges = [(int(a), int(b)) for a, b in zip(cuts[:-1], cuts[1:]) if b > a]
+    else:
+        per = max(1, int(frac * m / k))
+        for st in np.linspace(0, m, k, endpoint=False).astype(np.int64):
+            r_lo = int(np.searchsorted(o.orow, st, side="right") - 1)
+            r_hi = int(np.searchsorted(o.orow, min(m, st + per), side="left"))
+            r_hi = max(r_hi, r_lo + 1)
+            if not ranges or r_lo >= ranges[-1][1]:
+                ranges.append((r_lo, min(r_hi, o.n)))
     edges = sum(int(o.orow[b] - o.orow[a]) for a, b in ranges)
     f = edges / max(m, 1)
     t0 = time.perf_counter()
@@ -537,7 +543,11 @@ class Workload:
         self.windowed = self.T * 12 > args.resident_gb * 1e9
         self.chunk = args.chunk
         if self.windowed:
+            # free device memory plus what torch's allocator holds unused (the
+            # generator's temporaries), so the windows do not depend on
+            # whether the input was generated here or loaded
             free, _ = torch.cuda.mem_get_info(dev)
+            free += torch.cuda.memory_reserved(dev) - torch.cuda.memory_allocated(dev)
             self.chunk = int(min(args.chunk, self.T, 0.6 * free // 12))
         self.out = None if self.windowed else torch.empty((max(self.T, 1), 3), dtype=torch.int32,
                                                           device=dev)
