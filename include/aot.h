@@ -183,7 +183,8 @@ int aot_orient(const aot_graph* g, uint32_t flags, aot_oriented* out,
  *               (AOT_E_ARG with LEARNED); MERGE and PER_EDGE ignore
  *               heavy_min and the heavy arms.
  * aot_count stores the plan and strategy it resolved in the workspace;
- * aot_list and aot_digest given d = NULL use that plan, and always the
+ * aot_list and aot_digest use that plan unless d gives a table (d = NULL, the
+ * plain rule and the learned mode all take the count's plan), and always the
  * count's strategy.
  */
 #define AOT_DISPATCH_PLAIN 0

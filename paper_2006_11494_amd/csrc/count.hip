@@ -2143,7 +2143,9 @@ int emit_run(int32_t n, int64_t m, const int64_t* orow, const int32_t* ocol, con
     *err = "dispatch table holds an unknown arm or tile code";
     return -6;
   }
-  const bool stored = !d.given || d.model;     // use the plan the count resolved
+  // the plan the count resolved, unless a table is given: the plain rule's
+  // heavy arms depend on the count's statistics, the learned plan on its model
+  const bool stored = !d.given || !d.table;
   unsigned long long* dg = digest_mode ? w.digest : nullptr;
   unsigned long long* vc = reinterpret_cast<unsigned long long*>(vcount);
   // vertex counts come from edge support: the caller's array, or the count

@@ -422,3 +422,12 @@ def test_plain_rule_takes_the_sorted_copy_for_classes_with_wide_windows():
             assert table[16 + h] == want, (local, h, span, table[16 + h])
         if local == "id":
             assert 3 in [table[16 + h] for h in expect]     # the wide classes
+        # the write pass takes the count's plan, with a dispatch in plain mode too
+        aot.timing_start()
+        c = aot.count(o)
+        aot.list_triangles(o, c, dispatch=aot.Dispatch())
+        recs = aot.timing_stop()
+        arms = {(r["pass"], r["bucket"]): r["arm"] for r in recs if r["bucket"] >= 16}
+        for (p, b), arm in arms.items():
+            assert arm == table[b], (local, p, b, arm)
+        assert any(p == 1 for p, _ in arms)
