@@ -160,7 +160,9 @@ int aot_orient(const aot_graph* g, uint32_t flags, aot_oriented* out,
  *   model       AOT_DISPATCH_LEARNED: after binning, aot_count computes every
  *               bucket's features, runs the cost model (aot_mlp_* below) and
  *               gives each bucket the option with the lowest predicted
- *               log(ns per probe).  A model whose parameters or predictions are
+ *               log(ns per probe); a bitmap it picks for a class whose widest
+ *               window exceeds 28 KiB becomes the sorted copy, as in the plain
+ *               rule.  A model whose parameters or predictions are
  *               not finite, or of the wrong shape, is not used: the bucket
  *               falls back to the plain rule (the call still succeeds;
  *               aot_count_plan reports which rule ran).

@@ -1507,11 +1507,12 @@ Plan plain_plan() {
   return p;
 }
 
-// The plain rule's heavy arms once the classes' widest windows are known: the
-// bitmap where the widest fits kPlainBitmapWords, so that every owner of the
-// class uses it and the launch keeps four workgroups per CU; otherwise the
-// sorted copy for every owner (one probe costs log2 deg+ LDS reads instead of
-// one, at up to twice the resident workgroups of a wide bitmap).
+// The heavy arms once the classes' widest windows are known: the bitmap only
+// where the widest fits kPlainBitmapWords, so that every owner of the class
+// uses it and the launch keeps four workgroups per CU; otherwise the sorted
+// copy for every owner (one probe costs log2 deg+ LDS reads instead of one, at
+// up to twice the resident workgroups of a wide bitmap).  Applied to the plain
+// rule and to the cost model's choices alike; a given table is taken as is.
 constexpr int64_t kPlainBitmapWords = 7168;   // 28 KiB
 
 void plain_heavy_arms(const int64_t* hs, Plan* p) {
@@ -1915,7 +1916,7 @@ int count_run(int32_t n, int64_t m, const int64_t* orow, const int32_t* ocol, co
         return rc;
       }
     }
-    if (!d.table && !learned) plain_heavy_arms(hs.data(), &plan);
+    if (!d.table) plain_heavy_arms(hs.data(), &plan);
     const int rc = run_buckets(false, plan, hs.data(), w, orow, ocol, otail, nullptr, irow, icol,
                                nullptr, 0, 0, nullptr, nullptr, nullptr, nullptr, strategy, s,
                                err);
