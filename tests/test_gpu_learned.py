@@ -148,9 +148,10 @@ def test_learned_dispatch_gain():
     times plain and learned steps in turn on held-out graphs and prints the
     gain.  A rejected model is reported as a skip (the plain rule is kept, so
     there is nothing to time).  The judge only keeps a model that beats the
-    plain rule on its calibration graphs, so on held-out graphs of the same
-    families the learned form may not be slower beyond the timing noise of
-    these few-millisecond steps (10%)."""
+    plain rule by 2% on its calibration graphs: summed over the held-out graphs
+    of the same families the learned form must be faster than the plain rule,
+    and on none slower beyond the timing noise of these few-millisecond steps
+    (10%)."""
     need_gpu()
     net, report = learn.learn(scale=1, epochs=1000, repeats=2, log=say)
     assert report["loss_last"] < report["loss_first"]
@@ -160,6 +161,7 @@ def test_learned_dispatch_gain():
                     f"{report.get('judge_learned_ms', float('nan')):.3f} ms; the plain rule is kept")
     held_out = [inputs.rmat(17, 16, 2001, device="cuda"),
                 inputs.chung_lu(300_000, 40.0, 2.1, 30_000.0, 2002, device="cuda")]
+    plain_sum = learned_sum = 0.0
     for csr in held_out:
         o = aot.orient(csr.rowptr, csr.col)
         c = aot.count(o)
@@ -172,3 +174,7 @@ def test_learned_dispatch_gain():
         say(f"[learn] {csr.name}: plain {plain / 5:.3f} ms, learned {learned / 5:.3f} ms, "
             f"gain {plain / learned:.3f}x; plan {aot.count_plan(o, aot.count(o, d))[0]}")
         assert learned <= 1.10 * plain
+        plain_sum += plain
+        learned_sum += learned
+    say(f"[learn] held-out graphs: gain {plain_sum / learned_sum:.3f}x")
+    assert learned_sum < plain_sum
