@@ -143,7 +143,7 @@ int aot_orient(const aot_graph* g, uint32_t flags, aot_oriented* out,
  * arm picks the index the probes go into and its tile the lanes per edge.
  * The plain rule (mode AOT_DISPATCH_PLAIN) is fixed: light tiles by bin, and
  * per heavy class the LDS bitmap when the class's widest out-list window fits
- * 28 KiB (four workgroups per CU), else the LDS sorted copy; aot_count_plan
+ * 16 KiB (six workgroups per CU), else the LDS sorted copy; aot_count_plan
  * reports the arms it chose.  A table (mode AOT_DISPATCH_TABLE) gives one
  * code per bucket, e.g. chosen by the cost model.  Every choice gives
  * identical results.
@@ -161,7 +161,7 @@ int aot_orient(const aot_graph* g, uint32_t flags, aot_oriented* out,
  *               bucket's features, runs the cost model (aot_mlp_* below) and
  *               gives each bucket the option with the lowest predicted
  *               log(ns per probe); a bitmap it picks for a class whose widest
- *               window exceeds 28 KiB becomes the sorted copy, as in the plain
+ *               window exceeds 16 KiB becomes the sorted copy, as in the plain
  *               rule.  A model whose parameters or predictions are
  *               not finite, or of the wrong shape, is not used: the bucket
  *               falls back to the plain rule (the call still succeeds;

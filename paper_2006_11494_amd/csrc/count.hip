@@ -1509,11 +1509,12 @@ Plan plain_plan() {
 
 // The heavy arms once the classes' widest windows are known: the bitmap only
 // where the widest fits kPlainBitmapWords, so that every owner of the class
-// uses it and the launch keeps four workgroups per CU; otherwise the sorted
-// copy for every owner (one probe costs log2 deg+ LDS reads instead of one, at
-// up to twice the resident workgroups of a wide bitmap).  Applied to the plain
-// rule and to the cost model's choices alike; a given table is taken as is.
-constexpr int64_t kPlainBitmapWords = 7168;   // 28 KiB
+// uses it and the launch keeps six workgroups per CU (the probe kernels'
+// register limit, with 10 KiB of static LDS); otherwise the sorted copy for
+// every owner (one probe costs log2 deg+ LDS reads instead of one, at up to
+// twice the resident workgroups of a wide bitmap).  Applied to the plain rule
+// and to the cost model's choices alike; a given table is taken as is.
+constexpr int64_t kPlainBitmapWords = 4096;   // 16 KiB
 
 void plain_heavy_arms(const int64_t* hs, Plan* p) {
   for (int h = 0; h < kHeavyClasses; ++h) {

@@ -401,7 +401,7 @@ def test_bitmap_wider_than_its_lds_takes_the_sorted_copy():
 
 def test_plain_rule_takes_the_sorted_copy_for_classes_with_wide_windows():
     """The plain rule keeps the LDS bitmap for a heavy class whose widest
-    out-list window fits 28 KiB (7168 words) and gives every owner of any
+    out-list window fits 16 KiB (4096 words) and gives every owner of any
     other class the sorted copy; expected arms from the oracle's oriented
     graph (owners with deg+ >= 64, class ceil(log2 deg+))."""
     need_gpu()
@@ -418,7 +418,7 @@ def test_plain_rule_takes_the_sorted_copy_for_classes_with_wide_windows():
         table, learned = aot.count_plan(o, aot.count(o))
         assert not learned
         for h, span in expect.items():
-            want = 0 if (span + 31) // 32 <= 7168 else 3
+            want = 0 if (span + 31) // 32 <= 4096 else 3
             assert table[16 + h] == want, (local, h, span, table[16 + h])
         if local == "id":
             assert 3 in [table[16 + h] for h in expect]     # the wide classes
