@@ -53,7 +53,7 @@ enum : int {
 };
 
 constexpr int kSortClasses = 5;     // len <= 16, <= 64, <= 256, <= 4096, longer
-constexpr int kBitmapWords = 16384; // 64 KiB window for the long-list sort
+constexpr int kBitmapWords = 8192;  // 32 KiB window for the long-list sort
 constexpr int kGrid = 4096;         // grid of the grid-stride kernels
 constexpr int kRowUnroll = 4;       // chunks of kBlock entries per step on a workgroup's row
 constexpr int64_t kBigRow = 1024;   // core peel: rows updated by more than one wave,
@@ -827,7 +827,18 @@ __global__ __launch_bounds__(kBlock) void k_sort_block(int cbase, int cls, const
 // bitmap and written over itself in ascending order.  Every entry is read
 // four times and written twice however wide the row's range is.
 constexpr int64_t kBits = (int64_t)kBitmapWords * 32;
-constexpr int kMaxWindows = 4096;   // (INT32_MAX + 1) / kBits: every id range
+constexpr int kMaxWindows = 8192;   // (INT32_MAX + 1) / kBits: every id range
+
+// Windows a row of labels in [0, label_range) can span, and the dynamic LDS
+// of k_sort_bitmap: the bitmap, then the window offsets.  Labels are ranks
+// or ids below n, so with n = 2^26 the offsets take 1 KiB and four
+// workgroups share a CU.
+inline int sort_windows(int64_t label_range) {
+  return (int)std::min<int64_t>(kMaxWindows, (std::max<int64_t>(label_range, 1) - 1) / kBits + 1);
+}
+inline size_t sort_bitmap_lds(int64_t label_range) {
+  return sizeof(uint32_t) * (size_t)(kBitmapWords + sort_windows(label_range) + 1);
+}
 
 // Lanes (among the active ones) whose window w equals this lane's; w < 2^nbits.
 __device__ __forceinline__ uint64_t match_window(int w, int nbits, bool active) {
@@ -862,8 +873,8 @@ __device__ __forceinline__ int64_t emit_bitmap(const uint32_t* bm, int64_t w0, i
   return total;
 }
 
-// One workgroup per row and a 64 KiB bitmap leave room for one workgroup per
-// CU, so every pass over a row keeps kSortUnroll loads per thread in flight.
+// One workgroup per row; every pass over a row keeps kSortUnroll loads per
+// thread in flight.
 constexpr int kSortUnroll = 8;
 constexpr int32_t kRankSortMax = 512;    // buckets up to this size are ranked in LDS
 
@@ -871,10 +882,12 @@ __global__ __launch_bounds__(kBlock) void k_sort_bitmap(int cbase, int cls, cons
                                                         const int32_t* __restrict__ rows,
                                                         const int64_t* __restrict__ orow,
                                                         const int32_t* __restrict__ src,
-                                                        int32_t* __restrict__ dst) {
+                                                        int32_t* __restrict__ dst,
+                                                        int max_windows) {
   constexpr int U = kSortUnroll;
-  __shared__ uint32_t bm[kBitmapWords];
-  __shared__ int32_t woff[kMaxWindows + 1];
+  extern __shared__ uint32_t sort_lds[];
+  uint32_t* bm = sort_lds;                                            // kBitmapWords
+  int32_t* woff = reinterpret_cast<int32_t*>(sort_lds + kBitmapWords);  // max_windows + 1
   __shared__ int64_t tmp[kWavesPerBlock + 1];
   __shared__ int32_t red[2][kWavesPerBlock];
   __shared__ int32_t stmp[kWavesPerBlock + 1];
@@ -907,7 +920,7 @@ __global__ __launch_bounds__(kBlock) void k_sort_bitmap(int cbase, int cls, cons
     lo = red[0][0]; hi = red[1][0];
     for (int q = 1; q < kWavesPerBlock; ++q) { lo = min(lo, red[0][q]); hi = max(hi, red[1][q]); }
     __syncthreads();
-    const int nwin = (int)(((int64_t)hi - lo) / kBits) + 1;   // <= kMaxWindows
+    const int nwin = (int)(((int64_t)hi - lo) / kBits) + 1;   // <= max_windows
     if (nwin == 1) {
       for (int i = threadIdx.x; i < kBitmapWords; i += kBlock) bm[i] = 0u;
       __syncthreads();
@@ -951,7 +964,7 @@ __global__ __launch_bounds__(kBlock) void k_sort_bitmap(int cbase, int cls, cons
     __syncthreads();
     // exclusive prefix over the windows: each thread a run of consecutive ones
     {
-      constexpr int kPer = kMaxWindows / kBlock;
+      const int kPer = (max_windows + kBlock - 1) / kBlock;
       const int w0 = threadIdx.x * kPer;
       int32_t run = 0;
       for (int q = 0; q < kPer; ++q)
@@ -1078,7 +1091,8 @@ namespace {
 // Sorts every list of (offsets, src) into dst by its length class; cbase:
 // the counter slots holding the class sizes.
 hipError_t sort_lists(int cbase, unsigned g_small, const int32_t* counters, const int32_t* rows,
-                      const int64_t* offsets, const int32_t* src, int32_t* dst, hipStream_t s) {
+                      const int64_t* offsets, const int32_t* src, int32_t* dst,
+                      int64_t label_range, hipStream_t s) {
   k_sort_lanes<16><<<g_small, kBlock, 0, s>>>(cbase, 0, counters, rows, offsets, src, dst);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -1088,7 +1102,8 @@ hipError_t sort_lists(int cbase, unsigned g_small, const int32_t* counters, cons
   if ((e = hipGetLastError()) != hipSuccess) return e;
   k_sort_block<<<kGrid, kBlock, 0, s>>>(cbase, 3, counters, rows, offsets, src, dst);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  k_sort_bitmap<<<512, kBlock, 0, s>>>(cbase, 4, counters, rows, offsets, src, dst);
+  k_sort_bitmap<<<1024, kBlock, sort_bitmap_lds(label_range), s>>>(
+      cbase, 4, counters, rows, offsets, src, dst, sort_windows(label_range));
   return hipGetLastError();
 }
 
@@ -1296,7 +1311,7 @@ int orient_impl(int32_t n, int64_t nnz, const int64_t* rowptr, const int32_t* co
                                                                   counters, rows);
   AOT_TRY(hipGetLastError());
   const unsigned g_small = (unsigned)std::min<int64_t>(kGrid, cdiv(n, kBlock / 16) + 1);
-  AOT_TRY(sort_lists(kCSortCount, g_small, counters, rows, orow, unsorted, ocol, s));
+  AOT_TRY(sort_lists(kCSortCount, g_small, counters, rows, orow, unsorted, ocol, n, s));
 
   if (!in_by_rank) return 0;
   // sort each in-list into ascending rank (= edge order of the in-edges): the
@@ -1310,7 +1325,7 @@ int orient_impl(int32_t n, int64_t nnz, const int64_t* rowptr, const int32_t* co
   k_scatter_classes<kInLists><<<grid_for(n, kClassChunk), kBlock, 0, s>>>(n, dminus, perm, rowptr,
                                                                      counters, rows);
   AOT_TRY(hipGetLastError());
-  AOT_TRY(sort_lists(kCInCount, g_small, counters, rows, irow, unsorted, icol, s));
+  AOT_TRY(sort_lists(kCInCount, g_small, counters, rows, irow, unsorted, icol, n, s));
   return 0;
 }
 
