@@ -274,6 +274,37 @@ __global__ __launch_bounds__(kBlock) void k_line_samples(int64_t m, const int32_
     lsamp[q] = ocol[q * kLine];
 }
 
+// The items of one class whose owned edges hold triangles in [first, first +
+// count) (their smallest and largest owned edge, from the count pass, bound
+// the item's part of the list), appended to list in any order (each item
+// writes fixed slots) with one atomic per wave.  A write window then visits
+// only these instead of testing every item of the class on one workgroup each.
+__global__ __launch_bounds__(kBlock) void k_window_items(int64_t base, int64_t items,
+                                                         const int2* __restrict__ item_e,
+                                                         const int64_t* __restrict__ tri_off,
+                                                         int64_t first, int64_t count,
+                                                         int32_t* __restrict__ list,
+                                                         int32_t* __restrict__ n) {
+  for (int64_t i0 = (int64_t)blockIdx.x * kBlock; i0 < items; i0 += (int64_t)gridDim.x * kBlock) {
+    const int64_t i = i0 + threadIdx.x;
+    bool in = false;
+    if (i < items) {
+      const int2 r = item_e[base + i];
+      if (r.y >= r.x) {
+        const int64_t t0 = tri_off[r.x], t1 = tri_off[r.y + 1];
+        in = t1 > first && t0 < first + count && t1 > t0;
+      }
+    }
+    const uint64_t m = ballot(in);
+    if (!m) continue;
+    const int leader = __ffsll((long long)m) - 1;
+    int32_t at = 0;
+    if (lane_id() == leader) at = atomicAdd(n, (int32_t)__popcll(m));
+    at = __shfl(at, leader, kWave);
+    if (in) list[at + popc_below(m)] = (int32_t)(base + i);
+  }
+}
+
 // Work items per heavy class, the owner-list entries they stage, and the
 // largest owner-list span of the class (which sizes the bitmap arm's LDS).
 __global__ __launch_bounds__(kBlock) void k_item_count(int32_t n, const int64_t* __restrict__ orow,
@@ -536,6 +567,8 @@ struct HeavyArgs {
   const int32_t* lsamp = nullptr;  // count pass: lsamp[q] = ocol[kLine * q], the first
                                    // entry of every kLine-entry line of the out-lists
   int64_t item_base, item_count;
+  const int32_t* item_list = nullptr;     // write pass, windows: the items to visit,
+  const int32_t* item_list_n = nullptr;   // and how many (device), instead of them all
   const int64_t* orow;
   const int32_t* ocol;
   const int64_t* irow;
@@ -1162,8 +1195,10 @@ void k_heavy(HeavyArgs a) {
   if constexpr (!kEmit) {
     if (threadIdx.x == 0) sh.looks = 0;      // read after the last item's barriers
   }
-  for (int64_t it = blockIdx.x; it < a.item_count; it += gridDim.x)
-    heavy_item<kEmit, kDigest, kArms>(sh, lds, a, a.item_base + it, tri_block, look_block, dg);
+  const int64_t n_items = a.item_list_n ? (int64_t)*a.item_list_n : a.item_count;
+  for (int64_t it = blockIdx.x; it < n_items; it += gridDim.x)
+    heavy_item<kEmit, kDigest, kArms>(sh, lds, a, a.item_list ? a.item_list[it] : a.item_base + it,
+                                      tri_block, look_block, dg);
   heavy_finish<kEmit, kDigest>(sh, a, tri_block, look_block, dg);
 }
 
@@ -1613,6 +1648,8 @@ struct CountWs {
   int32_t* ieid;                     // [m] per in-list entry: owned in-edge id
   int32_t* hfirst;                   // [m] per heavy-owned edge: ocol index of its first hit
   int32_t* lsamp;                    // [m / kLine + 1] first entry of each line of ocol
+  int32_t* witems;                   // [items] the items a write window visits
+  int32_t* wcount;                   // [kHeavyClasses] their number per class
   int32_t* hist;                     // [kLightBins][chunks] light edges per chunk
   int64_t* hoff;                     // its exclusive scan
   int64_t* win;                      // window: edge range, then each bin's elist run
@@ -1635,6 +1672,8 @@ CountWs carve_count(Carve& c, int32_t n, int64_t m) {
   w.ieid = c.take<int32_t>(m);
   w.hfirst = c.take<int32_t>(m);
   w.lsamp = c.take<int32_t>(cdiv(m, kLine) + 1);
+  w.witems = c.take<int32_t>(max_items(n, m));
+  w.wcount = c.take<int32_t>(kHeavyClasses);
   const int64_t cells = kLightBins * cdiv(m, kScatterChunk);
   w.hist = c.take<int32_t>(cells);
   w.hoff = c.take<int64_t>(cells + 1);
@@ -1818,6 +1857,9 @@ int run_buckets(bool emit, const Plan& plan, const int64_t* hs, const CountWs& w
     }
     lbase += all;
   }
+  // a write window visits only the items whose triangles it holds
+  const bool compact = emit && !digest && win;
+  if (compact) AOT_TRY(fill_i32(w.wcount, kHeavyClasses, 0, s));
   for (int h = 0; h < kHeavyClasses; ++h) {
     const int64_t* st = hs + (kHeavyBase + h) * kStats;
     const int64_t items = st[kSItems];
@@ -1854,6 +1896,14 @@ int run_buckets(bool emit, const Plan& plan, const int64_t* hs, const CountWs& w
     const int rec = timing_begin(emit ? 1 : 0, kHeavyBase + h, arm, kBlock, st[kSEdges],
                                  emit ? st[kSLookups] : st[kSProbes], st[kSStaged],
                                  st[kSTriangles], s);
+    if (compact) {
+      k_window_items<<<grid_cap(cdiv(items, kBlock)), kBlock, 0, s>>>(
+          st[kSItemBase], items, w.item_e, tri_off, first, count, w.witems + st[kSItemBase],
+          w.wcount + h);
+      AOT_TRY(hipGetLastError());
+      a.item_list = w.witems + st[kSItemBase];
+      a.item_list_n = w.wcount + h;
+    }
     const size_t dyn = sizeof(uint32_t) * (size_t)std::max(a.idx_words, 1);
     AOT_TRY(launch_heavy(emit, digest, class_arms(arm, h, st[kSSpan], a.idx_words), a,
                          grid_cap(items), dyn, s));
