@@ -385,7 +385,8 @@ __global__ __launch_bounds__(kBlock) void k_orient_count(RowSet rs,
                                                          const int32_t* __restrict__ rank,
                                                          bool by_id,
                                                          int32_t* __restrict__ dplus,
-                                                         int32_t* __restrict__ dminus) {
+                                                         int32_t* __restrict__ dminus,
+                                                         int32_t* __restrict__ rcol) {
   constexpr int kGroups = kBlock / G;
   __shared__ int32_t red[kWavesPerBlock];
   const int gi = threadIdx.x / G, li = threadIdx.x % G;
@@ -416,10 +417,18 @@ __global__ __launch_bounds__(kBlock) void k_orient_count(RowSet rs,
             c[q] = col[beg + (ok[q] ? j : 0)];
           }
 #pragma unroll
-          for (int q = 0; q < kRowUnroll; ++q) cnt += ok[q] & (rank[c[q]] > r);
+          for (int q = 0; q < kRowUnroll; ++q) {
+            const int32_t x = rank[c[q]];
+            cnt += ok[q] & (x > r);
+            if (ok[q]) rcol[beg + j0 + q * G] = x;     // the write pass reads it back
+          }
         }
       } else {
-        for (int64_t j = li; j < deg; j += G) cnt += rank[col[beg + j]] > r;
+        for (int64_t j = li; j < deg; j += G) {
+          const int32_t x = rank[col[beg + j]];
+          cnt += x > r;
+          rcol[beg + j] = x;
+        }
       }
     }
     if constexpr (G <= kWave) {
@@ -448,27 +457,28 @@ template <int G>
 __device__ __forceinline__ void orient_write_long(int64_t r, int64_t o, bool by_id, int64_t beg,
                                                   int64_t deg, int64_t op, int64_t ip,
                                                   const int32_t* __restrict__ col,
-                                                  const int32_t* __restrict__ rank,
+                                                  const int32_t* __restrict__ rcol,
                                                   int32_t* __restrict__ unsorted,
                                                   int32_t* __restrict__ otail,
                                                   int32_t* __restrict__ icol) {
   __shared__ int32_t so[kRowUnroll][kWavesPerBlock], si[kRowUnroll][kWavesPerBlock];
   const int w = threadIdx.x / kWave;
   for (int64_t j0 = 0; j0 < deg; j0 += (int64_t)kBlock * kRowUnroll) {
-    int32_t rv[kRowUnroll];
+    int32_t rv[kRowUnroll], xs[kRowUnroll];
     bool out[kRowUnroll], in[kRowUnroll];
     uint64_t bo[kRowUnroll], bi[kRowUnroll];
 #pragma unroll
     for (int q = 0; q < kRowUnroll; ++q) {
       const int64_t j = j0 + q * kBlock + threadIdx.x;
       out[q] = j < deg;                   // valid, for now
-      rv[q] = col[beg + (out[q] ? j : 0)];
+      const int64_t at = beg + (out[q] ? j : 0);
+      xs[q] = rcol[at];                   // the ranks the count pass gathered
+      rv[q] = by_id ? col[at] : xs[q];
     }
 #pragma unroll
     for (int q = 0; q < kRowUnroll; ++q) {
       const bool valid = out[q];
-      const int32_t x = rank[rv[q]];
-      if (!by_id) rv[q] = x;
+      const int32_t x = xs[q];
       out[q] = valid && x > r;
       in[q] = valid && x < r;
       bo[q] = ballot(out[q]);
@@ -506,7 +516,8 @@ __global__ __launch_bounds__(kBlock) void k_orient_write(
     RowSet rs, const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
     const int32_t* __restrict__ perm, const int32_t* __restrict__ rank, bool by_id,
     const int64_t* __restrict__ orow, const int64_t* __restrict__ irow,
-    int32_t* __restrict__ unsorted, int32_t* __restrict__ otail, int32_t* __restrict__ icol) {
+    int32_t* __restrict__ unsorted, int32_t* __restrict__ otail, int32_t* __restrict__ icol,
+    const int32_t* __restrict__ rcol) {
   constexpr int kGroups = kBlock / G;
   __shared__ int32_t so[kWavesPerBlock], si[kWavesPerBlock];
   const int gi = threadIdx.x / G, li = threadIdx.x % G;
@@ -527,15 +538,14 @@ __global__ __launch_bounds__(kBlock) void k_orient_write(
       ip = irow[o];
     }
     if constexpr (G == kBlock) {
-      orient_write_long<G>(r, o, by_id, beg, deg, op, ip, col, rank, unsorted, otail, icol);
+      orient_write_long<G>(r, o, by_id, beg, deg, op, ip, col, rcol, unsorted, otail, icol);
       continue;
     }
     for (int64_t j0 = 0; j0 < deg; j0 += G) {
       const int64_t j = j0 + li;
       const bool valid = j < deg;
-      const int32_t cv = valid ? col[beg + j] : 0;
-      const int32_t x = valid ? rank[cv] : 0;
-      const int32_t rv = by_id ? cv : x;
+      const int32_t x = valid ? rcol[beg + j] : 0;    // gathered by the count pass
+      const int32_t rv = by_id ? (valid ? col[beg + j] : 0) : x;
       const bool out = valid && x > r;
       const bool in = valid && x < r;
       const uint64_t bo = ballot(out), bi = ballot(in);
@@ -1079,6 +1089,7 @@ size_t orient_workspace_bytes(int32_t n, int64_t nnz) {
   c.take<int32_t>(n);                               // dplus
   c.take<int32_t>(n);                               // dminus
   c.take<int32_t>(m);                               // unsorted
+  c.take<int32_t>(nnz);                             // rcol
   c.take<int32_t>(n);                               // rows_by_len
   c.take<int32_t>(kCounters);
   c.take<char>((int64_t)scan_workspace(n));
@@ -1178,6 +1189,7 @@ int orient_impl(int32_t n, int64_t nnz, const int64_t* rowptr, const int32_t* co
   int32_t* dplus = c.take<int32_t>(n);
   int32_t* dminus = c.take<int32_t>(n);
   int32_t* unsorted = c.take<int32_t>(m);
+  int32_t* rcol = c.take<int32_t>(nnz);   // rank of every symmetric entry, by input position
   int32_t* rows = c.take<int32_t>(n);
   int32_t* counters = c.take<int32_t>(kCounters);
   void* scan_tmp = c.take<char>((int64_t)scan_workspace(n));
@@ -1289,16 +1301,16 @@ int orient_impl(int32_t n, int64_t nnz, const int64_t* rowptr, const int32_t* co
                          [&](const RowSet& rs, unsigned grid, hipStream_t st) {          \
                            KERNEL<G><<<grid, kBlock, 0, st>>>(rs, __VA_ARGS__);          \
                          }))
-  ROWS(0, 4, k_orient_count, rowptr, col, eperm, erank, by_id, dplus, dminus);
-  ROWS(1, 16, k_orient_count, rowptr, col, eperm, erank, by_id, dplus, dminus);
-  ROWS(2, 64, k_orient_count, rowptr, col, eperm, erank, by_id, dplus, dminus);
-  ROWS(3, 256, k_orient_count, rowptr, col, eperm, erank, by_id, dplus, dminus);
+  ROWS(0, 4, k_orient_count, rowptr, col, eperm, erank, by_id, dplus, dminus, rcol);
+  ROWS(1, 16, k_orient_count, rowptr, col, eperm, erank, by_id, dplus, dminus, rcol);
+  ROWS(2, 64, k_orient_count, rowptr, col, eperm, erank, by_id, dplus, dminus, rcol);
+  ROWS(3, 256, k_orient_count, rowptr, col, eperm, erank, by_id, dplus, dminus, rcol);
   AOT_TRY(exclusive_scan(dplus, orow, n, scan_tmp, s));
   AOT_TRY(exclusive_scan(dminus, irow, n, scan_tmp, s));
-  ROWS(0, 4, k_orient_write, rowptr, col, eperm, erank, by_id, orow, irow, unsorted, otail, icol);
-  ROWS(1, 16, k_orient_write, rowptr, col, eperm, erank, by_id, orow, irow, unsorted, otail, icol);
-  ROWS(2, 64, k_orient_write, rowptr, col, eperm, erank, by_id, orow, irow, unsorted, otail, icol);
-  ROWS(3, 256, k_orient_write, rowptr, col, eperm, erank, by_id, orow, irow, unsorted, otail, icol);
+  ROWS(0, 4, k_orient_write, rowptr, col, eperm, erank, by_id, orow, irow, unsorted, otail, icol, rcol);
+  ROWS(1, 16, k_orient_write, rowptr, col, eperm, erank, by_id, orow, irow, unsorted, otail, icol, rcol);
+  ROWS(2, 64, k_orient_write, rowptr, col, eperm, erank, by_id, orow, irow, unsorted, otail, icol, rcol);
+  ROWS(3, 256, k_orient_write, rowptr, col, eperm, erank, by_id, orow, irow, unsorted, otail, icol, rcol);
 #undef ROWS
 
   // sort each out-list into ocol (with labels by id, rows of a valid CSR
