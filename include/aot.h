@@ -142,11 +142,12 @@ int aot_orient(const aot_graph* g, uint32_t flags, aot_oriented* out,
  * Dispatch of the probe kernels.  Edges are grouped into buckets; a bucket's
  * arm picks the index the probes go into and its tile the lanes per edge.
  * The plain rule (mode AOT_DISPATCH_PLAIN) is fixed: light tiles by bin, and
- * per heavy class the LDS bitmap when the class's widest out-list window fits
- * 16 KiB (six workgroups per CU), else the LDS sorted copy; aot_count_plan
- * reports the arms it chose.  A table (mode AOT_DISPATCH_TABLE) gives one
- * code per bucket, e.g. chosen by the cost model.  Every choice gives
- * identical results.
+ * the LDS bitmap for every heavy class; aot_count_plan reports the arms it
+ * chose.  A bitmap class reserves its widest out-list window, or 16 KiB (six
+ * workgroups per CU) if that is wider, or the sorted copy's deg+ words if
+ * those are more: an owner whose window does not fit takes the LDS sorted
+ * copy.  A table (mode AOT_DISPATCH_TABLE) gives one code per bucket, e.g.
+ * chosen by the cost model.  Every choice gives identical results.
  *   heavy_min   owners with deg+ >= heavy_min are processed owner-grouped with
  *               an LDS index (0 = library default, 64).
  *   table       host array of AOT_NUM_BUCKETS codes, or NULL: entry k in 0..7
@@ -160,9 +161,7 @@ int aot_orient(const aot_graph* g, uint32_t flags, aot_oriented* out,
  *   model       AOT_DISPATCH_LEARNED: after binning, aot_count computes every
  *               bucket's features, runs the cost model (aot_mlp_* below) and
  *               gives each bucket the option with the lowest predicted
- *               log(ns per probe); a bitmap it picks for a class whose widest
- *               window exceeds 16 KiB becomes the sorted copy, as in the plain
- *               rule.  A model whose parameters or predictions are
+ *               log(ns per probe).  A model whose parameters or predictions are
  *               not finite, or of the wrong shape, is not used: the bucket
  *               falls back to the plain rule (the call still succeeds;
  *               aot_count_plan reports which rule ran).

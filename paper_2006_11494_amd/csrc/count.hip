@@ -1532,31 +1532,14 @@ struct Plan {
 };
 
 // The plain rule: lanes per edge about the bin's c; heavy owners use the
-// bitmap (falling back to the sorted copy, then the global search, when it
-// does not fit).
+// bitmap, held to 16 KiB per class (an owner whose window does not fit takes
+// the sorted copy, then the global search).
 Plan plain_plan() {
   Plan p;
   for (int k = 0; k < kLightBins; ++k)
     p.light_tile[k] = k <= 2 ? 4 : k == 3 ? 8 : k == 4 ? 16 : k == 5 ? 32 : 64;
   for (int h = 0; h < kHeavyClasses; ++h) p.heavy_arm[h] = kArmBitmap;
   return p;
-}
-
-// The heavy arms once the classes' widest windows are known: the bitmap only
-// where the widest fits kPlainBitmapWords, so that every owner of the class
-// uses it and the launch keeps six workgroups per CU (the probe kernels'
-// register limit, with 10 KiB of static LDS); otherwise the sorted copy for
-// every owner (one probe costs log2 deg+ LDS reads instead of one, at up to
-// twice the resident workgroups of a wide bitmap).  Applied to the plain rule
-// and to the cost model's choices alike; a given table is taken as is.
-constexpr int64_t kPlainBitmapWords = 4096;   // 16 KiB
-
-void plain_heavy_arms(const int64_t* hs, Plan* p) {
-  for (int h = 0; h < kHeavyClasses; ++h) {
-    const int64_t* st = hs + (kHeavyBase + h) * kStats;
-    if (p->heavy_arm[h] == kArmBitmap && st[kSItems] > 0 && cdiv(st[kSSpan], 32) > kPlainBitmapWords)
-      p->heavy_arm[h] = kArmSorted;
-  }
 }
 
 bool valid_tile(int t) { return t == 4 || t == 8 || t == 16 || t == 32 || t == 64; }
@@ -1710,21 +1693,27 @@ hipError_t launch_light(int tile, unsigned grid, const LightArgs& a, int64_t bas
   return hipGetLastError();
 }
 
+// The most LDS a bitmap class reserves when its widest window is larger:
+// 16 KiB keeps six workgroups per CU (the probe kernels' register limit, with
+// 10 KiB of static LDS).
+constexpr int64_t kBitmapCapWords = 4096;
+
 // LDS words a heavy class's launch reserves for its index: enough for the
 // requested arm on every owner of the class (bitmap: the class's widest
 // span; hash: a power-of-two table of twice deg+; sorted: deg+), capped at
-// kMaxIndexWords, beyond which owners fall back to the next arm.  A class
-// whose widest bitmap exceeds the cap reserves only the sorted copy's
-// deg+ words: its narrow owners keep the bitmap within them, the others
-// take the sorted copy, and the launch keeps its occupancy instead of
-// holding the cap for owners that could not use it.
+// kMaxIndexWords, beyond which owners fall back to the next arm.  A bitmap
+// class whose widest window exceeds kBitmapCapWords reserves that many words,
+// or the sorted copy's deg+ if more: owners whose window fits keep the bitmap
+// (one LDS read per probe), the others take the sorted copy (log2 deg+ reads),
+// and the launch keeps its occupancy instead of holding a wide bitmap's words
+// (a 38 KiB bitmap leaves three workgroups per CU) for every owner.
 int index_words(int arm, int h, int64_t max_span) {
   const int64_t dmax = int64_t(1) << h;       // class h holds deg+ in (2^(h-1), 2^h]
   int64_t need = 0;
   if (arm == kArmBitmap) {
     need = (max_span + 31) / 32;
-    if (need <= kMaxIndexWords) return (int)std::max<int64_t>(need, 1);
-    return (int)std::min<int64_t>(dmax, kMaxIndexWords);
+    if (need <= kBitmapCapWords) return (int)std::max<int64_t>(need, 1);
+    return (int)std::min<int64_t>(std::max<int64_t>(dmax, kBitmapCapWords), kMaxIndexWords);
   }
   if (arm == kArmHash) {
     int64_t t = 2;
@@ -1967,7 +1956,6 @@ int count_run(int32_t n, int64_t m, const int64_t* orow, const int32_t* ocol, co
         return rc;
       }
     }
-    if (!d.table) plain_heavy_arms(hs.data(), &plan);
     const int rc = run_buckets(false, plan, hs.data(), w, orow, ocol, otail, nullptr, irow, icol,
                                nullptr, 0, 0, nullptr, nullptr, nullptr, nullptr, strategy, s,
                                err);
