@@ -263,7 +263,7 @@ def in_lists(o: Oriented):
 
 
 def edge_counts(o: Oriented, e_lo: int = 0, e_hi: int | None = None) -> np.ndarray:
-    """|N+(u) n N+(v)| for each directed edge in [e_lo, e_hi) (Algorithm 1, line 4)."""
+    """|N+(u) n N+(v)| for each directed edge in [e_lo, e_hi) (Algorithm 1's intersection step)."""
     lib = _load()
     e_hi = o.m if e_hi is None else e_hi
     out = np.zeros(max(e_hi - e_lo, 1), np.int32)

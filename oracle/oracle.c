@@ -279,7 +279,7 @@ static int32_t edge_tail(int32_t n, const int64_t* orow, int64_t e) {
   return lo;
 }
 
-/* cnt[i] = |N+(u) n N+(v)| for edges e = e_lo + i, e < e_hi (CF's line 4). */
+/* cnt[i] = |N+(u) n N+(v)| for edges e = e_lo + i, e < e_hi (CF's intersection step, Algorithm 1). */
 void orc_edge_counts(int32_t n, const int64_t* orow, const int32_t* ocol,
                      int64_t e_lo, int64_t e_hi, int32_t* cnt) {
   if (e_hi <= e_lo) return;
