@@ -390,10 +390,9 @@ def wide_and_narrow_windows():
 
 def test_bitmap_wider_than_its_lds_takes_the_sorted_copy():
     """With id labels the Chung-Lu owners' windows span most of the 600 k ids,
-    beyond what any LDS bitmap holds: their classes reserve only the sorted
-    copy's words and those owners take it.  The block's owners, in the same
-    classes, have windows of at most 300 ids and keep the bitmap inside
-    those words."""
+    beyond the 16 KiB a bitmap class reserves at most: those owners take the
+    sorted copy.  The block's owners, in the same classes, have windows of at
+    most 300 ids and keep the bitmap inside the class's reservation."""
     check_all(wide_and_narrow_windows(), "chunglu600k_block_id", local="id", windows=False,
               dispatches={k: DISPATCHES[k] for k in ("plain", "all_heavy_bitmap",
                                                      "all_heavy_hash", "mixed")})
