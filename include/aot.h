@@ -130,7 +130,10 @@ typedef struct aot_oriented {
  *           triangle set do not change; the list order follows the labels.
  *   out     caller-allocated arrays of the sizes listed in aot_oriented;
  *           out->n and out->m are written.
- *   ws      device workspace of at least aot_orient_workspace() bytes.
+ *   ws      device workspace of at least aot_orient_workspace() bytes (6.5 to
+ *           7 bytes per symmetric entry: each entry's rank, gathered once, and
+ *           the unsorted out-lists, plus O(n)); not read by later calls, so
+ *           work queued after this call on `stream` may reuse it.
  * Synchronises `stream` once (to size its launches).  AOT_E_GRAPH (only with
  * AOT_VALIDATE) if a row is unsorted, has a self-loop, a duplicate, an id out
  * of range, or the graph is not symmetric. */
